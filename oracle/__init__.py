@@ -1,0 +1,277 @@
+"""FP64 CPU oracle of the differentiable tile rasterizer.
+
+TEST INFRASTRUCTURE ONLY.  Imported by ``tests/``, by the smoke check and
+by the benchmark's CPU-baseline leg.  The GPU library and its Python
+binding never import this package, and this package never imports them.
+
+The arithmetic lives in ``oracle.c`` (double precision, one pixel at a
+time); this module compiles it with gcc, marshals NumPy arrays through
+ctypes and chains the stages into a forward and a backward.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lock = threading.Lock()
+_lib = None
+
+TILE = 16
+ALPHA_MIN = 1.0 / 255.0
+ALPHA_MAX = 0.99
+T_MIN = 1e-4
+GUARD_SKIP, GUARD_STOP, GUARD_CLAMP = 1, 2, 4
+
+
+def build(force: bool = False) -> str:
+    """Compile oracle.c into liboracle.so (gcc, -O2, OpenMP)."""
+    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-D_DEFAULT_SOURCE",
+                               "-Wall", "-Wno-unknown-pragmas", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+class _Cam(C.Structure):
+    _fields_ = [("fx", C.c_double), ("fy", C.c_double), ("cx", C.c_double), ("cy", C.c_double),
+                ("R", C.c_double * 9), ("t", C.c_double * 3), ("W", C.c_int32), ("H", C.c_int32),
+                ("znear", C.c_double), ("zfar", C.c_double)]
+
+
+class _Opt(C.Structure):
+    _fields_ = [("sh_degree", C.c_int32), ("dilation", C.c_double), ("aa", C.c_int32),
+                ("bg", C.c_double * 3)]
+
+
+_P = C.c_void_p
+
+
+class _Proj(C.Structure):
+    _fields_ = [(name, _P) for name in ("visible", "tcam", "cov2d", "rho", "conic", "mean2d", "depth",
+                                        "opac", "rgb", "clamped", "extent", "radius", "rect", "tiles")]
+
+
+def _load():
+    global _lib
+    with _lock:
+        if _lib is None:
+            build()
+            lib = C.CDLL(_LIB_PATH)
+            lib.orc_project.restype = C.c_int
+            lib.orc_bin.restype = C.c_int64
+            lib.orc_render.restype = C.c_int
+            lib.orc_render_bwd.restype = C.c_int
+            lib.orc_project_bwd.restype = C.c_int
+            lib.orc_num_threads.restype = C.c_int
+            _lib = lib
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return C.c_void_p(a.ctypes.data) if a is not None else None
+
+
+def num_threads() -> int:
+    return int(_load().orc_num_threads())
+
+
+def make_cam(cam) -> _Cam:
+    vm = np.asarray(cam.viewmat, np.float32).astype(np.float64)
+    c = _Cam()
+    c.fx, c.fy = float(np.float32(cam.fx)), float(np.float32(cam.fy))
+    c.cx, c.cy = float(np.float32(cam.cx)), float(np.float32(cam.cy))
+    for i in range(3):
+        for j in range(3):
+            c.R[3 * i + j] = vm[i, j]
+        c.t[i] = vm[i, 3]
+    c.W, c.H = int(cam.width), int(cam.height)
+    c.znear, c.zfar = float(np.float32(cam.near)), float(np.float32(cam.far))
+    return c
+
+
+def make_opt(sh_degree=3, dilation=0.3, aa=False, bg=(0.0, 0.0, 0.0)) -> _Opt:
+    o = _Opt()
+    o.sh_degree = int(sh_degree)
+    o.dilation = float(np.float32(dilation))
+    o.aa = int(bool(aa))
+    for k in range(3):
+        o.bg[k] = float(np.float32(bg[k]))
+    return o
+
+
+def _c64(a):
+    """Parameters enter the oracle as float64 (float32 inputs convert exactly)."""
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def sh_basis(dirs: np.ndarray) -> np.ndarray:
+    """Real SH basis (16 functions, degree <= 3) at unit directions [n][3]."""
+    d = np.ascontiguousarray(dirs, np.float64)
+    out = np.empty((d.shape[0], 16), np.float64)
+    _load().orc_sh_basis(C.c_int64(d.shape[0]), _ptr(d), _ptr(out))
+    return out
+
+
+def project(scene, cam, **opt) -> dict:
+    """Per-Gaussian FP64 projection of one view (EWA, colour, rectangle)."""
+    lib = _load()
+    n = scene.n
+    out = {
+        "visible": np.zeros(n, np.int32), "tcam": np.zeros((n, 3)), "cov2d": np.zeros((n, 3)),
+        "rho": np.zeros(n), "conic": np.zeros((n, 3)), "mean2d": np.zeros((n, 2)), "depth": np.zeros(n),
+        "opac": np.zeros(n), "rgb": np.zeros((n, 3)), "clamped": np.zeros((n, 3), np.int32),
+        "extent": np.zeros(n), "radius": np.zeros(n, np.int32), "rect": np.zeros((n, 4), np.int32),
+        "tiles": np.zeros(n, np.int32),
+    }
+    pr = _Proj(*[out[k].ctypes.data for k, _ in _Proj._fields_])
+    means, scales, quats = _c64(scene.means), _c64(scene.scales), _c64(scene.quats)
+    opac, sh = _c64(scene.opacities), _c64(scene.sh)
+    c, o = make_cam(cam), make_opt(**opt)
+    lib.orc_project(C.c_int64(n), _ptr(means), _ptr(scales), _ptr(quats), _ptr(opac), _ptr(sh),
+                    C.byref(c), C.byref(o), C.byref(pr))
+    return out
+
+
+def depth_key(depth: np.ndarray) -> np.ndarray:
+    """Sort key of a view-space depth: the bit pattern of its float32 value
+    (monotone for positive depths)."""
+    return np.ascontiguousarray(np.asarray(depth, np.float64).astype(np.float32)).view(np.uint32)
+
+
+def bin_pairs(rect, tiles, depth_keys, slot_view, cams) -> dict:
+    """Pairs (global tile, slot) sorted by (tile, depth key, slot) and the
+    [start, end) range of every global tile; views are concatenated."""
+    lib = _load()
+    rect = np.ascontiguousarray(rect, np.int32)
+    tiles = np.ascontiguousarray(tiles, np.int32)
+    depth_keys = np.ascontiguousarray(depth_keys, np.uint32)
+    slot_view = np.ascontiguousarray(slot_view, np.int32)
+    tx = np.array([c.tiles_x for c in cams], np.int32)
+    counts = np.array([c.n_tiles for c in cams], np.int64)
+    toff = np.concatenate([[0], np.cumsum(counts)[:-1]]).astype(np.int32)
+    n_tiles = int(counts.sum())
+    P = int(tiles.astype(np.int64).sum())
+    pair_tile = np.zeros(max(P, 1), np.uint32)
+    pair_slot = np.zeros(max(P, 1), np.uint32)
+    ranges = np.zeros((n_tiles, 2), np.uint32)
+    got = lib.orc_bin(C.c_int64(len(tiles)), _ptr(rect), _ptr(tiles), _ptr(depth_keys), _ptr(slot_view),
+                      _ptr(tx), _ptr(toff), C.c_int64(n_tiles), C.c_int64(P), _ptr(pair_tile),
+                      _ptr(pair_slot), _ptr(ranges))
+    assert got == P, (got, P)
+    return {"pair_tile": pair_tile[:P], "pair_slot": pair_slot[:P], "ranges": ranges,
+            "tile_off": toff.astype(np.int64), "n_pairs": P}
+
+
+def _twod(proj_list):
+    """Concatenate per-view 2D quantities into slot-indexed float64 arrays."""
+    cat = lambda k: np.ascontiguousarray(np.concatenate([p[k] for p in proj_list], 0), np.float64)
+    return cat("mean2d"), cat("conic"), cat("opac"), cat("rgb"), cat("depth")
+
+
+DEFAULT_GUARD = (1e-4, 1e-4, 1e-4)
+
+
+def render_view(cam, opt: dict, tile_off: int, twod, pair_slot, ranges, tile_mask=None,
+                guard_eps=DEFAULT_GUARD) -> dict:
+    lib = _load()
+    mean2d, conic, opac, rgb, depth = twod
+    H, W = cam.height, cam.width
+    out = {"rgb": np.zeros((H, W, 3)), "depth": np.zeros((H, W)), "alpha": np.zeros((H, W)),
+           "T": np.zeros((H, W)), "last": np.zeros((H, W), np.int32), "guard": np.zeros((H, W), np.uint8)}
+    g = np.ascontiguousarray(guard_eps, np.float64) if guard_eps is not None else None
+    mask = np.ascontiguousarray(tile_mask, np.uint8) if tile_mask is not None else None
+    lib.orc_render(C.byref(make_cam(cam)), C.byref(make_opt(**opt)), C.c_int64(tile_off), _ptr(mean2d),
+                   _ptr(conic), _ptr(opac), _ptr(rgb), _ptr(depth), _ptr(np.ascontiguousarray(pair_slot, np.uint32)),
+                   _ptr(np.ascontiguousarray(ranges, np.uint32)), _ptr(mask), _ptr(g), _ptr(out["rgb"]),
+                   _ptr(out["depth"]), _ptr(out["alpha"]), _ptr(out["T"]), _ptr(out["last"]), _ptr(out["guard"]))
+    return out
+
+
+def render_bwd_view(cam, opt: dict, tile_off: int, twod, pair_slot, ranges, g_rgb, g_depth, g_alpha,
+                    d2, absg, tile_mask=None):
+    lib = _load()
+    mean2d, conic, opac, rgb, depth = twod
+    g_rgb = np.ascontiguousarray(g_rgb, np.float64)
+    g_depth = np.ascontiguousarray(g_depth, np.float64)
+    g_alpha = np.ascontiguousarray(g_alpha, np.float64)
+    mask = np.ascontiguousarray(tile_mask, np.uint8) if tile_mask is not None else None
+    lib.orc_render_bwd(C.byref(make_cam(cam)), C.byref(make_opt(**opt)), C.c_int64(tile_off), _ptr(mean2d),
+                       _ptr(conic), _ptr(opac), _ptr(rgb), _ptr(depth),
+                       _ptr(np.ascontiguousarray(pair_slot, np.uint32)), _ptr(np.ascontiguousarray(ranges, np.uint32)),
+                       _ptr(mask), _ptr(g_rgb), _ptr(g_depth), _ptr(g_alpha), _ptr(d2), _ptr(absg))
+
+
+def project_bwd(scene, cam, opt: dict, d2_view, grads: dict):
+    """Adds one view's parameter gradients into ``grads`` (float64 arrays in
+    the parameter layouts); returns |d mean2d| per Gaussian."""
+    lib = _load()
+    n = scene.n
+    norm = np.zeros(n)
+    lib.orc_project_bwd(C.c_int64(n), _ptr(_c64(scene.means)), _ptr(_c64(scene.scales)), _ptr(_c64(scene.quats)),
+                        _ptr(_c64(scene.opacities)), _ptr(_c64(scene.sh)), C.byref(make_cam(cam)),
+                        C.byref(make_opt(**opt)), _ptr(np.ascontiguousarray(d2_view, np.float64)),
+                        _ptr(grads["means"]), _ptr(grads["scales"]), _ptr(grads["quats"]), _ptr(grads["opacities"]),
+                        _ptr(grads["sh"]), _ptr(norm))
+    return norm
+
+
+def forward(scene, cams, opt: dict | None = None, guard_eps=DEFAULT_GUARD, depth_keys=None) -> dict:
+    """Full FP64 forward over one or more views of the same Gaussians.
+
+    Returns per-view images (rgb, depth, alpha, T, last, guard) and the
+    intermediate stages (projections, pairs, ranges)."""
+    opt = dict(opt or {})
+    if not isinstance(cams, (list, tuple)):
+        cams = [cams]
+    projs = [project(scene, c, **opt) for c in cams]
+    n = scene.n
+    rect = np.concatenate([p["rect"] for p in projs], 0)
+    tiles = np.concatenate([p["tiles"] for p in projs], 0)
+    keys = depth_key(np.concatenate([p["depth"] for p in projs], 0)) if depth_keys is None else depth_keys
+    slot_view = np.repeat(np.arange(len(cams), dtype=np.int32), n)
+    bins = bin_pairs(rect, tiles, keys, slot_view, cams)
+    twod = _twod(projs)
+    images = [render_view(c, opt, int(bins["tile_off"][v]), twod, bins["pair_slot"], bins["ranges"],
+                          guard_eps=guard_eps) for v, c in enumerate(cams)]
+    return {"proj": projs, "bins": bins, "twod": twod, "images": images, "cams": list(cams), "opt": opt}
+
+
+def backward(scene, fwd: dict, g_images: list, absgrad: bool = True) -> dict:
+    """Analytic FP64 gradients for upstream image gradients
+    g_images[v] = (g_rgb [H][W][3], g_depth [H][W], g_alpha [H][W])."""
+    n = scene.n
+    cams, opt, bins, twod = fwd["cams"], fwd["opt"], fwd["bins"], fwd["twod"]
+    V = len(cams)
+    d2 = np.zeros((V * n, 10))
+    absg = np.zeros((V * n, 2)) if absgrad else None
+    for v, c in enumerate(cams):
+        gr, gd, ga = g_images[v]
+        render_bwd_view(c, opt, int(bins["tile_off"][v]), twod, bins["pair_slot"], bins["ranges"], gr, gd, ga,
+                        d2, absg)
+    grads = {"means": np.zeros((3, n)), "scales": np.zeros((3, n)), "quats": np.zeros((4, n)),
+             "opacities": np.zeros(n), "sh": np.zeros((16, 3, n))}
+    norms = np.zeros((V, n))
+    for v, c in enumerate(cams):
+        norms[v] = project_bwd(scene, c, opt, d2[v * n:(v + 1) * n], grads)
+    grads["mean2d_norm"] = norms
+    grads["d2"] = d2
+    if absg is not None:
+        grads["absgrad"] = absg.reshape(V, n, 2)
+    return grads
+
+
+def cov3d(q, s) -> np.ndarray:
+    """Sigma = R(q) diag(s)^2 R(q)^T (Eq. 1) of one Gaussian, 3x3."""
+    out = np.zeros(9)
+    qq = np.ascontiguousarray(q, np.float64)
+    ss = np.ascontiguousarray(s, np.float64)
+    _load().orc_cov3d(_ptr(qq), _ptr(ss), _ptr(out))
+    return out.reshape(3, 3)
