@@ -1,0 +1,184 @@
+/*
+ * gs.h -- C ABI of the MI355X (gfx950) differentiable Gaussian-splatting
+ * rasterizer: projection, tile binning and sort, front-to-back compositing
+ * of colour and depth, the analytic backward, and a continuous-batching
+ * render server.
+ *
+ * What is computed (paper, §3.1 "Preliminary"):
+ *   Eq. 1  each 3D Gaussian G(x) = exp(-1/2 (x - mu)^T Sigma^-1 (x - mu)),
+ *          Sigma = R S S^T R^T from a rotation (unit quaternion) and scales;
+ *   text   the Gaussians are projected onto the image plane as 2D Gaussians
+ *          G' (EWA linearisation of the perspective map) and "processed in
+ *          depth order";
+ *   Eq. 2  C(x_p) = sum_i c_i o_i G'_i(x_p) prod_{j<i} (1 - o_j G'_j(x_p)).
+ * Anti-aliasing (§3.5.4): the 2D covariance is dilated by `dilation` px^2
+ * and, with aa_compensate, the opacity is scaled by sqrt(det / det_dilated).
+ * Depth regulariser (§3.5.3): the accumulated depth sum_i z_i a_i T_i is
+ * rendered beside the colour; expected depth = depth / alpha.
+ * Densification statistics (§3.1, and AbsGS in §3.5.4): the backward
+ * returns |dL/d mean2d| per view and, optionally, the per-pixel absolute
+ * accumulation of dL/d mean2d.
+ * Level of detail (§3.4.2): the server picks a level per render-time
+ * partition from the partition-camera distance under a Gaussian budget.
+ *
+ * Rules the paper leaves open, fixed here: alpha = min(0.99, o' G');
+ * entries with alpha < 1/255 are skipped; a pixel stops before an entry
+ * that would take its transmittance below 1e-4; pixel centres at
+ * integer + 0.5; 16x16 tiles; a Gaussian covers the tiles of the square
+ * [floor(m) - r, floor(m) + r], r = ceil(3 sqrt(lambda_max)); ties in depth
+ * are broken by input order; colour = max(0, sum_lm sh_lm Y_lm(d) + 0.5)
+ * with real SH of degree <= 3 (m = -l..l order, Condon-Shortley phase).
+ *
+ * Conventions for every call:
+ *   - Array pointers are DEVICE pointers owned by the caller, contiguous,
+ *     float32 unless stated.  The library allocates no device memory in
+ *     these calls; scratch comes from a caller-provided workspace whose
+ *     size the matching *_workspace_size function returns (256-byte
+ *     aligned pointers required).
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Work is enqueued
+ *     asynchronously; gs_bin_sort is the one call that synchronises the
+ *     stream (it reads back the pair count).
+ *   - Return value 0 (GS_OK) or a negative GS_ERR_* code; nothing throws.
+ *     gs_last_error() returns the calling thread's last message.
+ *   - Gaussian parameters are structure-of-arrays over n Gaussians:
+ *     means [3][n], scales [3][n] (positive), quats [4][n] as (w, x, y, z)
+ *     (normalised inside), opacities [n] in (0, 1), sh [16][3][n]
+ *     (coefficient, channel, Gaussian).
+ *   - Several views of the same Gaussians are rendered in one launch per
+ *     stage (at most GS_MAX_VIEWS).  A "slot" is (view, Gaussian) with index
+ *     view * n + gaussian.  Tiles of all views share one numbering (view
+ *     tile offsets are the running sums of ceil(W/16) * ceil(H/16)); pixels
+ *     likewise (running sums of W * H), each view stored row-major.
+ */
+#ifndef GS_H
+#define GS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GS_OK 0
+#define GS_ERR_INVALID_ARG (-1)
+#define GS_ERR_CAPACITY (-2)
+#define GS_ERR_HIP (-3)
+#define GS_ERR_BUDGET (-4)
+#define GS_EAGAIN (-5)
+#define GS_ERR_INTERNAL (-6)
+
+#define GS_MAX_VIEWS 16
+#define GS_TILE 16
+#define GS_REC_FLOATS 12
+
+/* Pinhole camera.  viewmat is the row-major world-to-camera matrix
+ * [R | t; 0 0 0 1] with OpenCV axes (x right, y down, z forward).
+ * Gaussians with view depth outside [near_plane, far_plane] are culled. */
+typedef struct gs_camera {
+    float fx, fy, cx, cy;
+    float viewmat[16];
+    int32_t width, height;
+    float near_plane, far_plane;
+} gs_camera;
+
+typedef struct gs_options {
+    int32_t sh_degree;      /* 0..3: SH bands used for colour */
+    float dilation;         /* px^2 added to the 2D covariance diagonal (0.3) */
+    int32_t aa_compensate;  /* 1: opacity *= sqrt(det(S2D) / det(S2D + dilation I)) */
+    float bg[3];            /* background colour added as T_final * bg */
+} gs_options;
+
+typedef struct gs_gaussians {
+    const float *means, *scales, *quats, *opacities, *sh;
+    int64_t n;
+} gs_gaussians;
+
+/* Parameter gradients, same layouts as gs_gaussians; written (not added to),
+ * summed over the views of the call. */
+typedef struct gs_gaussians_grad {
+    float *d_means, *d_scales, *d_quats, *d_opacities, *d_sh;
+} gs_gaussians_grad;
+
+/* Projected per-slot records (n_views * n slots).
+ *   rec  [slots][12] float: mean2d x, y; qa, qb; qc, opacity', depth, 0;
+ *        r, g, b, 0.  (qa, qb, qc) = -log2(e) (A/2, B, C/2) for the conic
+ *        (A, B, C) of the dilated 2D covariance, so that
+ *        G' = exp2(qa dx^2 + qb dx dy + qc dy^2).
+ *   rect [slots][2] uint32: global id of the first tile of the rectangle;
+ *        rectangle width in tiles | (tiles per image row << 16).
+ *   tiles[slots] uint32: tiles in the rectangle, 0 if culled.
+ *   depth_key[slots] uint32: bit pattern of the float32 view depth
+ *        (0xFFFFFFFF if culled); the primary sort key inside a tile.
+ * Records of culled slots are left unwritten. */
+typedef struct gs_projected {
+    float *rec;
+    uint32_t *rect;
+    uint32_t *tiles;
+    uint32_t *depth_key;
+} gs_projected;
+
+const char *gs_last_error(void);
+const char *gs_version(void);
+
+/* Total tiles and pixels of a list of views. */
+int gs_views_extent(const gs_camera *cams, int32_t n_views, int64_t *n_tiles, int64_t *n_pixels);
+
+/* Projection and colour (§3.1 text after Eq. 1; §3.5.4 anti-aliasing).
+ * One thread per Gaussian handles every view, reading its parameters once.
+ * Errors: GS_ERR_INVALID_ARG for n <= 0 or n_views outside 1..GS_MAX_VIEWS,
+ * null pointers, image sizes outside 1..16384 or sh_degree outside 0..3. */
+int gs_project(const gs_gaussians *g, const gs_camera *cams, int32_t n_views, const gs_options *opt,
+               const gs_projected *out, void *stream);
+
+/* Scratch bytes needed by gs_bin_sort for n_slots slots and room for
+ * pair_capacity (tile, Gaussian) pairs. */
+size_t gs_bin_workspace_size(int64_t n_slots, int64_t pair_capacity);
+
+/* Tile binning and depth order ("processed in depth order", §3.1).
+ * Sorts slots by depth key (stable, so ties keep slot order), expands each
+ * slot into one pair per covered tile, stably sorts the pairs by global
+ * tile id, and writes
+ *   pair_vals[P]          slot of each pair, tile-major, depth order inside;
+ *   tile_ranges[T][2]     [start, end) of every global tile in pair_vals.
+ * *n_pairs receives P.  If P > pair_capacity nothing past the count is
+ * written and GS_ERR_CAPACITY is returned with *n_pairs = P, so the caller
+ * can grow its buffers and call again.  Synchronises `stream`. */
+int gs_bin_sort(const gs_projected *proj, const gs_camera *cams, int32_t n_views, int64_t n,
+                int64_t pair_capacity, uint32_t *pair_vals, uint32_t *tile_ranges, int64_t *n_pairs,
+                void *ws, size_t ws_bytes, void *stream);
+
+/* Front-to-back compositing (Eq. 2), one 256-thread workgroup per 16x16
+ * tile.  Outputs over all views' pixels: rgb [pix][3] (C + T_final * bg),
+ * depth [pix] (sum z a T), alpha [pix] (1 - T_final), T_final [pix] and
+ * last [pix] (1-based position in the tile's list of the last composited
+ * entry, 0 if none).  T_final and last feed gs_render_bwd. */
+int gs_render_fwd(const gs_projected *proj, const uint32_t *pair_vals, const uint32_t *tile_ranges,
+                  const gs_camera *cams, int32_t n_views, const gs_options *opt, float *rgb, float *depth,
+                  float *alpha, float *T_final, int32_t *last, void *stream);
+
+size_t gs_render_bwd_workspace_size(int64_t n_slots);
+
+/* Backward of compositing and projection.  Transmittance is recovered back
+ * to front from T_final and last instead of stored per-pixel lists.  Inputs
+ * d_rgb [pix][3], d_depth [pix], d_alpha [pix] (any may be NULL = zero).
+ * Outputs: parameter gradients summed over views (written, not added);
+ * mean2d_grad_norm [n_views][n] = |dL/d mean2d| in pixels per view;
+ * absgrad [n_views][n][2] (nullable) = sum over pixels of |dL_p/d mean2d|
+ * per axis.  The workspace holds per-slot 2D gradients. */
+int gs_render_bwd(const gs_gaussians *g, const gs_camera *cams, int32_t n_views, const gs_options *opt,
+                  const gs_projected *proj, const uint32_t *pair_vals, const uint32_t *tile_ranges,
+                  const float *T_final, const int32_t *last, const float *d_rgb, const float *d_depth,
+                  const float *d_alpha, const gs_gaussians_grad *out, float *mean2d_grad_norm, float *absgrad,
+                  void *ws, size_t ws_bytes, void *stream);
+
+/* Per-slot 2D gradients of the last gs_render_bwd call that used `ws`
+ * ([slots][12]: d mean2d x, y; d conic A, B, C; d opacity'; d rgb; d depth;
+ * |d mean2d| x, y accumulations) -- for inspection and tests. */
+const float *gs_render_bwd_grad2d(void *ws);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GS_H */

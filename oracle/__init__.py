@@ -188,9 +188,12 @@ def render_view(cam, opt: dict, tile_off: int, twod, pair_slot, ranges, tile_mas
            "T": np.zeros((H, W)), "last": np.zeros((H, W), np.int32), "guard": np.zeros((H, W), np.uint8)}
     g = np.ascontiguousarray(guard_eps, np.float64) if guard_eps is not None else None
     mask = np.ascontiguousarray(tile_mask, np.uint8) if tile_mask is not None else None
+    pair_slot = np.ascontiguousarray(pair_slot, np.uint32)
+    ranges = np.ascontiguousarray(ranges, np.uint32)
+    mean2d, conic, opac, rgb, depth = (np.ascontiguousarray(a, np.float64) for a in (mean2d, conic, opac, rgb, depth))
     lib.orc_render(C.byref(make_cam(cam)), C.byref(make_opt(**opt)), C.c_int64(tile_off), _ptr(mean2d),
-                   _ptr(conic), _ptr(opac), _ptr(rgb), _ptr(depth), _ptr(np.ascontiguousarray(pair_slot, np.uint32)),
-                   _ptr(np.ascontiguousarray(ranges, np.uint32)), _ptr(mask), _ptr(g), _ptr(out["rgb"]),
+                   _ptr(conic), _ptr(opac), _ptr(rgb), _ptr(depth), _ptr(pair_slot),
+                   _ptr(ranges), _ptr(mask), _ptr(g), _ptr(out["rgb"]),
                    _ptr(out["depth"]), _ptr(out["alpha"]), _ptr(out["T"]), _ptr(out["last"]), _ptr(out["guard"]))
     return out
 
@@ -203,9 +206,13 @@ def render_bwd_view(cam, opt: dict, tile_off: int, twod, pair_slot, ranges, g_rg
     g_depth = np.ascontiguousarray(g_depth, np.float64)
     g_alpha = np.ascontiguousarray(g_alpha, np.float64)
     mask = np.ascontiguousarray(tile_mask, np.uint8) if tile_mask is not None else None
+    pair_slot = np.ascontiguousarray(pair_slot, np.uint32)
+    ranges = np.ascontiguousarray(ranges, np.uint32)
+    mean2d, conic, opac, rgb, depth = (np.ascontiguousarray(a, np.float64) for a in (mean2d, conic, opac, rgb, depth))
+    assert d2.dtype == np.float64 and d2.flags.c_contiguous
+    assert absg is None or (absg.dtype == np.float64 and absg.flags.c_contiguous)
     lib.orc_render_bwd(C.byref(make_cam(cam)), C.byref(make_opt(**opt)), C.c_int64(tile_off), _ptr(mean2d),
-                       _ptr(conic), _ptr(opac), _ptr(rgb), _ptr(depth),
-                       _ptr(np.ascontiguousarray(pair_slot, np.uint32)), _ptr(np.ascontiguousarray(ranges, np.uint32)),
+                       _ptr(conic), _ptr(opac), _ptr(rgb), _ptr(depth), _ptr(pair_slot), _ptr(ranges),
                        _ptr(mask), _ptr(g_rgb), _ptr(g_depth), _ptr(g_alpha), _ptr(d2), _ptr(absg))
 
 
@@ -215,11 +222,16 @@ def project_bwd(scene, cam, opt: dict, d2_view, grads: dict):
     lib = _load()
     n = scene.n
     norm = np.zeros(n)
-    lib.orc_project_bwd(C.c_int64(n), _ptr(_c64(scene.means)), _ptr(_c64(scene.scales)), _ptr(_c64(scene.quats)),
-                        _ptr(_c64(scene.opacities)), _ptr(_c64(scene.sh)), C.byref(make_cam(cam)),
-                        C.byref(make_opt(**opt)), _ptr(np.ascontiguousarray(d2_view, np.float64)),
-                        _ptr(grads["means"]), _ptr(grads["scales"]), _ptr(grads["quats"]), _ptr(grads["opacities"]),
-                        _ptr(grads["sh"]), _ptr(norm))
+    # converted copies are held in locals so they outlive the call
+    means, scales, quats = _c64(scene.means), _c64(scene.scales), _c64(scene.quats)
+    opac, sh = _c64(scene.opacities), _c64(scene.sh)
+    d2 = np.ascontiguousarray(d2_view, np.float64)
+    for k in ("means", "scales", "quats", "opacities", "sh"):
+        assert grads[k].dtype == np.float64 and grads[k].flags.c_contiguous
+    c, o = make_cam(cam), make_opt(**opt)
+    lib.orc_project_bwd(C.c_int64(n), _ptr(means), _ptr(scales), _ptr(quats), _ptr(opac), _ptr(sh), C.byref(c),
+                        C.byref(o), _ptr(d2), _ptr(grads["means"]), _ptr(grads["scales"]), _ptr(grads["quats"]),
+                        _ptr(grads["opacities"]), _ptr(grads["sh"]), _ptr(norm))
     return norm
 
 

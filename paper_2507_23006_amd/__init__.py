@@ -1,0 +1,20 @@
+"""MI355X (gfx950) differentiable 3D-Gaussian tile rasterizer.
+
+The hot path -- projection, SH colour, tile binning and sort, compositing of
+colour and depth, and the backward -- runs in the HIP kernels of libgs.so
+behind the C ABI of include/gs.h.  This package only marshals torch tensors
+(device memory, streams) into that ABI; it has no CPU fallback.
+"""
+from ._lib import GsError, load, LIB_PATH
+from .rasterizer import (RenderOptions, RenderStats, Projected, Workspace, GsRasterize, rasterize, project,
+                         bin_sort, render_fwd, render_bwd, split_views, views_extent, grad2d_view, check_params)
+
+
+def build(verbose: bool = False) -> str:
+    from .build import build as _build
+    return _build(verbose)
+
+
+__all__ = ["GsError", "load", "LIB_PATH", "RenderOptions", "RenderStats", "Projected", "Workspace", "GsRasterize",
+           "rasterize", "project", "bin_sort", "render_fwd", "render_bwd", "split_views", "views_extent",
+           "grad2d_view", "check_params", "build"]

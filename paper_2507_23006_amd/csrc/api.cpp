@@ -1,0 +1,327 @@
+// C ABI of the rasterizer (declared in include/gs.h): argument checks,
+// per-view constant tables, workspace layout and the launch sequence of
+// each stage.  No call here allocates device memory.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "gs.h"
+#include "gs_internal.h"
+
+namespace gs {
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+#define GS_HIP(expr)                                                                              \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess) return fail(GS_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+#define GS_REQUIRE(cond, ...)                                 \
+    do {                                                      \
+        if (!(cond)) return fail(GS_ERR_INVALID_ARG, __VA_ARGS__); \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+// carves aligned regions out of a workspace; with base == nullptr it only
+// measures
+struct Carver {
+    char* base;
+    size_t off = 0;
+    explicit Carver(void* b) : base(static_cast<char*>(b)) {}
+    template <class T>
+    T* take(size_t count) {
+        T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+        off = align_up(off + count * sizeof(T));
+        return p;
+    }
+};
+
+int build_views(const gs_camera* cams, int32_t n_views, ViewTable* vt) {
+    GS_REQUIRE(cams != nullptr, "cams is NULL");
+    GS_REQUIRE(n_views >= 1 && n_views <= GS_MAX_VIEWS, "n_views=%d outside 1..%d", n_views, GS_MAX_VIEWS);
+    std::memset(vt, 0, sizeof(*vt));
+    int64_t tile_off = 0, pix_off = 0;
+    for (int v = 0; v < n_views; ++v) {
+        const gs_camera& c = cams[v];
+        GS_REQUIRE(c.width >= 1 && c.width <= 16384 && c.height >= 1 && c.height <= 16384,
+                   "view %d: image %dx%d outside 1..16384", v, c.width, c.height);
+        GS_REQUIRE(std::isfinite(c.fx) && std::isfinite(c.fy) && c.fx > 0.0f && c.fy > 0.0f,
+                   "view %d: focal lengths must be positive", v);
+        GS_REQUIRE(std::isfinite(c.cx) && std::isfinite(c.cy), "view %d: principal point not finite", v);
+        GS_REQUIRE(c.near_plane > 0.0f && c.far_plane > c.near_plane, "view %d: need 0 < near < far", v);
+        for (int i = 0; i < 16; ++i) GS_REQUIRE(std::isfinite(c.viewmat[i]), "view %d: viewmat not finite", v);
+        ViewK& V = vt->v[v];
+        for (int r = 0; r < 3; ++r) {
+            for (int k = 0; k < 3; ++k) V.R[3 * r + k] = c.viewmat[4 * r + k];
+            V.t[r] = c.viewmat[4 * r + 3];
+        }
+        for (int i = 0; i < 3; ++i)
+            V.campos[i] = -((double)V.R[i] * V.t[0] + (double)V.R[3 + i] * V.t[1] + (double)V.R[6 + i] * V.t[2]);
+        V.fx = c.fx; V.fy = c.fy; V.cx = c.cx; V.cy = c.cy;
+        V.znear = c.near_plane; V.zfar = c.far_plane;
+        const double W = c.width, H = c.height, cx = c.cx, cy = c.cy, fx = c.fx, fy = c.fy;
+        V.ulo = -(cx + 0.15 * W) / fx;
+        V.uhi = (W - cx + 0.15 * W) / fx;
+        V.vlo = -(cy + 0.15 * H) / fy;
+        V.vhi = (H - cy + 0.15 * H) / fy;
+        V.W = c.width; V.H = c.height;
+        V.tiles_x = (c.width + kTile - 1) / kTile;
+        V.tiles_y = (c.height + kTile - 1) / kTile;
+        V.tile_off = (int32_t)tile_off;
+        V.pix_off = pix_off;
+        tile_off += (int64_t)V.tiles_x * V.tiles_y;
+        pix_off += (int64_t)c.width * c.height;
+    }
+    GS_REQUIRE(tile_off < (1LL << 30), "too many tiles (%lld)", (long long)tile_off);
+    vt->n_views = n_views;
+    vt->total_tiles = (int32_t)tile_off;
+    return GS_OK;
+}
+
+int build_opt(const gs_options* o, OptK* k) {
+    GS_REQUIRE(o != nullptr, "options is NULL");
+    GS_REQUIRE(o->sh_degree >= 0 && o->sh_degree <= 3, "sh_degree=%d outside 0..3", o->sh_degree);
+    GS_REQUIRE(std::isfinite(o->dilation) && o->dilation >= 0.0f, "dilation must be >= 0");
+    k->sh_degree = o->sh_degree;
+    k->dilation = o->dilation;
+    k->aa = o->aa_compensate ? 1 : 0;
+    for (int i = 0; i < 3; ++i) k->bg[i] = o->bg[i];
+    return GS_OK;
+}
+
+int check_gaussians(const gs_gaussians* g, int32_t n_views) {
+    GS_REQUIRE(g != nullptr, "gaussians is NULL");
+    GS_REQUIRE(g->n >= 1, "n=%lld must be >= 1", (long long)g->n);
+    GS_REQUIRE(g->means && g->scales && g->quats && g->opacities && g->sh, "a Gaussian parameter pointer is NULL");
+    GS_REQUIRE(g->n * (int64_t)n_views <= 0xFFFFFF00LL, "n * n_views = %lld exceeds 32-bit slot ids",
+               (long long)(g->n * n_views));
+    return GS_OK;
+}
+
+int check_proj(const gs_projected* p) {
+    GS_REQUIRE(p != nullptr && p->rec && p->rect && p->tiles && p->depth_key, "projected buffers missing");
+    return GS_OK;
+}
+
+Projected to_proj(const gs_projected* p) {
+    return Projected{reinterpret_cast<float4*>(p->rec), reinterpret_cast<uint2*>(p->rect), p->tiles, p->depth_key};
+}
+
+int tile_bits(int64_t n_tiles) {
+    int b = 0;
+    while ((1LL << b) < n_tiles) ++b;
+    return b;
+}
+
+struct BinWs {
+    uint32_t *dkeys, *dvals, *dkeys_alt, *dvals_alt;
+    uint32_t* hist;
+    uint32_t *tiles_s, *offsets;
+    uint2* rect_s;
+    uint32_t* scan_tmp;
+    unsigned long long* total;
+    uint32_t *pkeys, *pkeys_alt, *pvals_alt;
+};
+
+size_t bin_layout(int64_t n_slots, int64_t cap, void* base, BinWs* w) {
+    Carver c(base);
+    const size_t N = (size_t)n_slots, Pc = (size_t)(cap > 0 ? cap : 1);
+    w->dkeys = c.take<uint32_t>(N);
+    w->dvals = c.take<uint32_t>(N);
+    w->dkeys_alt = c.take<uint32_t>(N);
+    w->dvals_alt = c.take<uint32_t>(N);
+    w->hist = c.take<uint32_t>(radix_hist_elems((uint32_t)(N > Pc ? N : Pc)));
+    w->tiles_s = c.take<uint32_t>(N);
+    w->offsets = c.take<uint32_t>(N);
+    w->rect_s = c.take<uint2>(N);
+    w->scan_tmp = c.take<uint32_t>(scan_tmp_elems((uint32_t)N));
+    w->total = c.take<unsigned long long>(2);
+    w->pkeys = c.take<uint32_t>(Pc);
+    w->pkeys_alt = c.take<uint32_t>(Pc);
+    w->pvals_alt = c.take<uint32_t>(Pc);
+    return c.off;
+}
+
+unsigned long long* pinned_scalar() {
+    thread_local unsigned long long* p = nullptr;
+    if (!p && hipHostMalloc(reinterpret_cast<void**>(&p), 64, hipHostMallocDefault) != hipSuccess) p = nullptr;
+    return p;
+}
+
+}  // namespace
+
+}  // namespace gs
+
+using namespace gs;
+
+extern "C" {
+
+const char* gs_last_error(void) { return g_err; }
+
+const char* gs_version(void) { return "gsmi-rasterizer 0.1 (gfx950)"; }
+
+int gs_views_extent(const gs_camera* cams, int32_t n_views, int64_t* n_tiles, int64_t* n_pixels) {
+    ViewTable vt;
+    int rc = build_views(cams, n_views, &vt);
+    if (rc) return rc;
+    int64_t pix = 0;
+    for (int v = 0; v < n_views; ++v) pix += (int64_t)cams[v].width * cams[v].height;
+    if (n_tiles) *n_tiles = vt.total_tiles;
+    if (n_pixels) *n_pixels = pix;
+    return GS_OK;
+}
+
+int gs_project(const gs_gaussians* g, const gs_camera* cams, int32_t n_views, const gs_options* opt,
+               const gs_projected* out, void* stream) {
+    try {
+        ViewTable vt;
+        OptK ok;
+        int rc;
+        if ((rc = build_views(cams, n_views, &vt)) || (rc = build_opt(opt, &ok)) ||
+            (rc = check_gaussians(g, n_views)) || (rc = check_proj(out)))
+            return rc;
+        GaussPtrs gp{g->means, g->scales, g->quats, g->opacities, g->sh};
+        GS_HIP(launch_project_fwd(gp, g->n, vt, ok, to_proj(out), (hipStream_t)stream));
+        return GS_OK;
+    } catch (...) {
+        return fail(GS_ERR_INTERNAL, "unexpected exception in gs_project");
+    }
+}
+
+size_t gs_bin_workspace_size(int64_t n_slots, int64_t pair_capacity) {
+    if (n_slots < 1) n_slots = 1;
+    BinWs w;
+    return bin_layout(n_slots, pair_capacity, nullptr, &w);
+}
+
+int gs_bin_sort(const gs_projected* proj, const gs_camera* cams, int32_t n_views, int64_t n, int64_t pair_capacity,
+                uint32_t* pair_vals, uint32_t* tile_ranges, int64_t* n_pairs, void* ws, size_t ws_bytes,
+                void* stream) {
+    try {
+        ViewTable vt;
+        int rc;
+        if ((rc = build_views(cams, n_views, &vt)) || (rc = check_proj(proj))) return rc;
+        GS_REQUIRE(n >= 1 && n * (int64_t)n_views <= 0xFFFFFF00LL, "bad n=%lld", (long long)n);
+        GS_REQUIRE(pair_vals && tile_ranges && n_pairs && ws, "NULL output or workspace");
+        GS_REQUIRE(pair_capacity >= 0 && pair_capacity <= 0xFFFFFF00LL, "pair_capacity out of range");
+        GS_REQUIRE(((uintptr_t)ws & (kAlign - 1)) == 0, "workspace must be 256-byte aligned");
+        const int64_t n_slots = n * n_views;
+        BinWs w;
+        const size_t need = bin_layout(n_slots, pair_capacity, ws, &w);
+        GS_REQUIRE(ws_bytes >= need, "workspace too small: %zu < %zu", ws_bytes, need);
+        hipStream_t s = (hipStream_t)stream;
+        const Projected pr = to_proj(proj);
+        const uint32_t N = (uint32_t)n_slots;
+
+        // 1. depth order of all slots (culled slots carry key 0xFFFFFFFF and sort last)
+        GS_HIP(launch_bin_prepare(pr, N, w.dkeys, w.dvals, s));
+        bool alt = false;
+        GS_HIP(radix_sort_pairs(w.dkeys, w.dvals, w.dkeys_alt, w.dvals_alt, N, 0, 32, w.hist, s, &alt));
+        const uint32_t* sorted_slot = alt ? w.dvals_alt : w.dvals;
+        // 2. per depth rank: tile count and rectangle; exclusive scan -> pair offsets
+        GS_HIP(launch_gather_sorted(sorted_slot, pr, N, w.tiles_s, w.rect_s, s));
+        GS_HIP(exclusive_scan_u32(w.tiles_s, w.offsets, N, w.scan_tmp, w.total, s));
+        unsigned long long* host = pinned_scalar();
+        if (!host) return fail(GS_ERR_HIP, "pinned host buffer unavailable");
+        GS_HIP(hipMemcpyAsync(host, w.total, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+        GS_HIP(hipStreamSynchronize(s));
+        const unsigned long long P = *host;
+        *n_pairs = (int64_t)P;
+        if (P > 0xFFFFFF00ULL) return fail(GS_ERR_CAPACITY, "pair count %llu exceeds 32-bit indices", P);
+        if ((int64_t)P > pair_capacity)
+            return fail(GS_ERR_CAPACITY, "pair count %llu exceeds capacity %lld", P, (long long)pair_capacity);
+        // 3. expand into (tile, slot) pairs in depth order, then stable sort by tile id
+        const int bits = tile_bits(vt.total_tiles);
+        const int passes = P <= 1 ? 0 : (bits + 7) / 8;   // radix_sort_pairs runs no pass for P <= 1
+        uint32_t* vals_primary = (passes % 2 == 0) ? pair_vals : w.pvals_alt;
+        uint32_t* vals_alt = (passes % 2 == 0) ? w.pvals_alt : pair_vals;
+        GS_HIP(launch_emit_pairs(w.offsets, w.rect_s, sorted_slot, N, (uint32_t)P, w.pkeys, vals_primary, s));
+        bool palt = false;
+        GS_HIP(radix_sort_pairs(w.pkeys, vals_primary, w.pkeys_alt, vals_alt, (uint32_t)P, 0, bits, w.hist, s, &palt));
+        const uint32_t* sorted_keys = palt ? w.pkeys_alt : w.pkeys;
+        if ((palt ? vals_alt : vals_primary) != pair_vals)
+            return fail(GS_ERR_INTERNAL, "tile sort ended in the wrong buffer");
+        // 4. [start, end) per tile
+        GS_HIP(launch_tile_ranges(sorted_keys, (uint32_t)P, tile_ranges, (uint32_t)vt.total_tiles, s));
+        return GS_OK;
+    } catch (...) {
+        return fail(GS_ERR_INTERNAL, "unexpected exception in gs_bin_sort");
+    }
+}
+
+int gs_render_fwd(const gs_projected* proj, const uint32_t* pair_vals, const uint32_t* tile_ranges,
+                  const gs_camera* cams, int32_t n_views, const gs_options* opt, float* rgb, float* depth,
+                  float* alpha, float* T_final, int32_t* last, void* stream) {
+    try {
+        ViewTable vt;
+        OptK ok;
+        int rc;
+        if ((rc = build_views(cams, n_views, &vt)) || (rc = build_opt(opt, &ok)) || (rc = check_proj(proj)))
+            return rc;
+        GS_REQUIRE(pair_vals && tile_ranges && rgb && depth && alpha && T_final && last, "NULL buffer");
+        GS_HIP(launch_render_fwd(to_proj(proj), pair_vals, reinterpret_cast<const uint2*>(tile_ranges), vt, ok, rgb,
+                                 depth, alpha, T_final, last, (hipStream_t)stream));
+        return GS_OK;
+    } catch (...) {
+        return fail(GS_ERR_INTERNAL, "unexpected exception in gs_render_fwd");
+    }
+}
+
+size_t gs_render_bwd_workspace_size(int64_t n_slots) {
+    if (n_slots < 1) n_slots = 1;
+    return align_up((size_t)n_slots * GS_REC_FLOATS * sizeof(float));
+}
+
+const float* gs_render_bwd_grad2d(void* ws) { return static_cast<const float*>(ws); }
+
+int gs_render_bwd(const gs_gaussians* g, const gs_camera* cams, int32_t n_views, const gs_options* opt,
+                  const gs_projected* proj, const uint32_t* pair_vals, const uint32_t* tile_ranges,
+                  const float* T_final, const int32_t* last, const float* d_rgb, const float* d_depth,
+                  const float* d_alpha, const gs_gaussians_grad* out, float* mean2d_grad_norm, float* absgrad,
+                  void* ws, size_t ws_bytes, void* stream) {
+    try {
+        ViewTable vt;
+        OptK ok;
+        int rc;
+        if ((rc = build_views(cams, n_views, &vt)) || (rc = build_opt(opt, &ok)) ||
+            (rc = check_gaussians(g, n_views)) || (rc = check_proj(proj)))
+            return rc;
+        GS_REQUIRE(pair_vals && tile_ranges && T_final && last && out && mean2d_grad_norm && ws, "NULL buffer");
+        GS_REQUIRE(out->d_means && out->d_scales && out->d_quats && out->d_opacities && out->d_sh,
+                   "NULL gradient output");
+        const int64_t n_slots = g->n * n_views;
+        GS_REQUIRE(ws_bytes >= gs_render_bwd_workspace_size(n_slots), "workspace too small");
+        hipStream_t s = (hipStream_t)stream;
+        float* grad2d = static_cast<float*>(ws);
+        GS_HIP(fill_u32(reinterpret_cast<uint32_t*>(grad2d), 0u, (size_t)n_slots * GS_REC_FLOATS, s));
+        const Projected pr = to_proj(proj);
+        GS_HIP(launch_render_bwd(pr, pair_vals, reinterpret_cast<const uint2*>(tile_ranges), vt, ok, T_final, last,
+                                 d_rgb, d_depth, d_alpha, grad2d, s));
+        GaussPtrs gp{g->means, g->scales, g->quats, g->opacities, g->sh};
+        GradPtrs go{out->d_means, out->d_scales, out->d_quats, out->d_opacities, out->d_sh};
+        GS_HIP(launch_project_bwd(gp, g->n, vt, ok, pr, grad2d, go, mean2d_grad_norm, absgrad, s));
+        return GS_OK;
+    } catch (...) {
+        return fail(GS_ERR_INTERNAL, "unexpected exception in gs_render_bwd");
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,164 @@
+// Internal definitions shared by the gfx950 kernels and the host side of
+// the library.  Not part of the public ABI (include/gs.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gs.h"
+
+namespace gs {
+
+constexpr int kTile = GS_TILE;
+constexpr int kTilePix = kTile * kTile;       // 256 pixels = 4 wave64s
+constexpr float kAlphaMax = 0.99f;
+constexpr float kAlphaMin = 1.0f / 255.0f;
+constexpr float kTMin = 1e-4f;
+constexpr double kLog2e = 1.4426950408889634;
+constexpr float kLn2 = 0.6931471805599453f;
+
+// Per-view constants, passed by value in kernel arguments (the whole table
+// stays under 3 KB).  Camera inputs are float32, so they are kept as float
+// and widened exactly in the kernels; quantities derived on the host are
+// double because projection runs in FP64 (it is HBM-bound, and FP64 VALU on
+// CDNA4 peaks as high as non-packed FP32).
+struct ViewK {
+    float R[9];           // world -> camera rotation, row-major
+    float t[3];
+    float fx, fy, cx, cy;
+    float znear, zfar;
+    double campos[3];     // camera centre in world space, -R^T t
+    double ulo, uhi, vlo, vhi;   // Jacobian clamp of x/z and y/z
+    int32_t W, H, tiles_x, tiles_y;
+    int32_t tile_off;     // first global tile id of this view
+    int32_t pad;
+    int64_t pix_off;      // first global pixel of this view
+};
+
+struct ViewTable {
+    ViewK v[GS_MAX_VIEWS];
+    int32_t n_views;
+    int32_t total_tiles;
+};
+
+struct OptK {
+    int32_t sh_degree;
+    float dilation;
+    int32_t aa;
+    float bg[3];
+};
+
+// Map a global tile id to its view (views are few; linear scan of kernargs).
+__device__ __forceinline__ int view_of_tile(const ViewTable& vt, int tile) {
+    int v = 0;
+    for (int i = 1; i < vt.n_views; ++i)
+        if (tile >= vt.v[i].tile_off) v = i;
+    return v;
+}
+
+// Real SH with the Condon-Shortley phase (m = -l..l per band), degree <= 3,
+// as polynomials valid on the unit sphere.  The constants are the
+// normalisations sqrt((2l+1)/(4 pi) (l-|m|)!/(l+|m|)!) times sqrt(2) for
+// m != 0, reduced to closed forms:
+//   k0 = 1/(2 sqrt(pi)), k1 = sqrt(3/(4 pi)), k2 = sqrt(15/pi)/2,
+//   k6 = sqrt(5/pi)/4, k8 = sqrt(15/pi)/4, k9 = sqrt(35/(2 pi))/4,
+//   k10 = sqrt(105/pi)/2, k11 = sqrt(21/(2 pi))/4, k12 = sqrt(7/pi)/4,
+//   k14 = sqrt(105/pi)/4.
+struct ShK {
+    static constexpr double k0 = 0.28209479177387814;
+    static constexpr double k1 = 0.4886025119029199;
+    static constexpr double k2 = 1.0925484305920792;
+    static constexpr double k6 = 0.31539156525252005;
+    static constexpr double k8 = 0.5462742152960396;
+    static constexpr double k9 = 0.5900435899266435;
+    static constexpr double k10 = 2.890611442640554;
+    static constexpr double k11 = 0.4570457994644658;
+    static constexpr double k12 = 0.3731763325901154;
+    static constexpr double k14 = 1.445305721320277;
+};
+
+template <class Real>
+__device__ __forceinline__ void sh_eval_basis(Real x, Real y, Real z, int degree, Real Y[16]) {
+    Y[0] = (Real)ShK::k0;
+    if (degree < 1) return;
+    Y[1] = -(Real)ShK::k1 * y;
+    Y[2] = (Real)ShK::k1 * z;
+    Y[3] = -(Real)ShK::k1 * x;
+    if (degree < 2) return;
+    const Real xx = x * x, yy = y * y, zz = z * z;
+    Y[4] = (Real)ShK::k2 * x * y;
+    Y[5] = -(Real)ShK::k2 * y * z;
+    Y[6] = (Real)ShK::k6 * ((Real)2 * zz - xx - yy);
+    Y[7] = -(Real)ShK::k2 * x * z;
+    Y[8] = (Real)ShK::k8 * (xx - yy);
+    if (degree < 3) return;
+    Y[9] = -(Real)ShK::k9 * y * ((Real)3 * xx - yy);
+    Y[10] = (Real)ShK::k10 * x * y * z;
+    Y[11] = -(Real)ShK::k11 * y * ((Real)4 * zz - xx - yy);
+    Y[12] = (Real)ShK::k12 * z * ((Real)2 * zz - (Real)3 * xx - (Real)3 * yy);
+    Y[13] = -(Real)ShK::k11 * x * ((Real)4 * zz - xx - yy);
+    Y[14] = (Real)ShK::k14 * z * (xx - yy);
+    Y[15] = -(Real)ShK::k9 * x * (xx - (Real)3 * yy);
+}
+
+}  // namespace gs
+
+// ---------------------------------------------------------------------------
+// host-side launch helpers (defined in the .hip sources)
+// ---------------------------------------------------------------------------
+namespace gs {
+
+struct Projected {
+    float4* rec;          // [slots][3]
+    uint2* rect;          // [slots]
+    uint32_t* tiles;      // [slots]
+    uint32_t* dkey;       // [slots]
+};
+
+struct GaussPtrs {
+    const float *means, *scales, *quats, *opac, *sh;
+};
+
+struct GradPtrs {
+    float *means, *scales, *quats, *opac, *sh;
+};
+
+hipError_t launch_project_fwd(const GaussPtrs& g, int64_t n, const ViewTable& vt, const OptK& opt,
+                              const Projected& out, hipStream_t s);
+
+// radix sort / scan primitives (sort.hip)
+size_t radix_hist_elems(uint32_t n);        // counters needed per pass
+hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt,
+                            uint32_t n, int begin_bit, int end_bit, uint32_t* hist, hipStream_t s,
+                            bool* result_in_alt);
+size_t scan_tmp_elems(uint32_t n);
+hipError_t exclusive_scan_u32(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* tmp,
+                              unsigned long long* total, hipStream_t s);
+hipError_t fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s);
+
+// binning (bin.hip)
+hipError_t launch_bin_prepare(const Projected& proj, uint32_t n_slots, uint32_t* dkeys_tmp, uint32_t* slots_tmp,
+                              hipStream_t s);
+hipError_t launch_gather_sorted(const uint32_t* sorted_slot, const Projected& proj, uint32_t n_slots,
+                                uint32_t* tiles_s, uint2* rect_s, hipStream_t s);
+hipError_t launch_emit_pairs(const uint32_t* offsets, const uint2* rect_s, const uint32_t* sorted_slot,
+                             uint32_t n_slots, uint32_t n_pairs, uint32_t* pair_key, uint32_t* pair_val,
+                             hipStream_t s);
+hipError_t launch_tile_ranges(const uint32_t* sorted_keys, uint32_t n_pairs, uint32_t* ranges, uint32_t n_tiles,
+                              hipStream_t s);
+
+// compositing (render.hip)
+hipError_t launch_render_fwd(const Projected& proj, const uint32_t* pair_vals, const uint2* ranges,
+                             const ViewTable& vt, const OptK& opt, float* rgb, float* depth, float* alpha,
+                             float* T_final, int32_t* last, hipStream_t s);
+hipError_t launch_render_bwd(const Projected& proj, const uint32_t* pair_vals, const uint2* ranges,
+                             const ViewTable& vt, const OptK& opt, const float* T_final, const int32_t* last,
+                             const float* d_rgb, const float* d_depth, const float* d_alpha, float* grad2d,
+                             hipStream_t s);
+
+// projection backward (project_bwd.hip)
+hipError_t launch_project_bwd(const GaussPtrs& g, int64_t n, const ViewTable& vt, const OptK& opt,
+                              const Projected& proj, const float* grad2d, const GradPtrs& out,
+                              float* mean2d_norm, float* absgrad, hipStream_t s);
+
+}  // namespace gs

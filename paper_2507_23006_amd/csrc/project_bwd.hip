@@ -1,0 +1,277 @@
+// Backward of projection and colour -- gfx950.
+//
+// One thread per Gaussian, looping over the views of the launch: it reads
+// the Gaussian's parameters once, recomputes the projection in FP64 for each
+// view, chains that view's 2D gradients (mean2d, conic, opacity', colour,
+// depth) back to the parameters, and writes the sums once.  With
+// Sigma_2D = V V^T and V = (J W) M, M = R(q) diag(s), the covariance
+// gradient flows as dV = 2 G V, d(JW) = dV M^T, dM += (JW)^T dV; dM is
+// accumulated over views and pushed through R(q) and s once at the end.
+// HBM-bound; geometry in FP64 for the same reason as the forward.
+//
+// Paper: backward of Eq. 1 and of the projection of §3.1; the per-view
+// |dL/d mean2d| is the image-space statistic that densification thresholds
+// (§3.1, §3.3 Eq. 4), and the absolute accumulation is the AbsGS statistic
+// of §3.5.4.
+#include "gs_internal.h"
+
+namespace gs {
+
+namespace {
+
+// gradient of each basis polynomial of sh_eval_basis with respect to (x, y, z)
+__device__ __forceinline__ void sh_basis_grad(float x, float y, float z, int k, float& gx, float& gy,
+                                              float& gz) {
+    const float xx = x * x, yy = y * y, zz = z * z;
+    const float k1 = (float)ShK::k1, k2 = (float)ShK::k2, k6 = (float)ShK::k6, k8 = (float)ShK::k8,
+                k9 = (float)ShK::k9, k10 = (float)ShK::k10, k11 = (float)ShK::k11, k12 = (float)ShK::k12,
+                k14 = (float)ShK::k14;
+    gx = gy = gz = 0.0f;
+    switch (k) {
+        case 1: gy = -k1; break;
+        case 2: gz = k1; break;
+        case 3: gx = -k1; break;
+        case 4: gx = k2 * y; gy = k2 * x; break;
+        case 5: gy = -k2 * z; gz = -k2 * y; break;
+        case 6: gx = -2.0f * k6 * x; gy = -2.0f * k6 * y; gz = 4.0f * k6 * z; break;
+        case 7: gx = -k2 * z; gz = -k2 * x; break;
+        case 8: gx = 2.0f * k8 * x; gy = -2.0f * k8 * y; break;
+        case 9: gx = -6.0f * k9 * x * y; gy = -3.0f * k9 * (xx - yy); break;
+        case 10: gx = k10 * y * z; gy = k10 * x * z; gz = k10 * x * y; break;
+        case 11: gx = 2.0f * k11 * x * y; gy = -k11 * (4.0f * zz - xx - 3.0f * yy); gz = -8.0f * k11 * y * z; break;
+        case 12: gx = -6.0f * k12 * x * z; gy = -6.0f * k12 * y * z; gz = k12 * (6.0f * zz - 3.0f * xx - 3.0f * yy); break;
+        case 13: gx = -k11 * (4.0f * zz - 3.0f * xx - yy); gy = 2.0f * k11 * x * y; gz = -8.0f * k11 * x * z; break;
+        case 14: gx = 2.0f * k14 * x * z; gy = -2.0f * k14 * y * z; gz = k14 * (xx - yy); break;
+        case 15: gx = -3.0f * k9 * (xx - yy); gy = 6.0f * k9 * x * y; break;
+        default: break;
+    }
+}
+
+constexpr int kG2 = 12;
+
+__global__ __launch_bounds__(256) void k_project_bwd(GaussPtrs gp, int64_t n, ViewTable vt, OptK opt, Projected proj,
+                                                     const float* __restrict__ grad2d, GradPtrs out,
+                                                     float* __restrict__ mean2d_norm, float* __restrict__ absgrad) {
+    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (g >= n) return;
+    const int nb = (opt.sh_degree + 1) * (opt.sh_degree + 1);
+
+    // per-view statistics, and which views see this Gaussian
+    uint32_t vis = 0;
+    for (int v = 0; v < vt.n_views; ++v) {
+        const int64_t slot = (int64_t)v * n + g;
+        const float* g2 = grad2d + slot * kG2;
+        const float dmx = g2[0], dmy = g2[1];
+        mean2d_norm[slot] = sqrtf(dmx * dmx + dmy * dmy);
+        if (absgrad) {
+            absgrad[2 * slot + 0] = g2[10];
+            absgrad[2 * slot + 1] = g2[11];
+        }
+        if (proj.tiles[slot]) vis |= 1u << v;
+    }
+    if (!vis) {
+        for (int c = 0; c < 3; ++c) out.means[c * n + g] = 0.0f;
+        for (int c = 0; c < 3; ++c) out.scales[c * n + g] = 0.0f;
+        for (int c = 0; c < 4; ++c) out.quats[c * n + g] = 0.0f;
+        out.opac[g] = 0.0f;
+        for (int k = 0; k < 48; ++k) out.sh[(int64_t)k * n + g] = 0.0f;
+        return;
+    }
+
+    const double mu0 = gp.means[g], mu1 = gp.means[n + g], mu2 = gp.means[2 * n + g];
+    const double s0 = gp.scales[g], s1 = gp.scales[n + g], s2 = gp.scales[2 * n + g];
+    const double q0 = gp.quats[g], q1 = gp.quats[n + g], q2 = gp.quats[2 * n + g], q3 = gp.quats[3 * n + g];
+    const double qn = sqrt(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
+    const double w = q0 / qn, x = q1 / qn, y = q2 / qn, z = q3 / qn;
+    double M[9];   // R(q) diag(s)
+    M[0] = (1.0 - 2.0 * (y * y + z * z)) * s0; M[1] = 2.0 * (x * y - w * z) * s1; M[2] = 2.0 * (x * z + w * y) * s2;
+    M[3] = 2.0 * (x * y + w * z) * s0; M[4] = (1.0 - 2.0 * (x * x + z * z)) * s1; M[5] = 2.0 * (y * z - w * x) * s2;
+    M[6] = 2.0 * (x * z - w * y) * s0; M[7] = 2.0 * (y * z + w * x) * s1; M[8] = (1.0 - 2.0 * (x * x + y * y)) * s2;
+    const double o = gp.opac[g];
+
+    double dmu[3] = {0.0, 0.0, 0.0};
+    double dM[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    double dop = 0.0;
+    bool first = true;    // the first visible view writes d_sh, later ones add to it
+
+    for (int v = 0; v < vt.n_views; ++v) {
+        if (!(vis & (1u << v))) continue;
+        const ViewK& V = vt.v[v];
+        const int64_t slot = (int64_t)v * n + g;
+        const float* g2 = grad2d + slot * kG2;
+        const double gmx = g2[0], gmy = g2[1], gA = g2[2], gB = g2[3], gC = g2[4], gop = g2[5];
+        const double gz = g2[9];
+        float W[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) W[i] = V.R[i];
+        const double tx = W[0] * mu0 + W[1] * mu1 + W[2] * mu2 + (double)V.t[0];
+        const double ty = W[3] * mu0 + W[4] * mu1 + W[5] * mu2 + (double)V.t[1];
+        const double tz = W[6] * mu0 + W[7] * mu1 + W[8] * mu2 + (double)V.t[2];
+        const double fx = V.fx, fy = V.fy;
+
+        // ---- colour: raw = sum_k sh_k Y_k(dhat) + 0.5, clamped at 0 (SH in FP32)
+        {
+            const double e0d = mu0 - V.campos[0], e1d = mu1 - V.campos[1], e2d = mu2 - V.campos[2];
+            const double dn = sqrt(e0d * e0d + e1d * e1d + e2d * e2d);
+            const double inv = 1.0 / dn;
+            const float d0 = (float)(e0d * inv), d1 = (float)(e1d * inv), d2 = (float)(e2d * inv);
+            float Y[16];
+            sh_eval_basis<float>(d0, d1, d2, opt.sh_degree, Y);
+            float raw0 = 0.5f, raw1 = 0.5f, raw2 = 0.5f;
+            for (int k = 0; k < 16; ++k) {
+                if (k < nb) {
+                    raw0 = fmaf(gp.sh[(int64_t)(3 * k + 0) * n + g], Y[k], raw0);
+                    raw1 = fmaf(gp.sh[(int64_t)(3 * k + 1) * n + g], Y[k], raw1);
+                    raw2 = fmaf(gp.sh[(int64_t)(3 * k + 2) * n + g], Y[k], raw2);
+                }
+            }
+            const float gr0 = raw0 < 0.0f ? 0.0f : g2[6];
+            const float gr1 = raw1 < 0.0f ? 0.0f : g2[7];
+            const float gr2 = raw2 < 0.0f ? 0.0f : g2[8];
+            float e0 = 0.0f, e1 = 0.0f, e2 = 0.0f;
+            for (int k = 0; k < 16; ++k) {
+                float* o0 = out.sh + (int64_t)(3 * k + 0) * n + g;
+                float* o1 = out.sh + (int64_t)(3 * k + 1) * n + g;
+                float* o2 = out.sh + (int64_t)(3 * k + 2) * n + g;
+                const float v0 = k < nb ? gr0 * Y[k] : 0.0f;
+                const float v1 = k < nb ? gr1 * Y[k] : 0.0f;
+                const float v2 = k < nb ? gr2 * Y[k] : 0.0f;
+                if (first) {
+                    *o0 = v0; *o1 = v1; *o2 = v2;
+                } else if (k < nb) {
+                    *o0 += v0; *o1 += v1; *o2 += v2;
+                }
+                if (k > 0 && k < nb) {
+                    const float gk = gr0 * gp.sh[(int64_t)(3 * k + 0) * n + g] +
+                                     gr1 * gp.sh[(int64_t)(3 * k + 1) * n + g] +
+                                     gr2 * gp.sh[(int64_t)(3 * k + 2) * n + g];
+                    float bx, by, bz;
+                    sh_basis_grad(d0, d1, d2, k, bx, by, bz);
+                    e0 = fmaf(gk, bx, e0); e1 = fmaf(gk, by, e1); e2 = fmaf(gk, bz, e2);
+                }
+            }
+            first = false;
+            const double dd = (double)e0 * d0 + (double)e1 * d1 + (double)e2 * d2;
+            dmu[0] += ((double)e0 - d0 * dd) * inv;
+            dmu[1] += ((double)e1 - d1 * dd) * inv;
+            dmu[2] += ((double)e2 - d2 * dd) * inv;
+        }
+
+        // ---- geometry, recomputed as in the forward
+        const double u = tx / tz, vv = ty / tz;
+        const bool ucl = u < V.ulo || u > V.uhi, vcl = vv < V.vlo || vv > V.vhi;
+        const double uc = fmin(fmax(u, V.ulo), V.uhi), vc = fmin(fmax(vv, V.vlo), V.vhi);
+        const double j00 = fx / tz, j02 = -fx * uc / tz, j11 = fy / tz, j12 = -fy * vc / tz;
+        double Tm[6];
+        Tm[0] = j00 * W[0] + j02 * W[6]; Tm[1] = j00 * W[1] + j02 * W[7]; Tm[2] = j00 * W[2] + j02 * W[8];
+        Tm[3] = j11 * W[3] + j12 * W[6]; Tm[4] = j11 * W[4] + j12 * W[7]; Tm[5] = j11 * W[5] + j12 * W[8];
+        double Vm[6];   // Tm M; Sigma_2D = Vm Vm^T
+        for (int r = 0; r < 2; ++r)
+            for (int c = 0; c < 3; ++c)
+                Vm[3 * r + c] = Tm[3 * r] * M[c] + Tm[3 * r + 1] * M[3 + c] + Tm[3 * r + 2] * M[6 + c];
+        const double ca = Vm[0] * Vm[0] + Vm[1] * Vm[1] + Vm[2] * Vm[2];
+        const double cb = Vm[0] * Vm[3] + Vm[1] * Vm[4] + Vm[2] * Vm[5];
+        const double cc = Vm[3] * Vm[3] + Vm[4] * Vm[4] + Vm[5] * Vm[5];
+        const double x0 = Vm[1] * Vm[5] - Vm[2] * Vm[4], x1 = Vm[2] * Vm[3] - Vm[0] * Vm[5],
+                     x2 = Vm[0] * Vm[4] - Vm[1] * Vm[3];
+        const double det2 = x0 * x0 + x1 * x1 + x2 * x2;
+        const double dil = (double)opt.dilation;
+        const double ad = ca + dil, cd = cc + dil;
+        const double detd = det2 + dil * (ca + cc) + dil * dil;
+        const double invd = 1.0 / detd;
+        const double A = cd * invd, B = -cb * invd, C = ad * invd;
+        const double rho = opt.aa ? (det2 > 0.0 ? sqrt(det2 * invd) : 0.0) : 1.0;
+
+        double dt0 = 0.0, dt1 = 0.0, dt2 = 0.0;
+        // mean2d = (fx tx/tz + cx, fy ty/tz + cy), depth = tz
+        dt0 += gmx * fx / tz;
+        dt2 -= gmx * fx * tx / (tz * tz);
+        dt1 += gmy * fy / tz;
+        dt2 -= gmy * fy * ty / (tz * tz);
+        dt2 += gz;
+        // conic = inverse of [[ad, cb], [cb, cd]]
+        double ga = gA * (-A * A) + gB * (-A * B) + gC * (-B * B);
+        double gb = gA * (-2.0 * A * B) + gB * (-(A * C + B * B)) + gC * (-2.0 * B * C);
+        double gc = gA * (-B * B) + gB * (-B * C) + gC * (-C * C);
+        // opacity' = o rho, rho = sqrt(det2 / detd)
+        dop += gop * rho;
+        if (opt.aa && rho > 0.0) {
+            const double k = gop * o / (2.0 * rho) * invd * invd;
+            ga += k * (cc * detd - det2 * cd);
+            gc += k * (ca * detd - det2 * ad);
+            gb += k * (-2.0 * cb * detd + 2.0 * cb * det2);
+        }
+        // Sigma_2D = Vm Vm^T with the symmetric gradient G = [[ga, gb/2], [gb/2, gc]]
+        const double G01 = 0.5 * gb;
+        double dVm[6];
+        for (int c = 0; c < 3; ++c) {
+            dVm[c] = 2.0 * (ga * Vm[c] + G01 * Vm[3 + c]);
+            dVm[3 + c] = 2.0 * (G01 * Vm[c] + gc * Vm[3 + c]);
+        }
+        // Vm = Tm M: dM += Tm^T dVm, dTm = dVm M^T
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) dM[3 * r + c] += Tm[r] * dVm[c] + Tm[3 + r] * dVm[3 + c];
+        double dTm[6];
+        for (int r = 0; r < 2; ++r)
+            for (int c = 0; c < 3; ++c)
+                dTm[3 * r + c] = dVm[3 * r] * M[3 * c] + dVm[3 * r + 1] * M[3 * c + 1] + dVm[3 * r + 2] * M[3 * c + 2];
+        // dJ = dTm W^T; J has entries (0,0), (0,2), (1,1), (1,2)
+        const double dJ00 = dTm[0] * W[0] + dTm[1] * W[1] + dTm[2] * W[2];
+        const double dJ02 = dTm[0] * W[6] + dTm[1] * W[7] + dTm[2] * W[8];
+        const double dJ11 = dTm[3] * W[3] + dTm[4] * W[4] + dTm[5] * W[5];
+        const double dJ12 = dTm[3] * W[6] + dTm[4] * W[7] + dTm[5] * W[8];
+        const double tz2 = tz * tz;
+        dt2 += dJ00 * (-fx / tz2) + dJ11 * (-fy / tz2);
+        if (!ucl) {
+            dt0 += dJ02 * (-fx / tz2);
+            dt2 += dJ02 * (2.0 * fx * tx / (tz2 * tz));
+        } else {
+            dt2 += dJ02 * (fx * uc / tz2);
+        }
+        if (!vcl) {
+            dt1 += dJ12 * (-fy / tz2);
+            dt2 += dJ12 * (2.0 * fy * ty / (tz2 * tz));
+        } else {
+            dt2 += dJ12 * (fy * vc / tz2);
+        }
+        // t = W mu + t_w
+        dmu[0] += W[0] * dt0 + W[3] * dt1 + W[6] * dt2;
+        dmu[1] += W[1] * dt0 + W[4] * dt1 + W[7] * dt2;
+        dmu[2] += W[2] * dt0 + W[5] * dt1 + W[8] * dt2;
+    }
+
+    // M = R(q) diag(s): ds_c = sum_r dM[r][c] R[r][c], dR[r][c] = dM[r][c] s_c
+    const double sc[3] = {s0, s1, s2};
+    double dR[9], ds[3] = {0.0, 0.0, 0.0};
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+            ds[c] += dM[3 * r + c] * M[3 * r + c] / sc[c];
+            dR[3 * r + c] = dM[3 * r + c] * sc[c];
+        }
+    // rotation of the unit quaternion (w, x, y, z)
+    double dq[4];
+    dq[0] = 2.0 * (-z * dR[1] + y * dR[2] + z * dR[3] - x * dR[5] - y * dR[6] + x * dR[7]);
+    dq[1] = 2.0 * (y * dR[1] + z * dR[2] + y * dR[3] - 2.0 * x * dR[4] - w * dR[5] + z * dR[6] + w * dR[7] - 2.0 * x * dR[8]);
+    dq[2] = 2.0 * (-2.0 * y * dR[0] + x * dR[1] + w * dR[2] + x * dR[3] + z * dR[5] - w * dR[6] + z * dR[7] - 2.0 * y * dR[8]);
+    dq[3] = 2.0 * (-2.0 * z * dR[0] - w * dR[1] + x * dR[2] + w * dR[3] - 2.0 * z * dR[4] + y * dR[5] + x * dR[6] + y * dR[7]);
+    // normalisation q / |q|
+    const double dot = dq[0] * w + dq[1] * x + dq[2] * y + dq[3] * z;
+    const double qh[4] = {w, x, y, z};
+    for (int c = 0; c < 3; ++c) out.means[c * n + g] = (float)dmu[c];
+    for (int c = 0; c < 3; ++c) out.scales[c * n + g] = (float)ds[c];
+    for (int c = 0; c < 4; ++c) out.quats[c * n + g] = (float)((dq[c] - qh[c] * dot) / qn);
+    out.opac[g] = (float)dop;
+}
+
+}  // namespace
+
+hipError_t launch_project_bwd(const GaussPtrs& g, int64_t n, const ViewTable& vt, const OptK& opt,
+                              const Projected& proj, const float* grad2d, const GradPtrs& out, float* mean2d_norm,
+                              float* absgrad, hipStream_t s) {
+    const unsigned blocks = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(k_project_bwd, dim3(blocks), dim3(256), 0, s, g, n, vt, opt, proj, grad2d, out, mean2d_norm,
+                       absgrad);
+    return hipGetLastError();
+}
+
+}  // namespace gs

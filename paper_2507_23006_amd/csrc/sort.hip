@@ -1,0 +1,343 @@
+// Device-wide primitives for binning: a stable LSD radix sort of
+// (uint32 key, uint32 value) pairs and an exclusive scan of uint32 -- gfx950.
+//
+// Radix pass = three launches (reduce-then-scan, no inter-workgroup
+// waiting, so no kernel can hang on a missing predecessor):
+//   1. upsweep: each workgroup counts the digits of its 4096-key tile;
+//      counts go to a digit-major table hist[digit][tile];
+//   2. the table is exclusive-scanned in digit-major order, which yields
+//      the global output offset of every (digit, tile);
+//   3. downsweep: each wave64 ranks its 1024 keys in 16 rounds of 64 with
+//      ballot-based digit matching (lanes with equal digits find each other
+//      through one __ballot per digit bit; rank = popcount of lower peers),
+//      keeping per-wave running digit counters in LDS.  Keys and values are
+//      then scattered into LDS in digit order and written out in runs, so
+//      global stores are contiguous per digit.
+// Stability: inside a wave items are ranked in (round, lane) order, waves
+// and tiles are concatenated in order, so equal keys keep input order.
+#include "gs_internal.h"
+
+namespace gs {
+
+namespace {
+
+constexpr int kSortThreads = 256;
+constexpr int kSortIpt = 16;                        // items per thread
+constexpr int kSortTile = kSortThreads * kSortIpt;  // 4096 keys per workgroup
+constexpr int kWaveItems = 64 * kSortIpt;           // 1024 keys per wave
+constexpr int kMaxRadixBits = 8;
+
+__device__ __forceinline__ unsigned long long lanemask_lt() {
+    const unsigned lane = __lane_id();
+    return lane ? (~0ull >> (64 - lane)) : 0ull;
+}
+
+// Mask of the active lanes whose `digit` equals this lane's, restricted to
+// lanes where `valid` holds.  `bits` ballots.
+__device__ __forceinline__ unsigned long long match_digit(uint32_t digit, bool valid, int bits) {
+    unsigned long long m = __ballot(valid);
+    for (int b = 0; b < bits; ++b) {
+        const bool bit = (digit >> b) & 1u;
+        const unsigned long long bb = __ballot(bit);
+        m &= bit ? bb : ~bb;
+    }
+    return m;
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_radix_upsweep(const uint32_t* __restrict__ keys, uint32_t n,
+                                                                int shift, int bits, uint32_t* __restrict__ hist,
+                                                                uint32_t n_tiles) {
+    __shared__ uint32_t cnt[4][1 << kMaxRadixBits];
+    const int radix = 1 << bits;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // rows are (1 << kMaxRadixBits) apart: clear the whole table, not 4 * radix entries
+    for (int i = threadIdx.x; i < 4 * (1 << kMaxRadixBits); i += kSortThreads) (&cnt[0][0])[i] = 0;
+    __syncthreads();
+    const uint32_t base = blockIdx.x * kSortTile + wave * kWaveItems;
+    const uint32_t mask = (uint32_t)radix - 1;
+    for (int r = 0; r < kSortIpt; ++r) {
+        const uint32_t idx = base + r * 64 + lane;
+        const bool valid = idx < n;
+        const uint32_t d = valid ? (keys[idx] >> shift) & mask : 0u;
+        const unsigned long long m = match_digit(d, valid, bits);
+        if (valid && lane == __ffsll((unsigned long long)m) - 1) cnt[wave][d] += (uint32_t)__popcll(m);
+    }
+    __syncthreads();
+    for (int d = threadIdx.x; d < radix; d += kSortThreads)
+        hist[(size_t)d * n_tiles + blockIdx.x] = cnt[0][d] + cnt[1][d] + cnt[2][d] + cnt[3][d];
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_radix_downsweep(
+    const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
+    uint32_t* __restrict__ vout, uint32_t n, int shift, int bits, const uint32_t* __restrict__ hist_scan,
+    uint32_t n_tiles) {
+    __shared__ uint32_t s_keys[kSortTile];
+    __shared__ uint32_t s_vals[kSortTile];
+    __shared__ uint32_t s_wcnt[4][1 << kMaxRadixBits];
+    __shared__ uint32_t s_bstart[1 << kMaxRadixBits];
+    __shared__ uint32_t s_goff[1 << kMaxRadixBits];
+    __shared__ uint32_t s_wsum[4];
+
+    const int radix = 1 << bits;
+    const uint32_t mask = (uint32_t)radix - 1;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int i = threadIdx.x; i < 4 * (1 << kMaxRadixBits); i += kSortThreads) (&s_wcnt[0][0])[i] = 0;
+    __syncthreads();
+
+    const uint32_t tile0 = blockIdx.x * kSortTile;
+    const uint32_t base = tile0 + wave * kWaveItems;
+    uint32_t key[kSortIpt], val[kSortIpt], rank[kSortIpt];
+#pragma unroll
+    for (int r = 0; r < kSortIpt; ++r) {
+        const uint32_t idx = base + r * 64 + lane;
+        const bool valid = idx < n;
+        key[r] = valid ? kin[idx] : 0u;
+        val[r] = valid ? vin[idx] : 0u;
+    }
+    const unsigned long long lt = lanemask_lt();
+#pragma unroll
+    for (int r = 0; r < kSortIpt; ++r) {
+        const uint32_t idx = base + r * 64 + lane;
+        const bool valid = idx < n;
+        const uint32_t d = (key[r] >> shift) & mask;
+        const unsigned long long m = match_digit(d, valid, bits);
+        uint32_t pre = 0;
+        if (valid) pre = s_wcnt[wave][d];
+        rank[r] = pre + (uint32_t)__popcll(m & lt);
+        // every lane of the wave reads the counter before the group leader
+        // rewrites it: one wave's LDS instructions execute in order; the
+        // wave barrier keeps the compiler from moving LDS accesses across
+        __builtin_amdgcn_wave_barrier();
+        if (valid && lane == __ffsll((unsigned long long)m) - 1) s_wcnt[wave][d] = pre + (uint32_t)__popcll(m);
+        __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+
+    // per digit: exclusive prefix over waves, block total, then an exclusive
+    // scan of the block totals over digits
+    uint32_t total = 0;
+    if ((int)threadIdx.x < radix) {
+        const int d = threadIdx.x;
+        const uint32_t c0 = s_wcnt[0][d], c1 = s_wcnt[1][d], c2 = s_wcnt[2][d], c3 = s_wcnt[3][d];
+        s_wcnt[0][d] = 0;
+        s_wcnt[1][d] = c0;
+        s_wcnt[2][d] = c0 + c1;
+        s_wcnt[3][d] = c0 + c1 + c2;
+        total = c0 + c1 + c2 + c3;
+        s_goff[d] = hist_scan[(size_t)d * n_tiles + blockIdx.x];
+    }
+    // block-wide exclusive scan of `total` (thread d holds digit d)
+    uint32_t incl = total;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += y;
+    }
+    if (lane == 63) s_wsum[wave] = incl;
+    __syncthreads();
+    uint32_t wpre = 0;
+    for (int w = 0; w < wave; ++w) wpre += s_wsum[w];
+    if ((int)threadIdx.x < radix) s_bstart[threadIdx.x] = wpre + incl - total;
+    __syncthreads();
+
+#pragma unroll
+    for (int r = 0; r < kSortIpt; ++r) {
+        const uint32_t idx = base + r * 64 + lane;
+        if (idx < n) {
+            const uint32_t d = (key[r] >> shift) & mask;
+            const uint32_t lp = s_bstart[d] + s_wcnt[wave][d] + rank[r];
+            s_keys[lp] = key[r];
+            s_vals[lp] = val[r];
+        }
+    }
+    __syncthreads();
+    const uint32_t count = min((uint32_t)kSortTile, n - tile0);
+    for (uint32_t i = threadIdx.x; i < count; i += kSortThreads) {
+        const uint32_t k = s_keys[i];
+        const uint32_t d = (k >> shift) & mask;
+        const uint32_t gp = s_goff[d] + (i - s_bstart[d]);
+        if (gp < n) {     // always true for a consistent histogram; guards the write
+            kout[gp] = k;
+            vout[gp] = s_vals[i];
+        }
+    }
+}
+
+// ---------------------------------------------------------------- scan
+
+constexpr int kScanThreads = 256;
+constexpr int kScanIpt = 16;
+constexpr int kScanTile = kScanThreads * kScanIpt;
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    return x;
+}
+
+// tile sums
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint32_t* __restrict__ in, uint32_t n,
+                                                              uint32_t* __restrict__ tsum) {
+    __shared__ uint32_t s_w[4];
+    const uint32_t base = blockIdx.x * kScanTile;
+    uint32_t acc = 0;
+#pragma unroll
+    for (int r = 0; r < kScanIpt; ++r) {
+        const uint32_t idx = base + r * kScanThreads + threadIdx.x;
+        if (idx < n) acc += in[idx];
+    }
+    const uint32_t w = wave_incl_scan(acc);
+    if ((threadIdx.x & 63) == 63) s_w[threadIdx.x >> 6] = w;
+    __syncthreads();
+    if (threadIdx.x == 0) tsum[blockIdx.x] = s_w[0] + s_w[1] + s_w[2] + s_w[3];
+}
+
+// exclusive scan of the tile sums in place (one workgroup), 64-bit total
+__global__ __launch_bounds__(1024) void k_scan_top(uint32_t* __restrict__ tsum, uint32_t nt,
+                                                   unsigned long long* __restrict__ total) {
+    __shared__ unsigned long long s_w[16];
+    __shared__ unsigned long long s_carry;
+    if (threadIdx.x == 0) s_carry = 0;
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (uint32_t c0 = 0; c0 < nt; c0 += 1024) {
+        const uint32_t idx = c0 + threadIdx.x;
+        const unsigned long long x = idx < nt ? tsum[idx] : 0ull;
+        unsigned long long incl = x;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const unsigned long long y = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += y;
+        }
+        if (lane == 63) s_w[wave] = incl;
+        __syncthreads();
+        unsigned long long pre = s_carry;
+        for (int w = 0; w < wave; ++w) pre += s_w[w];
+        if (idx < nt) tsum[idx] = (uint32_t)(pre + incl - x);
+        __syncthreads();
+        if (threadIdx.x == 1023) s_carry = pre + incl;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *total = s_carry;
+}
+
+// per-tile exclusive scan plus the tile's offset; items are blocked per
+// thread (16 consecutive) so that the in-thread prefix is sequential
+__global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t* __restrict__ in,
+                                                            uint32_t* __restrict__ out, uint32_t n,
+                                                            const uint32_t* __restrict__ tsum) {
+    __shared__ uint32_t s_buf[kScanTile];
+    __shared__ uint32_t s_w[4];
+    const uint32_t base = blockIdx.x * kScanTile;
+#pragma unroll
+    for (int r = 0; r < kScanIpt; ++r) {
+        const uint32_t i = r * kScanThreads + threadIdx.x;
+        s_buf[i] = (base + i < n) ? in[base + i] : 0u;
+    }
+    __syncthreads();
+    uint32_t v[kScanIpt];
+    uint32_t acc = 0;
+#pragma unroll
+    for (int r = 0; r < kScanIpt; ++r) {
+        v[r] = s_buf[threadIdx.x * kScanIpt + r];
+        acc += v[r];
+    }
+    const uint32_t incl = wave_incl_scan(acc);
+    if ((threadIdx.x & 63) == 63) s_w[threadIdx.x >> 6] = incl;
+    __syncthreads();
+    uint32_t pre = tsum[blockIdx.x] + incl - acc;
+    for (int w = 0; w < (int)(threadIdx.x >> 6); ++w) pre += s_w[w];
+#pragma unroll
+    for (int r = 0; r < kScanIpt; ++r) {
+        s_buf[threadIdx.x * kScanIpt + r] = pre;
+        pre += v[r];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kScanIpt; ++r) {
+        const uint32_t i = r * kScanThreads + threadIdx.x;
+        if (base + i < n) out[base + i] = s_buf[i];
+    }
+}
+
+__global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t v, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+}  // namespace
+
+size_t radix_hist_elems(uint32_t n) {
+    const size_t tiles = (n + kSortTile - 1) / kSortTile;
+    return (tiles ? tiles : 1) * (size_t)(1 << kMaxRadixBits) + scan_tmp_elems((uint32_t)(tiles * 256));
+}
+
+// tile sums, padded to an even count, then the 64-bit total
+static size_t scan_sums_elems(uint32_t n) {
+    const size_t t = (n + kScanTile - 1) / kScanTile;
+    return ((t ? t : 1) + 1) & ~size_t(1);
+}
+
+size_t scan_tmp_elems(uint32_t n) { return scan_sums_elems(n) + 2; }
+
+hipError_t fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s) {
+    if (!n) return hipSuccess;
+    size_t blocks = (n + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+
+hipError_t exclusive_scan_u32(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* tmp,
+                              unsigned long long* total, hipStream_t s) {
+    const uint32_t nt = (n + kScanTile - 1) / kScanTile;
+    if (n == 0) {
+        hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, (uint32_t*)total, 0u, (size_t)2);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nt), dim3(kScanThreads), 0, s, in, n, tmp);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, tmp, nt, total);
+    hipLaunchKernelGGL(k_scan_down, dim3(nt), dim3(kScanThreads), 0, s, in, out, n, tmp);
+    return hipGetLastError();
+}
+
+// Sorts keys/vals on bits [begin_bit, end_bit) with passes of <= 8 bits of
+// near-equal width.  The result lands in (keys, vals) or in the alternate
+// buffers; *result_in_alt says which.  `hist` needs radix_hist_elems(n).
+hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt, uint32_t n,
+                            int begin_bit, int end_bit, uint32_t* hist, hipStream_t s, bool* result_in_alt) {
+    *result_in_alt = false;
+    if (n <= 1 || end_bit <= begin_bit) return hipSuccess;
+    const int total_bits = end_bit - begin_bit;
+    const int passes = (total_bits + kMaxRadixBits - 1) / kMaxRadixBits;
+    const uint32_t tiles = (n + kSortTile - 1) / kSortTile;
+    const size_t hist_elems = (size_t)tiles * (1 << kMaxRadixBits);
+    uint32_t* scan_tmp = hist + hist_elems;
+    unsigned long long* total = reinterpret_cast<unsigned long long*>(scan_tmp + scan_sums_elems((uint32_t)hist_elems));
+    uint32_t *ki = keys, *vi = vals, *ko = keys_alt, *vo = vals_alt;
+    int shift = begin_bit;
+    for (int p = 0; p < passes; ++p) {
+        const int remaining = end_bit - shift;
+        const int bits = (remaining + (passes - p) - 1) / (passes - p);
+        const uint32_t radix_elems = (uint32_t)tiles << bits;
+        hipLaunchKernelGGL(k_radix_upsweep, dim3(tiles), dim3(kSortThreads), 0, s, ki, n, shift, bits, hist, tiles);
+        hipError_t e = exclusive_scan_u32(hist, hist, radix_elems, scan_tmp, total, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_radix_downsweep, dim3(tiles), dim3(kSortThreads), 0, s, ki, vi, ko, vo, n, shift, bits,
+                           hist, tiles);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        shift += bits;
+        uint32_t* t;
+        t = ki; ki = ko; ko = t;
+        t = vi; vi = vo; vo = t;
+        *result_in_alt = !*result_in_alt;
+    }
+    return hipSuccess;
+}
+
+}  // namespace gs

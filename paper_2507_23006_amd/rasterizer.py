@@ -1,0 +1,253 @@
+"""Torch-facing wrapper of libgs: device buffers and streams come from torch,
+every computation runs in the library's gfx950 kernels.
+
+Parameter layout (structure-of-arrays, float32, on the GPU):
+  means [3, N], scales [3, N] (positive), quats [4, N] as (w, x, y, z),
+  opacities [N] in (0, 1), sh [16, 3, N].
+Outputs of several views are concatenated per pixel (view-major, each view
+row-major); ``split_views`` reshapes them into per-view images.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib as L
+
+
+@dataclass
+class RenderOptions:
+    sh_degree: int = 3
+    dilation: float = 0.3
+    aa: bool = False            # opacity compensation of the dilation (Mip-Splatting style 2D filter)
+    bg: tuple = (0.0, 0.0, 0.0)
+    absgrad: bool = False       # also accumulate |dL_p/d mean2d| per pixel (AbsGS)
+
+    def c(self) -> L.GsOptions:
+        return L.make_options(self.sh_degree, self.dilation, self.aa, self.bg)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream() -> C.c_void_p:
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _check_param(t: torch.Tensor, name: str, shape) -> None:
+    if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous float32 CUDA tensor")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+
+def check_params(means, scales, quats, opacities, sh) -> int:
+    n = means.shape[-1]
+    _check_param(means, "means", (3, n))
+    _check_param(scales, "scales", (3, n))
+    _check_param(quats, "quats", (4, n))
+    _check_param(opacities, "opacities", (n,))
+    _check_param(sh, "sh", (16, 3, n))
+    return n
+
+
+def gaussians_struct(means, scales, quats, opacities, sh) -> L.GsGaussians:
+    g = L.GsGaussians()
+    g.means, g.scales, g.quats = means.data_ptr(), scales.data_ptr(), quats.data_ptr()
+    g.opacities, g.sh, g.n = opacities.data_ptr(), sh.data_ptr(), means.shape[-1]
+    return g
+
+
+class Workspace:
+    """Grow-only device scratch buffers, one per purpose (the library itself
+    never allocates device memory)."""
+
+    def __init__(self):
+        self._bufs = {}
+
+    def get(self, name: str, nbytes: int, device) -> torch.Tensor:
+        b = self._bufs.get(name)
+        if b is None or b.numel() < nbytes or b.device != device:
+            b = torch.empty(max(int(nbytes), 256) + 256, dtype=torch.uint8, device=device)
+            self._bufs[name] = b
+        return b
+
+    @staticmethod
+    def aligned(buf: torch.Tensor) -> int:
+        p = buf.data_ptr()
+        return (p + 255) & ~255
+
+
+_default_ws = Workspace()
+
+
+@dataclass
+class Projected:
+    rec: torch.Tensor        # [S, 12] float32
+    rect: torch.Tensor       # [S, 2] int32 (bit patterns of uint32)
+    tiles: torch.Tensor      # [S] int32
+    depth_key: torch.Tensor  # [S] int32 (bit patterns of uint32)
+
+    def c(self) -> L.GsProjected:
+        p = L.GsProjected()
+        p.rec, p.rect = self.rec.data_ptr(), self.rect.data_ptr()
+        p.tiles, p.depth_key = self.tiles.data_ptr(), self.depth_key.data_ptr()
+        return p
+
+
+def views_extent(cams) -> tuple:
+    lib = L.load()
+    arr = L.make_cameras(cams)
+    nt, npx = C.c_int64(), C.c_int64()
+    L.check(lib.gs_views_extent(arr, len(cams), C.byref(nt), C.byref(npx)))
+    return nt.value, npx.value
+
+
+def project(means, scales, quats, opacities, sh, cams, opts: RenderOptions) -> Projected:
+    lib = L.load()
+    n = check_params(means, scales, quats, opacities, sh)
+    S = n * len(cams)
+    dev = means.device
+    out = Projected(torch.empty((S, L.REC_FLOATS), dtype=torch.float32, device=dev),
+                    torch.empty((S, 2), dtype=torch.int32, device=dev),
+                    torch.empty((S,), dtype=torch.int32, device=dev),
+                    torch.empty((S,), dtype=torch.int32, device=dev))
+    g = gaussians_struct(means, scales, quats, opacities, sh)
+    L.check(lib.gs_project(C.byref(g), L.make_cameras(cams), len(cams), C.byref(opts.c()), C.byref(out.c()),
+                           _stream()))
+    return out
+
+
+def bin_sort(proj: Projected, cams, n: int, ws: Workspace | None = None, capacity_hint: int | None = None):
+    """Returns (pair_vals [P] int32, tile_ranges [T, 2] int32, P).  pair_vals
+    is a fresh tensor (torch's caching allocator), so results of several
+    calls can be alive at once; the capacity guess is remembered."""
+    lib = L.load()
+    ws = ws or _default_ws
+    dev = proj.rec.device
+    S = n * len(cams)
+    n_tiles, _ = views_extent(cams)
+    cap = int(capacity_hint or max(1 << 20, 4 * S, getattr(ws, "pair_capacity", 0)))
+    ranges = torch.empty((n_tiles, 2), dtype=torch.int32, device=dev)
+    cams_c = L.make_cameras(cams)
+    for _ in range(2):
+        pairs = torch.empty((cap,), dtype=torch.int32, device=dev)
+        wsz = lib.gs_bin_workspace_size(S, cap)
+        wbuf = ws.get("bin", wsz + 256, dev)
+        npairs = C.c_int64()
+        rc = lib.gs_bin_sort(C.byref(proj.c()), cams_c, len(cams), n, cap, _ptr(pairs), _ptr(ranges),
+                             C.byref(npairs), C.c_void_p(Workspace.aligned(wbuf)), wsz, _stream())
+        if rc == L.GS_ERR_CAPACITY and cap < npairs.value < 0xFFFFFF00:
+            cap = int(npairs.value * 1.25) + 1024
+            ws.pair_capacity = cap
+            continue
+        L.check(rc)
+        P = int(npairs.value)
+        return pairs[:P], ranges, P
+    raise L.GsError(L.GS_ERR_CAPACITY, "pair buffer could not be grown")
+
+
+def render_fwd(proj: Projected, pair_vals, ranges, cams, opts: RenderOptions) -> dict:
+    lib = L.load()
+    dev = proj.rec.device
+    _, npx = views_extent(cams)
+    out = {"rgb": torch.empty((npx, 3), dtype=torch.float32, device=dev),
+           "depth": torch.empty((npx,), dtype=torch.float32, device=dev),
+           "alpha": torch.empty((npx,), dtype=torch.float32, device=dev),
+           "T": torch.empty((npx,), dtype=torch.float32, device=dev),
+           "last": torch.empty((npx,), dtype=torch.int32, device=dev)}
+    L.check(lib.gs_render_fwd(C.byref(proj.c()), _ptr(pair_vals), _ptr(ranges), L.make_cameras(cams), len(cams),
+                              C.byref(opts.c()), _ptr(out["rgb"]), _ptr(out["depth"]), _ptr(out["alpha"]),
+                              _ptr(out["T"]), _ptr(out["last"]), _stream()))
+    return out
+
+
+def render_bwd(params, cams, opts: RenderOptions, proj: Projected, pair_vals, ranges, T, last, d_rgb, d_depth,
+               d_alpha, ws: Workspace | None = None) -> dict:
+    lib = L.load()
+    ws = ws or _default_ws
+    means, scales, quats, opacities, sh = params
+    n = check_params(means, scales, quats, opacities, sh)
+    V = len(cams)
+    dev = means.device
+    grads = {k: torch.empty_like(t) for k, t in zip(("means", "scales", "quats", "opacities", "sh"), params)}
+    norm = torch.empty((V, n), dtype=torch.float32, device=dev)
+    absg = torch.empty((V, n, 2), dtype=torch.float32, device=dev) if opts.absgrad else None
+    g = gaussians_struct(*params)
+    go = L.GsGaussiansGrad()
+    go.d_means, go.d_scales, go.d_quats = grads["means"].data_ptr(), grads["scales"].data_ptr(), grads["quats"].data_ptr()
+    go.d_opacities, go.d_sh = grads["opacities"].data_ptr(), grads["sh"].data_ptr()
+    wsz = lib.gs_render_bwd_workspace_size(n * V)
+    wbuf = ws.get("bwd", wsz + 256, dev)
+    cont = lambda t: t.contiguous() if t is not None else None
+    d_rgb, d_depth, d_alpha = cont(d_rgb), cont(d_depth), cont(d_alpha)
+    L.check(lib.gs_render_bwd(C.byref(g), L.make_cameras(cams), V, C.byref(opts.c()), C.byref(proj.c()),
+                              _ptr(pair_vals), _ptr(ranges), _ptr(T), _ptr(last), _ptr(d_rgb), _ptr(d_depth),
+                              _ptr(d_alpha), C.byref(go), _ptr(norm), _ptr(absg),
+                              C.c_void_p(Workspace.aligned(wbuf)), wsz, _stream()))
+    grads["mean2d_grad_norm"] = norm
+    grads["absgrad"] = absg
+    grads["_grad2d_ws"] = (wbuf, n * V)
+    return grads
+
+
+def grad2d_view(grads: dict) -> torch.Tensor:
+    """The per-slot 2D gradients [S, 12] left in the backward workspace."""
+    wbuf, S = grads["_grad2d_ws"]
+    off = Workspace.aligned(wbuf) - wbuf.data_ptr()
+    return wbuf[off:off + S * 48].view(torch.float32).view(S, 12)
+
+
+class RenderStats:
+    """Filled by the backward: per-view |dL/d mean2d| [V, N] in pixels, and
+    (with absgrad) the per-pixel absolute accumulation [V, N, 2]."""
+    mean2d_grad_norm = None
+    absgrad = None
+    n_pairs = 0
+
+
+class GsRasterize(torch.autograd.Function):
+    """Differentiable rasterization of several views of the same Gaussians.
+    Returns flat per-pixel outputs rgb [Npix, 3], depth [Npix] (sum of
+    z * alpha * T) and alpha [Npix]."""
+
+    @staticmethod
+    def forward(ctx, means, scales, quats, opacities, sh, cams, opts: RenderOptions, stats: RenderStats):
+        params = tuple(t.detach().contiguous() for t in (means, scales, quats, opacities, sh))
+        n = params[0].shape[-1]
+        proj = project(*params, cams, opts)
+        pair_vals, ranges, P = bin_sort(proj, cams, n)
+        out = render_fwd(proj, pair_vals, ranges, cams, opts)
+        ctx.save_for_backward(*params, proj.rec, proj.rect, proj.tiles, proj.depth_key, pair_vals, ranges,
+                              out["T"], out["last"])
+        ctx.cams, ctx.opts, ctx.stats = list(cams), opts, stats
+        if stats is not None:
+            stats.n_pairs = P
+        return out["rgb"], out["depth"], out["alpha"]
+
+    @staticmethod
+    def backward(ctx, d_rgb, d_depth, d_alpha):
+        (means, scales, quats, opacities, sh, rec, rect, tiles, dkey, pair_vals, ranges, T, last) = ctx.saved_tensors
+        proj = Projected(rec, rect, tiles, dkey)
+        g = render_bwd((means, scales, quats, opacities, sh), ctx.cams, ctx.opts, proj, pair_vals, ranges, T, last,
+                       d_rgb, d_depth, d_alpha)
+        if ctx.stats is not None:
+            ctx.stats.mean2d_grad_norm = g["mean2d_grad_norm"]
+            ctx.stats.absgrad = g["absgrad"]
+        return g["means"], g["scales"], g["quats"], g["opacities"], g["sh"], None, None, None
+
+
+def rasterize(means, scales, quats, opacities, sh, cams, opts: RenderOptions | None = None,
+              stats: RenderStats | None = None):
+    """Autograd entry point; returns flat (rgb, depth, alpha) over all views."""
+    return GsRasterize.apply(means, scales, quats, opacities, sh, list(cams), opts or RenderOptions(), stats)
+
+
+def split_views(flat: torch.Tensor, cams) -> list:
+    """Per-view [H, W, ...] views of a flat per-pixel tensor."""
+    sizes = [int(c.width) * int(c.height) for c in cams]
+    parts = torch.split(flat, sizes, dim=0)
+    return [p.view(int(c.height), int(c.width), *flat.shape[1:]) for p, c in zip(parts, cams)]

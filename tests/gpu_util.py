@@ -1,0 +1,73 @@
+"""Helpers shared by the GPU tests: move seeded scenes to the device, run the
+GPU path through the C ABI binding, and convert its records for the oracle.
+Test infrastructure only."""
+import math
+
+import numpy as np
+import torch
+
+import oracle
+
+LOG2E = 1.0 / math.log(2.0)
+
+
+def to_dev(scene, device="cuda:0", requires_grad=False):
+    ts = [torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(device)
+          for a in (scene.means, scene.scales, scene.quats, scene.opacities, scene.sh)]
+    if requires_grad:
+        for t in ts:
+            t.requires_grad_(True)
+    return ts
+
+
+def decode_records(rec: np.ndarray):
+    """GPU records [S, 12] -> oracle 2D quantities (float64, exact widening):
+    mean2d, conic (A, B, C) undoing the -log2(e) (1/2, 1, 1/2) scaling,
+    opacity', rgb, depth."""
+    rec = rec.astype(np.float64)
+    mean2d = rec[:, 0:2].copy()
+    conic = np.stack([-2.0 * rec[:, 2] / LOG2E, -rec[:, 3] / LOG2E, -2.0 * rec[:, 4] / LOG2E], 1)
+    return mean2d, conic, rec[:, 5].copy(), rec[:, 8:11].copy(), rec[:, 6].copy()
+
+
+def decode_rect(rect: np.ndarray, tiles: np.ndarray, cams, n):
+    """GPU rect words -> (tile x0, y0, x1, y1) per slot, view-local."""
+    rect = rect.view(np.uint32).astype(np.int64)
+    tiles = tiles.astype(np.int64)
+    out = np.zeros((len(tiles), 4), np.int64)
+    toff = np.cumsum([0] + [c.n_tiles for c in cams])[:-1]
+    for v, c in enumerate(cams):
+        sl = slice(v * n, (v + 1) * n)
+        base = rect[sl, 0] - toff[v]
+        w = rect[sl, 1] & 0xFFFF
+        tw = rect[sl, 1] >> 16
+        vis = tiles[sl] > 0
+        x0 = np.where(vis, base % c.tiles_x, 0)
+        y0 = np.where(vis, base // c.tiles_x, 0)
+        h = np.where(vis, tiles[sl] // np.maximum(w, 1), 0)
+        out[sl] = np.stack([x0, y0, x0 + w - 1, y0 + h - 1], 1) * vis[:, None]
+        assert np.all(tw[vis] == c.tiles_x)
+    return out
+
+
+def gpu_forward(gs, scene, cams, opts):
+    params = to_dev(scene)
+    n = scene.n
+    proj = gs.project(*params, cams, opts)
+    pairs, ranges, P = gs.bin_sort(proj, cams, n)
+    out = gs.render_fwd(proj, pairs, ranges, cams, opts)
+    torch.cuda.synchronize()
+    return params, proj, pairs, ranges, P, out
+
+
+def oracle_opt(opts):
+    return dict(sh_degree=opts.sh_degree, dilation=opts.dilation, aa=opts.aa, bg=opts.bg)
+
+
+def view_images(flat, cams):
+    out, off = [], 0
+    for c in cams:
+        k = c.width * c.height
+        out.append(flat[off:off + k].reshape(c.height, c.width, *flat.shape[1:]))
+        off += k
+    return out

@@ -1,0 +1,306 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Tolerances (derived in the design doc):
+  projection: mean2d |d| <= 1e-4 px; conic, opacity', depth, rgb relative
+      <= 2e-6 (FP64 arithmetic rounded once to FP32);
+  tile rectangles and counts: equal, except Gaussians whose extent or mean
+      sits within 1e-9 of an integer (none expected);
+  binning and sort: bit-exact on the GPU's own records (stage-chained);
+  compositing: max |d| <= 1e-4 on rgb and alpha, depth <= 1e-4 max(1, depth),
+      outside the guard band (pixels where an evaluated alpha is within a
+      relative eps of 1/255 or T(1 - alpha) within eps of 1e-4);
+  gradients: per group ||g - g_ref|| / ||g_ref|| <= 1e-3, and elementwise
+      |g - g_ref| <= 1e-3 |g_ref| + 1e-3 rms(g_ref) for >= 99.9% of entries.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synthetic as S
+from gpu_util import decode_records, decode_rect, gpu_forward, oracle_opt, to_dev, view_images
+
+pytestmark = pytest.mark.gpu
+
+
+def small_cam(W, H, f, tz=4.0):
+    vm = np.eye(4, dtype=np.float32)
+    vm[2, 3] = tz
+    return S.Camera(f, f, W / 2.0, H / 2.0, vm, W, H)
+
+
+def oblique_cam(W, H, f):
+    return S.Camera(f, f, W / 2.0, H / 2.0, S.look_at((1.6, -1.1, -3.3), (0.05, 0.1, 0.0), up=(0.3, -1, 0.2)), W, H)
+
+
+CASES = {
+    # name: (scene factory, cams, options)
+    "c1": (lambda: S.scene_c1(), [S.camera_c1()], dict(aa=False)),
+    "ragged_aa": (lambda: S.random_scene(3001, seed=5, log_scale_mu=-2.6), [oblique_cam(173, 91, 120.0)],
+                  dict(aa=True, bg=(0.1, 0.2, 0.3))),
+    "multiview": (lambda: S.random_scene(2500, seed=6, log_scale_mu=-2.5),
+                  [S.camera_c1(), oblique_cam(100, 70, 80.0), small_cam(37, 53, 40.0)], dict(aa=True, sh_degree=2)),
+}
+
+
+def _opts(gs, d):
+    return gs.RenderOptions(**d)
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_projection_matches_oracle(gpu_lib, case):
+    make, cams, od = CASES[case]
+    scene = make()
+    opts = _opts(gpu_lib, od)
+    params = to_dev(scene)
+    proj = gpu_lib.project(*params, cams, opts)
+    torch.cuda.synchronize()
+    rec = proj.rec.cpu().numpy()
+    tiles = proj.tiles.cpu().numpy()
+    rect = decode_rect(proj.rect.cpu().numpy(), tiles, cams, scene.n)
+    n = scene.n
+    for v, c in enumerate(cams):
+        p = oracle.project(scene, c, **oracle_opt(opts))
+        sl = slice(v * n, (v + 1) * n)
+        border = (p["tiles"] > 0) & ((np.abs(p["extent"] - np.round(p["extent"])) < 1e-9) |
+                                     np.any(np.abs(p["mean2d"] - np.round(p["mean2d"])) < 1e-9, axis=1))
+        ok = ~border
+        np.testing.assert_array_equal(tiles[sl][ok], p["tiles"][ok])
+        np.testing.assert_array_equal(rect[sl][ok], p["rect"][ok])
+        vis = (p["tiles"] > 0) & ok
+        assert vis.sum() > 10
+        m2, con, op, rgb, dep = decode_records(rec[sl])
+        np.testing.assert_allclose(m2[vis], p["mean2d"][vis], atol=1e-4, rtol=0)
+        np.testing.assert_allclose(con[vis], p["conic"][vis], rtol=2e-6, atol=1e-7 * np.abs(p["conic"][vis]).max())
+        np.testing.assert_allclose(op[vis], p["opac"][vis], rtol=2e-6, atol=1e-7)
+        np.testing.assert_allclose(dep[vis], p["depth"][vis], rtol=2e-7)
+        np.testing.assert_allclose(rgb[vis], p["rgb"][vis], rtol=2e-6, atol=2e-6)
+        keys = proj.depth_key.cpu().numpy().view(np.uint32)[sl]
+        np.testing.assert_array_equal(keys[vis], oracle.depth_key(p["depth"])[vis])
+        assert np.all(keys[tiles[sl] == 0] == 0xFFFFFFFF)
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_binning_bit_exact_stage_chained(gpu_lib, case):
+    make, cams, od = CASES[case]
+    scene = make()
+    opts = _opts(gpu_lib, od)
+    params, proj, pairs, ranges, P, _ = gpu_forward(gpu_lib, scene, cams, opts)
+    tiles = proj.tiles.cpu().numpy()
+    rect = decode_rect(proj.rect.cpu().numpy(), tiles, cams, scene.n)
+    keys = proj.depth_key.cpu().numpy().view(np.uint32)
+    slot_view = np.repeat(np.arange(len(cams), dtype=np.int32), scene.n)
+    ref = oracle.bin_pairs(rect, tiles, keys, slot_view, cams)
+    assert P == ref["n_pairs"] and P > 0
+    np.testing.assert_array_equal(pairs.cpu().numpy().view(np.uint32), ref["pair_slot"])
+    np.testing.assert_array_equal(ranges.cpu().numpy().view(np.uint32), ref["ranges"])
+
+
+def _guarded_compare(gpu_img, ref, guard, tol=1e-4):
+    ok = guard == 0
+    d_rgb = np.abs(gpu_img["rgb"] - ref["rgb"]).max(axis=-1)
+    d_a = np.abs(gpu_img["alpha"] - ref["alpha"])
+    d_d = np.abs(gpu_img["depth"] - ref["depth"]) / np.maximum(1.0, np.abs(ref["depth"]))
+    worst = max(d_rgb[ok].max(initial=0), d_a[ok].max(initial=0), d_d[ok].max(initial=0))
+    return worst, int((~ok).sum())
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_compositing_stage_chained(gpu_lib, case):
+    """Oracle compositing in FP64 on the GPU's own records and pair lists."""
+    make, cams, od = CASES[case]
+    scene = make()
+    opts = _opts(gpu_lib, od)
+    params, proj, pairs, ranges, P, out = gpu_forward(gpu_lib, scene, cams, opts)
+    twod = decode_records(proj.rec.cpu().numpy())
+    pv = pairs.cpu().numpy().view(np.uint32)
+    rg = ranges.cpu().numpy().view(np.uint32)
+    toff = np.cumsum([0] + [c.n_tiles for c in cams])[:-1]
+    gimgs = {k: view_images(out[k].cpu().numpy(), cams) for k in ("rgb", "depth", "alpha", "T", "last")}
+    for v, c in enumerate(cams):
+        ref = oracle.render_view(c, oracle_opt(opts), int(toff[v]), twod, pv, rg, guard_eps=(1e-5, 1e-5, 0.0))
+        g = {k: gimgs[k][v] for k in gimgs}
+        worst, guarded = _guarded_compare(g, ref, ref["guard"])
+        assert worst <= 1e-4, (v, worst)
+        assert guarded <= max(2, 1e-3 * c.n_pixels), guarded
+        same_last = (g["last"] == ref["last"]) | (ref["guard"] != 0)
+        assert same_last.all()
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_forward_end_to_end(gpu_lib, case):
+    """GPU image from raw parameters vs the FP64 oracle from raw parameters."""
+    make, cams, od = CASES[case]
+    scene = make()
+    opts = _opts(gpu_lib, od)
+    _, _, _, _, P, out = gpu_forward(gpu_lib, scene, cams, opts)
+    f = oracle.forward(scene, cams, oracle_opt(opts), guard_eps=(1e-3, 1e-4, 0.0))
+    assert f["bins"]["n_pairs"] == P
+    for v, c in enumerate(cams):
+        g = {k: view_images(out[k].cpu().numpy(), cams)[v] for k in ("rgb", "depth", "alpha", "T", "last")}
+        ref = f["images"][v]
+        worst, guarded = _guarded_compare(g, ref, ref["guard"])
+        assert worst <= 1e-4, (v, worst)
+        assert guarded <= max(4, 5e-3 * c.n_pixels), guarded
+
+
+def _linear_loss_grads(gpu_lib, scene, cams, opts, seed=7):
+    ws = [S.linear_loss_weights(c.height, c.width, seed=seed + v) for v, c in enumerate(cams)]
+    params = to_dev(scene, requires_grad=True)
+    stats = gpu_lib.RenderStats()
+    rgb, depth, alpha = gpu_lib.rasterize(*params, cams, opts, stats)
+    w_rgb = torch.from_numpy(np.concatenate([w[0].reshape(-1, 3) for w in ws])).cuda()
+    w_d = torch.from_numpy(np.concatenate([w[1].reshape(-1) for w in ws])).cuda()
+    w_a = torch.from_numpy(np.concatenate([w[2].reshape(-1) for w in ws])).cuda()
+    loss = (w_rgb * rgb).sum() + (w_d * depth).sum() + (w_a * alpha).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    g = {k: p.grad.cpu().numpy().astype(np.float64) for k, p in
+         zip(("means", "scales", "quats", "opacities", "sh"), params)}
+    return g, ws, stats
+
+
+def _compare_grads(g, ref, groups=("means", "scales", "quats", "opacities", "sh")):
+    for k in groups:
+        a, b = g[k].ravel(), ref[k].ravel()
+        nb = np.linalg.norm(b)
+        assert nb > 0, k
+        rel = np.linalg.norm(a - b) / nb
+        assert rel <= 1e-3, (k, rel)
+        rms = np.sqrt(np.mean(b * b))
+        good = np.abs(a - b) <= 1e-3 * np.abs(b) + 1e-3 * rms
+        assert good.mean() >= 0.999, (k, good.mean())
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_gradients_match_oracle(gpu_lib, case):
+    make, cams, od = CASES[case]
+    scene = make()
+    opts = _opts(gpu_lib, dict(od, absgrad=True))
+    g, ws, stats = _linear_loss_grads(gpu_lib, scene, cams, opts)
+    f = oracle.forward(scene, cams, oracle_opt(opts))
+    ref = oracle.backward(scene, f, ws)
+    _compare_grads(g, ref)
+    norm = stats.mean2d_grad_norm.cpu().numpy()
+    rn = ref["mean2d_norm"]
+    assert np.linalg.norm(norm - rn) / np.linalg.norm(rn) <= 1e-3
+    ab = stats.absgrad.cpu().numpy()
+    assert np.linalg.norm(ab - ref["absgrad"]) / np.linalg.norm(ref["absgrad"]) <= 1e-3
+
+
+def test_gradients_match_finite_differences(gpu_lib):
+    """GPU gradient vs FP64 central differences of the oracle on 64 sampled
+    parameters (8 per group, SH split into DC and higher bands)."""
+    scene = S.random_scene(600, seed=12, log_scale_mu=-2.3)
+    cam = oblique_cam(96, 72, 75.0)
+    opts = gpu_lib.RenderOptions(aa=True, bg=(0.2, 0.3, 0.1))
+    g, ws, _ = _linear_loss_grads(gpu_lib, scene, [cam], opts)
+    w = ws[0]
+    sc64 = S.Scene(*(np.asarray(a, np.float64).copy() for a in
+                     (scene.means, scene.scales, scene.quats, scene.opacities, scene.sh)))
+    od = oracle_opt(opts)
+
+    def loss(sc):
+        im = oracle.forward(sc, cam, od)["images"][0]
+        return float((w[0] * im["rgb"]).sum() + (w[1] * im["depth"]).sum() + (w[2] * im["alpha"]).sum())
+
+    def perturbed(group, idx, delta):
+        arrs = {k: getattr(sc64, k).copy() for k in ("means", "scales", "quats", "opacities", "sh")}
+        arrs[group][idx] += delta
+        return S.Scene(arrs["means"], arrs["scales"], arrs["quats"], arrs["opacities"], arrs["sh"])
+
+    f = oracle.forward(sc64, cam, od)
+    vis = np.nonzero(f["proj"][0]["tiles"] > 0)[0]
+    rng = np.random.default_rng(7)
+    groups = [("means", (3,)), ("scales", (3,)), ("quats", (4,)), ("opacities", ()), ("sh_dc", (1, 3)),
+              ("sh_rest", (15, 3)), ("means", (3,)), ("scales", (3,))]
+    checked, total = 0, 0
+    for gname, shape in groups:
+        for _ in range(8):
+            i = int(rng.choice(vis))
+            if gname == "sh_dc":
+                group, idx = "sh", (0, int(rng.integers(0, 3)), i)
+            elif gname == "sh_rest":
+                group, idx = "sh", (1 + int(rng.integers(0, 15)), int(rng.integers(0, 3)), i)
+            else:
+                group, idx = gname, tuple(int(rng.integers(0, s)) for s in shape) + (i,)
+            theta = getattr(sc64, group)[idx]
+            h = 1e-6 * max(1.0, abs(theta))
+            fd = [(loss(perturbed(group, idx, k * h)) - loss(perturbed(group, idx, -k * h))) / (2 * k * h)
+                  for k in (1, 2)]
+            total += 1
+            if abs(fd[0] - fd[1]) > 1e-4 * (abs(fd[0]) + 1e-6):
+                continue      # a discrete event within 2h of theta
+            rms = np.sqrt(np.mean(g[group] ** 2))
+            assert abs(g[group][idx] - fd[0]) <= 1e-3 * abs(fd[0]) + 1e-3 * rms, (group, idx, g[group][idx], fd)
+            checked += 1
+    assert total == 64 and checked >= 56
+
+
+def test_forward_is_deterministic(gpu_lib):
+    scene = S.random_scene(5000, seed=9, log_scale_mu=-2.7)
+    cams = [oblique_cam(200, 150, 150.0)]
+    opts = gpu_lib.RenderOptions(aa=True)
+    a = gpu_forward(gpu_lib, scene, cams, opts)[-1]
+    b = gpu_forward(gpu_lib, scene, cams, opts)[-1]
+    for k in a:
+        assert torch.equal(a[k], b[k]), k
+
+
+def test_permutation_invariance_bitwise(gpu_lib):
+    scene = S.random_scene(3000, seed=10, log_scale_mu=-2.7)
+    cams = [oblique_cam(128, 96, 100.0)]
+    opts = gpu_lib.RenderOptions()
+    a = gpu_forward(gpu_lib, scene, cams, opts)[-1]
+    perm = np.random.default_rng(2).permutation(scene.n)
+    b = gpu_forward(gpu_lib, scene.subset(perm), cams, opts)[-1]
+    keys = oracle.depth_key(oracle.project(scene, cams[0])["depth"])
+    vis = oracle.project(scene, cams[0])["tiles"] > 0
+    assert len(np.unique(keys[vis])) == vis.sum()      # distinct depths, so order is unique
+    for k in ("rgb", "depth", "alpha", "T"):
+        assert torch.equal(a[k], b[k]), k
+
+
+def test_everything_culled(gpu_lib):
+    scene = S.random_scene(1000, seed=3)
+    cam = small_cam(64, 48, 50.0, tz=-10.0)      # all Gaussians behind the camera
+    opts = gpu_lib.RenderOptions(bg=(0.5, 0.25, 1.0))
+    _, proj, pairs, ranges, P, out = gpu_forward(gpu_lib, scene, [cam], opts)
+    assert P == 0
+    assert torch.all(out["T"] == 1.0) and torch.all(out["last"] == 0)
+    assert torch.allclose(out["rgb"], torch.tensor([0.5, 0.25, 1.0], device="cuda").expand_as(out["rgb"]))
+    params = to_dev(scene, requires_grad=True)
+    rgb, depth, alpha = gpu_lib.rasterize(*params, [cam], opts)
+    (rgb.sum() + depth.sum() + alpha.sum()).backward()
+    for p in params:
+        assert torch.all(p.grad == 0)
+
+
+def test_single_gaussian_and_tiny_image(gpu_lib):
+    sh = np.zeros((16, 3, 1), np.float32)
+    sh[0, :, 0] = 1.0
+    scene = S.Scene(np.array([[0.0], [0.0], [0.0]], np.float32), np.full((3, 1), 0.3, np.float32),
+                    np.array([[1.0], [0.0], [0.0], [0.0]], np.float32), np.array([0.7], np.float32), sh)
+    for W, H in ((1, 1), (17, 3), (16, 16)):
+        cam = small_cam(W, H, 20.0)
+        opts = gpu_lib.RenderOptions(sh_degree=0)
+        _, _, _, _, P, out = gpu_forward(gpu_lib, scene, [cam], opts)
+        f = oracle.forward(scene, cam, oracle_opt(opts))
+        ref = f["images"][0]
+        assert P == f["bins"]["n_pairs"]
+        np.testing.assert_allclose(out["rgb"].cpu().numpy().reshape(H, W, 3), ref["rgb"], atol=1e-5)
+
+
+def test_invalid_arguments_raise(gpu_lib):
+    scene = S.random_scene(10, seed=1)
+    params = to_dev(scene)
+    opts = gpu_lib.RenderOptions()
+    bad = small_cam(0, 10, 10.0)
+    with pytest.raises(gpu_lib.GsError):
+        gpu_lib.project(*params, [bad], opts)
+    with pytest.raises(gpu_lib.GsError):
+        gpu_lib.project(*params, [small_cam(10, 10, 10.0)] * 17, opts)
+    with pytest.raises(gpu_lib.GsError):
+        gpu_lib.project(*params, [small_cam(10, 10, 10.0)], gpu_lib.RenderOptions(sh_degree=4))

@@ -464,3 +464,20 @@ def test_gradient_with_clamped_jacobian():
             assert abs(g[group][idx] - fd[0]) <= 2e-6 * abs(g[group][idx]) + 2e-7, (group, idx, g[group][idx], fd)
             checked += 1
     assert checked >= 12
+
+
+def test_float32_and_float64_inputs_give_identical_results():
+    """The wrapper converts float32 parameters to float64 copies; the copies
+    must stay alive through the C calls (a freed copy gives garbage)."""
+    sc32 = S.random_scene(300, seed=31, log_scale_mu=-2.0)
+    sc64 = scene64(sc32)
+    cam = oblique_cam()
+    w = S.linear_loss_weights(cam.height, cam.width, seed=7)
+    res = []
+    for sc in (sc32, sc64):
+        f = oracle.forward(sc, cam, dict(aa=True))
+        g = oracle.backward(sc, f, [w])
+        res.append((f["images"][0]["rgb"], g))
+    assert np.array_equal(res[0][0], res[1][0])
+    for k in GROUPS:      # the OpenMP backward sums in varying order: equal up to rounding
+        np.testing.assert_allclose(res[0][1][k], res[1][1][k], rtol=1e-10, atol=1e-14, err_msg=k)
