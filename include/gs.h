@@ -157,6 +157,13 @@ int gs_render_fwd(const gs_projected *proj, const uint32_t *pair_vals, const uin
                   const gs_camera *cams, int32_t n_views, const gs_options *opt, float *rgb, float *depth,
                   float *alpha, float *T_final, int32_t *last, void *stream);
 
+/* Measurement only: per pixel, the number of list entries compositing has
+ * to evaluate (through the one that stops the pixel, else the whole list),
+ * written to n_eval [pix].  The unit of work behind the compositing
+ * throughput figures; not needed to render. */
+int gs_render_count(const gs_projected *proj, const uint32_t *pair_vals, const uint32_t *tile_ranges,
+                    const gs_camera *cams, int32_t n_views, int32_t *n_eval, void *stream);
+
 size_t gs_render_bwd_workspace_size(int64_t n_slots);
 
 /* Backward of compositing and projection.  Transmittance is recovered back
@@ -171,6 +178,18 @@ int gs_render_bwd(const gs_gaussians *g, const gs_camera *cams, int32_t n_views,
                   const float *T_final, const int32_t *last, const float *d_rgb, const float *d_depth,
                   const float *d_alpha, const gs_gaussians_grad *out, float *mean2d_grad_norm, float *absgrad,
                   void *ws, size_t ws_bytes, void *stream);
+
+/* The two halves of gs_render_bwd, for callers that schedule or time them
+ * separately.  gs_composite_bwd overwrites grad2d [slots][12] (fields as in
+ * gs_render_bwd_grad2d) with the compositing backward; gs_project_bwd chains
+ * grad2d to the parameters (outputs as in gs_render_bwd). */
+int gs_composite_bwd(const gs_projected *proj, const uint32_t *pair_vals, const uint32_t *tile_ranges,
+                     const gs_camera *cams, int32_t n_views, const gs_options *opt, const float *T_final,
+                     const int32_t *last, const float *d_rgb, const float *d_depth, const float *d_alpha,
+                     int64_t n_slots, float *grad2d, void *stream);
+int gs_project_bwd(const gs_gaussians *g, const gs_camera *cams, int32_t n_views, const gs_options *opt,
+                   const gs_projected *proj, const float *grad2d, const gs_gaussians_grad *out,
+                   float *mean2d_grad_norm, float *absgrad, void *stream);
 
 /* Per-slot 2D gradients of the last gs_render_bwd call that used `ws`
  * ([slots][12]: d mean2d x, y; d conic A, B, C; d opacity'; d rgb; d depth;

@@ -176,7 +176,11 @@ def _twod(proj_list):
     return cat("mean2d"), cat("conic"), cat("opac"), cat("rgb"), cat("depth")
 
 
-DEFAULT_GUARD = (1e-4, 1e-4, 1e-4)
+# Guard band of the compared float32 implementation (see composite_pixel in
+# oracle.c): alpha relative floor, per-step T floor, clamp floor, relative
+# rounding of the stored mean (float32: 2^-24).
+DEFAULT_GUARD = (2e-6, 1e-6, 1e-6, 2.0 ** -24)
+STAGE_GUARD = (2e-6, 1e-6, 1e-6, 0.0)     # means taken exactly from the compared records
 
 
 def render_view(cam, opt: dict, tile_off: int, twod, pair_slot, ranges, tile_mask=None,

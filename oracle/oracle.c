@@ -434,10 +434,18 @@ typedef struct {
 
 /* Composites one pixel; returns the number of composited entries and fills
  * `ent` (if non-NULL, capacity `cap`) with them in front-to-back order. */
+/* Guard band.  guard_eps (nullable) = {e_alpha, e_T, e_clamp, e_mean}: a
+ * compared implementation evaluates alpha with relative error at most
+ * e_alpha + |d power / d mean| * (|m| + 1) * e_mean (e_mean models a mean
+ * stored with that relative rounding), and T with the accumulated relative
+ * error of the alphas before it plus e_T.  A pixel is flagged when a skip
+ * (alpha vs 1/255), stop (T(1 - alpha) vs 1e-4) or clamp (o' G' vs 0.99)
+ * decision lies inside that error. */
 static int composite_pixel(const o2d_t *g, const uint32_t *pair_slot, uint32_t start, uint32_t end,
                            double px, double py, const double *guard_eps, double out[7],
                            int *last_out, int *guard_out, oentry_t *ent, int cap) {
     double T = 1.0, C[3] = {0.0, 0.0, 0.0}, D = 0.0;
+    double errT = 0.0;     /* relative error bound of T so far */
     int last = 0, guard = 0, n = 0;
     for (uint32_t k = start; k < end; k++) {
         int s = (int)pair_slot[k];
@@ -448,13 +456,20 @@ static int composite_pixel(const o2d_t *g, const uint32_t *pair_slot, uint32_t s
         double G = exp(power);
         double raw = g->opac[s] * G;
         double alpha = raw < ORC_ALPHA_MAX ? raw : ORC_ALPHA_MAX;
+        double ea = 0.0;   /* relative error bound of alpha */
         if (guard_eps) {
-            if (fabs(alpha - ORC_ALPHA_MIN) <= guard_eps[0] * ORC_ALPHA_MIN) guard |= ORC_GUARD_SKIP;
-            if (fabs(raw - ORC_ALPHA_MAX) <= guard_eps[2] * ORC_ALPHA_MAX) guard |= ORC_GUARD_CLAMP;
+            double gx = fabs(cn[0] * dx + cn[1] * dy), gy = fabs(cn[1] * dx + cn[2] * dy);
+            ea = guard_eps[0] + (gx * (fabs(m[0]) + 1.0) + gy * (fabs(m[1]) + 1.0)) * guard_eps[3];
+            if (fabs(alpha - ORC_ALPHA_MIN) <= ea * ORC_ALPHA_MIN) guard |= ORC_GUARD_SKIP;
+            if (fabs(raw - ORC_ALPHA_MAX) <= (ea + guard_eps[2]) * ORC_ALPHA_MAX) guard |= ORC_GUARD_CLAMP;
         }
         if (alpha < ORC_ALPHA_MIN) continue;
         double Tn = T * (1.0 - alpha);
-        if (guard_eps && fabs(Tn - ORC_T_MIN) <= guard_eps[1] * ORC_T_MIN) guard |= ORC_GUARD_STOP;
+        if (guard_eps) {
+            double eTn = errT + ea * alpha / (1.0 - alpha) + guard_eps[1];
+            if (fabs(Tn - ORC_T_MIN) <= eTn * ORC_T_MIN) guard |= ORC_GUARD_STOP;
+            errT = eTn;
+        }
         if (Tn < ORC_T_MIN) break;
         if (ent && n < cap) {
             ent[n].pos = (int)(k - start);

@@ -7,7 +7,7 @@ behind the C ABI of include/gs.h.  This package only marshals torch tensors
 """
 from ._lib import GsError, load, LIB_PATH
 from .rasterizer import (RenderOptions, RenderStats, Projected, Workspace, GsRasterize, rasterize, project,
-                         bin_sort, render_fwd, render_bwd, split_views, views_extent, grad2d_view, check_params)
+                         bin_sort, render_fwd, render_bwd, split_views, views_extent, grad2d_view, check_params, set_stage_hook, render_count)
 
 
 def build(verbose: bool = False) -> str:
@@ -17,4 +17,4 @@ def build(verbose: bool = False) -> str:
 
 __all__ = ["GsError", "load", "LIB_PATH", "RenderOptions", "RenderStats", "Projected", "Workspace", "GsRasterize",
            "rasterize", "project", "bin_sort", "render_fwd", "render_bwd", "split_views", "views_extent",
-           "grad2d_view", "check_params", "build"]
+           "grad2d_view", "check_params", "set_stage_hook", "render_count", "build"]

@@ -285,6 +285,21 @@ int gs_render_fwd(const gs_projected* proj, const uint32_t* pair_vals, const uin
     }
 }
 
+int gs_render_count(const gs_projected* proj, const uint32_t* pair_vals, const uint32_t* tile_ranges,
+                    const gs_camera* cams, int32_t n_views, int32_t* n_eval, void* stream) {
+    try {
+        ViewTable vt;
+        int rc;
+        if ((rc = build_views(cams, n_views, &vt)) || (rc = check_proj(proj))) return rc;
+        GS_REQUIRE(pair_vals && tile_ranges && n_eval, "NULL buffer");
+        GS_HIP(launch_render_count(to_proj(proj), pair_vals, reinterpret_cast<const uint2*>(tile_ranges), vt, n_eval,
+                                   (hipStream_t)stream));
+        return GS_OK;
+    } catch (...) {
+        return fail(GS_ERR_INTERNAL, "unexpected exception in gs_render_count");
+    }
+}
+
 size_t gs_render_bwd_workspace_size(int64_t n_slots) {
     if (n_slots < 1) n_slots = 1;
     return align_up((size_t)n_slots * GS_REC_FLOATS * sizeof(float));
@@ -321,6 +336,51 @@ int gs_render_bwd(const gs_gaussians* g, const gs_camera* cams, int32_t n_views,
         return GS_OK;
     } catch (...) {
         return fail(GS_ERR_INTERNAL, "unexpected exception in gs_render_bwd");
+    }
+}
+
+int gs_composite_bwd(const gs_projected* proj, const uint32_t* pair_vals, const uint32_t* tile_ranges,
+                     const gs_camera* cams, int32_t n_views, const gs_options* opt, const float* T_final,
+                     const int32_t* last, const float* d_rgb, const float* d_depth, const float* d_alpha,
+                     int64_t n_slots, float* grad2d, void* stream) {
+    try {
+        ViewTable vt;
+        OptK ok;
+        int rc;
+        if ((rc = build_views(cams, n_views, &vt)) || (rc = build_opt(opt, &ok)) || (rc = check_proj(proj)))
+            return rc;
+        GS_REQUIRE(pair_vals && tile_ranges && T_final && last && grad2d, "NULL buffer");
+        GS_REQUIRE(n_slots >= 1 && n_slots <= 0xFFFFFF00LL, "bad n_slots");
+        hipStream_t s = (hipStream_t)stream;
+        GS_HIP(fill_u32(reinterpret_cast<uint32_t*>(grad2d), 0u, (size_t)n_slots * GS_REC_FLOATS, s));
+        GS_HIP(launch_render_bwd(to_proj(proj), pair_vals, reinterpret_cast<const uint2*>(tile_ranges), vt, ok, T_final,
+                                 last, d_rgb, d_depth, d_alpha, grad2d, s));
+        return GS_OK;
+    } catch (...) {
+        return fail(GS_ERR_INTERNAL, "unexpected exception in gs_composite_bwd");
+    }
+}
+
+int gs_project_bwd(const gs_gaussians* g, const gs_camera* cams, int32_t n_views, const gs_options* opt,
+                   const gs_projected* proj, const float* grad2d, const gs_gaussians_grad* out,
+                   float* mean2d_grad_norm, float* absgrad, void* stream) {
+    try {
+        ViewTable vt;
+        OptK ok;
+        int rc;
+        if ((rc = build_views(cams, n_views, &vt)) || (rc = build_opt(opt, &ok)) ||
+            (rc = check_gaussians(g, n_views)) || (rc = check_proj(proj)))
+            return rc;
+        GS_REQUIRE(grad2d && out && mean2d_grad_norm, "NULL buffer");
+        GS_REQUIRE(out->d_means && out->d_scales && out->d_quats && out->d_opacities && out->d_sh,
+                   "NULL gradient output");
+        GaussPtrs gp{g->means, g->scales, g->quats, g->opacities, g->sh};
+        GradPtrs go{out->d_means, out->d_scales, out->d_quats, out->d_opacities, out->d_sh};
+        GS_HIP(launch_project_bwd(gp, g->n, vt, ok, to_proj(proj), grad2d, go, mean2d_grad_norm, absgrad,
+                                  (hipStream_t)stream));
+        return GS_OK;
+    } catch (...) {
+        return fail(GS_ERR_INTERNAL, "unexpected exception in gs_project_bwd");
     }
 }
 

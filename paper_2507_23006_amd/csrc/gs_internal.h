@@ -151,6 +151,8 @@ hipError_t launch_tile_ranges(const uint32_t* sorted_keys, uint32_t n_pairs, uin
 hipError_t launch_render_fwd(const Projected& proj, const uint32_t* pair_vals, const uint2* ranges,
                              const ViewTable& vt, const OptK& opt, float* rgb, float* depth, float* alpha,
                              float* T_final, int32_t* last, hipStream_t s);
+hipError_t launch_render_count(const Projected& proj, const uint32_t* pair_vals, const uint2* ranges,
+                               const ViewTable& vt, int32_t* n_eval, hipStream_t s);
 hipError_t launch_render_bwd(const Projected& proj, const uint32_t* pair_vals, const uint2* ranges,
                              const ViewTable& vt, const OptK& opt, const float* T_final, const int32_t* last,
                              const float* d_rgb, const float* d_depth, const float* d_alpha, float* grad2d,

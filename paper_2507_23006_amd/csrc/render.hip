@@ -105,6 +105,53 @@ __global__ __launch_bounds__(256) void k_render_fwd(const float4* __restrict__ r
     last_out[pix] = last;
 }
 
+// Per pixel: how many list entries the forward must evaluate (up to and
+// including the one that stops the pixel, else the whole list).  The unit
+// of work of compositing; used for the roofline, never on the render path.
+__global__ __launch_bounds__(256) void k_render_count(const float4* __restrict__ rec,
+                                                      const uint32_t* __restrict__ pair_vals,
+                                                      const uint2* __restrict__ ranges, ViewTable vt,
+                                                      int32_t* __restrict__ n_eval) {
+    __shared__ float4 s0[kFwdBatch], s1[kFwdBatch];
+    const int tile = blockIdx.x;
+    const int v = view_of_tile(vt, tile);
+    const ViewK& V = vt.v[v];
+    const int lt = tile - V.tile_off;
+    const int ty = lt / V.tiles_x, tx = lt - ty * V.tiles_x;
+    const int px = tx * kTile + (threadIdx.x & 15), py = ty * kTile + (threadIdx.x >> 4);
+    const bool inside = px < V.W && py < V.H;
+    const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
+    const uint2 rg = ranges[tile];
+    float T = 1.0f;
+    int count = 0;
+    bool done = !inside;
+    for (uint32_t b0 = rg.x; b0 < rg.y; b0 += kFwdBatch) {
+        if (__syncthreads_count(!done) == 0) break;
+        const uint32_t j = b0 + threadIdx.x;
+        if (j < rg.y) {
+            const uint32_t s = pair_vals[j];
+            s0[threadIdx.x] = rec[3 * (size_t)s + 0];
+            s1[threadIdx.x] = rec[3 * (size_t)s + 1];
+        }
+        __syncthreads();
+        if (!done) {
+            const int cnt = (int)min((uint32_t)kFwdBatch, rg.y - b0);
+            for (int k = 0; k < cnt; ++k) {
+                ++count;
+                const Eval e = eval_entry(s0[k], s1[k], fpx, fpy);
+                if (!e.keep) continue;
+                const float Tn = T * (1.0f - e.alpha);
+                if (Tn < kTMin) {
+                    done = true;
+                    break;
+                }
+                T = Tn;
+            }
+        }
+    }
+    if (inside) n_eval[V.pix_off + (int64_t)py * V.W + px] = count;
+}
+
 // sum over the 64 lanes; lane 63 holds the result
 __device__ __forceinline__ float wave_sum_lane63(float x) {
     x += __builtin_amdgcn_update_dpp(0.0f, x, 0x111, 0xf, 0xf, false);   // row_shr:1
@@ -246,6 +293,13 @@ hipError_t launch_render_fwd(const Projected& proj, const uint32_t* pair_vals, c
     if (vt.total_tiles <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_render_fwd, dim3(vt.total_tiles), dim3(256), 0, s, proj.rec, pair_vals, ranges, vt, opt, rgb,
                        depth, alpha, T_final, last);
+    return hipGetLastError();
+}
+
+hipError_t launch_render_count(const Projected& proj, const uint32_t* pair_vals, const uint2* ranges,
+                               const ViewTable& vt, int32_t* n_eval, hipStream_t s) {
+    if (vt.total_tiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_render_count, dim3(vt.total_tiles), dim3(256), 0, s, proj.rec, pair_vals, ranges, vt, n_eval);
     return hipGetLastError();
 }
 

@@ -165,6 +165,32 @@ def render_fwd(proj: Projected, pair_vals, ranges, cams, opts: RenderOptions) ->
     return out
 
 
+def render_count(proj: Projected, pair_vals, ranges, cams) -> torch.Tensor:
+    """Per-pixel number of list entries compositing evaluates (measurement)."""
+    lib = L.load()
+    _, npx = views_extent(cams)
+    out = torch.empty((npx,), dtype=torch.int32, device=proj.rec.device)
+    L.check(lib.gs_render_count(C.byref(proj.c()), _ptr(pair_vals), _ptr(ranges), L.make_cameras(cams), len(cams),
+                                _ptr(out), _stream()))
+    return out
+
+
+_stage_hook = None
+
+
+def set_stage_hook(fn) -> None:
+    """fn(name) is called on the host right after each stage is enqueued
+    (project, bin_sort, render_fwd, composite_bwd, project_bwd); used by the
+    benchmark to record stream events.  None disables it."""
+    global _stage_hook
+    _stage_hook = fn
+
+
+def _mark(name: str) -> None:
+    if _stage_hook is not None:
+        _stage_hook(name)
+
+
 def render_bwd(params, cams, opts: RenderOptions, proj: Projected, pair_vals, ranges, T, last, d_rgb, d_depth,
                d_alpha, ws: Workspace | None = None) -> dict:
     lib = L.load()
@@ -182,12 +208,17 @@ def render_bwd(params, cams, opts: RenderOptions, proj: Projected, pair_vals, ra
     go.d_opacities, go.d_sh = grads["opacities"].data_ptr(), grads["sh"].data_ptr()
     wsz = lib.gs_render_bwd_workspace_size(n * V)
     wbuf = ws.get("bwd", wsz + 256, dev)
+    g2 = C.c_void_p(Workspace.aligned(wbuf))
     cont = lambda t: t.contiguous() if t is not None else None
     d_rgb, d_depth, d_alpha = cont(d_rgb), cont(d_depth), cont(d_alpha)
-    L.check(lib.gs_render_bwd(C.byref(g), L.make_cameras(cams), V, C.byref(opts.c()), C.byref(proj.c()),
-                              _ptr(pair_vals), _ptr(ranges), _ptr(T), _ptr(last), _ptr(d_rgb), _ptr(d_depth),
-                              _ptr(d_alpha), C.byref(go), _ptr(norm), _ptr(absg),
-                              C.c_void_p(Workspace.aligned(wbuf)), wsz, _stream()))
+    cams_c, opt_c, proj_c = L.make_cameras(cams), opts.c(), proj.c()
+    _mark("bwd_begin")
+    L.check(lib.gs_composite_bwd(C.byref(proj_c), _ptr(pair_vals), _ptr(ranges), cams_c, V, C.byref(opt_c), _ptr(T),
+                                 _ptr(last), _ptr(d_rgb), _ptr(d_depth), _ptr(d_alpha), n * V, g2, _stream()))
+    _mark("composite_bwd")
+    L.check(lib.gs_project_bwd(C.byref(g), cams_c, V, C.byref(opt_c), C.byref(proj_c), g2, C.byref(go), _ptr(norm),
+                               _ptr(absg), _stream()))
+    _mark("project_bwd")
     grads["mean2d_grad_norm"] = norm
     grads["absgrad"] = absg
     grads["_grad2d_ws"] = (wbuf, n * V)
@@ -219,8 +250,11 @@ class GsRasterize(torch.autograd.Function):
         params = tuple(t.detach().contiguous() for t in (means, scales, quats, opacities, sh))
         n = params[0].shape[-1]
         proj = project(*params, cams, opts)
+        _mark("project")
         pair_vals, ranges, P = bin_sort(proj, cams, n)
+        _mark("bin_sort")
         out = render_fwd(proj, pair_vals, ranges, cams, opts)
+        _mark("render_fwd")
         ctx.save_for_backward(*params, proj.rec, proj.rect, proj.tiles, proj.depth_key, pair_vals, ranges,
                               out["T"], out["last"])
         ctx.cams, ctx.opts, ctx.stats = list(cams), opts, stats

@@ -120,7 +120,7 @@ def test_compositing_stage_chained(gpu_lib, case):
     toff = np.cumsum([0] + [c.n_tiles for c in cams])[:-1]
     gimgs = {k: view_images(out[k].cpu().numpy(), cams) for k in ("rgb", "depth", "alpha", "T", "last")}
     for v, c in enumerate(cams):
-        ref = oracle.render_view(c, oracle_opt(opts), int(toff[v]), twod, pv, rg, guard_eps=(1e-5, 1e-5, 0.0))
+        ref = oracle.render_view(c, oracle_opt(opts), int(toff[v]), twod, pv, rg, guard_eps=oracle.STAGE_GUARD)
         g = {k: gimgs[k][v] for k in gimgs}
         worst, guarded = _guarded_compare(g, ref, ref["guard"])
         assert worst <= 1e-4, (v, worst)
@@ -136,14 +136,14 @@ def test_forward_end_to_end(gpu_lib, case):
     scene = make()
     opts = _opts(gpu_lib, od)
     _, _, _, _, P, out = gpu_forward(gpu_lib, scene, cams, opts)
-    f = oracle.forward(scene, cams, oracle_opt(opts), guard_eps=(1e-3, 1e-4, 0.0))
+    f = oracle.forward(scene, cams, oracle_opt(opts), guard_eps=oracle.DEFAULT_GUARD)
     assert f["bins"]["n_pairs"] == P
     for v, c in enumerate(cams):
         g = {k: view_images(out[k].cpu().numpy(), cams)[v] for k in ("rgb", "depth", "alpha", "T", "last")}
         ref = f["images"][v]
         worst, guarded = _guarded_compare(g, ref, ref["guard"])
         assert worst <= 1e-4, (v, worst)
-        assert guarded <= max(4, 5e-3 * c.n_pixels), guarded
+        assert guarded <= max(2, 1e-3 * c.n_pixels), guarded
 
 
 def _linear_loss_grads(gpu_lib, scene, cams, opts, seed=7):
@@ -252,13 +252,15 @@ def test_forward_is_deterministic(gpu_lib):
 def test_permutation_invariance_bitwise(gpu_lib):
     scene = S.random_scene(3000, seed=10, log_scale_mu=-2.7)
     cams = [oblique_cam(128, 96, 100.0)]
+    # keep Gaussians whose float32 depth keys are distinct, so that the
+    # depth order (and hence the image) does not depend on input order
+    keys = oracle.depth_key(oracle.project(scene, cams[0])["depth"])
+    _, first, counts = np.unique(keys, return_index=True, return_counts=True)
+    scene = scene.subset(np.sort(first[counts == 1]))
     opts = gpu_lib.RenderOptions()
     a = gpu_forward(gpu_lib, scene, cams, opts)[-1]
     perm = np.random.default_rng(2).permutation(scene.n)
     b = gpu_forward(gpu_lib, scene.subset(perm), cams, opts)[-1]
-    keys = oracle.depth_key(oracle.project(scene, cams[0])["depth"])
-    vis = oracle.project(scene, cams[0])["tiles"] > 0
-    assert len(np.unique(keys[vis])) == vis.sum()      # distinct depths, so order is unique
     for k in ("rgb", "depth", "alpha", "T"):
         assert torch.equal(a[k], b[k]), k
 
