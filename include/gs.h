@@ -101,9 +101,12 @@ typedef struct gs_gaussians_grad {
 } gs_gaussians_grad;
 
 /* Projected per-slot records (n_views * n slots).
- *   rec  [slots][12] float: mean2d x, y; qa, qb; qc, opacity', depth, 0;
- *        r, g, b, 0.  (qa, qb, qc) = -log2(e) (A/2, B, C/2) for the conic
- *        (A, B, C) of the dilated 2D covariance, so that
+ *   rec  [slots][12] float: floor(mean2d x), floor(mean2d y); qa, qb;
+ *        qc, opacity', depth, frac(mean2d x); r, g, b, frac(mean2d y).
+ *        The mean is split into an exact integer part and a fraction so
+ *        compositing can form tile-relative coordinates without the rounding
+ *        of large pixel coordinates.  (qa, qb, qc) = -log2(e) (A/2, B, C/2)
+ *        for the conic (A, B, C) of the dilated 2D covariance, so that
  *        G' = exp2(qa dx^2 + qb dx dy + qc dy^2).
  *   rect [slots][2] uint32: global id of the first tile of the rectangle;
  *        rectangle width in tiles | (tiles per image row << 16).

@@ -177,10 +177,12 @@ def _twod(proj_list):
 
 
 # Guard band of the compared float32 implementation (see composite_pixel in
-# oracle.c): alpha relative floor, per-step T floor, clamp floor, relative
-# rounding of the stored mean (float32: 2^-24).
-DEFAULT_GUARD = (2e-6, 1e-6, 1e-6, 2.0 ** -24)
-STAGE_GUARD = (2e-6, 1e-6, 1e-6, 0.0)     # means taken exactly from the compared records
+# oracle.c): alpha relative floor (float32 conic coefficients, the exponent
+# polynomial and exp2: about 3e-6 for |power| <= 6), per-step T floor (two
+# float32 roundings of T(1 - alpha)), clamp floor, relative rounding of the
+# tile-relative mean (float32: 2^-24).
+DEFAULT_GUARD = (4e-6, 2.4e-7, 1e-6, 2.0 ** -24)
+STAGE_GUARD = DEFAULT_GUARD
 
 
 def render_view(cam, opt: dict, tile_off: int, twod, pair_slot, ranges, tile_mask=None,

@@ -436,11 +436,12 @@ typedef struct {
  * `ent` (if non-NULL, capacity `cap`) with them in front-to-back order. */
 /* Guard band.  guard_eps (nullable) = {e_alpha, e_T, e_clamp, e_mean}: a
  * compared implementation evaluates alpha with relative error at most
- * e_alpha + |d power / d mean| * (|m| + 1) * e_mean (e_mean models a mean
- * stored with that relative rounding), and T with the accumulated relative
- * error of the alphas before it plus e_T.  A pixel is flagged when a skip
- * (alpha vs 1/255), stop (T(1 - alpha) vs 1e-4) or clamp (o' G' vs 0.99)
- * decision lies inside that error. */
+ * e_alpha + |d power / d mean| * (|dx| + 17) * e_mean (e_mean models a mean
+ * held relative to its 16x16 tile's origin with that relative rounding; the
+ * tile-relative mean is at most |dx| + 16 from the origin), and T with the
+ * accumulated relative error of the alphas before it plus e_T.  A pixel is
+ * flagged when a skip (alpha vs 1/255), stop (T(1 - alpha) vs 1e-4) or clamp
+ * (o' G' vs 0.99) decision lies inside that error. */
 static int composite_pixel(const o2d_t *g, const uint32_t *pair_slot, uint32_t start, uint32_t end,
                            double px, double py, const double *guard_eps, double out[7],
                            int *last_out, int *guard_out, oentry_t *ent, int cap) {
@@ -459,7 +460,7 @@ static int composite_pixel(const o2d_t *g, const uint32_t *pair_slot, uint32_t s
         double ea = 0.0;   /* relative error bound of alpha */
         if (guard_eps) {
             double gx = fabs(cn[0] * dx + cn[1] * dy), gy = fabs(cn[1] * dx + cn[2] * dy);
-            ea = guard_eps[0] + (gx * (fabs(m[0]) + 1.0) + gy * (fabs(m[1]) + 1.0)) * guard_eps[3];
+            ea = guard_eps[0] + (gx * (fabs(dx) + 17.0) + gy * (fabs(dy) + 17.0)) * guard_eps[3];
             if (fabs(alpha - ORC_ALPHA_MIN) <= ea * ORC_ALPHA_MIN) guard |= ORC_GUARD_SKIP;
             if (fabs(raw - ORC_ALPHA_MAX) <= (ea + guard_eps[2]) * ORC_ALPHA_MAX) guard |= ORC_GUARD_CLAMP;
         }

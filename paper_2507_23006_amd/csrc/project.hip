@@ -111,10 +111,15 @@ __global__ __launch_bounds__(256) void k_project_fwd(GaussPtrs gp, int64_t n, Vi
                     const double rho = opt.aa ? (det2 > 0.0 ? sqrt(det2 / detd) : 0.0) : 1.0;
                     const double invd = 1.0 / detd;
                     const double A = cd * invd, B = -cb * invd, C = ad * invd;
-                    out.rec[3 * slot + 0] = make_float4((float)mx, (float)my, (float)(-0.5 * kLog2e * A),
+                    // mean = integer part (exact in float32) + fraction, so that the
+                    // compositing kernels can form a tile-relative mean without the
+                    // rounding of a large absolute pixel coordinate
+                    const double fmx = floor(mx), fmy = floor(my);
+                    out.rec[3 * slot + 0] = make_float4((float)fmx, (float)fmy, (float)(-0.5 * kLog2e * A),
                                                         (float)(-kLog2e * B));
                     out.rec[3 * slot + 1] = make_float4((float)(-0.5 * kLog2e * C), (float)(opac * rho), (float)tz,
-                                                        0.0f);
+                                                        (float)(mx - fmx));
+                    out.rec[3 * slot + 2].w = (float)(my - fmy);
                     out.rect[slot] = make_uint2((uint32_t)(V.tile_off + iy0 * TW + ix0),
                                                 (uint32_t)w | ((uint32_t)TW << 16));
                     vis_mask |= 1u << v;
@@ -148,7 +153,11 @@ __global__ __launch_bounds__(256) void k_project_fwd(GaussPtrs gp, int64_t n, Vi
                 c[2] = fmaf(gp.sh[(int64_t)(3 * k + 2) * n + g], Y[k], c[2]);
             }
         }
-        out.rec[3 * slot + 2] = make_float4(fmaxf(c[0], 0.0f), fmaxf(c[1], 0.0f), fmaxf(c[2], 0.0f), 0.0f);
+        float4 r2 = out.rec[3 * slot + 2];
+        r2.x = fmaxf(c[0], 0.0f);
+        r2.y = fmaxf(c[1], 0.0f);
+        r2.z = fmaxf(c[2], 0.0f);
+        out.rec[3 * slot + 2] = r2;
     }
 }
 

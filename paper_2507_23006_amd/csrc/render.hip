@@ -39,6 +39,13 @@ __device__ __forceinline__ Eval eval_entry(const float4 a, const float4 b, float
     return e;
 }
 
+// Record -> LDS form: the mean relative to the tile origin (integer part
+// minus the origin is exact; adding the stored fraction rounds once, at the
+// scale of the tile rather than of the image).
+__device__ __forceinline__ float4 stage_geom(const float4 r0, const float4 r1, const float4 r2, float ox, float oy) {
+    return make_float4((r0.x - ox) + r1.w, (r0.y - oy) + r2.w, r0.z, r0.w);
+}
+
 constexpr int kFwdBatch = 256;
 
 __global__ __launch_bounds__(256) void k_render_fwd(const float4* __restrict__ rec,
@@ -55,7 +62,8 @@ __global__ __launch_bounds__(256) void k_render_fwd(const float4* __restrict__ r
     const int ty = lt / V.tiles_x, tx = lt - ty * V.tiles_x;
     const int px = tx * kTile + (threadIdx.x & 15), py = ty * kTile + (threadIdx.x >> 4);
     const bool inside = px < V.W && py < V.H;
-    const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
+    const float ox = (float)(tx * kTile), oy = (float)(ty * kTile);
+    const float fpx = (float)(threadIdx.x & 15) + 0.5f, fpy = (float)(threadIdx.x >> 4) + 0.5f;
     const uint2 rg = ranges[tile];
 
     float T = 1.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f, D = 0.0f;
@@ -67,9 +75,10 @@ __global__ __launch_bounds__(256) void k_render_fwd(const float4* __restrict__ r
         const uint32_t j = b0 + threadIdx.x;
         if (j < rg.y) {
             const uint32_t s = pair_vals[j];
-            s0[threadIdx.x] = rec[3 * (size_t)s + 0];
-            s1[threadIdx.x] = rec[3 * (size_t)s + 1];
-            s2[threadIdx.x] = rec[3 * (size_t)s + 2];
+            const float4 r0 = rec[3 * (size_t)s + 0], r1 = rec[3 * (size_t)s + 1], r2 = rec[3 * (size_t)s + 2];
+            s0[threadIdx.x] = stage_geom(r0, r1, r2, ox, oy);
+            s1[threadIdx.x] = r1;
+            s2[threadIdx.x] = r2;
         }
         __syncthreads();
         if (!done) {
@@ -120,7 +129,8 @@ __global__ __launch_bounds__(256) void k_render_count(const float4* __restrict__
     const int ty = lt / V.tiles_x, tx = lt - ty * V.tiles_x;
     const int px = tx * kTile + (threadIdx.x & 15), py = ty * kTile + (threadIdx.x >> 4);
     const bool inside = px < V.W && py < V.H;
-    const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
+    const float ox = (float)(tx * kTile), oy = (float)(ty * kTile);
+    const float fpx = (float)(threadIdx.x & 15) + 0.5f, fpy = (float)(threadIdx.x >> 4) + 0.5f;
     const uint2 rg = ranges[tile];
     float T = 1.0f;
     int count = 0;
@@ -130,8 +140,9 @@ __global__ __launch_bounds__(256) void k_render_count(const float4* __restrict__
         const uint32_t j = b0 + threadIdx.x;
         if (j < rg.y) {
             const uint32_t s = pair_vals[j];
-            s0[threadIdx.x] = rec[3 * (size_t)s + 0];
-            s1[threadIdx.x] = rec[3 * (size_t)s + 1];
+            const float4 r0 = rec[3 * (size_t)s + 0], r1 = rec[3 * (size_t)s + 1], r2 = rec[3 * (size_t)s + 2];
+            s0[threadIdx.x] = stage_geom(r0, r1, r2, ox, oy);
+            s1[threadIdx.x] = r1;
         }
         __syncthreads();
         if (!done) {
@@ -185,7 +196,8 @@ __global__ __launch_bounds__(256) void k_render_bwd(const float4* __restrict__ r
     const int ty = lt / V.tiles_x, tx = lt - ty * V.tiles_x;
     const int px = tx * kTile + (threadIdx.x & 15), py = ty * kTile + (threadIdx.x >> 4);
     const bool inside = px < V.W && py < V.H;
-    const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
+    const float ox = (float)(tx * kTile), oy = (float)(ty * kTile);
+    const float fpx = (float)(threadIdx.x & 15) + 0.5f, fpy = (float)(threadIdx.x >> 4) + 0.5f;
     const uint2 rg = ranges[tile];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
 
@@ -220,9 +232,10 @@ __global__ __launch_bounds__(256) void k_render_bwd(const float4* __restrict__ r
         if ((int)threadIdx.x < cnt) {
             const uint32_t s = pair_vals[rg.x + b_start + threadIdx.x];
             s_slot[threadIdx.x] = s;
-            s0[threadIdx.x] = rec[3 * (size_t)s + 0];
-            s1[threadIdx.x] = rec[3 * (size_t)s + 1];
-            s2[threadIdx.x] = rec[3 * (size_t)s + 2];
+            const float4 r0 = rec[3 * (size_t)s + 0], r1 = rec[3 * (size_t)s + 1], r2 = rec[3 * (size_t)s + 2];
+            s0[threadIdx.x] = stage_geom(r0, r1, r2, ox, oy);
+            s1[threadIdx.x] = r1;
+            s2[threadIdx.x] = r2;
         }
         __syncthreads();
         for (int k = cnt - 1; k >= 0; --k) {

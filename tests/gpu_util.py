@@ -22,10 +22,10 @@ def to_dev(scene, device="cuda:0", requires_grad=False):
 
 def decode_records(rec: np.ndarray):
     """GPU records [S, 12] -> oracle 2D quantities (float64, exact widening):
-    mean2d, conic (A, B, C) undoing the -log2(e) (1/2, 1, 1/2) scaling,
+    mean2d (integer part + fraction), conic (A, B, C) undoing the -log2(e) (1/2, 1, 1/2) scaling,
     opacity', rgb, depth."""
     rec = rec.astype(np.float64)
-    mean2d = rec[:, 0:2].copy()
+    mean2d = np.stack([rec[:, 0] + rec[:, 7], rec[:, 1] + rec[:, 11]], 1)
     conic = np.stack([-2.0 * rec[:, 2] / LOG2E, -rec[:, 3] / LOG2E, -2.0 * rec[:, 4] / LOG2E], 1)
     return mean2d, conic, rec[:, 5].copy(), rec[:, 8:11].copy(), rec[:, 6].copy()
 
