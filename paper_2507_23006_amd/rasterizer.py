@@ -124,7 +124,8 @@ def project(means, scales, quats, opacities, sh, cams, opts: RenderOptions) -> P
 def bin_sort(proj: Projected, cams, n: int, ws: Workspace | None = None, capacity_hint: int | None = None):
     """Returns (pair_vals [P] int32, tile_ranges [T, 2] int32, P).  pair_vals
     is a fresh tensor (torch's caching allocator), so results of several
-    calls can be alive at once; the capacity guess is remembered."""
+    calls can be alive at once; the capacity guess is remembered.  With P = 0
+    pair_vals has one unused element."""
     lib = L.load()
     ws = ws or _default_ws
     dev = proj.rec.device
@@ -146,7 +147,9 @@ def bin_sort(proj: Projected, cams, n: int, ws: Workspace | None = None, capacit
             continue
         L.check(rc)
         P = int(npairs.value)
-        return pairs[:P], ranges, P
+        # an empty view has a null data pointer in torch; with no pairs hand
+        # back one (never read) element so the buffer pointer stays valid
+        return (pairs[:P] if P > 0 else pairs[:1]), ranges, P
     raise L.GsError(L.GS_ERR_CAPACITY, "pair buffer could not be grown")
 
 
