@@ -70,7 +70,8 @@ extern "C" {
 
 #define GS_MAX_VIEWS 16
 #define GS_TILE 16
-#define GS_REC_FLOATS 12
+#define GS_REC_FLOATS 16
+#define GS_GRAD2D_FLOATS 12
 
 /* Pinhole camera.  viewmat is the row-major world-to-camera matrix
  * [R | t; 0 0 0 1] with OpenCV axes (x right, y down, z forward).
@@ -101,13 +102,18 @@ typedef struct gs_gaussians_grad {
 } gs_gaussians_grad;
 
 /* Projected per-slot records (n_views * n slots).
- *   rec  [slots][12] float: floor(mean2d x), floor(mean2d y); qa, qb;
- *        qc, opacity', depth, frac(mean2d x); r, g, b, frac(mean2d y).
+ *   rec  [slots][16] float: floor(mean2d x), floor(mean2d y); qa, qb;
+ *        qc, opacity', depth, frac(mean2d x); r, g, b, frac(mean2d y);
+ *        hx, hy, 0, 0.
  *        The mean is split into an exact integer part and a fraction so
  *        compositing can form tile-relative coordinates without the rounding
  *        of large pixel coordinates.  (qa, qb, qc) = -log2(e) (A/2, B, C/2)
  *        for the conic (A, B, C) of the dilated 2D covariance, so that
- *        G' = exp2(qa dx^2 + qb dx dy + qc dy^2).
+ *        G' = exp2(qa dx^2 + qb dx dy + qc dy^2).  (hx, hy) are half-widths
+ *        of a box around the mean outside which opacity' G' < 1/255 at every
+ *        pixel centre (with a margin over float32 rounding; negative when
+ *        opacity' < 1/255): compositing skips entries whose box misses its
+ *        pixels, which leaves every result unchanged.
  *   rect [slots][2] uint32: global id of the first tile of the rectangle;
  *        rectangle width in tiles | (tiles per image row << 16).
  *   tiles[slots] uint32: tiles in the rectangle, 0 if culled.
@@ -161,9 +167,10 @@ int gs_render_fwd(const gs_projected *proj, const uint32_t *pair_vals, const uin
                   float *alpha, float *T_final, int32_t *last, void *stream);
 
 /* Measurement only: per pixel, the number of list entries compositing has
- * to evaluate (through the one that stops the pixel, else the whole list),
- * written to n_eval [pix].  The unit of work behind the compositing
- * throughput figures; not needed to render. */
+ * to evaluate -- entries whose (hx, hy) box contains the pixel centre, up to
+ * and including the one that stops the pixel -- written to n_eval [pix].
+ * The unit of work behind the compositing throughput figures; not needed
+ * to render. */
 int gs_render_count(const gs_projected *proj, const uint32_t *pair_vals, const uint32_t *tile_ranges,
                     const gs_camera *cams, int32_t n_views, int32_t *n_eval, void *stream);
 

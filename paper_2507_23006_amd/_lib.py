@@ -17,7 +17,8 @@ GS_ERR_BUDGET = -4
 GS_EAGAIN = -5
 GS_ERR_INTERNAL = -6
 GS_MAX_VIEWS = 16
-REC_FLOATS = 12
+REC_FLOATS = 16
+GRAD2D_FLOATS = 12
 
 _ERRNAMES = {GS_ERR_INVALID_ARG: "GS_ERR_INVALID_ARG", GS_ERR_CAPACITY: "GS_ERR_CAPACITY",
              GS_ERR_HIP: "GS_ERR_HIP", GS_ERR_BUDGET: "GS_ERR_BUDGET", GS_EAGAIN: "GS_EAGAIN",

@@ -109,7 +109,7 @@ __device__ __forceinline__ void sh_eval_basis(Real x, Real y, Real z, int degree
 namespace gs {
 
 struct Projected {
-    float4* rec;          // [slots][3]
+    float4* rec;          // [slots][4]
     uint2* rect;          // [slots]
     uint32_t* tiles;      // [slots]
     uint32_t* dkey;       // [slots]

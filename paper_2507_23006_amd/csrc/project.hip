@@ -115,11 +115,23 @@ __global__ __launch_bounds__(256) void k_project_fwd(GaussPtrs gp, int64_t n, Vi
                     // compositing kernels can form a tile-relative mean without the
                     // rounding of a large absolute pixel coordinate
                     const double fmx = floor(mx), fmy = floor(my);
-                    out.rec[3 * slot + 0] = make_float4((float)fmx, (float)fmy, (float)(-0.5 * kLog2e * A),
+                    out.rec[4 * slot + 0] = make_float4((float)fmx, (float)fmy, (float)(-0.5 * kLog2e * A),
                                                         (float)(-kLog2e * B));
-                    out.rec[3 * slot + 1] = make_float4((float)(-0.5 * kLog2e * C), (float)(opac * rho), (float)tz,
+                    out.rec[4 * slot + 1] = make_float4((float)(-0.5 * kLog2e * C), (float)(opac * rho), (float)tz,
                                                         (float)(mx - fmx));
-                    out.rec[3 * slot + 2].w = (float)(my - fmy);
+                    out.rec[4 * slot + 2].w = (float)(my - fmy);
+                    // box of the region where opacity' G' >= (1 - 1e-5) / 255: the
+                    // ellipse x^T Sigma'^-1 x <= 2 tau has half-widths
+                    // sqrt(2 tau Sigma'_xx), sqrt(2 tau Sigma'_yy); the 1e-5 covers
+                    // the float32 error of alpha, the margins that of the box and mean
+                    const double o2 = opac * rho;
+                    float hx = -1.0f, hy = -1.0f;
+                    if ((float)o2 >= kAlphaMin) {
+                        const double tau = log(255.0 * o2) + 1e-5;
+                        hx = (float)(sqrt(2.0 * tau * ad) * (1.0 + 1e-6) + 1e-3);
+                        hy = (float)(sqrt(2.0 * tau * cd) * (1.0 + 1e-6) + 1e-3);
+                    }
+                    out.rec[4 * slot + 3] = make_float4(hx, hy, 0.0f, 0.0f);
                     out.rect[slot] = make_uint2((uint32_t)(V.tile_off + iy0 * TW + ix0),
                                                 (uint32_t)w | ((uint32_t)TW << 16));
                     vis_mask |= 1u << v;
@@ -153,11 +165,11 @@ __global__ __launch_bounds__(256) void k_project_fwd(GaussPtrs gp, int64_t n, Vi
                 c[2] = fmaf(gp.sh[(int64_t)(3 * k + 2) * n + g], Y[k], c[2]);
             }
         }
-        float4 r2 = out.rec[3 * slot + 2];
+        float4 r2 = out.rec[4 * slot + 2];
         r2.x = fmaxf(c[0], 0.0f);
         r2.y = fmaxf(c[1], 0.0f);
         r2.z = fmaxf(c[2], 0.0f);
-        out.rec[3 * slot + 2] = r2;
+        out.rec[4 * slot + 2] = r2;
     }
 }
 

@@ -47,7 +47,7 @@ __device__ __forceinline__ void sh_basis_grad(float x, float y, float z, int k, 
     }
 }
 
-constexpr int kG2 = 12;
+constexpr int kG2 = GS_GRAD2D_FLOATS;
 
 __global__ __launch_bounds__(256) void k_project_bwd(GaussPtrs gp, int64_t n, ViewTable vt, OptK opt, Projected proj,
                                                      const float* __restrict__ grad2d, GradPtrs out,

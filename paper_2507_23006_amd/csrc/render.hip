@@ -1,18 +1,18 @@
 // Front-to-back compositing (Eq. 2) and its backward -- gfx950.
 //
-// One 256-thread workgroup (four wave64s) per 16x16 tile, one pixel per
-// thread.  The tile's depth-ordered list is walked in batches: each thread
-// gathers one projected record (three 16-byte loads) into LDS, then every
-// thread evaluates the whole batch from LDS; all lanes of a wave read the
-// same record, which the LDS serves as a conflict-free broadcast.  The
-// forward keeps no per-pixel lists: it stores the final transmittance and
-// the position of the last composited entry, and the backward walks the
-// list back to front, recovering T_i = T_{i+1} / (1 - alpha_i).
+// Four wave64s per 16x16 tile, each owning an 8x8 quadrant (one pixel per
+// lane) and walking the tile's depth-ordered list independently.  Records
+// are staged in LDS in chunks of 64, culled against the quadrant with each
+// record's alpha box and compacted by ballot; all lanes then read the same
+// staged record, which the LDS serves as a broadcast.  The forward keeps no
+// per-pixel lists: it stores the final transmittance and the position of the
+// last composited entry, and the backward walks the list back to front,
+// recovering T_i = T_{i+1} / (1 - alpha_i).
 //
 // Backward per entry: gradients are summed over the wave with DPP
-// row-shift / row-broadcast adds (six VALU steps, result in lane 63),
-// across the four waves in LDS, and then added to the per-slot 2D gradient
-// buffer with one float atomic per nonzero field.
+// row-shift / row-broadcast adds (six VALU steps, result in lane 63) into an
+// LDS row; after each chunk the wave adds the rows to the per-slot 2D
+// gradient buffer with one float atomic per nonzero field.
 #include "gs_internal.h"
 
 namespace gs {
@@ -46,7 +46,98 @@ __device__ __forceinline__ float4 stage_geom(const float4 r0, const float4 r1, c
     return make_float4((r0.x - ox) + r1.w, (r0.y - oy) + r2.w, r0.z, r0.w);
 }
 
-constexpr int kFwdBatch = 256;
+// Four independent wave64s per 16x16 tile, one 8x8 quadrant each, one
+// pixel per lane.  A wave walks the tile's list in chunks of 64: every lane
+// gathers one record, tests the record's box (opacity' G' >= 1/255 region,
+// with margins) against the wave's quadrant, and the ballot of survivors
+// compacts them, in list order, into the wave's LDS slice.  The wave then
+// evaluates only the survivors: an entry whose box misses every pixel of the
+// quadrant has alpha < 1/255 there and would be skipped anyway, so results
+// are unchanged while the horizon tiles' long lists of tiny, distant
+// Gaussians cost a fraction of the work.  The per-entry update is predicated
+// (selects, no branches).  Waves of a tile never wait for each other.
+constexpr int kChunk = 64;
+constexpr int kWaves = 4;
+
+struct PixelCoords {
+    int v;
+    float ox, oy;          // tile origin in pixels
+    float fpx, fpy;        // pixel centre relative to the tile origin
+    float qcx, qcy;        // centre of the wave's quadrant (pixel-centre span +-3.5)
+    bool inside;
+    int64_t pix;
+};
+
+__device__ __forceinline__ PixelCoords pixel_coords(const ViewTable& vt, int tile, int wave, int lane) {
+    PixelCoords c;
+    c.v = view_of_tile(vt, tile);
+    const ViewK& V = vt.v[c.v];
+    const int lt = tile - V.tile_off;
+    const int ty = lt / V.tiles_x, tx = lt - ty * V.tiles_x;
+    const int qx0 = (wave & 1) * 8, qy0 = (wave >> 1) * 8;
+    const int lx = qx0 + (lane & 7), ly = qy0 + (lane >> 3);
+    c.ox = (float)(tx * kTile);
+    c.oy = (float)(ty * kTile);
+    c.fpx = (float)lx + 0.5f;
+    c.fpy = (float)ly + 0.5f;
+    c.qcx = (float)qx0 + 4.0f;
+    c.qcy = (float)qy0 + 4.0f;
+    const int px = tx * kTile + lx, py = ty * kTile + ly;
+    c.inside = px < V.W && py < V.H;
+    c.pix = V.pix_off + (int64_t)py * V.W + px;
+    return c;
+}
+
+// does the record's alpha box reach the wave's quadrant of pixel centres?
+__device__ __forceinline__ bool box_hits_quadrant(const float4 g, const float4 r3, float qcx, float qcy) {
+    const float mx = g.x, my = g.y;
+    return fabsf(mx - qcx) <= r3.x + 3.5f + 1e-3f + 1e-6f * fabsf(mx) &&
+           fabsf(my - qcy) <= r3.y + 3.5f + 1e-3f + 1e-6f * fabsf(my) && r3.x >= 0.0f;
+}
+
+__device__ __forceinline__ unsigned long long lanes_below(int lane) {
+    return lane ? (~0ull >> (64 - lane)) : 0ull;
+}
+
+struct WaveStage {
+    float4 g[kChunk];      // tile-relative mean, qa, qb
+    float4 b[kChunk];      // qc, opacity', depth, -
+    float4 c[kChunk];      // r, g, b, -
+    int pos[kChunk];       // 1-based position in the tile list
+    uint32_t slot[kChunk];
+};
+
+// Gathers list entries [j0, j0 + 64) of the tile (clipped to `end`), keeps
+// those whose box reaches the quadrant, compacts them in order into `st`;
+// returns the number kept.  Wave-uniform.
+__device__ __forceinline__ int stage_chunk(const float4* __restrict__ rec, const uint32_t* __restrict__ pair_vals,
+                                           uint32_t list0, uint32_t j0, uint32_t end, const PixelCoords& pc,
+                                           int lane, WaveStage& st) {
+    const uint32_t j = j0 + lane;
+    bool hit = false;
+    float4 g, r1, r2;
+    uint32_t s = 0;
+    if (j < end) {
+        s = pair_vals[j];
+        const float4 r0 = rec[4 * (size_t)s + 0];
+        r1 = rec[4 * (size_t)s + 1];
+        r2 = rec[4 * (size_t)s + 2];
+        const float4 r3 = rec[4 * (size_t)s + 3];
+        g = stage_geom(r0, r1, r2, pc.ox, pc.oy);
+        hit = box_hits_quadrant(g, r3, pc.qcx, pc.qcy);
+    }
+    const unsigned long long m = __ballot(hit);
+    if (hit) {
+        const int d = __popcll(m & lanes_below(lane));
+        st.g[d] = g;
+        st.b[d] = r1;
+        st.c[d] = r2;
+        st.pos[d] = (int)(j - list0) + 1;
+        st.slot[d] = s;
+    }
+    __builtin_amdgcn_wave_barrier();
+    return __popcll(m);
+}
 
 __global__ __launch_bounds__(256) void k_render_fwd(const float4* __restrict__ rec,
                                                     const uint32_t* __restrict__ pair_vals,
@@ -54,113 +145,89 @@ __global__ __launch_bounds__(256) void k_render_fwd(const float4* __restrict__ r
                                                     float* __restrict__ rgb, float* __restrict__ depth,
                                                     float* __restrict__ alpha_out, float* __restrict__ T_out,
                                                     int32_t* __restrict__ last_out) {
-    __shared__ float4 s0[kFwdBatch], s1[kFwdBatch], s2[kFwdBatch];
+    __shared__ WaveStage stage[kWaves];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int tile = blockIdx.x;
-    const int v = view_of_tile(vt, tile);
-    const ViewK& V = vt.v[v];
-    const int lt = tile - V.tile_off;
-    const int ty = lt / V.tiles_x, tx = lt - ty * V.tiles_x;
-    const int px = tx * kTile + (threadIdx.x & 15), py = ty * kTile + (threadIdx.x >> 4);
-    const bool inside = px < V.W && py < V.H;
-    const float ox = (float)(tx * kTile), oy = (float)(ty * kTile);
-    const float fpx = (float)(threadIdx.x & 15) + 0.5f, fpy = (float)(threadIdx.x >> 4) + 0.5f;
+    const PixelCoords pc = pixel_coords(vt, tile, wave, lane);
+    WaveStage& st = stage[wave];
     const uint2 rg = ranges[tile];
 
     float T = 1.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f, D = 0.0f;
     int last = 0;
-    bool done = !inside;
-    for (uint32_t b0 = rg.x; b0 < rg.y; b0 += kFwdBatch) {
-        // barrier: every pixel of the tile done ends the walk; also guards LDS reuse
-        if (__syncthreads_count(!done) == 0) break;
-        const uint32_t j = b0 + threadIdx.x;
-        if (j < rg.y) {
-            const uint32_t s = pair_vals[j];
-            const float4 r0 = rec[3 * (size_t)s + 0], r1 = rec[3 * (size_t)s + 1], r2 = rec[3 * (size_t)s + 2];
-            s0[threadIdx.x] = stage_geom(r0, r1, r2, ox, oy);
-            s1[threadIdx.x] = r1;
-            s2[threadIdx.x] = r2;
+    bool alive = pc.inside;
+    for (uint32_t j0 = rg.x; j0 < rg.y; j0 += kChunk) {
+        if (__ballot(alive) == 0) break;     // every pixel of the quadrant has stopped
+        const int n = stage_chunk(rec, pair_vals, rg.x, j0, rg.y, pc, lane, st);
+        for (int k = 0; k < n; ++k) {
+            const float4 a = st.g[k], b = st.b[k];
+            const Eval e = eval_entry(a, b, pc.fpx, pc.fpy);
+            const float Tn = T * (1.0f - e.alpha);
+            const bool keep = alive && e.keep;
+            const bool stop = keep && Tn < kTMin;
+            const bool use = keep && !stop;
+            const float w = use ? e.alpha * T : 0.0f;
+            const float4 c = st.c[k];
+            c0 = fmaf(c.x, w, c0);
+            c1 = fmaf(c.y, w, c1);
+            c2 = fmaf(c.z, w, c2);
+            D = fmaf(b.z, w, D);
+            T = use ? Tn : T;
+            last = use ? st.pos[k] : last;
+            alive = alive && !stop;
         }
-        __syncthreads();
-        if (!done) {
-            const int cnt = (int)min((uint32_t)kFwdBatch, rg.y - b0);
-            for (int k = 0; k < cnt; ++k) {
-                const float4 a = s0[k], b = s1[k];
-                const Eval e = eval_entry(a, b, fpx, fpy);
-                if (!e.keep) continue;
-                const float Tn = T * (1.0f - e.alpha);
-                if (Tn < kTMin) {
-                    done = true;
-                    break;
-                }
-                const float4 c = s2[k];
-                const float w = e.alpha * T;
-                c0 = fmaf(c.x, w, c0);
-                c1 = fmaf(c.y, w, c1);
-                c2 = fmaf(c.z, w, c2);
-                D = fmaf(b.z, w, D);
-                T = Tn;
-                last = (int)(b0 - rg.x) + k + 1;
-            }
-        }
+        __builtin_amdgcn_wave_barrier();     // the chunk is consumed before the next one is staged
     }
-    if (!inside) return;
-    const int64_t pix = V.pix_off + (int64_t)py * V.W + px;
-    rgb[3 * pix + 0] = fmaf(T, opt.bg[0], c0);
-    rgb[3 * pix + 1] = fmaf(T, opt.bg[1], c1);
-    rgb[3 * pix + 2] = fmaf(T, opt.bg[2], c2);
-    depth[pix] = D;
-    alpha_out[pix] = 1.0f - T;
-    T_out[pix] = T;
-    last_out[pix] = last;
+    if (!pc.inside) return;
+    const int64_t p = pc.pix;
+    rgb[3 * p + 0] = fmaf(T, opt.bg[0], c0);
+    rgb[3 * p + 1] = fmaf(T, opt.bg[1], c1);
+    rgb[3 * p + 2] = fmaf(T, opt.bg[2], c2);
+    depth[p] = D;
+    alpha_out[p] = 1.0f - T;
+    T_out[p] = T;
+    last_out[p] = last;
 }
 
-// Per pixel: how many list entries the forward must evaluate (up to and
-// including the one that stops the pixel, else the whole list).  The unit
-// of work of compositing; used for the roofline, never on the render path.
+// Per pixel: the number of list entries compositing must evaluate -- those
+// whose box contains the pixel centre, up to and including the one that
+// stops the pixel.  The unit of work of compositing; measurement only.
 __global__ __launch_bounds__(256) void k_render_count(const float4* __restrict__ rec,
                                                       const uint32_t* __restrict__ pair_vals,
                                                       const uint2* __restrict__ ranges, ViewTable vt,
                                                       int32_t* __restrict__ n_eval) {
-    __shared__ float4 s0[kFwdBatch], s1[kFwdBatch];
+    __shared__ WaveStage stage[kWaves];
+    __shared__ float2 sbox[kWaves][kChunk];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int tile = blockIdx.x;
-    const int v = view_of_tile(vt, tile);
-    const ViewK& V = vt.v[v];
-    const int lt = tile - V.tile_off;
-    const int ty = lt / V.tiles_x, tx = lt - ty * V.tiles_x;
-    const int px = tx * kTile + (threadIdx.x & 15), py = ty * kTile + (threadIdx.x >> 4);
-    const bool inside = px < V.W && py < V.H;
-    const float ox = (float)(tx * kTile), oy = (float)(ty * kTile);
-    const float fpx = (float)(threadIdx.x & 15) + 0.5f, fpy = (float)(threadIdx.x >> 4) + 0.5f;
+    const PixelCoords pc = pixel_coords(vt, tile, wave, lane);
+    WaveStage& st = stage[wave];
     const uint2 rg = ranges[tile];
     float T = 1.0f;
     int count = 0;
-    bool done = !inside;
-    for (uint32_t b0 = rg.x; b0 < rg.y; b0 += kFwdBatch) {
-        if (__syncthreads_count(!done) == 0) break;
-        const uint32_t j = b0 + threadIdx.x;
-        if (j < rg.y) {
-            const uint32_t s = pair_vals[j];
-            const float4 r0 = rec[3 * (size_t)s + 0], r1 = rec[3 * (size_t)s + 1], r2 = rec[3 * (size_t)s + 2];
-            s0[threadIdx.x] = stage_geom(r0, r1, r2, ox, oy);
-            s1[threadIdx.x] = r1;
+    bool alive = pc.inside;
+    for (uint32_t j0 = rg.x; j0 < rg.y; j0 += kChunk) {
+        if (__ballot(alive) == 0) break;
+        const int n = stage_chunk(rec, pair_vals, rg.x, j0, rg.y, pc, lane, st);
+        if (lane < n) {
+            const float4 r3 = rec[4 * (size_t)st.slot[lane] + 3];
+            sbox[wave][lane] = make_float2(r3.x, r3.y);
         }
-        __syncthreads();
-        if (!done) {
-            const int cnt = (int)min((uint32_t)kFwdBatch, rg.y - b0);
-            for (int k = 0; k < cnt; ++k) {
-                ++count;
-                const Eval e = eval_entry(s0[k], s1[k], fpx, fpy);
-                if (!e.keep) continue;
-                const float Tn = T * (1.0f - e.alpha);
-                if (Tn < kTMin) {
-                    done = true;
-                    break;
-                }
-                T = Tn;
-            }
+        __builtin_amdgcn_wave_barrier();
+        for (int k = 0; k < n; ++k) {
+            const float4 a = st.g[k], b = st.b[k];
+            const float2 h = sbox[wave][k];
+            const bool covers = fabsf(pc.fpx - a.x) <= h.x && fabsf(pc.fpy - a.y) <= h.y;
+            const Eval e = eval_entry(a, b, pc.fpx, pc.fpy);
+            const float Tn = T * (1.0f - e.alpha);
+            const bool keep = alive && e.keep;
+            const bool stop = keep && Tn < kTMin;
+            count += (alive && covers) ? 1 : 0;
+            T = (keep && !stop) ? Tn : T;
+            alive = alive && !stop;
         }
+        __builtin_amdgcn_wave_barrier();
     }
-    if (inside) n_eval[V.pix_off + (int64_t)py * V.W + px] = count;
+    if (pc.inside) n_eval[pc.pix] = count;
 }
 
 // sum over the 64 lanes; lane 63 holds the result
@@ -174,9 +241,13 @@ __device__ __forceinline__ float wave_sum_lane63(float x) {
     return x;
 }
 
-constexpr int kBwdBatch = 64;
-constexpr int kG2 = 12;   // per-slot 2D gradient fields
+constexpr int kG2 = GS_GRAD2D_FLOATS;   // per-slot 2D gradient fields
 
+// Backward: each wave walks its quadrant's list back to front from the
+// deepest `last` of its pixels, in chunks staged and culled as in the
+// forward.  Per surviving entry the lanes' gradients are summed with DPP
+// into a per-wave LDS row; after each chunk the wave adds the rows to the
+// per-slot 2D gradient buffer with float atomics (zeros skipped).
 __global__ __launch_bounds__(256) void k_render_bwd(const float4* __restrict__ rec,
                                                     const uint32_t* __restrict__ pair_vals,
                                                     const uint2* __restrict__ ranges, ViewTable vt, OptK opt,
@@ -184,100 +255,71 @@ __global__ __launch_bounds__(256) void k_render_bwd(const float4* __restrict__ r
                                                     const int32_t* __restrict__ last_in,
                                                     const float* __restrict__ d_rgb, const float* __restrict__ d_depth,
                                                     const float* __restrict__ d_alpha, float* __restrict__ grad2d) {
-    __shared__ float4 s0[kBwdBatch], s1[kBwdBatch], s2[kBwdBatch];
-    __shared__ uint32_t s_slot[kBwdBatch];
-    __shared__ float s_red[4][kBwdBatch][kG2];
-    __shared__ int s_maxlast;
-
-    const int tile = blockIdx.x;
-    const int v = view_of_tile(vt, tile);
-    const ViewK& V = vt.v[v];
-    const int lt = tile - V.tile_off;
-    const int ty = lt / V.tiles_x, tx = lt - ty * V.tiles_x;
-    const int px = tx * kTile + (threadIdx.x & 15), py = ty * kTile + (threadIdx.x >> 4);
-    const bool inside = px < V.W && py < V.H;
-    const float ox = (float)(tx * kTile), oy = (float)(ty * kTile);
-    const float fpx = (float)(threadIdx.x & 15) + 0.5f, fpy = (float)(threadIdx.x >> 4) + 0.5f;
-    const uint2 rg = ranges[tile];
+    __shared__ WaveStage stage[kWaves];
+    __shared__ float s_red[kWaves][kChunk][kG2];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int tile = blockIdx.x;
+    const PixelCoords pc = pixel_coords(vt, tile, wave, lane);
+    WaveStage& st = stage[wave];
+    const uint2 rg = ranges[tile];
 
     float T = 1.0f, gC0 = 0.0f, gC1 = 0.0f, gC2 = 0.0f, gD = 0.0f, gA = 0.0f;
     int last = 0;
-    if (inside) {
-        const int64_t pix = V.pix_off + (int64_t)py * V.W + px;
-        T = T_final[pix];
-        last = last_in[pix];
+    if (pc.inside) {
+        const int64_t p = pc.pix;
+        T = T_final[p];
+        last = last_in[p];
         if (d_rgb) {
-            gC0 = d_rgb[3 * pix + 0];
-            gC1 = d_rgb[3 * pix + 1];
-            gC2 = d_rgb[3 * pix + 2];
+            gC0 = d_rgb[3 * p + 0];
+            gC1 = d_rgb[3 * p + 1];
+            gC2 = d_rgb[3 * p + 2];
         }
-        if (d_depth) gD = d_depth[pix];
-        if (d_alpha) gA = d_alpha[pix];
+        if (d_depth) gD = d_depth[p];
+        if (d_alpha) gA = d_alpha[p];
     }
-    if (threadIdx.x == 0) s_maxlast = 0;
-    __syncthreads();
-    if (last > 0) atomicMax(&s_maxlast, last);
-    __syncthreads();
-    const int maxlast = s_maxlast;
+    int maxlast = last;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) maxlast = max(maxlast, __shfl_xor(maxlast, off, 64));
 
     // R = remaining colour behind the entry divided by T after it; starts at bg
     float R0 = opt.bg[0], R1 = opt.bg[1], R2 = opt.bg[2], RD = 0.0f, Q = 1.0f;
     const float ln2 = kLn2;
 
-    for (int b_end = maxlast; b_end > 0; b_end -= kBwdBatch) {
-        const int b_start = max(0, b_end - kBwdBatch);
-        const int cnt = b_end - b_start;
-        __syncthreads();   // previous batch fully consumed
-        if ((int)threadIdx.x < cnt) {
-            const uint32_t s = pair_vals[rg.x + b_start + threadIdx.x];
-            s_slot[threadIdx.x] = s;
-            const float4 r0 = rec[3 * (size_t)s + 0], r1 = rec[3 * (size_t)s + 1], r2 = rec[3 * (size_t)s + 2];
-            s0[threadIdx.x] = stage_geom(r0, r1, r2, ox, oy);
-            s1[threadIdx.x] = r1;
-            s2[threadIdx.x] = r2;
-        }
-        __syncthreads();
-        for (int k = cnt - 1; k >= 0; --k) {
-            const int pos = b_start + k;           // 0-based position in the tile list
-            const float4 a = s0[k], b = s1[k], c = s2[k];
-            const Eval e = eval_entry(a, b, fpx, fpy);
-            const bool contrib = pos < last && e.keep;
+    for (int b_end = maxlast; b_end > 0; b_end -= kChunk) {
+        const int b_start = max(0, b_end - kChunk);
+        const int n = stage_chunk(rec, pair_vals, rg.x, rg.x + (uint32_t)b_start, rg.x + (uint32_t)b_end, pc, lane, st);
+        for (int k = n - 1; k >= 0; --k) {
+            const float4 a = st.g[k], b = st.b[k], c = st.c[k];
+            const int pos = st.pos[k];        // 1-based
+            const Eval e = eval_entry(a, b, pc.fpx, pc.fpy);
+            const bool con = pos <= last && e.keep;
+            const float one_m = 1.0f - e.alpha;
+            const float Ti = T * __builtin_amdgcn_rcpf(one_m);
             float g[kG2];
-#pragma unroll
-            for (int f = 0; f < kG2; ++f) g[f] = 0.0f;
-            if (contrib) {
-                const float one_m = 1.0f - e.alpha;
-                const float Ti = T * __builtin_amdgcn_rcpf(one_m);
-                const float w = e.alpha * Ti;
-                const float dal = Ti * (gC0 * (c.x - R0) + gC1 * (c.y - R1) + gC2 * (c.z - R2) + gD * (b.z - RD) +
-                                        gA * Q);
-                g[6] = gC0 * w;
-                g[7] = gC1 * w;
-                g[8] = gC2 * w;
-                g[9] = gD * w;
-                if (e.raw < kAlphaMax) {
-                    g[5] = dal * e.G;
-                    const float dp = dal * e.alpha;          // dL/d power
-                    // conic (A, B, C) = -ln2 (2 qa, qb, 2 qc)
-                    const float dmx = -dp * ln2 * (2.0f * a.z * e.dx + a.w * e.dy);
-                    const float dmy = -dp * ln2 * (a.w * e.dx + 2.0f * b.x * e.dy);
-                    g[0] = dmx;
-                    g[1] = dmy;
-                    g[2] = -0.5f * e.dx * e.dx * dp;
-                    g[3] = -e.dx * e.dy * dp;
-                    g[4] = -0.5f * e.dy * e.dy * dp;
-                    g[10] = fabsf(dmx);
-                    g[11] = fabsf(dmy);
-                }
-                R0 = fmaf(R0, one_m, c.x * e.alpha);
-                R1 = fmaf(R1, one_m, c.y * e.alpha);
-                R2 = fmaf(R2, one_m, c.z * e.alpha);
-                RD = fmaf(RD, one_m, b.z * e.alpha);
-                Q *= one_m;
-                T = Ti;
-            }
-            if (__ballot(contrib)) {
+            const float w = con ? e.alpha * Ti : 0.0f;
+            const float dal = Ti * (gC0 * (c.x - R0) + gC1 * (c.y - R1) + gC2 * (c.z - R2) + gD * (b.z - RD) + gA * Q);
+            g[6] = gC0 * w;
+            g[7] = gC1 * w;
+            g[8] = gC2 * w;
+            g[9] = gD * w;
+            const float dal_u = (con && e.raw < kAlphaMax) ? dal : 0.0f;
+            g[5] = dal_u * e.G;
+            const float dp = dal_u * e.alpha;          // dL/d power
+            // conic (A, B, C) = -ln2 (2 qa, qb, 2 qc)
+            g[0] = -dp * ln2 * (2.0f * a.z * e.dx + a.w * e.dy);
+            g[1] = -dp * ln2 * (a.w * e.dx + 2.0f * b.x * e.dy);
+            g[2] = -0.5f * e.dx * e.dx * dp;
+            g[3] = -e.dx * e.dy * dp;
+            g[4] = -0.5f * e.dy * e.dy * dp;
+            g[10] = fabsf(g[0]);
+            g[11] = fabsf(g[1]);
+            R0 = con ? fmaf(R0, one_m, c.x * e.alpha) : R0;
+            R1 = con ? fmaf(R1, one_m, c.y * e.alpha) : R1;
+            R2 = con ? fmaf(R2, one_m, c.z * e.alpha) : R2;
+            RD = con ? fmaf(RD, one_m, b.z * e.alpha) : RD;
+            Q = con ? Q * one_m : Q;
+            T = con ? Ti : T;
+            if (__ballot(con)) {
 #pragma unroll
                 for (int f = 0; f < kG2; ++f) g[f] = wave_sum_lane63(g[f]);
                 if (lane == 63) {
@@ -289,12 +331,13 @@ __global__ __launch_bounds__(256) void k_render_bwd(const float4* __restrict__ r
                 for (int f = 0; f < kG2; ++f) s_red[wave][k][f] = 0.0f;
             }
         }
-        __syncthreads();
-        for (int i = threadIdx.x; i < cnt * kG2; i += 256) {
+        __builtin_amdgcn_wave_barrier();
+        for (int i = lane; i < n * kG2; i += 64) {
             const int k = i / kG2, f = i - k * kG2;
-            const float sum = s_red[0][k][f] + s_red[1][k][f] + s_red[2][k][f] + s_red[3][k][f];
-            if (sum != 0.0f) atomicAdd(&grad2d[(size_t)s_slot[k] * kG2 + f], sum);
+            const float sum = s_red[wave][k][f];
+            if (sum != 0.0f) atomicAdd(&grad2d[(size_t)st.slot[k] * kG2 + f], sum);
         }
+        __builtin_amdgcn_wave_barrier();
     }
 }
 

@@ -86,7 +86,7 @@ _default_ws = Workspace()
 
 @dataclass
 class Projected:
-    rec: torch.Tensor        # [S, 12] float32
+    rec: torch.Tensor        # [S, 16] float32
     rect: torch.Tensor       # [S, 2] int32 (bit patterns of uint32)
     tiles: torch.Tensor      # [S] int32
     depth_key: torch.Tensor  # [S] int32 (bit patterns of uint32)

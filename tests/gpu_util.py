@@ -21,7 +21,7 @@ def to_dev(scene, device="cuda:0", requires_grad=False):
 
 
 def decode_records(rec: np.ndarray):
-    """GPU records [S, 12] -> oracle 2D quantities (float64, exact widening):
+    """GPU records [S, 16] -> oracle 2D quantities (float64, exact widening):
     mean2d (integer part + fraction), conic (A, B, C) undoing the -log2(e) (1/2, 1, 1/2) scaling,
     opacity', rgb, depth."""
     rec = rec.astype(np.float64)
