@@ -93,8 +93,7 @@ def main():
     H, W = cam.height, cam.width
     tgt_rgb = torch.from_numpy(S.target_rgb(H, W, seed=1)).to(dev).view(-1, 3)
     tgt_d = torch.from_numpy(S.target_depth(H, W, seed=1, lo=20.0, hi=45.0)).to(dev).view(-1)
-    params = [torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(dev).requires_grad_(True)
-              for a in (scene.means, scene.scales, scene.quats, scene.opacities, scene.sh)]
+    params = [torch.from_numpy(a).to(dev).requires_grad_(True) for a in scene.param_arrays()]
     opts = gs.RenderOptions(sh_degree=3, dilation=0.3, aa=True, absgrad=False)
     print(f"# workload ready in {time.time() - t_gen:.1f} s", file=sys.stderr, flush=True)
 
@@ -163,8 +162,8 @@ def main():
         n_front = int((proj.depth_key.view(torch.int32) != -1).sum().item())
         tiles = proj.tiles
         n_vis = int((tiles > 0).sum().item())
-        e_fwd = int(gs.render_count(proj, pv, rg, cams).to(torch.int64).sum().item())
-        e_bwd = int(out["last"].to(torch.int64).sum().item())
+        counts = gs.render_count(proj, pv, rg, cams).to(torch.int64).sum(0).tolist()
+        e_fwd, e_bwd = int(counts[0]), int(counts[1])
     npix = W * H
 
     # roofline of the dominant stage

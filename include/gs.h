@@ -40,10 +40,12 @@
  *     stream (it reads back the pair count).
  *   - Return value 0 (GS_OK) or a negative GS_ERR_* code; nothing throws.
  *     gs_last_error() returns the calling thread's last message.
- *   - Gaussian parameters are structure-of-arrays over n Gaussians:
- *     means [3][n], scales [3][n] (positive), quats [4][n] as (w, x, y, z)
- *     (normalised inside), opacities [n] in (0, 1), sh [16][3][n]
- *     (coefficient, channel, Gaussian).
+ *   - Gaussian parameters over n Gaussians: means [3][n], scales [3][n]
+ *     (positive), quats [4][n] as (w, x, y, z) (normalised inside) and
+ *     opacities [n] in (0, 1) are structure-of-arrays; sh [n][16][3]
+ *     (Gaussian, coefficient, channel) keeps each Gaussian's 48 colour
+ *     coefficients in one 192-byte row, so that the few Gaussians a view
+ *     sees read whole rows (16-byte aligned base pointer required).
  *   - Several views of the same Gaussians are rendered in one launch per
  *     stage (at most GS_MAX_VIEWS).  A "slot" is (view, Gaussian) with index
  *     view * n + gaussian.  Tiles of all views share one numbering (view
@@ -166,11 +168,12 @@ int gs_render_fwd(const gs_projected *proj, const uint32_t *pair_vals, const uin
                   const gs_camera *cams, int32_t n_views, const gs_options *opt, float *rgb, float *depth,
                   float *alpha, float *T_final, int32_t *last, void *stream);
 
-/* Measurement only: per pixel, the number of list entries compositing has
- * to evaluate -- entries whose (hx, hy) box contains the pixel centre, up to
- * and including the one that stops the pixel -- written to n_eval [pix].
- * The unit of work behind the compositing throughput figures; not needed
- * to render. */
+/* Measurement only: per pixel, the numbers of list entries compositing has
+ * to evaluate, written to n_eval [pix][2]: [0] the forward's -- entries whose
+ * (hx, hy) box contains the pixel centre, up to and including the one that
+ * stops the pixel; [1] the backward's -- the same entries up to and including
+ * the pixel's last composited one.  The units of work behind the compositing
+ * throughput figures; not needed to render. */
 int gs_render_count(const gs_projected *proj, const uint32_t *pair_vals, const uint32_t *tile_ranges,
                     const gs_camera *cams, int32_t n_views, int32_t *n_eval, void *stream);
 
@@ -190,9 +193,11 @@ int gs_render_bwd(const gs_gaussians *g, const gs_camera *cams, int32_t n_views,
                   void *ws, size_t ws_bytes, void *stream);
 
 /* The two halves of gs_render_bwd, for callers that schedule or time them
- * separately.  gs_composite_bwd overwrites grad2d [slots][12] (fields as in
- * gs_render_bwd_grad2d) with the compositing backward; gs_project_bwd chains
- * grad2d to the parameters (outputs as in gs_render_bwd). */
+ * separately.  gs_composite_bwd overwrites the rows of grad2d [slots][12]
+ * (fields as in gs_render_bwd_grad2d) whose slot has tiles > 0 with the
+ * compositing backward and leaves the other rows unwritten; gs_project_bwd
+ * chains grad2d to the parameters (outputs as in gs_render_bwd), reading
+ * only those rows. */
 int gs_composite_bwd(const gs_projected *proj, const uint32_t *pair_vals, const uint32_t *tile_ranges,
                      const gs_camera *cams, int32_t n_views, const gs_options *opt, const float *T_final,
                      const int32_t *last, const float *d_rgb, const float *d_depth, const float *d_alpha,
@@ -203,7 +208,8 @@ int gs_project_bwd(const gs_gaussians *g, const gs_camera *cams, int32_t n_views
 
 /* Per-slot 2D gradients of the last gs_render_bwd call that used `ws`
  * ([slots][12]: d mean2d x, y; d conic A, B, C; d opacity'; d rgb; d depth;
- * |d mean2d| x, y accumulations) -- for inspection and tests. */
+ * |d mean2d| x, y accumulations; rows of slots with tiles == 0 are
+ * unwritten) -- for inspection and tests. */
 const float *gs_render_bwd_grad2d(void *ws);
 
 #ifdef __cplusplus

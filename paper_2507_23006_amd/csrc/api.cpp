@@ -326,7 +326,7 @@ int gs_render_bwd(const gs_gaussians* g, const gs_camera* cams, int32_t n_views,
         GS_REQUIRE(ws_bytes >= gs_render_bwd_workspace_size(n_slots), "workspace too small");
         hipStream_t s = (hipStream_t)stream;
         float* grad2d = static_cast<float*>(ws);
-        GS_HIP(fill_u32(reinterpret_cast<uint32_t*>(grad2d), 0u, (size_t)n_slots * GS_GRAD2D_FLOATS, s));
+        GS_HIP(zero_seen_grad2d(proj->tiles, grad2d, n_slots, s));
         const Projected pr = to_proj(proj);
         GS_HIP(launch_render_bwd(pr, pair_vals, reinterpret_cast<const uint2*>(tile_ranges), vt, ok, T_final, last,
                                  d_rgb, d_depth, d_alpha, grad2d, s));
@@ -352,7 +352,7 @@ int gs_composite_bwd(const gs_projected* proj, const uint32_t* pair_vals, const 
         GS_REQUIRE(pair_vals && tile_ranges && T_final && last && grad2d, "NULL buffer");
         GS_REQUIRE(n_slots >= 1 && n_slots <= 0xFFFFFF00LL, "bad n_slots");
         hipStream_t s = (hipStream_t)stream;
-        GS_HIP(fill_u32(reinterpret_cast<uint32_t*>(grad2d), 0u, (size_t)n_slots * GS_GRAD2D_FLOATS, s));
+        GS_HIP(zero_seen_grad2d(proj->tiles, grad2d, n_slots, s));
         GS_HIP(launch_render_bwd(to_proj(proj), pair_vals, reinterpret_cast<const uint2*>(tile_ranges), vt, ok, T_final,
                                  last, d_rgb, d_depth, d_alpha, grad2d, s));
         return GS_OK;

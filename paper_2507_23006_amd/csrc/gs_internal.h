@@ -135,6 +135,8 @@ size_t scan_tmp_elems(uint32_t n);
 hipError_t exclusive_scan_u32(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* tmp,
                               unsigned long long* total, hipStream_t s);
 hipError_t fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s);
+// zero the [12]-float 2D-gradient rows of slots with tiles > 0
+hipError_t zero_seen_grad2d(const uint32_t* tiles, float* grad2d, int64_t n_slots, hipStream_t s);
 
 // binning (bin.hip)
 hipError_t launch_bin_prepare(const Projected& proj, uint32_t n_slots, uint32_t* dkeys_tmp, uint32_t* slots_tmp,

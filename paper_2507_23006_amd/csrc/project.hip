@@ -143,9 +143,11 @@ __global__ __launch_bounds__(256) void k_project_fwd(GaussPtrs gp, int64_t n, Vi
     }
     if (!vis_mask) return;
 
-    // view-dependent colour; coefficients are streamed (a second view's
-    // reads hit the cache) to keep register pressure low
+    // view-dependent colour; the Gaussian's coefficients are one contiguous
+    // 192-byte row, read as 16-byte vectors only by the lanes that need them
     const int nb = (opt.sh_degree + 1) * (opt.sh_degree + 1);
+    const int nq = (3 * nb + 3) >> 2;    // float4s that hold the used coefficients
+    const float4* shq = reinterpret_cast<const float4*>(gp.sh) + 12 * g;
     for (int v = 0; v < vt.n_views; ++v) {
         if (!(vis_mask & (1u << v))) continue;
         const ViewK& V = vt.v[v];
@@ -156,13 +158,19 @@ __global__ __launch_bounds__(256) void k_project_fwd(GaussPtrs gp, int64_t n, Vi
         const double inv = 1.0 / sqrt(e0 * e0 + e1 * e1 + e2 * e2);
         float Y[16];
         sh_eval_basis<float>((float)(e0 * inv), (float)(e1 * inv), (float)(e2 * inv), opt.sh_degree, Y);
+        float shv[48];
+#pragma unroll
+        for (int q = 0; q < 12; ++q) {
+            const float4 t = q < nq ? shq[q] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            shv[4 * q + 0] = t.x; shv[4 * q + 1] = t.y; shv[4 * q + 2] = t.z; shv[4 * q + 3] = t.w;
+        }
         float c[3] = {0.5f, 0.5f, 0.5f};
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
             if (k < nb) {
-                c[0] = fmaf(gp.sh[(int64_t)(3 * k + 0) * n + g], Y[k], c[0]);
-                c[1] = fmaf(gp.sh[(int64_t)(3 * k + 1) * n + g], Y[k], c[1]);
-                c[2] = fmaf(gp.sh[(int64_t)(3 * k + 2) * n + g], Y[k], c[2]);
+                c[0] = fmaf(shv[3 * k + 0], Y[k], c[0]);
+                c[1] = fmaf(shv[3 * k + 1], Y[k], c[1]);
+                c[2] = fmaf(shv[3 * k + 2], Y[k], c[2]);
             }
         }
         float4 r2 = out.rec[4 * slot + 2];

@@ -1,9 +1,15 @@
 // Backward of projection and colour -- gfx950.
 //
-// One thread per Gaussian, looping over the views of the launch: it reads
-// the Gaussian's parameters once, recomputes the projection in FP64 for each
-// view, chains that view's 2D gradients (mean2d, conic, opacity', colour,
-// depth) back to the parameters, and writes the sums once.  With
+// A workgroup owns a span of 1024 consecutive Gaussians.  It first finds
+// which of them some view sees (tiles > 0), writes the per-view statistics
+// and the zero gradients of the others with coalesced stores, and packs the
+// seen ones into an LDS list; then one thread per listed Gaussian reads its
+// parameters once, recomputes the projection in FP64 for each view that
+// sees it, chains that view's 2D gradients (mean2d, conic, opacity', colour,
+// depth) back to the parameters, and writes the sums once.  Only a small
+// fraction of a large scene is in view, so the compaction keeps the FP64
+// chain on full waves and the parameter reads on the Gaussians that need
+// them; 2D gradients of unseen slots are never read.  With
 // Sigma_2D = V V^T and V = (J W) M, M = R(q) diag(s), the covariance
 // gradient flows as dV = 2 G V, d(JW) = dV M^T, dM += (JW)^T dV; dM is
 // accumulated over views and pushed through R(q) and s once at the end.
@@ -48,36 +54,18 @@ __device__ __forceinline__ void sh_basis_grad(float x, float y, float z, int k, 
 }
 
 constexpr int kG2 = GS_GRAD2D_FLOATS;
+constexpr int kPB = 256;                  // threads per workgroup
+constexpr int kSpanPer = 4;               // Gaussians per thread in the scan
+constexpr int kSpan = kPB * kSpanPer;     // Gaussians per workgroup
 
-__global__ __launch_bounds__(256) void k_project_bwd(GaussPtrs gp, int64_t n, ViewTable vt, OptK opt, Projected proj,
-                                                     const float* __restrict__ grad2d, GradPtrs out,
-                                                     float* __restrict__ mean2d_norm, float* __restrict__ absgrad) {
-    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (g >= n) return;
+// full chain for one seen Gaussian g; vis = mask of the views that see it
+__device__ __forceinline__ void project_bwd_one(const GaussPtrs& gp, int64_t n, const ViewTable& vt,
+                                                const OptK& opt, const float* __restrict__ grad2d,
+                                                const GradPtrs& out, int64_t g, uint32_t vis) {
     const int nb = (opt.sh_degree + 1) * (opt.sh_degree + 1);
-
-    // per-view statistics, and which views see this Gaussian
-    uint32_t vis = 0;
-    for (int v = 0; v < vt.n_views; ++v) {
-        const int64_t slot = (int64_t)v * n + g;
-        const float* g2 = grad2d + slot * kG2;
-        const float dmx = g2[0], dmy = g2[1];
-        mean2d_norm[slot] = sqrtf(dmx * dmx + dmy * dmy);
-        if (absgrad) {
-            absgrad[2 * slot + 0] = g2[10];
-            absgrad[2 * slot + 1] = g2[11];
-        }
-        if (proj.tiles[slot]) vis |= 1u << v;
-    }
-    if (!vis) {
-        for (int c = 0; c < 3; ++c) out.means[c * n + g] = 0.0f;
-        for (int c = 0; c < 3; ++c) out.scales[c * n + g] = 0.0f;
-        for (int c = 0; c < 4; ++c) out.quats[c * n + g] = 0.0f;
-        out.opac[g] = 0.0f;
-        for (int k = 0; k < 48; ++k) out.sh[(int64_t)k * n + g] = 0.0f;
-        return;
-    }
-
+    const int nq = (3 * nb + 3) >> 2;    // float4s of a coefficient row in use
+    const float4* shq = reinterpret_cast<const float4*>(gp.sh) + 12 * g;
+    float4* dshq = reinterpret_cast<float4*>(out.sh) + 12 * g;
     const double mu0 = gp.means[g], mu1 = gp.means[n + g], mu2 = gp.means[2 * n + g];
     const double s0 = gp.scales[g], s1 = gp.scales[n + g], s2 = gp.scales[2 * n + g];
     const double q0 = gp.quats[g], q1 = gp.quats[n + g], q2 = gp.quats[2 * n + g], q3 = gp.quats[3 * n + g];
@@ -117,38 +105,47 @@ __global__ __launch_bounds__(256) void k_project_bwd(GaussPtrs gp, int64_t n, Vi
             const float d0 = (float)(e0d * inv), d1 = (float)(e1d * inv), d2 = (float)(e2d * inv);
             float Y[16];
             sh_eval_basis<float>(d0, d1, d2, opt.sh_degree, Y);
+            float shv[48];
+#pragma unroll
+            for (int q = 0; q < 12; ++q) {
+                const float4 t = q < nq ? shq[q] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                shv[4 * q + 0] = t.x; shv[4 * q + 1] = t.y; shv[4 * q + 2] = t.z; shv[4 * q + 3] = t.w;
+            }
             float raw0 = 0.5f, raw1 = 0.5f, raw2 = 0.5f;
+#pragma unroll
             for (int k = 0; k < 16; ++k) {
                 if (k < nb) {
-                    raw0 = fmaf(gp.sh[(int64_t)(3 * k + 0) * n + g], Y[k], raw0);
-                    raw1 = fmaf(gp.sh[(int64_t)(3 * k + 1) * n + g], Y[k], raw1);
-                    raw2 = fmaf(gp.sh[(int64_t)(3 * k + 2) * n + g], Y[k], raw2);
+                    raw0 = fmaf(shv[3 * k + 0], Y[k], raw0);
+                    raw1 = fmaf(shv[3 * k + 1], Y[k], raw1);
+                    raw2 = fmaf(shv[3 * k + 2], Y[k], raw2);
                 }
             }
             const float gr0 = raw0 < 0.0f ? 0.0f : g2[6];
             const float gr1 = raw1 < 0.0f ? 0.0f : g2[7];
             const float gr2 = raw2 < 0.0f ? 0.0f : g2[8];
             float e0 = 0.0f, e1 = 0.0f, e2 = 0.0f;
+            float dsh[48];
+#pragma unroll
             for (int k = 0; k < 16; ++k) {
-                float* o0 = out.sh + (int64_t)(3 * k + 0) * n + g;
-                float* o1 = out.sh + (int64_t)(3 * k + 1) * n + g;
-                float* o2 = out.sh + (int64_t)(3 * k + 2) * n + g;
-                const float v0 = k < nb ? gr0 * Y[k] : 0.0f;
-                const float v1 = k < nb ? gr1 * Y[k] : 0.0f;
-                const float v2 = k < nb ? gr2 * Y[k] : 0.0f;
-                if (first) {
-                    *o0 = v0; *o1 = v1; *o2 = v2;
-                } else if (k < nb) {
-                    *o0 += v0; *o1 += v1; *o2 += v2;
-                }
+                const float yk = k < nb ? Y[k] : 0.0f;
+                dsh[3 * k + 0] = gr0 * yk;
+                dsh[3 * k + 1] = gr1 * yk;
+                dsh[3 * k + 2] = gr2 * yk;
                 if (k > 0 && k < nb) {
-                    const float gk = gr0 * gp.sh[(int64_t)(3 * k + 0) * n + g] +
-                                     gr1 * gp.sh[(int64_t)(3 * k + 1) * n + g] +
-                                     gr2 * gp.sh[(int64_t)(3 * k + 2) * n + g];
+                    const float gk = gr0 * shv[3 * k + 0] + gr1 * shv[3 * k + 1] + gr2 * shv[3 * k + 2];
                     float bx, by, bz;
                     sh_basis_grad(d0, d1, d2, k, bx, by, bz);
                     e0 = fmaf(gk, bx, e0); e1 = fmaf(gk, by, e1); e2 = fmaf(gk, bz, e2);
                 }
+            }
+#pragma unroll
+            for (int q = 0; q < 12; ++q) {
+                float4 t = make_float4(dsh[4 * q + 0], dsh[4 * q + 1], dsh[4 * q + 2], dsh[4 * q + 3]);
+                if (!first && q < nq) {
+                    const float4 p = dshq[q];
+                    t.x += p.x; t.y += p.y; t.z += p.z; t.w += p.w;
+                }
+                if (first || q < nq) dshq[q] = t;
             }
             first = false;
             const double dd = (double)e0 * d0 + (double)e1 * d1 + (double)e2 * d2;
@@ -263,13 +260,79 @@ __global__ __launch_bounds__(256) void k_project_bwd(GaussPtrs gp, int64_t n, Vi
     out.opac[g] = (float)dop;
 }
 
+
+__global__ __launch_bounds__(kPB) void k_project_bwd(GaussPtrs gp, int64_t n, ViewTable vt, OptK opt,
+                                                     Projected proj, const float* __restrict__ grad2d, GradPtrs out,
+                                                     float* __restrict__ mean2d_norm, float* __restrict__ absgrad) {
+    __shared__ uint32_t s_list[kSpan];     // local index | view mask << 16
+    __shared__ uint8_t s_seen[kSpan];
+    __shared__ uint32_t s_count;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int64_t g0 = (int64_t)blockIdx.x * kSpan;
+    if (tid == 0) s_count = 0;
+    __syncthreads();
+
+    // pass 1: statistics, visibility, zeros of unseen Gaussians, compaction
+    for (int i = 0; i < kSpanPer; ++i) {
+        const int loc = i * kPB + tid;
+        const int64_t g = g0 + loc;
+        uint32_t vis = 0;
+        if (g < n) {
+            for (int v = 0; v < vt.n_views; ++v) {
+                const int64_t slot = (int64_t)v * n + g;
+                const bool seen = proj.tiles[slot] != 0;
+                float nrm = 0.0f, ax = 0.0f, ay = 0.0f;
+                if (seen) {
+                    const float* g2 = grad2d + slot * kG2;
+                    const float dmx = g2[0], dmy = g2[1];
+                    nrm = sqrtf(dmx * dmx + dmy * dmy);
+                    ax = g2[10];
+                    ay = g2[11];
+                    vis |= 1u << v;
+                }
+                mean2d_norm[slot] = nrm;
+                if (absgrad) reinterpret_cast<float2*>(absgrad)[slot] = make_float2(ax, ay);
+            }
+            if (!vis) {
+                for (int c = 0; c < 3; ++c) out.means[c * n + g] = 0.0f;
+                for (int c = 0; c < 3; ++c) out.scales[c * n + g] = 0.0f;
+                for (int c = 0; c < 4; ++c) out.quats[c * n + g] = 0.0f;
+                out.opac[g] = 0.0f;
+            }
+        }
+        s_seen[loc] = vis ? 1 : 0;
+        const uint64_t m = __ballot(vis != 0);
+        if (m) {
+            const int below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
+            uint32_t base = 0;
+            if (lane == 0) base = atomicAdd(&s_count, (uint32_t)__popcll(m));
+            base = __shfl(base, 0);
+            if (vis) s_list[base + below] = (uint32_t)loc | (vis << 16);
+        }
+    }
+    __syncthreads();
+
+    // zero coefficient rows of unseen Gaussians: coalesced 16-byte stores
+    const int64_t rows = n - g0 < kSpan ? n - g0 : kSpan;
+    float4* dsh = reinterpret_cast<float4*>(out.sh) + 12 * g0;
+    for (int q = tid; q < 12 * rows; q += kPB)
+        if (!s_seen[q / 12]) dsh[q] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+
+    // pass 2: the chain, one thread per seen Gaussian
+    const uint32_t cnt = s_count;
+    for (uint32_t j = tid; j < cnt; j += kPB) {
+        const uint32_t e = s_list[j];
+        project_bwd_one(gp, n, vt, opt, grad2d, out, g0 + (e & 0xFFFFu), e >> 16);
+    }
+}
+
 }  // namespace
 
 hipError_t launch_project_bwd(const GaussPtrs& g, int64_t n, const ViewTable& vt, const OptK& opt,
                               const Projected& proj, const float* grad2d, const GradPtrs& out, float* mean2d_norm,
                               float* absgrad, hipStream_t s) {
-    const unsigned blocks = (unsigned)((n + 255) / 256);
-    hipLaunchKernelGGL(k_project_bwd, dim3(blocks), dim3(256), 0, s, g, n, vt, opt, proj, grad2d, out, mean2d_norm,
+    const unsigned blocks = (unsigned)((n + kSpan - 1) / kSpan);
+    hipLaunchKernelGGL(k_project_bwd, dim3(blocks), dim3(kPB), 0, s, g, n, vt, opt, proj, grad2d, out, mean2d_norm,
                        absgrad);
     return hipGetLastError();
 }

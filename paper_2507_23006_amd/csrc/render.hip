@@ -203,7 +203,7 @@ __global__ __launch_bounds__(256) void k_render_count(const float4* __restrict__
     WaveStage& st = stage[wave];
     const uint2 rg = ranges[tile];
     float T = 1.0f;
-    int count = 0;
+    int count = 0, count_last = 0;
     bool alive = pc.inside;
     for (uint32_t j0 = rg.x; j0 < rg.y; j0 += kChunk) {
         if (__ballot(alive) == 0) break;
@@ -222,12 +222,13 @@ __global__ __launch_bounds__(256) void k_render_count(const float4* __restrict__
             const bool keep = alive && e.keep;
             const bool stop = keep && Tn < kTMin;
             count += (alive && covers) ? 1 : 0;
+            count_last = (keep && !stop) ? count : count_last;
             T = (keep && !stop) ? Tn : T;
             alive = alive && !stop;
         }
         __builtin_amdgcn_wave_barrier();
     }
-    if (pc.inside) n_eval[pc.pix] = count;
+    if (pc.inside) reinterpret_cast<int2*>(n_eval)[pc.pix] = make_int2(count, count_last);
 }
 
 // sum over the 64 lanes; lane 63 holds the result
@@ -341,6 +342,18 @@ __global__ __launch_bounds__(256) void k_render_bwd(const float4* __restrict__ r
     }
 }
 
+// 2D-gradient rows of the slots that some tile lists (tiles > 0): the only
+// rows the compositing backward accumulates into and the only ones read
+__global__ __launch_bounds__(256) void k_zero_seen_rows(const uint32_t* __restrict__ tiles, float4* __restrict__ grad2d,
+                                                        int64_t n_slots) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n_slots || tiles[i] == 0) return;
+    const float4 z = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    grad2d[3 * i + 0] = z;
+    grad2d[3 * i + 1] = z;
+    grad2d[3 * i + 2] = z;
+}
+
 }  // namespace
 
 hipError_t launch_render_fwd(const Projected& proj, const uint32_t* pair_vals, const uint2* ranges,
@@ -366,6 +379,13 @@ hipError_t launch_render_bwd(const Projected& proj, const uint32_t* pair_vals, c
     if (vt.total_tiles <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_render_bwd, dim3(vt.total_tiles), dim3(256), 0, s, proj.rec, pair_vals, ranges, vt, opt,
                        T_final, last, d_rgb, d_depth, d_alpha, grad2d);
+    return hipGetLastError();
+}
+
+hipError_t zero_seen_grad2d(const uint32_t* tiles, float* grad2d, int64_t n_slots, hipStream_t s) {
+    const unsigned blocks = (unsigned)((n_slots + 255) / 256);
+    hipLaunchKernelGGL(k_zero_seen_rows, dim3(blocks), dim3(256), 0, s, tiles, reinterpret_cast<float4*>(grad2d),
+                       n_slots);
     return hipGetLastError();
 }
 

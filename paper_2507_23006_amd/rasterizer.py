@@ -50,7 +50,7 @@ def check_params(means, scales, quats, opacities, sh) -> int:
     _check_param(scales, "scales", (3, n))
     _check_param(quats, "quats", (4, n))
     _check_param(opacities, "opacities", (n,))
-    _check_param(sh, "sh", (16, 3, n))
+    _check_param(sh, "sh", (n, 16, 3))
     return n
 
 
@@ -169,10 +169,11 @@ def render_fwd(proj: Projected, pair_vals, ranges, cams, opts: RenderOptions) ->
 
 
 def render_count(proj: Projected, pair_vals, ranges, cams) -> torch.Tensor:
-    """Per-pixel number of list entries compositing evaluates (measurement)."""
+    """Per-pixel numbers of list entries the forward [:, 0] and the backward
+    [:, 1] compositing evaluate (measurement)."""
     lib = L.load()
     _, npx = views_extent(cams)
-    out = torch.empty((npx,), dtype=torch.int32, device=proj.rec.device)
+    out = torch.empty((npx, 2), dtype=torch.int32, device=proj.rec.device)
     L.check(lib.gs_render_count(C.byref(proj.c()), _ptr(pair_vals), _ptr(ranges), L.make_cameras(cams), len(cams),
                                 _ptr(out), _stream()))
     return out

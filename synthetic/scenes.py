@@ -65,6 +65,13 @@ class Scene:
     def n(self) -> int:
         return int(self.opacities.shape[0])
 
+    def param_arrays(self) -> list:
+        """The five parameter arrays as contiguous float32 in the layout the
+        rasterizer library takes: the colour coefficients as one row per
+        Gaussian, (N, 16, 3); the others as stored."""
+        return [np.ascontiguousarray(a, dtype=np.float32)
+                for a in (self.means, self.scales, self.quats, self.opacities, self.sh.transpose(2, 0, 1))]
+
     def subset(self, idx: np.ndarray) -> "Scene":
         return Scene(np.ascontiguousarray(self.means[:, idx]),
                      np.ascontiguousarray(self.scales[:, idx]),

@@ -12,12 +12,20 @@ LOG2E = 1.0 / math.log(2.0)
 
 
 def to_dev(scene, device="cuda:0", requires_grad=False):
-    ts = [torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(device)
-          for a in (scene.means, scene.scales, scene.quats, scene.opacities, scene.sh)]
+    ts = [torch.from_numpy(a).to(device) for a in scene.param_arrays()]
     if requires_grad:
         for t in ts:
             t.requires_grad_(True)
     return ts
+
+
+def grads_oracle_layout(params):
+    """Parameter gradients of GPU tensors as float64 arrays in the oracle's
+    layouts (the colour coefficients back to (16, 3, N))."""
+    g = {k: p.grad.cpu().numpy().astype(np.float64) for k, p in
+         zip(("means", "scales", "quats", "opacities", "sh"), params)}
+    g["sh"] = np.ascontiguousarray(g["sh"].transpose(1, 2, 0))
+    return g
 
 
 def decode_records(rec: np.ndarray):

@@ -20,7 +20,8 @@ import torch
 
 import oracle
 import synthetic as S
-from gpu_util import decode_records, decode_rect, gpu_forward, oracle_opt, to_dev, view_images
+from gpu_util import (decode_records, decode_rect, gpu_forward, grads_oracle_layout, oracle_opt, to_dev,
+                      view_images)
 
 pytestmark = pytest.mark.gpu
 
@@ -146,6 +147,60 @@ def test_forward_end_to_end(gpu_lib, case):
         assert guarded <= max(2, 1e-3 * c.n_pixels), guarded
 
 
+@pytest.mark.parametrize("case", ["c1", "ragged_aa"])
+def test_alpha_box_covers_every_contribution(gpu_lib, case):
+    """Each record's (hx, hy) box must contain every pixel centre where the
+    entry's alpha o' G' reaches the skip threshold 1/255 (FP64 on the decoded
+    record, with a relative slack of 1e-6 below the threshold); compositing
+    leaves the entries outside the box unevaluated."""
+    make, cams, od = CASES[case]
+    scene = make()
+    opts = _opts(gpu_lib, od)
+    _, proj, pairs, ranges, P, _ = gpu_forward(gpu_lib, scene, cams, opts)
+    rec = proj.rec.cpu().numpy()
+    mean2d, conic, opac, _, _ = decode_records(rec)
+    hx, hy = rec[:, 12].astype(np.float64), rec[:, 13].astype(np.float64)
+    pv = pairs.cpu().numpy().view(np.uint32)[:P].astype(np.int64)
+    rg = ranges.cpu().numpy().view(np.uint32).astype(np.int64)
+    cam = cams[0]
+    ys, xs = np.mgrid[0:16, 0:16]
+    checked = 0
+    for t in range(cam.n_tiles):
+        sl = pv[rg[t, 0]:rg[t, 1]]
+        if len(sl) == 0:
+            continue
+        px = (t % cam.tiles_x) * 16 + xs.ravel() + 0.5
+        py = (t // cam.tiles_x) * 16 + ys.ravel() + 0.5
+        inside = (px < cam.width) & (py < cam.height)
+        dx = px[None, :] - mean2d[sl, 0:1]
+        dy = py[None, :] - mean2d[sl, 1:2]
+        A, B, C = conic[sl, 0:1], conic[sl, 1:2], conic[sl, 2:3]
+        power = -0.5 * (A * dx * dx + C * dy * dy) - B * dx * dy
+        alpha = opac[sl, None] * np.exp(np.minimum(power, 0.0))
+        hot = (alpha >= (1.0 - 1e-6) / 255.0) & (power <= 0) & inside[None, :]
+        covered = (np.abs(dx) <= hx[sl, None]) & (np.abs(dy) <= hy[sl, None])
+        assert np.all(covered[hot]), (t, int((hot & ~covered).sum()))
+        checked += int(hot.sum())
+    assert checked > 0
+
+
+def test_render_count_is_consistent(gpu_lib):
+    make, cams, od = CASES["ragged_aa"]
+    scene = make()
+    opts = _opts(gpu_lib, od)
+    _, proj, pairs, ranges, P, out = gpu_forward(gpu_lib, scene, cams, opts)
+    cnt = gpu_lib.render_count(proj, pairs, ranges, cams).cpu().numpy().astype(np.int64)
+    last = out["last"].cpu().numpy().astype(np.int64)
+    cam = cams[0]
+    rg = ranges.cpu().numpy().view(np.uint32).astype(np.int64)
+    py, px = np.divmod(np.arange(cam.n_pixels), cam.width)
+    list_len = (rg[:, 1] - rg[:, 0])[(py // 16) * cam.tiles_x + px // 16]
+    assert np.all(cnt[:, 1] <= cnt[:, 0]) and np.all(cnt[:, 0] <= list_len)
+    assert np.all(cnt[:, 1] <= last)
+    assert np.all(cnt[last > 0, 1] >= 1) and np.all(cnt[last == 0, 1] == 0)
+    assert cnt[:, 1].sum() > 0
+
+
 def _linear_loss_grads(gpu_lib, scene, cams, opts, seed=7):
     ws = [S.linear_loss_weights(c.height, c.width, seed=seed + v) for v, c in enumerate(cams)]
     params = to_dev(scene, requires_grad=True)
@@ -157,9 +212,7 @@ def _linear_loss_grads(gpu_lib, scene, cams, opts, seed=7):
     loss = (w_rgb * rgb).sum() + (w_d * depth).sum() + (w_a * alpha).sum()
     loss.backward()
     torch.cuda.synchronize()
-    g = {k: p.grad.cpu().numpy().astype(np.float64) for k, p in
-         zip(("means", "scales", "quats", "opacities", "sh"), params)}
-    return g, ws, stats
+    return grads_oracle_layout(params), ws, stats
 
 
 def _compare_grads(g, ref, groups=("means", "scales", "quats", "opacities", "sh")):
