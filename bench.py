@@ -47,7 +47,25 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-crop", type=int, default=16, help="oracle baseline renders 1/crop of the pixels")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving trace")
+    ap.add_argument("--serve-requests", type=int, default=2000, help="requests of the serving trace")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only copy a MIB-MiB device buffer 3 times (reference kernel for HBM byte counters)")
     return ap.parse_args()
+
+
+def copy_probe(mib):
+    """A plain device-to-device copy of known size: what the HBM byte counters
+    read for it scales the counters of the rasterizer's kernels."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4, "copies": 3}))
 
 
 def n_tiles_of(n_pix):
@@ -57,16 +75,16 @@ def n_tiles_of(n_pix):
 def stage_bytes(n, n_front, n_vis, n_pairs, n_pix, n_views=1):
     """Algorithmic HBM bytes of each memory-bound stage for one launch."""
     return {
-        # means of all (12) + scales, quats, opacity of those in front (32) + SH of
-        # visible (192); writes: tiles + depth key of all (8) + record 48 + rect 8 of visible
-        "project": 12 * n + 32 * n_front + 192 * n_vis + 8 * n * n_views + 56 * n_vis,
+        # means of all (12) + scales, quats, opacity of those in front (32) + SH row of
+        # visible (192); writes: tiles + depth key of all (8) + record 64 + rect 8 of visible
+        "project": 12 * n + 32 * n_front + 192 * n_vis + 8 * n * n_views + 72 * n_vis,
         # depth sort: 4 passes x (read key 4 + read key+val 8 + write 8) on all slots,
         # gather + scan (4 + 8 + 4 + 8), emission (8 per pair + 12 per visible),
         # tile sort passes x (4 + 8 + 8) per pair, ranges (4 per pair)
         "bin_sort": (4 * 20 * n * n_views + 24 * n * n_views + 8 * n_pairs + 12 * n_vis
                      + max(1, math.ceil(math.log2(max(2, n_tiles_of(n_pix))) / 8)) * 20 * n_pairs + 4 * n_pairs),
-        # params of visible 236 + 2D grads 48 + outputs 236 + norm 4
-        "project_bwd": 12 * n + 4 * n + (236 + 48) * n_vis + 236 * n + 4 * n,
+        # tiles of all (4); params 236 + 2D grads 48 of visible; gradients 236 + norm 4 of all
+        "project_bwd": 4 * n * n_views + (236 + 48) * n_vis + 236 * n + 4 * n * n_views,
     }
 
 
@@ -77,6 +95,9 @@ def main():
               "How the path would shard is described in DESIGN.md.", file=sys.stderr)
         sys.exit(2)
 
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
     import torch
     import paper_2507_23006_amd as gs
     import synthetic as S
@@ -181,6 +202,11 @@ def main():
             roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None}
 
+    serve = None
+    if not args.no_serve:
+        del params, stats, proj, pv, rg, out
+        serve = serve_bench(gs, S, torch, scene, opts, args.serve_requests)
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(scene, cam, args.cpu_crop)
@@ -204,14 +230,71 @@ def main():
                    "n_gaussians": scene.n, "width": W, "height": H, "views": 1},
         "render_mpix_s": round(npix / (ms_fwd * 1e-3) / 1e6, 1),
         "render_ms": round(ms_fwd, 3),
-        "serve_p50_ms": None,
-        "serve_p99_ms": None,
+        "serve_p50_ms": serve["served"]["p50_ms"] if serve else None,
+        "serve_p99_ms": serve["served"]["p99_ms"] if serve else None,
+        "serve": serve,
         "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
         "workload_stats": {"visible": n_vis, "in_front": n_front, "pairs": P, "evals_fwd": e_fwd, "evals_bwd": e_bwd},
         "roofline": roof,
         "cpu_baseline": cpu,
     }
     print(json.dumps(rec), flush=True)
+
+
+def serve_bench(gs, S, torch, fine, opts, n_requests):
+    """Open-loop serving trace on the level-of-detail stand-in of the urban
+    block: levels of 1M, 3M and 6M Gaussians resident in HBM, 30 m render-time
+    partitions, thresholds (30, 60, inf) m; Poisson arrivals at 150 req/s,
+    resolutions 640x360 / 1280x720 / 1920x1080 and budgets 1M / 3M / 6M
+    drawn uniformly.  Run twice on the same trace: "plain" (one request per
+    launch, one stream, FIFO) and "served" (continuous batching of up to 8
+    views, two worker streams).  Latency = completion - scheduled arrival."""
+    t_gen = time.time()
+    lod = S.lod_scene_c4(fine)
+    sc, offsets = lod.combined()
+    params = [torch.from_numpy(a).cuda() for a in sc.param_arrays()]
+    table = gs.LodTable(lod.part_min, lod.part_max, offsets, lod.counts, lod.thresholds,
+                        3.0 * float(sc.scales.max()))
+    trace = S.serve_trace_c4(n_requests=n_requests)
+    npx = [r["camera"].width * r["camera"].height for r in trace]
+    flat = torch.empty(3 * sum(npx), dtype=torch.float32, device="cuda")
+    outs, off = [], 0
+    for r, k in zip(trace, npx):
+        outs.append(flat[3 * off:3 * (off + k)].view(r["camera"].height, r["camera"].width, 3))
+        off += k
+    print(f"# serving scene ready in {time.time() - t_gen:.1f} s ({sc.n} Gaussians in {len(lod.levels)} levels, "
+          f"{lod.counts.shape[1]} partitions)", file=sys.stderr, flush=True)
+    modes = {
+        "plain": gs.ServeConfig(max_views_per_batch=1, n_streams=1, slot_capacity=6_000_000,
+                                pair_capacity=48_000_000, pixel_capacity=1 << 21, queue_capacity=n_requests),
+        "served": gs.ServeConfig(max_views_per_batch=8, n_streams=2, slot_capacity=24_000_000,
+                                 pair_capacity=96_000_000, pixel_capacity=1 << 24, queue_capacity=n_requests),
+    }
+    res = {}
+    for name, cfg in modes.items():
+        srv = gs.Server(params, table, opts, cfg)
+        t0 = srv.now() + 0.5
+        for r, o in zip(trace, outs):
+            srv.submit(r["camera"], r["budget"], o, t0 + r["t"])
+        n_done, n_fail, views, t_print = 0, 0, 0, time.time()
+        while n_done < len(trace):
+            for c in srv.poll(max_items=512, timeout_us=200_000):
+                n_done += 1
+                n_fail += c["status"] != 0
+            if time.time() - t_print > 5.0:
+                print(f"# {name}: {n_done}/{len(trace)} served", file=sys.stderr, flush=True)
+                t_print = time.time()
+        st = srv.stats()
+        srv.close()
+        res[name] = {"p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
+                     "mean_ms": round(st["mean_ms"], 3), "max_ms": round(st["max_ms"], 3),
+                     "req_per_s": round(st["req_per_s"], 2), "mpix_per_s": round(st["mpix_per_s"], 1),
+                     "mean_batch_views": round(st["mean_batch_views"], 3), "batches": st["batches"],
+                     "completed": st["completed"], "failed": st["failed"]}
+        print(f"# {name}: {res[name]}", file=sys.stderr, flush=True)
+    res["trace"] = (f"{len(trace)} requests, Poisson {len(trace) / trace[-1]['t']:.0f} req/s over "
+                    f"{trace[-1]['t']:.1f} s, offered {sum(npx) / trace[-1]['t'] / 1e6:.0f} Mpix/s")
+    return res
 
 
 def _ev(torch):

@@ -212,6 +212,111 @@ int gs_project_bwd(const gs_gaussians *g, const gs_camera *cams, int32_t n_views
  * unwritten) -- for inspection and tests. */
 const float *gs_render_bwd_grad2d(void *ws);
 
+/* ------------------------------------------------------------------------
+ * Level-of-detail selection and serving (§3.4.2 "Detail Level Selection",
+ * Fig. 3b; distance thresholds as in Tab. 13).
+ *
+ * A level-of-detail scene holds levels 1 (coarsest) .. L (finest) of every
+ * render-time partition.  All levels live in ONE set of parameter arrays
+ * (gs_gaussians with n = the sum of all levels' sizes); the Gaussians of
+ * (level l, partition p) are the contiguous range
+ * [offsets[(l-1) * P + p], + counts[(l-1) * P + p]).
+ * ---------------------------------------------------------------------- */
+#define GS_MAX_LEVELS 8
+
+typedef struct gs_lod_table {
+    int32_t n_levels;            /* L, 1..GS_MAX_LEVELS */
+    int32_t n_parts;             /* P >= 1 */
+    const float *part_min;       /* [P][3] world AABB of the partition (host memory) */
+    const float *part_max;       /* [P][3] */
+    const int64_t *offsets;      /* [L][P] first Gaussian of (level, partition) (host memory) */
+    const int64_t *counts;       /* [L][P] its number of Gaussians */
+    /* thresholds[k]: largest partition-camera distance at which level L - k
+     * is used (k = 0 .. L-1, increasing; the last is normally +inf) */
+    float thresholds[GS_MAX_LEVELS];
+    float margin;                /* metres added on every side of each AABB for the view test */
+} gs_lod_table;
+
+/* Host-only.  Chooses a level per partition for one camera:
+ *   - a partition is culled (level 0) when its AABB grown by `margin` lies
+ *     entirely outside one of the five planes of the view frustum (near
+ *     plane, and the four sides through the image border widened by 15 % of
+ *     the image size per side, as in the projection's Jacobian clamp);
+ *   - otherwise its distance d is the distance from the camera centre to the
+ *     nearest point of the (un-grown) AABB, 0 inside, and its level is the
+ *     finest level L - k with d <= thresholds[k] (level 1 beyond all);
+ *   - budget: while the selected Gaussians exceed `budget`, the farthest
+ *     partition among those at the finest level in use above 1 drops one
+ *     level (ties: lower partition id first); once every selected partition
+ *     is at level 1, the farthest ones are dropped (level 0).
+ * Writes level [P] and *total (selected Gaussians).  GS_ERR_BUDGET when the
+ * budget cannot hold even the nearest visible partition at level 1;
+ * GS_ERR_INVALID_ARG for a malformed table or camera. */
+int gs_lod_select(const gs_lod_table *table, const gs_camera *cam, int64_t budget, int32_t *level,
+                  int64_t *total);
+
+/* Serving: a native request queue with worker threads, one HIP stream and
+ * one set of device buffers per worker (allocated by gs_serve_create, the
+ * only allocating call).  Each request is a camera, a Gaussian budget and a
+ * device output image [H][W][3] float32 owned by the caller.  Requests wait
+ * until their arrival time; a free worker takes every arrived request at the
+ * head of the queue, in order, while the batch stays within
+ * max_views_per_batch and the worker's slot, pixel and tile capacities
+ * (admission), projects each view's selected segments, bins all views of the
+ * batch in one sort and composites them in one multi-view launch, then
+ * copies each image to its request's output.  A batch whose pairs overflow
+ * pair_capacity is split in halves and retried; a single request that still
+ * overflows completes with GS_ERR_CAPACITY.  The rendered image is the
+ * image gs_render_fwd gives for the selected Gaussians alone, whatever the
+ * batch. */
+typedef struct gs_serve_config {
+    int32_t max_views_per_batch;   /* 1..GS_MAX_VIEWS; 1 = one request per launch */
+    int32_t n_streams;             /* worker threads / HIP streams, 1..8 */
+    int64_t slot_capacity;         /* selected Gaussians per batch, summed over its views */
+    int64_t pair_capacity;         /* (tile, Gaussian) pairs per batch */
+    int64_t pixel_capacity;        /* pixels per batch */
+    int32_t queue_capacity;        /* pending requests; gs_serve_submit returns GS_EAGAIN beyond */
+} gs_serve_config;
+
+typedef struct gs_completion {
+    uint64_t ticket;
+    int32_t status;                /* GS_OK or a GS_ERR_* code */
+    int32_t batch_views;           /* views in the batch that rendered it */
+    int64_t n_gaussians;           /* Gaussians selected for the request */
+    int64_t n_pairs;               /* pairs of the whole batch */
+    double t_arrival, t_start, t_done;   /* seconds on the server clock (gs_serve_now) */
+} gs_completion;
+
+typedef struct gs_serve_stats {
+    int64_t submitted, completed, failed, batches;
+    double mean_batch_views;
+    double p50_ms, p99_ms, mean_ms, max_ms;   /* latency = t_done - t_arrival, completed requests */
+    double span_s;                 /* first arrival to last completion */
+    double req_per_s, mpix_per_s;  /* over span_s */
+} gs_serve_stats;
+
+typedef struct gs_server gs_server;
+
+/* `scene` and `table` (with the arrays they point to) are copied: device
+ * parameter pointers must stay valid until gs_serve_destroy.  Worker
+ * threads use device `device`. */
+int gs_serve_create(const gs_gaussians *scene, const gs_lod_table *table, const gs_options *opt,
+                    const gs_serve_config *cfg, int32_t device, gs_server **out);
+/* Seconds since the server was created (the clock of arrival times). */
+double gs_serve_now(const gs_server *srv);
+/* Queues one request arriving at t_arrival (server clock; it is not started
+ * before).  Selection errors (GS_ERR_BUDGET, GS_ERR_INVALID_ARG) and
+ * requests larger than one batch's capacities (GS_ERR_CAPACITY) are returned
+ * here; GS_EAGAIN when the queue is full. */
+int gs_serve_submit(gs_server *srv, const gs_camera *cam, int64_t budget, float *out_rgb, double t_arrival,
+                    uint64_t *ticket);
+/* Waits up to timeout_us for completions and returns up to max of them. */
+int gs_serve_poll(gs_server *srv, gs_completion *done, int32_t max, int32_t timeout_us, int32_t *n_done);
+int gs_serve_stats_get(gs_server *srv, gs_serve_stats *out);
+/* Stops the workers after their current batch; requests still queued are
+ * dropped.  Frees the server's device buffers. */
+int gs_serve_destroy(gs_server *srv);
+
 #ifdef __cplusplus
 }
 #endif

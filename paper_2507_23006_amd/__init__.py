@@ -2,12 +2,14 @@
 
 The hot path -- projection, SH colour, tile binning and sort, compositing of
 colour and depth, and the backward -- runs in the HIP kernels of libgs.so
-behind the C ABI of include/gs.h.  This package only marshals torch tensors
+behind the C ABI of include/gs.h, as do the level-of-detail selection and
+the batching server for rendering requests.  This package only marshals torch tensors
 (device memory, streams) into that ABI; it has no CPU fallback.
 """
 from ._lib import GsError, load, LIB_PATH
 from .rasterizer import (RenderOptions, RenderStats, Projected, Workspace, GsRasterize, rasterize, project,
                          bin_sort, render_fwd, render_bwd, split_views, views_extent, grad2d_view, check_params, set_stage_hook, render_count)
+from .serving import LodTable, lod_select, ServeConfig, Server
 
 
 def build(verbose: bool = False) -> str:
@@ -17,4 +19,5 @@ def build(verbose: bool = False) -> str:
 
 __all__ = ["GsError", "load", "LIB_PATH", "RenderOptions", "RenderStats", "Projected", "Workspace", "GsRasterize",
            "rasterize", "project", "bin_sort", "render_fwd", "render_bwd", "split_views", "views_extent",
-           "grad2d_view", "check_params", "set_stage_hook", "render_count", "build"]
+           "grad2d_view", "check_params", "set_stage_hook", "render_count", "build", "LodTable", "lod_select",
+           "ServeConfig", "Server"]

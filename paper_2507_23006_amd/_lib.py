@@ -56,6 +56,33 @@ class GsProjected(C.Structure):
     _fields_ = [("rec", C.c_void_p), ("rect", C.c_void_p), ("tiles", C.c_void_p), ("depth_key", C.c_void_p)]
 
 
+GS_MAX_LEVELS = 8
+
+
+class GsLodTable(C.Structure):
+    _fields_ = [("n_levels", C.c_int32), ("n_parts", C.c_int32), ("part_min", C.c_void_p),
+                ("part_max", C.c_void_p), ("offsets", C.c_void_p), ("counts", C.c_void_p),
+                ("thresholds", C.c_float * GS_MAX_LEVELS), ("margin", C.c_float)]
+
+
+class GsServeConfig(C.Structure):
+    _fields_ = [("max_views_per_batch", C.c_int32), ("n_streams", C.c_int32), ("slot_capacity", C.c_int64),
+                ("pair_capacity", C.c_int64), ("pixel_capacity", C.c_int64), ("queue_capacity", C.c_int32)]
+
+
+class GsCompletion(C.Structure):
+    _fields_ = [("ticket", C.c_uint64), ("status", C.c_int32), ("batch_views", C.c_int32),
+                ("n_gaussians", C.c_int64), ("n_pairs", C.c_int64), ("t_arrival", C.c_double),
+                ("t_start", C.c_double), ("t_done", C.c_double)]
+
+
+class GsServeStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64), ("batches", C.c_int64),
+                ("mean_batch_views", C.c_double), ("p50_ms", C.c_double), ("p99_ms", C.c_double),
+                ("mean_ms", C.c_double), ("max_ms", C.c_double), ("span_s", C.c_double),
+                ("req_per_s", C.c_double), ("mpix_per_s", C.c_double)]
+
+
 # exported symbols and their ctypes signatures
 _P, _I32, _I64, _SZ = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
 SIGNATURES = {
@@ -72,6 +99,13 @@ SIGNATURES = {
     "gs_composite_bwd": (C.c_int, [_P, _P, _P, _P, _I32, _P, _P, _P, _P, _P, _P, _I64, _P, _P]),
     "gs_project_bwd": (C.c_int, [_P, _P, _I32, _P, _P, _P, _P, _P, _P, _P]),
     "gs_render_count": (C.c_int, [_P, _P, _P, _P, _I32, _P, _P]),
+    "gs_lod_select": (C.c_int, [_P, _P, _I64, _P, _P]),
+    "gs_serve_create": (C.c_int, [_P, _P, _P, _P, _I32, _P]),
+    "gs_serve_now": (C.c_double, [_P]),
+    "gs_serve_submit": (C.c_int, [_P, _P, _I64, _P, C.c_double, _P]),
+    "gs_serve_poll": (C.c_int, [_P, _P, _I32, _I32, _P]),
+    "gs_serve_stats_get": (C.c_int, [_P, _P]),
+    "gs_serve_destroy": (C.c_int, [_P]),
 }
 
 _lock = threading.Lock()

@@ -10,12 +10,16 @@
 
 #include "gs.h"
 #include "gs_internal.h"
+#include "host.h"
 
 namespace gs {
+namespace host {
 
 namespace {
-
 thread_local char g_err[512] = "";
+}  // namespace
+
+const char* last_error() { return g_err; }
 
 int fail(int code, const char* fmt, ...) {
     va_list ap;
@@ -24,35 +28,6 @@ int fail(int code, const char* fmt, ...) {
     va_end(ap);
     return code;
 }
-
-#define GS_HIP(expr)                                                                              \
-    do {                                                                                          \
-        hipError_t e_ = (expr);                                                                   \
-        if (e_ != hipSuccess) return fail(GS_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_)); \
-    } while (0)
-
-#define GS_REQUIRE(cond, ...)                                 \
-    do {                                                      \
-        if (!(cond)) return fail(GS_ERR_INVALID_ARG, __VA_ARGS__); \
-    } while (0)
-
-constexpr size_t kAlign = 256;
-
-size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
-
-// carves aligned regions out of a workspace; with base == nullptr it only
-// measures
-struct Carver {
-    char* base;
-    size_t off = 0;
-    explicit Carver(void* b) : base(static_cast<char*>(b)) {}
-    template <class T>
-    T* take(size_t count) {
-        T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
-        off = align_up(off + count * sizeof(T));
-        return p;
-    }
-};
 
 int build_views(const gs_camera* cams, int32_t n_views, ViewTable* vt) {
     GS_REQUIRE(cams != nullptr, "cams is NULL");
@@ -106,6 +81,8 @@ int build_opt(const gs_options* o, OptK* k) {
     for (int i = 0; i < 3; ++i) k->bg[i] = o->bg[i];
     return GS_OK;
 }
+
+namespace {
 
 int check_gaussians(const gs_gaussians* g, int32_t n_views) {
     GS_REQUIRE(g != nullptr, "gaussians is NULL");
@@ -168,13 +145,66 @@ unsigned long long* pinned_scalar() {
 
 }  // namespace
 
+size_t bin_workspace_bytes(int64_t n_slots, int64_t pair_capacity) {
+    if (n_slots < 1) n_slots = 1;
+    BinWs w;
+    return bin_layout(n_slots, pair_capacity, nullptr, &w);
+}
+
+int bin_sort_slots(const Projected& pr, const ViewTable& vt, int64_t n_slots, int64_t pair_capacity,
+                   uint32_t* pair_vals, uint32_t* tile_ranges, int64_t* n_pairs, void* ws, size_t ws_bytes,
+                   hipStream_t s) {
+    GS_REQUIRE(n_slots >= 1 && n_slots <= 0xFFFFFF00LL, "bad slot count %lld", (long long)n_slots);
+    GS_REQUIRE(pair_vals && tile_ranges && n_pairs && ws, "NULL output or workspace");
+    GS_REQUIRE(pair_capacity >= 0 && pair_capacity <= 0xFFFFFF00LL, "pair_capacity out of range");
+    GS_REQUIRE(((uintptr_t)ws & (kAlign - 1)) == 0, "workspace must be 256-byte aligned");
+    BinWs w;
+    const size_t need = bin_layout(n_slots, pair_capacity, ws, &w);
+    GS_REQUIRE(ws_bytes >= need, "workspace too small: %zu < %zu", ws_bytes, need);
+    const uint32_t N = (uint32_t)n_slots;
+
+    // 1. depth order of all slots (culled slots carry key 0xFFFFFFFF and sort last)
+    GS_HIP(launch_bin_prepare(pr, N, w.dkeys, w.dvals, s));
+    bool alt = false;
+    GS_HIP(radix_sort_pairs(w.dkeys, w.dvals, w.dkeys_alt, w.dvals_alt, N, 0, 32, w.hist, s, &alt));
+    const uint32_t* sorted_slot = alt ? w.dvals_alt : w.dvals;
+    // 2. per depth rank: tile count and rectangle; exclusive scan -> pair offsets
+    GS_HIP(launch_gather_sorted(sorted_slot, pr, N, w.tiles_s, w.rect_s, s));
+    GS_HIP(exclusive_scan_u32(w.tiles_s, w.offsets, N, w.scan_tmp, w.total, s));
+    unsigned long long* host = pinned_scalar();
+    if (!host) return fail(GS_ERR_HIP, "pinned host buffer unavailable");
+    GS_HIP(hipMemcpyAsync(host, w.total, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    GS_HIP(hipStreamSynchronize(s));
+    const unsigned long long P = *host;
+    *n_pairs = (int64_t)P;
+    if (P > 0xFFFFFF00ULL) return fail(GS_ERR_CAPACITY, "pair count %llu exceeds 32-bit indices", P);
+    if ((int64_t)P > pair_capacity)
+        return fail(GS_ERR_CAPACITY, "pair count %llu exceeds capacity %lld", P, (long long)pair_capacity);
+    // 3. expand into (tile, slot) pairs in depth order, then stable sort by tile id
+    const int bits = tile_bits(vt.total_tiles);
+    const int passes = P <= 1 ? 0 : (bits + 7) / 8;   // radix_sort_pairs runs no pass for P <= 1
+    uint32_t* vals_primary = (passes % 2 == 0) ? pair_vals : w.pvals_alt;
+    uint32_t* vals_alt = (passes % 2 == 0) ? w.pvals_alt : pair_vals;
+    GS_HIP(launch_emit_pairs(w.offsets, w.rect_s, sorted_slot, N, (uint32_t)P, w.pkeys, vals_primary, s));
+    bool palt = false;
+    GS_HIP(radix_sort_pairs(w.pkeys, vals_primary, w.pkeys_alt, vals_alt, (uint32_t)P, 0, bits, w.hist, s, &palt));
+    const uint32_t* sorted_keys = palt ? w.pkeys_alt : w.pkeys;
+    if ((palt ? vals_alt : vals_primary) != pair_vals)
+        return fail(GS_ERR_INTERNAL, "tile sort ended in the wrong buffer");
+    // 4. [start, end) per tile
+    GS_HIP(launch_tile_ranges(sorted_keys, (uint32_t)P, tile_ranges, (uint32_t)vt.total_tiles, s));
+    return GS_OK;
+}
+
+}  // namespace host
 }  // namespace gs
 
 using namespace gs;
+using namespace gs::host;
 
 extern "C" {
 
-const char* gs_last_error(void) { return g_err; }
+const char* gs_last_error(void) { return last_error(); }
 
 const char* gs_version(void) { return "gsmi-rasterizer 0.1 (gfx950)"; }
 
@@ -207,9 +237,7 @@ int gs_project(const gs_gaussians* g, const gs_camera* cams, int32_t n_views, co
 }
 
 size_t gs_bin_workspace_size(int64_t n_slots, int64_t pair_capacity) {
-    if (n_slots < 1) n_slots = 1;
-    BinWs w;
-    return bin_layout(n_slots, pair_capacity, nullptr, &w);
+    return bin_workspace_bytes(n_slots, pair_capacity);
 }
 
 int gs_bin_sort(const gs_projected* proj, const gs_camera* cams, int32_t n_views, int64_t n, int64_t pair_capacity,
@@ -223,45 +251,8 @@ int gs_bin_sort(const gs_projected* proj, const gs_camera* cams, int32_t n_views
         GS_REQUIRE(pair_vals && tile_ranges && n_pairs && ws, "NULL output or workspace");
         GS_REQUIRE(pair_capacity >= 0 && pair_capacity <= 0xFFFFFF00LL, "pair_capacity out of range");
         GS_REQUIRE(((uintptr_t)ws & (kAlign - 1)) == 0, "workspace must be 256-byte aligned");
-        const int64_t n_slots = n * n_views;
-        BinWs w;
-        const size_t need = bin_layout(n_slots, pair_capacity, ws, &w);
-        GS_REQUIRE(ws_bytes >= need, "workspace too small: %zu < %zu", ws_bytes, need);
-        hipStream_t s = (hipStream_t)stream;
-        const Projected pr = to_proj(proj);
-        const uint32_t N = (uint32_t)n_slots;
-
-        // 1. depth order of all slots (culled slots carry key 0xFFFFFFFF and sort last)
-        GS_HIP(launch_bin_prepare(pr, N, w.dkeys, w.dvals, s));
-        bool alt = false;
-        GS_HIP(radix_sort_pairs(w.dkeys, w.dvals, w.dkeys_alt, w.dvals_alt, N, 0, 32, w.hist, s, &alt));
-        const uint32_t* sorted_slot = alt ? w.dvals_alt : w.dvals;
-        // 2. per depth rank: tile count and rectangle; exclusive scan -> pair offsets
-        GS_HIP(launch_gather_sorted(sorted_slot, pr, N, w.tiles_s, w.rect_s, s));
-        GS_HIP(exclusive_scan_u32(w.tiles_s, w.offsets, N, w.scan_tmp, w.total, s));
-        unsigned long long* host = pinned_scalar();
-        if (!host) return fail(GS_ERR_HIP, "pinned host buffer unavailable");
-        GS_HIP(hipMemcpyAsync(host, w.total, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
-        GS_HIP(hipStreamSynchronize(s));
-        const unsigned long long P = *host;
-        *n_pairs = (int64_t)P;
-        if (P > 0xFFFFFF00ULL) return fail(GS_ERR_CAPACITY, "pair count %llu exceeds 32-bit indices", P);
-        if ((int64_t)P > pair_capacity)
-            return fail(GS_ERR_CAPACITY, "pair count %llu exceeds capacity %lld", P, (long long)pair_capacity);
-        // 3. expand into (tile, slot) pairs in depth order, then stable sort by tile id
-        const int bits = tile_bits(vt.total_tiles);
-        const int passes = P <= 1 ? 0 : (bits + 7) / 8;   // radix_sort_pairs runs no pass for P <= 1
-        uint32_t* vals_primary = (passes % 2 == 0) ? pair_vals : w.pvals_alt;
-        uint32_t* vals_alt = (passes % 2 == 0) ? w.pvals_alt : pair_vals;
-        GS_HIP(launch_emit_pairs(w.offsets, w.rect_s, sorted_slot, N, (uint32_t)P, w.pkeys, vals_primary, s));
-        bool palt = false;
-        GS_HIP(radix_sort_pairs(w.pkeys, vals_primary, w.pkeys_alt, vals_alt, (uint32_t)P, 0, bits, w.hist, s, &palt));
-        const uint32_t* sorted_keys = palt ? w.pkeys_alt : w.pkeys;
-        if ((palt ? vals_alt : vals_primary) != pair_vals)
-            return fail(GS_ERR_INTERNAL, "tile sort ended in the wrong buffer");
-        // 4. [start, end) per tile
-        GS_HIP(launch_tile_ranges(sorted_keys, (uint32_t)P, tile_ranges, (uint32_t)vt.total_tiles, s));
-        return GS_OK;
+        return bin_sort_slots(to_proj(proj), vt, n * n_views, pair_capacity, pair_vals, tile_ranges, n_pairs, ws,
+                              ws_bytes, (hipStream_t)stream);
     } catch (...) {
         return fail(GS_ERR_INTERNAL, "unexpected exception in gs_bin_sort");
     }

@@ -126,6 +126,19 @@ struct GradPtrs {
 hipError_t launch_project_fwd(const GaussPtrs& g, int64_t n, const ViewTable& vt, const OptK& opt,
                               const Projected& out, hipStream_t s);
 
+// a run of consecutive Gaussians [gstart, gstart + len) projected into view
+// `view` at slots [slot_start, slot_start + len); len is implied by the next
+// segment's slot_start (or the slot count)
+struct SlotSeg {
+    int64_t gstart;
+    uint32_t slot_start;
+    uint32_t view;
+};
+
+hipError_t launch_project_slots(const GaussPtrs& g, int64_t n, const ViewTable& vt, const OptK& opt,
+                                const SlotSeg* segs, int32_t n_seg, uint32_t n_slots, const Projected& out,
+                                hipStream_t s);
+
 // radix sort / scan primitives (sort.hip)
 size_t radix_hist_elems(uint32_t n);        // counters needed per pass
 hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt,

@@ -1,10 +1,12 @@
 // Projection of 3D Gaussians to 2D (EWA) with SH colour -- gfx950.
 //
-// One thread per Gaussian; the thread walks every view of the launch so the
-// Gaussian's parameters are read from HBM once.  Reads are structure-of-
-// arrays (one coalesced dword stream per component); records are written as
-// float4 triples so the compositing kernels can gather one record with
-// three 16-byte loads.  Arithmetic is FP64: the kernel is bound by HBM and
+// Two launch shapes share the per-view arithmetic: one thread per Gaussian
+// walking every view of the launch (training: all views see the same
+// Gaussians, whose parameters are then read from HBM once), or one thread
+// per slot of a segment table (served views, each with its own selection of
+// level-of-detail segments).  Geometry reads are structure-of-arrays;
+// records are written as four float4s so the compositing kernels gather a
+// record with 16-byte loads.  Arithmetic is FP64: the kernel is bound by HBM and
 // CDNA4 executes FP64 FMAs at the non-packed FP32 rate, so the geometry that
 // decides tile rectangles and depth keys carries no FP32 rounding.
 //
@@ -29,156 +31,197 @@ __device__ __forceinline__ void quat_rotation(double w, double x, double y, doub
     R[8] = 1.0 - 2.0 * (x * x + y * y);
 }
 
+// camera-space position t = R mu + t_w of a mean in view V
+__device__ __forceinline__ void view_point(const ViewK& V, double mu0, double mu1, double mu2, double& tx, double& ty,
+                                           double& tz) {
+    tx = (double)V.R[0] * mu0 + (double)V.R[1] * mu1 + (double)V.R[2] * mu2 + (double)V.t[0];
+    ty = (double)V.R[3] * mu0 + (double)V.R[4] * mu1 + (double)V.R[5] * mu2 + (double)V.t[1];
+    tz = (double)V.R[6] * mu0 + (double)V.R[7] * mu1 + (double)V.R[8] * mu2 + (double)V.t[2];
+}
+
+// M = R(q) diag(s) and the opacity of Gaussian g; false for a zero quaternion
+__device__ __forceinline__ bool load_shape(const GaussPtrs& gp, int64_t n, int64_t g, double M[9], double& opac) {
+    const double s0 = gp.scales[g], s1 = gp.scales[n + g], s2 = gp.scales[2 * n + g];
+    double qw = gp.quats[g], qx = gp.quats[n + g], qy = gp.quats[2 * n + g], qz = gp.quats[3 * n + g];
+    const double qn = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+    if (!(qn > 0.0)) return false;
+    const double inv = 1.0 / qn;
+    double Rq[9];
+    quat_rotation(qw * inv, qx * inv, qy * inv, qz * inv, Rq);
+    M[0] = Rq[0] * s0; M[1] = Rq[1] * s1; M[2] = Rq[2] * s2;
+    M[3] = Rq[3] * s0; M[4] = Rq[4] * s1; M[5] = Rq[5] * s2;
+    M[6] = Rq[6] * s0; M[7] = Rq[7] * s1; M[8] = Rq[8] * s2;
+    opac = gp.opac[g];
+    return true;
+}
+
+// 2D Gaussian of (t, M, opac) in view V: writes the record's geometry words
+// (float4s 0, 1, 3 and the .w of 2) and the rectangle of `slot`; returns the
+// number of tiles covered, 0 when culled
+__device__ __forceinline__ uint32_t project_view(const ViewK& V, const OptK& opt, double tx, double ty, double tz,
+                                                 const double M[9], double opac, const Projected& out,
+                                                 int64_t slot) {
+    const double W0 = V.R[0], W1 = V.R[1], W2 = V.R[2], W3 = V.R[3], W4 = V.R[4], W5 = V.R[5], W6 = V.R[6],
+                 W7 = V.R[7], W8 = V.R[8];
+    const double fx = V.fx, fy = V.fy;
+    const double u = tx / tz, vv = ty / tz;
+    const double uc = fmin(fmax(u, V.ulo), V.uhi);
+    const double vc = fmin(fmax(vv, V.vlo), V.vhi);
+    const double j00 = fx / tz, j02 = -fx * uc / tz, j11 = fy / tz, j12 = -fy * vc / tz;
+    // Tm = J W (2x3), Vm = Tm M (2x3): Sigma_2D = Vm Vm^T
+    const double T0 = j00 * W0 + j02 * W6, T1 = j00 * W1 + j02 * W7, T2 = j00 * W2 + j02 * W8;
+    const double T3 = j11 * W3 + j12 * W6, T4 = j11 * W4 + j12 * W7, T5 = j11 * W5 + j12 * W8;
+    const double a0 = T0 * M[0] + T1 * M[3] + T2 * M[6];
+    const double a1 = T0 * M[1] + T1 * M[4] + T2 * M[7];
+    const double a2 = T0 * M[2] + T1 * M[5] + T2 * M[8];
+    const double b0 = T3 * M[0] + T4 * M[3] + T5 * M[6];
+    const double b1 = T3 * M[1] + T4 * M[4] + T5 * M[7];
+    const double b2 = T3 * M[2] + T4 * M[5] + T5 * M[8];
+    const double ca = a0 * a0 + a1 * a1 + a2 * a2;
+    const double cb = a0 * b0 + a1 * b1 + a2 * b2;
+    const double cc = b0 * b0 + b1 * b1 + b2 * b2;
+    // det(Sigma_2D) = |a x b|^2 (Lagrange identity, no cancellation)
+    const double x0 = a1 * b2 - a2 * b1, x1 = a2 * b0 - a0 * b2, x2 = a0 * b1 - a1 * b0;
+    const double det2 = x0 * x0 + x1 * x1 + x2 * x2;
+    const double dil = (double)opt.dilation;
+    const double ad = ca + dil, cd = cc + dil;
+    const double detd = det2 + dil * (ca + cc) + dil * dil;
+    const double mx = fx * u + (double)V.cx, my = fy * vv + (double)V.cy;
+    const double lmax = 0.5 * (ad + cd) + sqrt(0.25 * (ad - cd) * (ad - cd) + cb * cb);
+    const double ext = 3.0 * sqrt(lmax);
+    if (!(detd > 0.0 && isfinite(ext) && isfinite(mx) && isfinite(my))) return 0;
+    const double r = ceil(ext);
+    const int TW = V.tiles_x, TH = V.tiles_y;
+    double x0t = floor((floor(mx) - r) * (1.0 / kTile)), x1t = floor((floor(mx) + r) * (1.0 / kTile));
+    double y0t = floor((floor(my) - r) * (1.0 / kTile)), y1t = floor((floor(my) + r) * (1.0 / kTile));
+    x0t = fmax(x0t, 0.0);
+    y0t = fmax(y0t, 0.0);
+    x1t = fmin(x1t, (double)(TW - 1));
+    y1t = fmin(y1t, (double)(TH - 1));
+    if (!(x0t <= x1t && y0t <= y1t)) return 0;
+    const int ix0 = (int)x0t, iy0 = (int)y0t, ix1 = (int)x1t, iy1 = (int)y1t;
+    const int w = ix1 - ix0 + 1, h = iy1 - iy0 + 1;
+    const double rho = opt.aa ? (det2 > 0.0 ? sqrt(det2 / detd) : 0.0) : 1.0;
+    const double invd = 1.0 / detd;
+    const double A = cd * invd, B = -cb * invd, C = ad * invd;
+    // mean = integer part (exact in float32) + fraction, so that the
+    // compositing kernels can form a tile-relative mean without the
+    // rounding of a large absolute pixel coordinate
+    const double fmx = floor(mx), fmy = floor(my);
+    out.rec[4 * slot + 0] = make_float4((float)fmx, (float)fmy, (float)(-0.5 * kLog2e * A), (float)(-kLog2e * B));
+    out.rec[4 * slot + 1] = make_float4((float)(-0.5 * kLog2e * C), (float)(opac * rho), (float)tz, (float)(mx - fmx));
+    out.rec[4 * slot + 2].w = (float)(my - fmy);
+    // box of the region where opacity' G' >= (1 - 1e-5) / 255: the ellipse
+    // x^T Sigma'^-1 x <= 2 tau has half-widths sqrt(2 tau Sigma'_xx),
+    // sqrt(2 tau Sigma'_yy); the 1e-5 covers the float32 error of alpha, the
+    // margins that of the box and mean
+    const double o2 = opac * rho;
+    float hx = -1.0f, hy = -1.0f;
+    if ((float)o2 >= kAlphaMin) {
+        const double tau = log(255.0 * o2) + 1e-5;
+        hx = (float)(sqrt(2.0 * tau * ad) * (1.0 + 1e-6) + 1e-3);
+        hy = (float)(sqrt(2.0 * tau * cd) * (1.0 + 1e-6) + 1e-3);
+    }
+    out.rec[4 * slot + 3] = make_float4(hx, hy, 0.0f, 0.0f);
+    out.rect[slot] = make_uint2((uint32_t)(V.tile_off + iy0 * TW + ix0), (uint32_t)w | ((uint32_t)TW << 16));
+    return (uint32_t)(w * h);
+}
+
+// view-dependent colour of a mean seen by V into the record's .xyz of
+// float4 2; the coefficient row is read as 16-byte vectors
+__device__ __forceinline__ void colour_view(const ViewK& V, const OptK& opt, double mu0, double mu1, double mu2,
+                                            const float4* __restrict__ shq, const Projected& out, int64_t slot) {
+    const int nb = (opt.sh_degree + 1) * (opt.sh_degree + 1);
+    const int nq = (3 * nb + 3) >> 2;    // float4s that hold the used coefficients
+    // direction in FP64 (mu and the camera centre are large numbers), the
+    // SH polynomial in FP32
+    const double e0 = mu0 - V.campos[0], e1 = mu1 - V.campos[1], e2 = mu2 - V.campos[2];
+    const double inv = 1.0 / sqrt(e0 * e0 + e1 * e1 + e2 * e2);
+    float Y[16];
+    sh_eval_basis<float>((float)(e0 * inv), (float)(e1 * inv), (float)(e2 * inv), opt.sh_degree, Y);
+    float shv[48];
+#pragma unroll
+    for (int q = 0; q < 12; ++q) {
+        const float4 t = q < nq ? shq[q] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        shv[4 * q + 0] = t.x; shv[4 * q + 1] = t.y; shv[4 * q + 2] = t.z; shv[4 * q + 3] = t.w;
+    }
+    float c[3] = {0.5f, 0.5f, 0.5f};
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        if (k < nb) {
+            c[0] = fmaf(shv[3 * k + 0], Y[k], c[0]);
+            c[1] = fmaf(shv[3 * k + 1], Y[k], c[1]);
+            c[2] = fmaf(shv[3 * k + 2], Y[k], c[2]);
+        }
+    }
+    float4 r2 = out.rec[4 * slot + 2];
+    r2.x = fmaxf(c[0], 0.0f);
+    r2.y = fmaxf(c[1], 0.0f);
+    r2.z = fmaxf(c[2], 0.0f);
+    out.rec[4 * slot + 2] = r2;
+}
+
+// every view of the launch sees the same n Gaussians: slot = view * n + g.
+// One thread per Gaussian walks the views, so its parameters are read once.
 __global__ __launch_bounds__(256) void k_project_fwd(GaussPtrs gp, int64_t n, ViewTable vt, OptK opt,
                                                      Projected out) {
     const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (g >= n) return;
     const double mu0 = gp.means[g], mu1 = gp.means[n + g], mu2 = gp.means[2 * n + g];
-
-    bool have_M = false;
-    double M[9];          // Rq * diag(s)
+    bool have_M = false, shape_ok = false;
+    double M[9];
     double opac = 0.0;
     uint32_t vis_mask = 0;
-
     for (int v = 0; v < vt.n_views; ++v) {
         const ViewK& V = vt.v[v];
         const int64_t slot = (int64_t)v * n + g;
-        const double W0 = V.R[0], W1 = V.R[1], W2 = V.R[2], W3 = V.R[3], W4 = V.R[4], W5 = V.R[5],
-                     W6 = V.R[6], W7 = V.R[7], W8 = V.R[8];
-        const double tx = W0 * mu0 + W1 * mu1 + W2 * mu2 + (double)V.t[0];
-        const double ty = W3 * mu0 + W4 * mu1 + W5 * mu2 + (double)V.t[1];
-        const double tz = W6 * mu0 + W7 * mu1 + W8 * mu2 + (double)V.t[2];
-        bool ok = tz >= (double)V.znear && tz <= (double)V.zfar;
-        if (ok && !have_M) {
-            const double s0 = gp.scales[g], s1 = gp.scales[n + g], s2 = gp.scales[2 * n + g];
-            double qw = gp.quats[g], qx = gp.quats[n + g], qy = gp.quats[2 * n + g], qz = gp.quats[3 * n + g];
-            const double qn = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
-            if (qn > 0.0) {
-                const double inv = 1.0 / qn;
-                double Rq[9];
-                quat_rotation(qw * inv, qx * inv, qy * inv, qz * inv, Rq);
-                M[0] = Rq[0] * s0; M[1] = Rq[1] * s1; M[2] = Rq[2] * s2;
-                M[3] = Rq[3] * s0; M[4] = Rq[4] * s1; M[5] = Rq[5] * s2;
-                M[6] = Rq[6] * s0; M[7] = Rq[7] * s1; M[8] = Rq[8] * s2;
-                opac = gp.opac[g];
+        double tx, ty, tz;
+        view_point(V, mu0, mu1, mu2, tx, ty, tz);
+        uint32_t ntiles = 0;
+        if (tz >= (double)V.znear && tz <= (double)V.zfar) {
+            if (!have_M) {
+                shape_ok = load_shape(gp, n, g, M, opac);
                 have_M = true;
             }
+            if (shape_ok) ntiles = project_view(V, opt, tx, ty, tz, M, opac, out, slot);
         }
-        ok = ok && have_M;
-        uint32_t ntiles = 0;
-        if (ok) {
-            const double fx = V.fx, fy = V.fy;
-            const double u = tx / tz, vv = ty / tz;
-            const double uc = fmin(fmax(u, V.ulo), V.uhi);
-            const double vc = fmin(fmax(vv, V.vlo), V.vhi);
-            const double j00 = fx / tz, j02 = -fx * uc / tz, j11 = fy / tz, j12 = -fy * vc / tz;
-            // Tm = J W (2x3), Vm = Tm M (2x3): Sigma_2D = Vm Vm^T
-            const double T0 = j00 * W0 + j02 * W6, T1 = j00 * W1 + j02 * W7, T2 = j00 * W2 + j02 * W8;
-            const double T3 = j11 * W3 + j12 * W6, T4 = j11 * W4 + j12 * W7, T5 = j11 * W5 + j12 * W8;
-            const double a0 = T0 * M[0] + T1 * M[3] + T2 * M[6];
-            const double a1 = T0 * M[1] + T1 * M[4] + T2 * M[7];
-            const double a2 = T0 * M[2] + T1 * M[5] + T2 * M[8];
-            const double b0 = T3 * M[0] + T4 * M[3] + T5 * M[6];
-            const double b1 = T3 * M[1] + T4 * M[4] + T5 * M[7];
-            const double b2 = T3 * M[2] + T4 * M[5] + T5 * M[8];
-            const double ca = a0 * a0 + a1 * a1 + a2 * a2;
-            const double cb = a0 * b0 + a1 * b1 + a2 * b2;
-            const double cc = b0 * b0 + b1 * b1 + b2 * b2;
-            // det(Sigma_2D) = |a x b|^2 (Lagrange identity, no cancellation)
-            const double x0 = a1 * b2 - a2 * b1, x1 = a2 * b0 - a0 * b2, x2 = a0 * b1 - a1 * b0;
-            const double det2 = x0 * x0 + x1 * x1 + x2 * x2;
-            const double dil = (double)opt.dilation;
-            const double ad = ca + dil, cd = cc + dil;
-            const double detd = det2 + dil * (ca + cc) + dil * dil;
-            const double mx = fx * u + (double)V.cx, my = fy * vv + (double)V.cy;
-            const double lmax = 0.5 * (ad + cd) + sqrt(0.25 * (ad - cd) * (ad - cd) + cb * cb);
-            const double ext = 3.0 * sqrt(lmax);
-            ok = detd > 0.0 && isfinite(ext) && isfinite(mx) && isfinite(my);
-            if (ok) {
-                const double r = ceil(ext);
-                const int TW = V.tiles_x, TH = V.tiles_y;
-                double x0t = floor((floor(mx) - r) * (1.0 / kTile)), x1t = floor((floor(mx) + r) * (1.0 / kTile));
-                double y0t = floor((floor(my) - r) * (1.0 / kTile)), y1t = floor((floor(my) + r) * (1.0 / kTile));
-                x0t = fmax(x0t, 0.0);
-                y0t = fmax(y0t, 0.0);
-                x1t = fmin(x1t, (double)(TW - 1));
-                y1t = fmin(y1t, (double)(TH - 1));
-                ok = x0t <= x1t && y0t <= y1t;
-                if (ok) {
-                    const int ix0 = (int)x0t, iy0 = (int)y0t, ix1 = (int)x1t, iy1 = (int)y1t;
-                    const int w = ix1 - ix0 + 1, h = iy1 - iy0 + 1;
-                    ntiles = (uint32_t)(w * h);
-                    const double rho = opt.aa ? (det2 > 0.0 ? sqrt(det2 / detd) : 0.0) : 1.0;
-                    const double invd = 1.0 / detd;
-                    const double A = cd * invd, B = -cb * invd, C = ad * invd;
-                    // mean = integer part (exact in float32) + fraction, so that the
-                    // compositing kernels can form a tile-relative mean without the
-                    // rounding of a large absolute pixel coordinate
-                    const double fmx = floor(mx), fmy = floor(my);
-                    out.rec[4 * slot + 0] = make_float4((float)fmx, (float)fmy, (float)(-0.5 * kLog2e * A),
-                                                        (float)(-kLog2e * B));
-                    out.rec[4 * slot + 1] = make_float4((float)(-0.5 * kLog2e * C), (float)(opac * rho), (float)tz,
-                                                        (float)(mx - fmx));
-                    out.rec[4 * slot + 2].w = (float)(my - fmy);
-                    // box of the region where opacity' G' >= (1 - 1e-5) / 255: the
-                    // ellipse x^T Sigma'^-1 x <= 2 tau has half-widths
-                    // sqrt(2 tau Sigma'_xx), sqrt(2 tau Sigma'_yy); the 1e-5 covers
-                    // the float32 error of alpha, the margins that of the box and mean
-                    const double o2 = opac * rho;
-                    float hx = -1.0f, hy = -1.0f;
-                    if ((float)o2 >= kAlphaMin) {
-                        const double tau = log(255.0 * o2) + 1e-5;
-                        hx = (float)(sqrt(2.0 * tau * ad) * (1.0 + 1e-6) + 1e-3);
-                        hy = (float)(sqrt(2.0 * tau * cd) * (1.0 + 1e-6) + 1e-3);
-                    }
-                    out.rec[4 * slot + 3] = make_float4(hx, hy, 0.0f, 0.0f);
-                    out.rect[slot] = make_uint2((uint32_t)(V.tile_off + iy0 * TW + ix0),
-                                                (uint32_t)w | ((uint32_t)TW << 16));
-                    vis_mask |= 1u << v;
-                }
-            }
-        }
+        if (ntiles) vis_mask |= 1u << v;
         out.tiles[slot] = ntiles;
         out.dkey[slot] = ntiles ? __float_as_uint((float)tz) : 0xFFFFFFFFu;
     }
     if (!vis_mask) return;
-
-    // view-dependent colour; the Gaussian's coefficients are one contiguous
-    // 192-byte row, read as 16-byte vectors only by the lanes that need them
-    const int nb = (opt.sh_degree + 1) * (opt.sh_degree + 1);
-    const int nq = (3 * nb + 3) >> 2;    // float4s that hold the used coefficients
     const float4* shq = reinterpret_cast<const float4*>(gp.sh) + 12 * g;
-    for (int v = 0; v < vt.n_views; ++v) {
-        if (!(vis_mask & (1u << v))) continue;
-        const ViewK& V = vt.v[v];
-        const int64_t slot = (int64_t)v * n + g;
-        // direction in FP64 (mu and the camera centre are large numbers),
-        // the SH polynomial in FP32
-        const double e0 = mu0 - V.campos[0], e1 = mu1 - V.campos[1], e2 = mu2 - V.campos[2];
-        const double inv = 1.0 / sqrt(e0 * e0 + e1 * e1 + e2 * e2);
-        float Y[16];
-        sh_eval_basis<float>((float)(e0 * inv), (float)(e1 * inv), (float)(e2 * inv), opt.sh_degree, Y);
-        float shv[48];
-#pragma unroll
-        for (int q = 0; q < 12; ++q) {
-            const float4 t = q < nq ? shq[q] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-            shv[4 * q + 0] = t.x; shv[4 * q + 1] = t.y; shv[4 * q + 2] = t.z; shv[4 * q + 3] = t.w;
-        }
-        float c[3] = {0.5f, 0.5f, 0.5f};
-#pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            if (k < nb) {
-                c[0] = fmaf(shv[3 * k + 0], Y[k], c[0]);
-                c[1] = fmaf(shv[3 * k + 1], Y[k], c[1]);
-                c[2] = fmaf(shv[3 * k + 2], Y[k], c[2]);
-            }
-        }
-        float4 r2 = out.rec[4 * slot + 2];
-        r2.x = fmaxf(c[0], 0.0f);
-        r2.y = fmaxf(c[1], 0.0f);
-        r2.z = fmaxf(c[2], 0.0f);
-        out.rec[4 * slot + 2] = r2;
+    for (int v = 0; v < vt.n_views; ++v)
+        if (vis_mask & (1u << v)) colour_view(vt.v[v], opt, mu0, mu1, mu2, shq, out, (int64_t)v * n + g);
+}
+
+// Views with their own selections of Gaussians (served requests): slot s
+// belongs to the last segment with slot_start <= s, and maps to Gaussian
+// gstart + (s - slot_start) seen by that segment's view.  One thread per slot.
+__global__ __launch_bounds__(256) void k_project_slots(GaussPtrs gp, int64_t n, ViewTable vt, OptK opt,
+                                                       const SlotSeg* __restrict__ segs, int32_t n_seg,
+                                                       uint32_t n_slots, Projected out) {
+    const uint32_t s = blockIdx.x * 256 + threadIdx.x;
+    if (s >= n_slots) return;
+    int lo = 0, hi = n_seg;      // invariant: segs[lo].slot_start <= s, answer in [lo, hi)
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (segs[mid].slot_start <= s) lo = mid; else hi = mid;
     }
+    const SlotSeg sg = segs[lo];
+    const int64_t g = sg.gstart + (int64_t)(s - sg.slot_start);
+    const ViewK& V = vt.v[sg.view];
+    const double mu0 = gp.means[g], mu1 = gp.means[n + g], mu2 = gp.means[2 * n + g];
+    double tx, ty, tz;
+    view_point(V, mu0, mu1, mu2, tx, ty, tz);
+    uint32_t ntiles = 0;
+    if (tz >= (double)V.znear && tz <= (double)V.zfar) {
+        double M[9], opac;
+        if (load_shape(gp, n, g, M, opac)) ntiles = project_view(V, opt, tx, ty, tz, M, opac, out, s);
+    }
+    out.tiles[s] = ntiles;
+    out.dkey[s] = ntiles ? __float_as_uint((float)tz) : 0xFFFFFFFFu;
+    if (ntiles) colour_view(V, opt, mu0, mu1, mu2, reinterpret_cast<const float4*>(gp.sh) + 12 * g, out, s);
 }
 
 }  // namespace
@@ -187,6 +230,15 @@ hipError_t launch_project_fwd(const GaussPtrs& g, int64_t n, const ViewTable& vt
                               const Projected& out, hipStream_t s) {
     const unsigned blocks = (unsigned)((n + 255) / 256);
     hipLaunchKernelGGL(k_project_fwd, dim3(blocks), dim3(256), 0, s, g, n, vt, opt, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_project_slots(const GaussPtrs& g, int64_t n, const ViewTable& vt, const OptK& opt,
+                                const SlotSeg* segs, int32_t n_seg, uint32_t n_slots, const Projected& out,
+                                hipStream_t s) {
+    if (!n_slots) return hipSuccess;
+    hipLaunchKernelGGL(k_project_slots, dim3((n_slots + 255) / 256), dim3(256), 0, s, g, n, vt, opt, segs, n_seg,
+                       n_slots, out);
     return hipGetLastError();
 }
 

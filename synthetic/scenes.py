@@ -93,6 +93,15 @@ class LodScene:
     thresholds: tuple = (30.0, 60.0, math.inf)   # finest level used up to d0, ...
     extra: dict = field(default_factory=dict)
 
+    def combined(self):
+        """All levels in one parameter set (coarsest first) and the start of
+        every (level, partition) range in it: (Scene, offsets (L, P) int64)."""
+        base = np.concatenate([[0], np.cumsum([lv.n for lv in self.levels])[:-1]]).astype(np.int64)
+        cat = lambda name, axis: np.ascontiguousarray(
+            np.concatenate([getattr(lv, name) for lv in self.levels], axis=axis))
+        sc = Scene(cat("means", 1), cat("scales", 1), cat("quats", 1), cat("opacities", 0), cat("sh", 2))
+        return sc, self.offsets + base[:, None]
+
 
 # --------------------------------------------------------------------------
 # cameras
@@ -114,7 +123,7 @@ def look_at(eye, target, up=(0.0, 0.0, 1.0)) -> np.ndarray:
     return m.astype(np.float32)
 
 
-def _pose_camera(eye, yaw, pitch, width, height, hfov_deg=70.0) -> Camera:
+def pose_camera(eye, yaw, pitch, width, height, hfov_deg=70.0) -> Camera:
     fwd = np.array([math.cos(pitch) * math.cos(yaw),
                     math.cos(pitch) * math.sin(yaw),
                     math.sin(pitch)])
@@ -146,7 +155,7 @@ def camera_c3(seed: int = 2) -> Camera:
     eye = np.array([0.0, 0.0, 1.7]) + rng.normal(0.0, 0.02, 3)
     yaw = math.radians(rng.normal(0.0, 0.2))
     pitch = math.radians(-5.0 + rng.normal(0.0, 0.2))
-    return _pose_camera(eye, yaw, pitch, 1920, 1080)
+    return pose_camera(eye, yaw, pitch, 1920, 1080)
 
 
 def cameras_c5() -> list:
@@ -157,7 +166,7 @@ def cameras_c5() -> list:
     for k in range(8):
         x = -87.5 + 25.0 * k
         yaw = 0.0 if k % 2 == 0 else math.pi
-        cams.append(_pose_camera((x, 0.0, 1.7), yaw, math.radians(-5.0), *res[k]))
+        cams.append(pose_camera((x, 0.0, 1.7), yaw, math.radians(-5.0), *res[k]))
     return cams
 
 
@@ -318,7 +327,7 @@ def serve_trace_c4(n_requests: int = 2000, rate: float = 150.0, seed: int = 3):
         pitch = math.radians(rng.uniform(-10.0, 5.0))
         w, h = res_choices[rng.integers(0, 3)]
         budget = budgets[rng.integers(0, 3)]
-        reqs.append({"t": float(arrivals[i]), "camera": _pose_camera(eye, yaw, pitch, w, h),
+        reqs.append({"t": float(arrivals[i]), "camera": pose_camera(eye, yaw, pitch, w, h),
                      "budget": int(budget)})
     return reqs
 

@@ -1,0 +1,144 @@
+"""Serving path through the C ABI: level-of-detail selection, segment-table
+projection, batched binning and compositing, admission and batch splitting.
+
+Each served image must (a) equal, bit for bit, the image of the same request
+served alone -- views of a batch share no tiles and each keeps its own slot
+order -- and (b) match the FP64 oracle's render of exactly the selected
+Gaussians (same tolerance and guard band as the end-to-end forward test).
+"""
+import math
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synthetic as S
+from gpu_util import oracle_opt
+
+pytestmark = pytest.mark.gpu
+
+THRESH = (12.0, 24.0, math.inf)
+CAPS = dict(slot_capacity=1_000_000, pair_capacity=4_000_000, pixel_capacity=1 << 20)
+
+
+@pytest.fixture(scope="module")
+def lod_setup(gpu_lib):
+    gs = gpu_lib
+    fine = S.scene_urban(60_000, 12, seed=4, extent=60.0)
+    lod = S.lod_scene_c4(fine, part_size=12.0, extent=60.0)
+    sc, offsets = lod.combined()
+    params = [torch.from_numpy(a).cuda() for a in sc.param_arrays()]
+    margin = 3.0 * float(sc.scales.max())
+    table = gs.LodTable(lod.part_min, lod.part_max, offsets, lod.counts, THRESH, margin)
+    rng = np.random.default_rng(11)
+    reqs = []
+    for i in range(12):
+        W, H = [(96, 64), (128, 72), (160, 90)][i % 3]
+        cam = S.pose_camera((rng.uniform(-40, 40), rng.uniform(-3, 3), 1.7), rng.uniform(0, 2 * math.pi),
+                             math.radians(rng.uniform(-10, 5)), W, H)
+        budget = [10 ** 9, 40_000, 15_000][i % 3]
+        reqs.append((cam, budget))
+    return gs, sc, offsets, params, table, reqs
+
+
+def wait_all(srv, tickets, timeout_s=120.0):
+    done = {}
+    t_end = time.time() + timeout_s
+    while len(done) < len(tickets):
+        assert time.time() < t_end, f"served {len(done)} of {len(tickets)}"
+        for c in srv.poll(timeout_us=100_000):
+            done[c["ticket"]] = c
+    return done
+
+
+def serve(gs, params, table, opts, reqs, cfg, t_arrival=None):
+    srv = gs.Server(params, table, opts, cfg)
+    try:
+        outs, tickets = [], []
+        for cam, budget in reqs:
+            out = torch.full((cam.height, cam.width, 3), -1.0, device="cuda")
+            tickets.append(srv.submit(cam, budget, out, t_arrival))
+            outs.append(out)
+        done = wait_all(srv, tickets)
+        stats = srv.stats()
+    finally:
+        srv.close()
+    return outs, [done[t] for t in tickets], stats
+
+
+def selected_subset(table, offsets, cam, budget, gs):
+    lv, total = gs.lod_select(table, cam, budget)
+    idx = [np.arange(offsets[l - 1, p], offsets[l - 1, p] + table.counts[l - 1, p])
+           for p, l in enumerate(lv) if l > 0]
+    idx = np.concatenate(idx) if idx else np.zeros(0, np.int64)
+    assert len(idx) == total
+    return idx
+
+
+def test_served_images_match_oracle_and_ignore_batching(lod_setup):
+    gs, sc, offsets, params, table, reqs = lod_setup
+    opts = gs.RenderOptions(sh_degree=3, aa=True)
+    alone, c1, _ = serve(gs, params, table, opts, reqs, gs.ServeConfig(max_views_per_batch=1, n_streams=1, **CAPS))
+    assert all(c["status"] == 0 and c["batch_views"] == 1 for c in c1)
+    mixed, c2, st = serve(gs, params, table, opts, reqs, gs.ServeConfig(max_views_per_batch=8, n_streams=2, **CAPS),
+                          t_arrival=0.0)
+    assert all(c["status"] == 0 for c in c2)
+    assert max(c["batch_views"] for c in c2) > 1          # batches did form
+    assert st["completed"] == len(reqs) and st["failed"] == 0
+    for a, b in zip(alone, mixed):
+        assert torch.equal(a, b)
+    for i in (0, 4, 8, 10):
+        cam, budget = reqs[i]
+        idx = selected_subset(table, offsets, cam, budget, gs)
+        assert c1[i]["n_gaussians"] == len(idx)
+        f = oracle.forward(sc.subset(idx), cam, oracle_opt(opts), guard_eps=oracle.DEFAULT_GUARD)
+        ref = f["images"][0]
+        ok = ref["guard"] == 0
+        err = np.abs(alone[i].cpu().numpy() - ref["rgb"]).max(-1)
+        assert err[ok].max() <= 1e-4, (i, err[ok].max())
+        assert (~ok).sum() <= max(2, 1e-3 * cam.n_pixels)
+
+
+def test_admission_splits_batches_and_reports_errors(lod_setup):
+    gs, sc, offsets, params, table, reqs = lod_setup
+    opts = gs.RenderOptions(sh_degree=3, aa=True)
+    alone, c1, _ = serve(gs, params, table, opts, reqs, gs.ServeConfig(max_views_per_batch=1, n_streams=1, **CAPS))
+    pmax = max(c["n_pairs"] for c in c1)
+    # a pair pool of 1.5 requests: batches of 8 must be split to fit
+    cfg = gs.ServeConfig(max_views_per_batch=8, n_streams=1, slot_capacity=1_000_000, pair_capacity=int(1.5 * pmax),
+                         pixel_capacity=1 << 20)
+    split, c2, _ = serve(gs, params, table, opts, reqs, cfg, t_arrival=0.0)
+    assert all(c["status"] == 0 for c in c2)
+    assert all(c["n_pairs"] <= cfg.pair_capacity for c in c2)
+    for a, b in zip(alone, split):
+        assert torch.equal(a, b)
+    # a pool smaller than the largest single request: that request fails alone
+    big = int(np.argmax([c["n_pairs"] for c in c1]))
+    cfg = gs.ServeConfig(max_views_per_batch=4, n_streams=1, slot_capacity=1_000_000, pair_capacity=max(1, pmax - 1),
+                         pixel_capacity=1 << 20)
+    _, c3, st = serve(gs, params, table, opts, reqs, cfg, t_arrival=0.0)
+    assert c3[big]["status"] == gs._lib.GS_ERR_CAPACITY and c3[big]["batch_views"] == 1
+    assert st["failed"] >= 1
+    # queue bound, budget below the nearest partition, request above one batch
+    srv = gs.Server(params, table, opts, gs.ServeConfig(queue_capacity=2, slot_capacity=1_000_000, pair_capacity=1_000_000,
+                                                          pixel_capacity=64 * 64))
+    try:
+        cam, _ = reqs[0]
+        small = S.pose_camera((0.0, 0.0, 1.7), 0.3, 0.0, 48, 32)
+        keep = [torch.empty((32, 48, 3), device="cuda") for _ in range(3)]
+        far = srv.now() + 1000.0
+        srv.submit(small, 10 ** 9, keep[0], far)
+        srv.submit(small, 10 ** 9, keep[1], far)
+        with pytest.raises(gs.GsError) as e:
+            srv.submit(small, 10 ** 9, keep[2], far)
+        assert e.value.code == gs._lib.GS_EAGAIN
+        with pytest.raises(gs.GsError) as e:
+            srv.submit(small, 0, keep[2], far)
+        assert e.value.code == gs._lib.GS_ERR_BUDGET
+        with pytest.raises(gs.GsError) as e:
+            srv.submit(cam, 10 ** 9, torch.empty((cam.height, cam.width, 3), device="cuda"), far)
+        assert e.value.code == gs._lib.GS_ERR_CAPACITY
+    finally:
+        srv.close()
