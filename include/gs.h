@@ -121,12 +121,17 @@ typedef struct gs_gaussians_grad {
  *   tiles[slots] uint32: tiles in the rectangle, 0 if culled.
  *   depth_key[slots] uint32: bit pattern of the float32 view depth
  *        (0xFFFFFFFF if culled); the primary sort key inside a tile.
+ *   tile_order [tiles of all views] uint32, optional (NULL = tile index
+ *        order): gs_bin_sort writes a launch order of the tiles, longest
+ *        lists first, and the compositing calls launch their workgroups in
+ *        that order.  Scheduling only: results do not depend on it.
  * Records of culled slots are left unwritten. */
 typedef struct gs_projected {
     float *rec;
     uint32_t *rect;
     uint32_t *tiles;
     uint32_t *depth_key;
+    uint32_t *tile_order;
 } gs_projected;
 
 const char *gs_last_error(void);

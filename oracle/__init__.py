@@ -48,7 +48,7 @@ class _Cam(C.Structure):
 
 class _Opt(C.Structure):
     _fields_ = [("sh_degree", C.c_int32), ("dilation", C.c_double), ("aa", C.c_int32),
-                ("bg", C.c_double * 3)]
+                ("bg", C.c_double * 3), ("tile_cull", C.c_int32)]
 
 
 _P = C.c_void_p
@@ -97,11 +97,12 @@ def make_cam(cam) -> _Cam:
     return c
 
 
-def make_opt(sh_degree=3, dilation=0.3, aa=False, bg=(0.0, 0.0, 0.0)) -> _Opt:
+def make_opt(sh_degree=3, dilation=0.3, aa=False, bg=(0.0, 0.0, 0.0), tile_cull=True) -> _Opt:
     o = _Opt()
     o.sh_degree = int(sh_degree)
     o.dilation = float(np.float32(dilation))
     o.aa = int(bool(aa))
+    o.tile_cull = int(bool(tile_cull))
     for k in range(3):
         o.bg[k] = float(np.float32(bg[k]))
     return o

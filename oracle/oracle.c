@@ -57,6 +57,7 @@ typedef struct {
     double dilation;         /* px^2 added to the 2D covariance diagonal */
     int32_t aa;              /* 1: opacity compensation by rho */
     double bg[3];
+    int32_t tile_cull;       /* 1: tile rectangle narrowed to the alpha box (project_one) */
 } oopt_t;
 
 /* per-slot projection outputs (arrays of n entries times the component count) */
@@ -305,6 +306,29 @@ static void project_one(const ocam_t *cam, const oopt_t *opt, const double mu[3]
     if (fy0 < 0.0) fy0 = 0.0;
     if (fx1 > TW - 1) fx1 = TW - 1;
     if (fy1 > TH - 1) fy1 = TH - 1;
+    if (opt->tile_cull) {
+        /* Tile-based culling (adopted in §3.4.2 to skip Gaussians of negligible
+         * contribution in a tile).  A pixel centre can pass the skip rule only
+         * where o' G' >= 1/255, i.e. inside the ellipse d^T Sigma'^-1 d <= 2 tau,
+         * tau = ln(255 o'), whose bounding box has half-widths
+         * sqrt(2 tau Sigma'_xx) and sqrt(2 tau Sigma'_yy).  The box is widened
+         * by margins for the float32 arithmetic of the compositing kernels
+         * (1e-5 on tau, relative 1e-6 and 1e-3 px on the half-widths) and the
+         * rectangle keeps only tiles holding pixel centres inside it, so no
+         * image changes.  With o' below 1/255 (compared in float32) nothing
+         * passes anywhere and the Gaussian is culled. */
+        if (!((float)P->opac >= 1.0f / 255.0f)) return;
+        double tau = log(255.0 * P->opac) + 1e-5;
+        double hx = sqrt(2.0 * tau * P->ad) * (1.0 + 1e-6) + 1e-3;
+        double hy = sqrt(2.0 * tau * P->cd) * (1.0 + 1e-6) + 1e-3;
+        /* pixels p with |p + 0.5 - m| <= h, then their tiles */
+        double bx0 = floor(ceil(P->mean2d[0] - hx - 0.5) / ORC_TILE), bx1 = floor(floor(P->mean2d[0] + hx - 0.5) / ORC_TILE);
+        double by0 = floor(ceil(P->mean2d[1] - hy - 0.5) / ORC_TILE), by1 = floor(floor(P->mean2d[1] + hy - 0.5) / ORC_TILE);
+        if (bx0 > fx0) fx0 = bx0;
+        if (by0 > fy0) fy0 = by0;
+        if (bx1 < fx1) fx1 = bx1;
+        if (by1 < fy1) fy1 = by1;
+    }
     if (!(fx0 <= fx1 && fy0 <= fy1)) return;
     P->radius = (int)(r < 2e9 ? r : 2e9);
     P->rect[0] = (int)fx0; P->rect[1] = (int)fy0; P->rect[2] = (int)fx1; P->rect[3] = (int)fy1;

@@ -53,7 +53,8 @@ class GsGaussiansGrad(C.Structure):
 
 
 class GsProjected(C.Structure):
-    _fields_ = [("rec", C.c_void_p), ("rect", C.c_void_p), ("tiles", C.c_void_p), ("depth_key", C.c_void_p)]
+    _fields_ = [("rec", C.c_void_p), ("rect", C.c_void_p), ("tiles", C.c_void_p), ("depth_key", C.c_void_p),
+                ("tile_order", C.c_void_p)]
 
 
 GS_MAX_LEVELS = 8

@@ -99,7 +99,8 @@ int check_proj(const gs_projected* p) {
 }
 
 Projected to_proj(const gs_projected* p) {
-    return Projected{reinterpret_cast<float4*>(p->rec), reinterpret_cast<uint2*>(p->rect), p->tiles, p->depth_key};
+    return Projected{reinterpret_cast<float4*>(p->rec), reinterpret_cast<uint2*>(p->rect), p->tiles, p->depth_key,
+                     p->tile_order};
 }
 
 int tile_bits(int64_t n_tiles) {
@@ -107,6 +108,8 @@ int tile_bits(int64_t n_tiles) {
     while ((1LL << b) < n_tiles) ++b;
     return b;
 }
+
+constexpr int kTotals = 16 + 16 * kBinPairParts;
 
 struct BinWs {
     uint32_t *dkeys, *dvals, *dkeys_alt, *dvals_alt;
@@ -130,16 +133,19 @@ size_t bin_layout(int64_t n_slots, int64_t cap, void* base, BinWs* w) {
     w->offsets = c.take<uint32_t>(N);
     w->rect_s = c.take<uint2>(N);
     w->scan_tmp = c.take<uint32_t>(scan_tmp_elems((uint32_t)N));
-    w->total = c.take<unsigned long long>(2);
+    w->total = c.take<unsigned long long>(kTotals);   // [0] visible, [8] offsets total, [16 + 16k] pair parts
     w->pkeys = c.take<uint32_t>(Pc);
     w->pkeys_alt = c.take<uint32_t>(Pc);
     w->pvals_alt = c.take<uint32_t>(Pc);
     return c.off;
 }
 
+// per-thread pinned read-back buffer of kTotals counters
 unsigned long long* pinned_scalar() {
     thread_local unsigned long long* p = nullptr;
-    if (!p && hipHostMalloc(reinterpret_cast<void**>(&p), 64, hipHostMallocDefault) != hipSuccess) p = nullptr;
+    if (!p && hipHostMalloc(reinterpret_cast<void**>(&p), kTotals * sizeof(unsigned long long),
+                            hipHostMallocDefault) != hipSuccess)
+        p = nullptr;
     return p;
 }
 
@@ -163,36 +169,48 @@ int bin_sort_slots(const Projected& pr, const ViewTable& vt, int64_t n_slots, in
     GS_REQUIRE(ws_bytes >= need, "workspace too small: %zu < %zu", ws_bytes, need);
     const uint32_t N = (uint32_t)n_slots;
 
-    // 1. depth order of all slots (culled slots carry key 0xFFFFFFFF and sort last)
-    GS_HIP(launch_bin_prepare(pr, N, w.dkeys, w.dvals, s));
-    bool alt = false;
-    GS_HIP(radix_sort_pairs(w.dkeys, w.dvals, w.dkeys_alt, w.dvals_alt, N, 0, 32, w.hist, s, &alt));
-    const uint32_t* sorted_slot = alt ? w.dvals_alt : w.dvals;
-    // 2. per depth rank: tile count and rectangle; exclusive scan -> pair offsets
-    GS_HIP(launch_gather_sorted(sorted_slot, pr, N, w.tiles_s, w.rect_s, s));
+    // 1. visible slots in slot order (flags, scan, scatter) and the pair count
+    //    (sum of all tile counts); one read-back gives both sizes
+    GS_HIP(fill_u32(reinterpret_cast<uint32_t*>(w.total), 0u, 2 * kTotals, s));
+    GS_HIP(launch_visible_flags(pr, N, w.tiles_s, w.total + 16, s));
     GS_HIP(exclusive_scan_u32(w.tiles_s, w.offsets, N, w.scan_tmp, w.total, s));
+    GS_HIP(launch_compact_visible(pr, w.offsets, N, w.dkeys, w.dvals, s));
     unsigned long long* host = pinned_scalar();
     if (!host) return fail(GS_ERR_HIP, "pinned host buffer unavailable");
-    GS_HIP(hipMemcpyAsync(host, w.total, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    GS_HIP(hipMemcpyAsync(host, w.total, kTotals * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
     GS_HIP(hipStreamSynchronize(s));
-    const unsigned long long P = *host;
+    unsigned long long P = 0;
+    for (int k = 0; k < kBinPairParts; ++k) P += host[16 + 16 * k];
+    const unsigned long long V = host[0];
     *n_pairs = (int64_t)P;
     if (P > 0xFFFFFF00ULL) return fail(GS_ERR_CAPACITY, "pair count %llu exceeds 32-bit indices", P);
     if ((int64_t)P > pair_capacity)
         return fail(GS_ERR_CAPACITY, "pair count %llu exceeds capacity %lld", P, (long long)pair_capacity);
+    if (V > N || (V == 0) != (P == 0)) return fail(GS_ERR_INTERNAL, "inconsistent counts (%llu visible, %llu pairs)", V, P);
+    const uint32_t NV = (uint32_t)V;
+    // 2. depth order of the visible slots (stable: ties stay in slot order);
+    //    per depth rank its tile count and rectangle; exclusive scan -> pair offsets
+    bool alt = false;
+    GS_HIP(radix_sort_pairs(w.dkeys, w.dvals, w.dkeys_alt, w.dvals_alt, NV, 0, 32, w.hist, s, &alt));
+    const uint32_t* sorted_slot = alt ? w.dvals_alt : w.dvals;
+    if (NV) {
+        GS_HIP(launch_gather_sorted(sorted_slot, pr, NV, w.tiles_s, w.rect_s, s));
+        GS_HIP(exclusive_scan_u32(w.tiles_s, w.offsets, NV, w.scan_tmp, w.total + 8, s));
+    }
     // 3. expand into (tile, slot) pairs in depth order, then stable sort by tile id
     const int bits = tile_bits(vt.total_tiles);
     const int passes = P <= 1 ? 0 : (bits + 7) / 8;   // radix_sort_pairs runs no pass for P <= 1
     uint32_t* vals_primary = (passes % 2 == 0) ? pair_vals : w.pvals_alt;
     uint32_t* vals_alt = (passes % 2 == 0) ? w.pvals_alt : pair_vals;
-    GS_HIP(launch_emit_pairs(w.offsets, w.rect_s, sorted_slot, N, (uint32_t)P, w.pkeys, vals_primary, s));
+    GS_HIP(launch_emit_pairs(w.offsets, w.rect_s, sorted_slot, NV, (uint32_t)P, w.pkeys, vals_primary, s));
     bool palt = false;
     GS_HIP(radix_sort_pairs(w.pkeys, vals_primary, w.pkeys_alt, vals_alt, (uint32_t)P, 0, bits, w.hist, s, &palt));
     const uint32_t* sorted_keys = palt ? w.pkeys_alt : w.pkeys;
     if ((palt ? vals_alt : vals_primary) != pair_vals)
         return fail(GS_ERR_INTERNAL, "tile sort ended in the wrong buffer");
-    // 4. [start, end) per tile
+    // 4. [start, end) per tile, and the compositing launch order
     GS_HIP(launch_tile_ranges(sorted_keys, (uint32_t)P, tile_ranges, (uint32_t)vt.total_tiles, s));
+    if (pr.tile_order) GS_HIP(launch_tile_order(tile_ranges, (uint32_t)vt.total_tiles, pr.tile_order, s));
     return GS_OK;
 }
 

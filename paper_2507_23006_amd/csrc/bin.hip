@@ -1,23 +1,52 @@
 // Tile binning -- gfx950.
 //
 // "Processed in depth order" (§3.1) per tile, ties by input order, is built
-// depth-first: slots are sorted once by their 32-bit depth key (N items),
-// expanded into (tile, slot) pairs in that order, and the pairs are then
-// stably sorted by tile id only (ceil(log2 tiles) bits, 2-3 passes) instead
-// of sorting P pairs on a 45-49 bit (tile, depth) key.  Stability of the
-// tile sort keeps the depth order inside every tile.
+// depth-first: the visible slots are compacted in slot order (a scan), sorted
+// once by their 32-bit depth key, expanded into (tile, slot) pairs in that
+// order, and the pairs are then stably sorted by tile id only
+// (ceil(log2 tiles) bits, 2-3 passes) instead of sorting P pairs on a 45-49
+// bit (tile, depth) key.  Stability of both sorts keeps the depth order
+// inside every tile, ties by slot index.
 #include "gs_internal.h"
 
 namespace gs {
 
 namespace {
 
-__global__ void k_bin_prepare(const uint32_t* __restrict__ dkey, uint32_t n, uint32_t* __restrict__ keys,
-                              uint32_t* __restrict__ slots) {
+// 1 for slots that cover a tile; the block sums of tiles add up to the pair
+// count, spread over kPairParts counters (one atomic address would serialise
+// thousands of workgroups from all XCDs); the counters must start at 0
+constexpr int kPairParts = 64;
+
+__global__ __launch_bounds__(256) void k_visible_flags(const uint32_t* __restrict__ tiles, uint32_t n,
+                                                       uint32_t* __restrict__ flags,
+                                                       unsigned long long* __restrict__ pair_parts) {
+    __shared__ unsigned long long s_sum[4];
     const uint32_t i = blockIdx.x * 256 + threadIdx.x;
-    if (i < n) {
-        keys[i] = dkey[i];
-        slots[i] = i;
+    const uint32_t t = i < n ? tiles[i] : 0u;
+    if (i < n) flags[i] = t ? 1u : 0u;
+    unsigned long long v = t;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if ((threadIdx.x & 63) == 0) s_sum[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned long long b = s_sum[0] + s_sum[1] + s_sum[2] + s_sum[3];
+        if (b) atomicAdd(&pair_parts[16 * (blockIdx.x % kPairParts)], b);   // one 128-byte line each
+    }
+}
+
+// visible slots, in slot order, with their depth keys: the input of the
+// depth sort (culled slots never enter it)
+__global__ __launch_bounds__(256) void k_compact_visible(const uint32_t* __restrict__ tiles,
+                                                         const uint32_t* __restrict__ pos,
+                                                         const uint32_t* __restrict__ dkey, uint32_t n,
+                                                         uint32_t* __restrict__ keys, uint32_t* __restrict__ slots) {
+    const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n && tiles[i]) {
+        const uint32_t d = pos[i];
+        keys[d] = dkey[i];
+        slots[d] = i;
     }
 }
 
@@ -94,11 +123,64 @@ __global__ void k_tile_ranges(const uint32_t* __restrict__ keys, uint32_t n, uin
     if (p == n - 1 || keys[p + 1] != k) ranges[k].y = p + 1;
 }
 
+// Launch order of the tiles for compositing: longest lists first, so that
+// the slowest workgroups start early instead of forming the tail of the
+// launch (longest-processing-time-first list scheduling).  One workgroup:
+// tiles are bucketed by 1/8-octave steps of their list length (LDS counts),
+// the buckets are scanned from the longest down, and every tile takes the
+// next place of its bucket.  Order inside a bucket is arbitrary; results do
+// not depend on it.
+constexpr int kOrderThreads = 1024;
+constexpr int kOrderBuckets = 256;
+
+__device__ __forceinline__ int order_bucket(const uint2 r) {
+    const uint32_t len = r.y - r.x;
+    const int b = (int)(8.0f * __log2f((float)len + 1.0f));
+    return kOrderBuckets - 1 - min(b, kOrderBuckets - 1);   // longest first
+}
+
+__global__ __launch_bounds__(kOrderThreads) void k_tile_order(const uint2* __restrict__ ranges, uint32_t n_tiles,
+                                                              uint32_t* __restrict__ order) {
+    __shared__ uint32_t s_cnt[kOrderBuckets];
+    const int tid = threadIdx.x;
+    for (int b = tid; b < kOrderBuckets; b += kOrderThreads) s_cnt[b] = 0;
+    __syncthreads();
+    for (uint32_t t = tid; t < n_tiles; t += kOrderThreads) atomicAdd(&s_cnt[order_bucket(ranges[t])], 1u);
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t run = 0;
+        for (int b = 0; b < kOrderBuckets; ++b) {
+            const uint32_t c = s_cnt[b];
+            s_cnt[b] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+    for (uint32_t t = tid; t < n_tiles; t += kOrderThreads) {
+        const uint32_t at = atomicAdd(&s_cnt[order_bucket(ranges[t])], 1u);
+        order[at] = t;
+    }
+}
+
 }  // namespace
 
-hipError_t launch_bin_prepare(const Projected& proj, uint32_t n_slots, uint32_t* keys, uint32_t* slots,
-                              hipStream_t s) {
-    hipLaunchKernelGGL(k_bin_prepare, dim3((n_slots + 255) / 256), dim3(256), 0, s, proj.dkey, n_slots, keys, slots);
+hipError_t launch_tile_order(const uint32_t* ranges, uint32_t n_tiles, uint32_t* order, hipStream_t s) {
+    hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(kOrderThreads), 0, s, reinterpret_cast<const uint2*>(ranges),
+                       n_tiles, order);
+    return hipGetLastError();
+}
+
+hipError_t launch_visible_flags(const Projected& proj, uint32_t n_slots, uint32_t* flags,
+                                unsigned long long* pair_parts, hipStream_t s) {
+    hipLaunchKernelGGL(k_visible_flags, dim3((n_slots + 255) / 256), dim3(256), 0, s, proj.tiles, n_slots, flags,
+                       pair_parts);
+    return hipGetLastError();
+}
+
+hipError_t launch_compact_visible(const Projected& proj, const uint32_t* pos, uint32_t n_slots, uint32_t* keys,
+                                  uint32_t* slots, hipStream_t s) {
+    hipLaunchKernelGGL(k_compact_visible, dim3((n_slots + 255) / 256), dim3(256), 0, s, proj.tiles, pos, proj.dkey,
+                       n_slots, keys, slots);
     return hipGetLastError();
 }
 

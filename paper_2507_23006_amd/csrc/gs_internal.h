@@ -113,6 +113,7 @@ struct Projected {
     uint2* rect;          // [slots]
     uint32_t* tiles;      // [slots]
     uint32_t* dkey;       // [slots]
+    uint32_t* tile_order; // [tiles] compositing launch order, or null for tile index order
 };
 
 struct GaussPtrs {
@@ -152,8 +153,12 @@ hipError_t fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s);
 hipError_t zero_seen_grad2d(const uint32_t* tiles, float* grad2d, int64_t n_slots, hipStream_t s);
 
 // binning (bin.hip)
-hipError_t launch_bin_prepare(const Projected& proj, uint32_t n_slots, uint32_t* dkeys_tmp, uint32_t* slots_tmp,
-                              hipStream_t s);
+// pair_parts: kBinPairParts partial pair counts, 16 u64 apart (zeroed by the caller)
+constexpr int kBinPairParts = 64;
+hipError_t launch_visible_flags(const Projected& proj, uint32_t n_slots, uint32_t* flags,
+                                unsigned long long* pair_parts, hipStream_t s);
+hipError_t launch_compact_visible(const Projected& proj, const uint32_t* pos, uint32_t n_slots, uint32_t* keys,
+                                  uint32_t* slots, hipStream_t s);
 hipError_t launch_gather_sorted(const uint32_t* sorted_slot, const Projected& proj, uint32_t n_slots,
                                 uint32_t* tiles_s, uint2* rect_s, hipStream_t s);
 hipError_t launch_emit_pairs(const uint32_t* offsets, const uint2* rect_s, const uint32_t* sorted_slot,
@@ -161,6 +166,8 @@ hipError_t launch_emit_pairs(const uint32_t* offsets, const uint2* rect_s, const
                              hipStream_t s);
 hipError_t launch_tile_ranges(const uint32_t* sorted_keys, uint32_t n_pairs, uint32_t* ranges, uint32_t n_tiles,
                               hipStream_t s);
+// tile launch order for compositing, longest lists first
+hipError_t launch_tile_order(const uint32_t* ranges, uint32_t n_tiles, uint32_t* order, hipStream_t s);
 
 // compositing (render.hip)
 hipError_t launch_render_fwd(const Projected& proj, const uint32_t* pair_vals, const uint2* ranges,

@@ -98,10 +98,26 @@ __device__ __forceinline__ uint32_t project_view(const ViewK& V, const OptK& opt
     y0t = fmax(y0t, 0.0);
     x1t = fmin(x1t, (double)(TW - 1));
     y1t = fmin(y1t, (double)(TH - 1));
+    // Tile-based culling: alpha = o' G' reaches 1/255 only inside the ellipse
+    // x^T Sigma'^-1 x <= 2 tau, tau = ln(255 o'), whose bounding box has
+    // half-widths sqrt(2 tau Sigma'_xx), sqrt(2 tau Sigma'_yy).  Widened by
+    // margins for the float32 compositing arithmetic (1e-5 on tau, relative
+    // 1e-6 and 1e-3 px), the box keeps the tiles whose pixel centres it
+    // reaches; the rectangle drops the others, which no entry could change.
+    // The box also travels in the record for the per-quadrant culling.
+    const double rho = opt.aa ? (det2 > 0.0 ? sqrt(det2 / detd) : 0.0) : 1.0;
+    const double o2 = opac * rho;
+    if (!((float)o2 >= kAlphaMin)) return 0;     // below the skip threshold everywhere
+    const double tau = log(255.0 * o2) + 1e-5;
+    const double hxd = sqrt(2.0 * tau * ad) * (1.0 + 1e-6) + 1e-3;
+    const double hyd = sqrt(2.0 * tau * cd) * (1.0 + 1e-6) + 1e-3;
+    x0t = fmax(x0t, floor(ceil(mx - hxd - 0.5) * (1.0 / kTile)));
+    x1t = fmin(x1t, floor(floor(mx + hxd - 0.5) * (1.0 / kTile)));
+    y0t = fmax(y0t, floor(ceil(my - hyd - 0.5) * (1.0 / kTile)));
+    y1t = fmin(y1t, floor(floor(my + hyd - 0.5) * (1.0 / kTile)));
     if (!(x0t <= x1t && y0t <= y1t)) return 0;
     const int ix0 = (int)x0t, iy0 = (int)y0t, ix1 = (int)x1t, iy1 = (int)y1t;
     const int w = ix1 - ix0 + 1, h = iy1 - iy0 + 1;
-    const double rho = opt.aa ? (det2 > 0.0 ? sqrt(det2 / detd) : 0.0) : 1.0;
     const double invd = 1.0 / detd;
     const double A = cd * invd, B = -cb * invd, C = ad * invd;
     // mean = integer part (exact in float32) + fraction, so that the
@@ -111,18 +127,7 @@ __device__ __forceinline__ uint32_t project_view(const ViewK& V, const OptK& opt
     out.rec[4 * slot + 0] = make_float4((float)fmx, (float)fmy, (float)(-0.5 * kLog2e * A), (float)(-kLog2e * B));
     out.rec[4 * slot + 1] = make_float4((float)(-0.5 * kLog2e * C), (float)(opac * rho), (float)tz, (float)(mx - fmx));
     out.rec[4 * slot + 2].w = (float)(my - fmy);
-    // box of the region where opacity' G' >= (1 - 1e-5) / 255: the ellipse
-    // x^T Sigma'^-1 x <= 2 tau has half-widths sqrt(2 tau Sigma'_xx),
-    // sqrt(2 tau Sigma'_yy); the 1e-5 covers the float32 error of alpha, the
-    // margins that of the box and mean
-    const double o2 = opac * rho;
-    float hx = -1.0f, hy = -1.0f;
-    if ((float)o2 >= kAlphaMin) {
-        const double tau = log(255.0 * o2) + 1e-5;
-        hx = (float)(sqrt(2.0 * tau * ad) * (1.0 + 1e-6) + 1e-3);
-        hy = (float)(sqrt(2.0 * tau * cd) * (1.0 + 1e-6) + 1e-3);
-    }
-    out.rec[4 * slot + 3] = make_float4(hx, hy, 0.0f, 0.0f);
+    out.rec[4 * slot + 3] = make_float4((float)hxd, (float)hyd, 0.0f, 0.0f);
     out.rect[slot] = make_uint2((uint32_t)(V.tile_off + iy0 * TW + ix0), (uint32_t)w | ((uint32_t)TW << 16));
     return (uint32_t)(w * h);
 }

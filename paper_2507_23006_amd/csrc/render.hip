@@ -9,10 +9,10 @@
 // last composited entry, and the backward walks the list back to front,
 // recovering T_i = T_{i+1} / (1 - alpha_i).
 //
-// Backward per entry: gradients are summed over the wave with DPP
-// row-shift / row-broadcast adds (six VALU steps, result in lane 63) into an
-// LDS row; after each chunk the wave adds the rows to the per-slot 2D
-// gradient buffer with one float atomic per nonzero field.
+// Backward per entry: the 12 gradient fields are summed over the wave by
+// halving lane exchanges (permlane swaps, then DPP row shifts) into an LDS
+// row; after each chunk the wave adds the rows to the per-slot 2D gradient
+// buffer with one float atomic per nonzero field.
 #include "gs_internal.h"
 
 namespace gs {
@@ -58,6 +58,13 @@ __device__ __forceinline__ float4 stage_geom(const float4 r0, const float4 r1, c
 // (selects, no branches).  Waves of a tile never wait for each other.
 constexpr int kChunk = 64;
 constexpr int kWaves = 4;
+
+// the workgroup's tile: its place in the launch order (an order that is not
+// a permutation of the tiles falls back to the index, so no access strays)
+__device__ __forceinline__ int launch_tile(const uint32_t* __restrict__ tile_order, const ViewTable& vt) {
+    const uint32_t t = tile_order ? tile_order[blockIdx.x] : blockIdx.x;
+    return t < (uint32_t)vt.total_tiles ? (int)t : (int)blockIdx.x;
+}
 
 struct PixelCoords {
     int v;
@@ -139,15 +146,63 @@ __device__ __forceinline__ int stage_chunk(const float4* __restrict__ rec, const
     return __popcll(m);
 }
 
+// One lane's list entry, loaded a chunk ahead of its use so that the two
+// dependent gathers (pair value, then record) overlap the evaluation of the
+// previous chunk instead of stalling the wave.
+struct Gather {
+    float4 r0, r1, r2, r3;
+    uint32_t slot;
+};
+
+constexpr uint32_t kNoSlot = 0xFFFFFFFFu;
+
+__device__ __forceinline__ uint32_t load_slot(const uint32_t* __restrict__ pair_vals, uint32_t j, uint32_t end) {
+    return j < end ? pair_vals[j] : kNoSlot;
+}
+
+__device__ __forceinline__ Gather load_entry(const float4* __restrict__ rec, uint32_t s) {
+    Gather g;
+    g.slot = s;
+    if (s != kNoSlot) {
+        g.r0 = rec[4 * (size_t)s + 0];
+        g.r1 = rec[4 * (size_t)s + 1];
+        g.r2 = rec[4 * (size_t)s + 2];
+        g.r3 = rec[4 * (size_t)s + 3];
+    } else {
+        g.r0 = g.r1 = g.r2 = g.r3 = make_float4(0.0f, 0.0f, 0.0f, -1.0f);
+    }
+    return g;
+}
+
+// box test, ballot and in-order compaction of a gathered chunk into `st`;
+// pos = the lane's 1-based position in the tile list.  Wave-uniform result.
+__device__ __forceinline__ int stage_gathered(const Gather& e, int pos, const PixelCoords& pc, int lane,
+                                              WaveStage& st) {
+    const float4 g = stage_geom(e.r0, e.r1, e.r2, pc.ox, pc.oy);
+    const bool hit = e.slot != kNoSlot && box_hits_quadrant(g, e.r3, pc.qcx, pc.qcy);
+    const unsigned long long m = __ballot(hit);
+    if (hit) {
+        const int d = __popcll(m & lanes_below(lane));
+        st.g[d] = g;
+        st.b[d] = e.r1;
+        st.c[d] = e.r2;
+        st.pos[d] = pos;
+        st.slot[d] = e.slot;
+    }
+    __builtin_amdgcn_wave_barrier();
+    return __popcll(m);
+}
+
 __global__ __launch_bounds__(256) void k_render_fwd(const float4* __restrict__ rec,
                                                     const uint32_t* __restrict__ pair_vals,
-                                                    const uint2* __restrict__ ranges, ViewTable vt, OptK opt,
+                                                    const uint2* __restrict__ ranges,
+                                                    const uint32_t* __restrict__ tile_order, ViewTable vt, OptK opt,
                                                     float* __restrict__ rgb, float* __restrict__ depth,
                                                     float* __restrict__ alpha_out, float* __restrict__ T_out,
                                                     int32_t* __restrict__ last_out) {
     __shared__ WaveStage stage[kWaves];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int tile = blockIdx.x;
+    const int tile = launch_tile(tile_order, vt);
     const PixelCoords pc = pixel_coords(vt, tile, wave, lane);
     WaveStage& st = stage[wave];
     const uint2 rg = ranges[tile];
@@ -155,9 +210,13 @@ __global__ __launch_bounds__(256) void k_render_fwd(const float4* __restrict__ r
     float T = 1.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f, D = 0.0f;
     int last = 0;
     bool alive = pc.inside;
+    Gather cur = load_entry(rec, load_slot(pair_vals, rg.x + lane, rg.y));
+    uint32_t s_next = load_slot(pair_vals, rg.x + kChunk + lane, rg.y);
     for (uint32_t j0 = rg.x; j0 < rg.y; j0 += kChunk) {
         if (__ballot(alive) == 0) break;     // every pixel of the quadrant has stopped
-        const int n = stage_chunk(rec, pair_vals, rg.x, j0, rg.y, pc, lane, st);
+        const int n = stage_gathered(cur, (int)(j0 - rg.x) + lane + 1, pc, lane, st);
+        cur = load_entry(rec, s_next);                                   // next chunk's records
+        s_next = load_slot(pair_vals, j0 + 2 * kChunk + lane, rg.y);     // and the one after's slots
         for (int k = 0; k < n; ++k) {
             const float4 a = st.g[k], b = st.b[k];
             const Eval e = eval_entry(a, b, pc.fpx, pc.fpy);
@@ -193,12 +252,13 @@ __global__ __launch_bounds__(256) void k_render_fwd(const float4* __restrict__ r
 // stops the pixel.  The unit of work of compositing; measurement only.
 __global__ __launch_bounds__(256) void k_render_count(const float4* __restrict__ rec,
                                                       const uint32_t* __restrict__ pair_vals,
-                                                      const uint2* __restrict__ ranges, ViewTable vt,
+                                                      const uint2* __restrict__ ranges,
+                                                      const uint32_t* __restrict__ tile_order, ViewTable vt,
                                                       int32_t* __restrict__ n_eval) {
     __shared__ WaveStage stage[kWaves];
     __shared__ float2 sbox[kWaves][kChunk];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int tile = blockIdx.x;
+    const int tile = launch_tile(tile_order, vt);
     const PixelCoords pc = pixel_coords(vt, tile, wave, lane);
     WaveStage& st = stage[wave];
     const uint2 rg = ranges[tile];
@@ -231,27 +291,50 @@ __global__ __launch_bounds__(256) void k_render_count(const float4* __restrict__
     if (pc.inside) reinterpret_cast<int2*>(n_eval)[pc.pix] = make_int2(count, count_last);
 }
 
-// sum over the 64 lanes; lane 63 holds the result
-__device__ __forceinline__ float wave_sum_lane63(float x) {
+__device__ __forceinline__ float row_total_lane15(float x) {
+    // inclusive sums within each row of 16 lanes; lane 15 of the row ends with the row's total
     x += __builtin_amdgcn_update_dpp(0.0f, x, 0x111, 0xf, 0xf, false);   // row_shr:1
     x += __builtin_amdgcn_update_dpp(0.0f, x, 0x112, 0xf, 0xf, false);   // row_shr:2
     x += __builtin_amdgcn_update_dpp(0.0f, x, 0x114, 0xf, 0xf, false);   // row_shr:4
     x += __builtin_amdgcn_update_dpp(0.0f, x, 0x118, 0xf, 0xf, false);   // row_shr:8
-    x += __builtin_amdgcn_update_dpp(0.0f, x, 0x142, 0xa, 0xf, false);   // row_bcast:15
-    x += __builtin_amdgcn_update_dpp(0.0f, x, 0x143, 0xc, 0xf, false);   // row_bcast:31
     return x;
+}
+
+// Sums 12 per-lane values over the wave by halving exchanges: the lane
+// halves swap six values (v_permlane32_swap) so that each half sums six
+// fields over lane pairs, the rows swap three (v_permlane16_swap) so that
+// each row of 16 sums three fields over 4 lanes, and DPP row shifts finish
+// the three row sums.  Lane 16 r + 15 ends with the totals of fields
+// 3r .. 3r + 2 in out[0..2] (30 VALU steps instead of 6 per field).
+__device__ __forceinline__ void wave_sum12(const float v[12], float out[3]) {
+    float a[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        const auto p = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[j]), __float_as_uint(v[j + 6]), false,
+                                                        false);
+        // lanes 0-31: field j over (l, l + 32); lanes 32-63: field j + 6 over (l - 32, l)
+        a[j] = __uint_as_float(p[0]) + __uint_as_float(p[1]);
+    }
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const auto p = __builtin_amdgcn_permlane16_swap(__float_as_uint(a[j]), __float_as_uint(a[j + 3]), false,
+                                                        false);
+        // row r: field 3 r + j over the 4 lanes l, l +- 16, l +- 32 of its column
+        out[j] = row_total_lane15(__uint_as_float(p[0]) + __uint_as_float(p[1]));
+    }
 }
 
 constexpr int kG2 = GS_GRAD2D_FLOATS;   // per-slot 2D gradient fields
 
 // Backward: each wave walks its quadrant's list back to front from the
 // deepest `last` of its pixels, in chunks staged and culled as in the
-// forward.  Per surviving entry the lanes' gradients are summed with DPP
-// into a per-wave LDS row; after each chunk the wave adds the rows to the
+// forward.  Per surviving entry the lanes' gradients are summed by
+// wave_sum12 into a per-wave LDS row; after each chunk the wave adds the rows to the
 // per-slot 2D gradient buffer with float atomics (zeros skipped).
 __global__ __launch_bounds__(256) void k_render_bwd(const float4* __restrict__ rec,
                                                     const uint32_t* __restrict__ pair_vals,
-                                                    const uint2* __restrict__ ranges, ViewTable vt, OptK opt,
+                                                    const uint2* __restrict__ ranges,
+                                                    const uint32_t* __restrict__ tile_order, ViewTable vt, OptK opt,
                                                     const float* __restrict__ T_final,
                                                     const int32_t* __restrict__ last_in,
                                                     const float* __restrict__ d_rgb, const float* __restrict__ d_depth,
@@ -259,7 +342,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(const float4* __restrict__ r
     __shared__ WaveStage stage[kWaves];
     __shared__ float s_red[kWaves][kChunk][kG2];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int tile = blockIdx.x;
+    const int tile = launch_tile(tile_order, vt);
     const PixelCoords pc = pixel_coords(vt, tile, wave, lane);
     WaveStage& st = stage[wave];
     const uint2 rg = ranges[tile];
@@ -286,9 +369,19 @@ __global__ __launch_bounds__(256) void k_render_bwd(const float4* __restrict__ r
     float R0 = opt.bg[0], R1 = opt.bg[1], R2 = opt.bg[2], RD = 0.0f, Q = 1.0f;
     const float ln2 = kLn2;
 
+    // chunk [b_end - 64, b_end) of positions, clipped at 0, walked from the
+    // back; lane l of a chunk gathers position b_start + l
+    auto chunk_slot = [&](int b_end_) {
+        const int b_start_ = max(0, b_end_ - kChunk);
+        return b_end_ > 0 ? load_slot(pair_vals, rg.x + (uint32_t)(b_start_ + lane), rg.x + (uint32_t)b_end_) : kNoSlot;
+    };
+    Gather cur = load_entry(rec, chunk_slot(maxlast));
+    uint32_t s_next = chunk_slot(maxlast - kChunk);
     for (int b_end = maxlast; b_end > 0; b_end -= kChunk) {
         const int b_start = max(0, b_end - kChunk);
-        const int n = stage_chunk(rec, pair_vals, rg.x, rg.x + (uint32_t)b_start, rg.x + (uint32_t)b_end, pc, lane, st);
+        const int n = stage_gathered(cur, b_start + lane + 1, pc, lane, st);
+        cur = load_entry(rec, s_next);
+        s_next = chunk_slot(b_end - 2 * kChunk);
         for (int k = n - 1; k >= 0; --k) {
             const float4 a = st.g[k], b = st.b[k], c = st.c[k];
             const int pos = st.pos[k];        // 1-based
@@ -321,11 +414,13 @@ __global__ __launch_bounds__(256) void k_render_bwd(const float4* __restrict__ r
             Q = con ? Q * one_m : Q;
             T = con ? Ti : T;
             if (__ballot(con)) {
-#pragma unroll
-                for (int f = 0; f < kG2; ++f) g[f] = wave_sum_lane63(g[f]);
-                if (lane == 63) {
-#pragma unroll
-                    for (int f = 0; f < kG2; ++f) s_red[wave][k][f] = g[f];
+                float tot[3];
+                wave_sum12(g, tot);
+                if ((lane & 15) == 15) {
+                    const int f0 = 3 * (lane >> 4);
+                    s_red[wave][k][f0 + 0] = tot[0];
+                    s_red[wave][k][f0 + 1] = tot[1];
+                    s_red[wave][k][f0 + 2] = tot[2];
                 }
             } else if (lane == 0) {
 #pragma unroll
@@ -360,15 +455,16 @@ hipError_t launch_render_fwd(const Projected& proj, const uint32_t* pair_vals, c
                              const ViewTable& vt, const OptK& opt, float* rgb, float* depth, float* alpha,
                              float* T_final, int32_t* last, hipStream_t s) {
     if (vt.total_tiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_render_fwd, dim3(vt.total_tiles), dim3(256), 0, s, proj.rec, pair_vals, ranges, vt, opt, rgb,
-                       depth, alpha, T_final, last);
+    hipLaunchKernelGGL(k_render_fwd, dim3(vt.total_tiles), dim3(256), 0, s, proj.rec, pair_vals, ranges,
+                       proj.tile_order, vt, opt, rgb, depth, alpha, T_final, last);
     return hipGetLastError();
 }
 
 hipError_t launch_render_count(const Projected& proj, const uint32_t* pair_vals, const uint2* ranges,
                                const ViewTable& vt, int32_t* n_eval, hipStream_t s) {
     if (vt.total_tiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_render_count, dim3(vt.total_tiles), dim3(256), 0, s, proj.rec, pair_vals, ranges, vt, n_eval);
+    hipLaunchKernelGGL(k_render_count, dim3(vt.total_tiles), dim3(256), 0, s, proj.rec, pair_vals, ranges,
+                       proj.tile_order, vt, n_eval);
     return hipGetLastError();
 }
 
@@ -377,8 +473,8 @@ hipError_t launch_render_bwd(const Projected& proj, const uint32_t* pair_vals, c
                              const float* d_rgb, const float* d_depth, const float* d_alpha, float* grad2d,
                              hipStream_t s) {
     if (vt.total_tiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_render_bwd, dim3(vt.total_tiles), dim3(256), 0, s, proj.rec, pair_vals, ranges, vt, opt,
-                       T_final, last, d_rgb, d_depth, d_alpha, grad2d);
+    hipLaunchKernelGGL(k_render_bwd, dim3(vt.total_tiles), dim3(256), 0, s, proj.rec, pair_vals, ranges,
+                       proj.tile_order, vt, opt, T_final, last, d_rgb, d_depth, d_alpha, grad2d);
     return hipGetLastError();
 }
 

@@ -240,7 +240,7 @@ namespace {
 
 void free_worker(Worker* w) {
     if (!w) return;
-    void* dev[] = {w->proj.rec, w->proj.rect, w->proj.tiles, w->proj.dkey, w->segs_dev, w->pairs, w->ranges,
+    void* dev[] = {w->proj.rec, w->proj.rect, w->proj.tiles, w->proj.dkey, w->proj.tile_order, w->segs_dev, w->pairs, w->ranges,
                    w->bin_ws, w->rgb, w->depth, w->alpha, w->T, w->last};
     for (void* p : dev)
         if (p) (void)hipFree(p);
@@ -266,6 +266,7 @@ int alloc_worker(gs_server* s, Worker* w) {
                          hipHostMallocDefault));
     GS_HIP(dev_alloc(&w->pairs, (size_t)Pc));
     GS_HIP(dev_alloc(&w->ranges, 2 * (size_t)s->tile_cap));
+    GS_HIP(dev_alloc(&w->proj.tile_order, (size_t)s->tile_cap));
     w->bin_ws_bytes = bin_workspace_bytes(S, Pc);
     GS_HIP(hipMalloc(&w->bin_ws, w->bin_ws_bytes));
     GS_HIP(dev_alloc(&w->rgb, 3 * (size_t)X));
@@ -308,6 +309,7 @@ int render_batch(Worker* w, Request* r, int nb, int64_t* n_pairs) {
         if (rc) return rc;
     } else {
         GS_HIP(fill_u32(w->ranges, 0u, 2 * (size_t)vt.total_tiles, w->stream));
+        GS_HIP(launch_tile_order(w->ranges, (uint32_t)vt.total_tiles, w->proj.tile_order, w->stream));
     }
     GS_HIP(launch_render_fwd(w->proj, w->pairs, reinterpret_cast<const uint2*>(w->ranges), vt, s->opt, w->rgb,
                              w->depth, w->alpha, w->T, w->last, w->stream));

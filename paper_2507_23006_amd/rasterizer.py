@@ -90,11 +90,13 @@ class Projected:
     rect: torch.Tensor       # [S, 2] int32 (bit patterns of uint32)
     tiles: torch.Tensor      # [S] int32
     depth_key: torch.Tensor  # [S] int32 (bit patterns of uint32)
+    tile_order: torch.Tensor | None = None   # [T] int32, written by bin_sort
 
     def c(self) -> L.GsProjected:
         p = L.GsProjected()
         p.rec, p.rect = self.rec.data_ptr(), self.rect.data_ptr()
         p.tiles, p.depth_key = self.tiles.data_ptr(), self.depth_key.data_ptr()
+        p.tile_order = self.tile_order.data_ptr() if self.tile_order is not None else None
         return p
 
 
@@ -111,10 +113,12 @@ def project(means, scales, quats, opacities, sh, cams, opts: RenderOptions) -> P
     n = check_params(means, scales, quats, opacities, sh)
     S = n * len(cams)
     dev = means.device
+    n_tiles, _ = views_extent(cams)
     out = Projected(torch.empty((S, L.REC_FLOATS), dtype=torch.float32, device=dev),
                     torch.empty((S, 2), dtype=torch.int32, device=dev),
                     torch.empty((S,), dtype=torch.int32, device=dev),
-                    torch.empty((S,), dtype=torch.int32, device=dev))
+                    torch.empty((S,), dtype=torch.int32, device=dev),
+                    torch.empty((n_tiles,), dtype=torch.int32, device=dev))
     g = gaussians_struct(means, scales, quats, opacities, sh)
     L.check(lib.gs_project(C.byref(g), L.make_cameras(cams), len(cams), C.byref(opts.c()), C.byref(out.c()),
                            _stream()))

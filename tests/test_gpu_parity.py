@@ -184,6 +184,20 @@ def test_alpha_box_covers_every_contribution(gpu_lib, case):
     assert checked > 0
 
 
+@pytest.mark.parametrize("case", ["c1", "multiview"])
+def test_tile_order_is_a_longest_first_permutation(gpu_lib, case):
+    make, cams, od = CASES[case]
+    scene = make()
+    _, proj, pairs, ranges, P, _ = gpu_forward(gpu_lib, scene, cams, _opts(gpu_lib, od))
+    order = proj.tile_order.cpu().numpy().astype(np.int64)
+    n_tiles = sum(c.n_tiles for c in cams)
+    assert np.array_equal(np.sort(order), np.arange(n_tiles))
+    rg = ranges.cpu().numpy().view(np.uint32).astype(np.int64)
+    lens = (rg[:, 1] - rg[:, 0])[order]
+    # non-increasing in 1/8-octave buckets of the list length
+    assert np.all(np.diff(np.floor(8 * np.log2(lens + 1.0))) <= 0)
+
+
 def test_render_count_is_consistent(gpu_lib):
     make, cams, od = CASES["ragged_aa"]
     scene = make()

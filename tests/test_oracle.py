@@ -146,9 +146,15 @@ def test_projection_matches_finite_difference_jacobian():
 
 
 def test_extent_and_rect_rule():
+    """The 3-sigma rectangle rule (tile culling off), and the culled
+    rectangles inside it."""
     cam = S.camera_c1()
     sc = S.scene_c1()
-    p = oracle.project(sc, cam)
+    p = oracle.project(sc, cam, tile_cull=False)
+    q = oracle.project(sc, cam)
+    assert np.all(q["visible"] <= p["visible"]) and q["tiles"].sum() < p["tiles"].sum()
+    vq = q["visible"] == 1
+    assert np.all(q["rect"][vq, :2] >= p["rect"][vq, :2]) and np.all(q["rect"][vq, 2:] <= p["rect"][vq, 2:])
     vis = p["visible"] == 1
     cov = p["cov2d"][vis]
     d = float(np.float32(0.3))
@@ -163,6 +169,61 @@ def test_extent_and_rect_rule():
     np.testing.assert_array_equal(p["tiles"][vis], (rect[:, 2] - rect[:, 0] + 1) * (rect[:, 3] - rect[:, 1] + 1))
     assert np.all(p["tiles"][~vis] == 0)
 
+
+
+def _alpha_tiles(p, cam, i):
+    """Tiles holding a pixel centre where Gaussian i reaches alpha >= 1/255
+    (FP64 brute force over its 3-sigma rectangle)."""
+    x0, y0, x1, y1 = p["rect"][i]
+    xs = np.arange(x0 * 16, min(cam.width, (x1 + 1) * 16)) + 0.5
+    ys = np.arange(y0 * 16, min(cam.height, (y1 + 1) * 16)) + 0.5
+    X, Y = np.meshgrid(xs, ys)
+    dx, dy = X - p["mean2d"][i, 0], Y - p["mean2d"][i, 1]
+    A, B, C = p["conic"][i]
+    power = -0.5 * (A * dx * dx + C * dy * dy) - B * dx * dy
+    alpha = np.minimum(0.99, p["opac"][i] * np.exp(power))
+    hot = (alpha >= 1.0 / 255.0) & (power <= 0)
+    return set(zip((X[hot] // 16).astype(int).tolist(), (Y[hot] // 16).astype(int).tolist()))
+
+
+@pytest.mark.parametrize("which", ["c1", "oblique_aa"])
+def test_tile_culling_keeps_every_reachable_tile(which):
+    """Tile-based culling (paper §3.4.2) may only drop tiles where the
+    Gaussian cannot pass the skip rule at any pixel centre."""
+    if which == "c1":
+        sc, cam, opt = S.scene_c1(), S.camera_c1(), {}
+    else:
+        sc = S.random_scene(1500, seed=21, log_scale_mu=-2.4)
+        sc.opacities[:40] = np.float32(0.0035)     # below the skip threshold everywhere
+        cam = S.Camera(110.0, 110.0, 70.0, 45.0, S.look_at((1.4, -1.3, -3.1), (0.0, 0.1, 0.0)), 140, 90)
+        opt = dict(aa=True)
+    p = oracle.project(sc, cam, tile_cull=False, **opt)
+    q = oracle.project(sc, cam, **opt)
+    dropped = 0
+    for i in np.nonzero(p["visible"])[0]:
+        need = _alpha_tiles(p, cam, i)
+        if not q["visible"][i]:
+            assert not need, i
+            dropped += 1
+            continue
+        x0, y0, x1, y1 = q["rect"][i]
+        assert all(x0 <= tx <= x1 and y0 <= ty <= y1 for tx, ty in need), i
+    assert q["tiles"].sum() < p["tiles"].sum()
+    if which == "oblique_aa":
+        assert dropped > 0
+
+
+@pytest.mark.parametrize("aa", [False, True])
+def test_tile_culling_leaves_images_unchanged(aa):
+    sc = S.random_scene(2500, seed=22, log_scale_mu=-2.5)
+    cams = [S.camera_c1(), S.Camera(90.0, 90.0, 50.0, 35.0, S.look_at((1.0, 1.5, -3.0), (0.0, 0.0, 0.0)), 100, 70)]
+    opt = dict(aa=aa, bg=(0.1, 0.2, 0.3))
+    f0 = oracle.forward(sc, cams, dict(opt, tile_cull=False), guard_eps=None)
+    f1 = oracle.forward(sc, cams, opt, guard_eps=None)
+    assert f1["bins"]["n_pairs"] < f0["bins"]["n_pairs"]
+    for a, b in zip(f0["images"], f1["images"]):
+        for k in ("rgb", "depth", "alpha", "T"):
+            assert np.array_equal(a[k], b[k]), k
 
 def test_near_plane_culls():
     cam = small_cam(tz=0.0)
@@ -331,11 +392,15 @@ def test_matches_numpy_brute_force(seed, aa, deg, bg):
     sc = S.random_scene(96, seed=seed, log_scale_mu=-2.3)
     cam = small_cam(W=40 + seed, H=33, f=35.0) if seed % 2 == 0 else oblique_cam(W=40 + seed, H=33, f=35.0)
     opt = dict(sh_degree=deg, aa=aa, bg=bg)
-    im = oracle.forward(sc, cam, opt)["images"][0]
     ref = brute.render(sc, cam, **opt)
-    for k in ("rgb", "depth", "alpha", "T"):
-        np.testing.assert_allclose(im[k], ref[k], atol=1e-13, err_msg=k)
-    np.testing.assert_array_equal(im["last"], ref["last"])
+    # the brute force lists every Gaussian of the 3-sigma rectangle, so list
+    # positions (last) compare with tile culling off; images with it on too
+    for cull in (False, True):
+        im = oracle.forward(sc, cam, dict(opt, tile_cull=cull))["images"][0]
+        for k in ("rgb", "depth", "alpha", "T"):
+            np.testing.assert_allclose(im[k], ref[k], atol=1e-13, err_msg=k)
+        if not cull:
+            np.testing.assert_array_equal(im["last"], ref["last"])
 
 
 # --------------------------------------------------------------- gradients
