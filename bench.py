@@ -207,6 +207,9 @@ def main():
         del params, stats, proj, pv, rg, out
         serve = serve_bench(gs, S, torch, scene, opts, args.serve_requests)
 
+    if roof is not None:
+        roof["traffic"] = counted_traffic(roof["kernel"])
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(scene, cam, args.cpu_crop)
@@ -239,6 +242,30 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(rec), flush=True)
+
+
+STAGE_KERNEL = {"render_fwd": "k_render_fwd", "composite_bwd": "k_render_bwd", "project": "k_project_fwd",
+                "project_bwd": "k_project_bwd"}
+
+
+def counted_traffic(stage):
+    """HBM bytes per launch of the stage's kernel from the committed
+    rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE scaled by a plain
+    device copy), or None when the summary is missing or the compositing
+    source has changed since the counters were taken."""
+    import hashlib
+    root = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(root, "profiles", "counters_urban6M_1080p.md")
+    src = os.path.join(root, "paper_2507_23006_amd", "csrc", "render.hip")
+    try:
+        line = next(l for l in open(path) if l.strip().startswith("COUNTERS "))
+        rec = json.loads(line.strip()[len("COUNTERS "):])
+        if rec["render_hip_sha256"] != hashlib.sha256(open(src, "rb").read()).hexdigest():
+            return None
+        k = rec["kernels"][STAGE_KERNEL[stage]]
+        return int(k["read_bytes"] + k["write_bytes"])
+    except (OSError, StopIteration, KeyError, ValueError):
+        return None
 
 
 def serve_bench(gs, S, torch, fine, opts, n_requests):

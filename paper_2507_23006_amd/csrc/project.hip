@@ -166,75 +166,184 @@ __device__ __forceinline__ void colour_view(const ViewK& V, const OptK& opt, dou
     out.rec[4 * slot + 2] = r2;
 }
 
-// every view of the launch sees the same n Gaussians: slot = view * n + g.
-// One thread per Gaussian walks the views, so its parameters are read once.
-__global__ __launch_bounds__(256) void k_project_fwd(GaussPtrs gp, int64_t n, ViewTable vt, OptK opt,
-                                                     Projected out) {
-    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (g >= n) return;
+// Conservative pre-test of project_view: false only when the Gaussian
+// certainly covers no tile.  With M = R(q) diag(s), R orthonormal,
+// lambda_max(Sigma_2D) = |J W M|^2 <= |J|_F^2 s_max^2, so the 3-sigma radius
+// is at most 3 sqrt(|J|_F^2 s_max^2 + dilation); if even that rectangle
+// misses the image, or the opacity is below the skip threshold (o' = o rho
+// <= o), the exact test culls too.
+__device__ __forceinline__ bool may_cover(const ViewK& V, const OptK& opt, double tx, double ty, double tz,
+                                          double smax, float opac) {
+    if (!(opac >= kAlphaMin)) return false;
+    const double u = tx / tz, vv = ty / tz;
+    const double uc = fmin(fmax(u, V.ulo), V.uhi), vc = fmin(fmax(vv, V.vlo), V.vhi);
+    const double fx = V.fx, fy = V.fy;
+    const double jf2 = (fx * fx * (1.0 + uc * uc) + fy * fy * (1.0 + vc * vc)) / (tz * tz);
+    const double rb = ceil(3.0 * sqrt(jf2 * smax * smax + (double)opt.dilation) * (1.0 + 1e-6)) + 1.0;
+    const double mx = fx * u + (double)V.cx, my = fy * vv + (double)V.cy;
+    if (!(isfinite(rb) && isfinite(mx) && isfinite(my))) return true;    // the exact path decides
+    const double fmx = floor(mx), fmy = floor(my);
+    return fmx + rb >= 0.0 && fmx - rb <= (double)(V.tiles_x * kTile - 1) && fmy + rb >= 0.0 &&
+           fmy - rb <= (double)(V.tiles_y * kTile - 1);
+}
+
+// exact projection and colour of Gaussian g into the views of `cand`; slot
+// of view v = slot_base + v * slot_stride
+__device__ __forceinline__ void project_candidate(const GaussPtrs& gp, int64_t n, const ViewTable& vt,
+                                                  const OptK& opt, const Projected& out, int64_t g, uint32_t cand,
+                                                  int64_t slot_base, int64_t slot_stride) {
     const double mu0 = gp.means[g], mu1 = gp.means[n + g], mu2 = gp.means[2 * n + g];
-    bool have_M = false, shape_ok = false;
-    double M[9];
-    double opac = 0.0;
-    uint32_t vis_mask = 0;
+    double M[9], opac = 0.0;
+    const bool shape_ok = load_shape(gp, n, g, M, opac);
+    uint32_t vis = 0;
     for (int v = 0; v < vt.n_views; ++v) {
+        if (!(cand & (1u << v))) continue;
         const ViewK& V = vt.v[v];
-        const int64_t slot = (int64_t)v * n + g;
+        const int64_t slot = slot_base + v * slot_stride;
         double tx, ty, tz;
         view_point(V, mu0, mu1, mu2, tx, ty, tz);
-        uint32_t ntiles = 0;
-        if (tz >= (double)V.znear && tz <= (double)V.zfar) {
-            if (!have_M) {
-                shape_ok = load_shape(gp, n, g, M, opac);
-                have_M = true;
-            }
-            if (shape_ok) ntiles = project_view(V, opt, tx, ty, tz, M, opac, out, slot);
-        }
-        if (ntiles) vis_mask |= 1u << v;
+        const uint32_t ntiles = shape_ok ? project_view(V, opt, tx, ty, tz, M, opac, out, slot) : 0u;
+        if (ntiles) vis |= 1u << v;
         out.tiles[slot] = ntiles;
         out.dkey[slot] = ntiles ? __float_as_uint((float)tz) : 0xFFFFFFFFu;
     }
-    if (!vis_mask) return;
     const float4* shq = reinterpret_cast<const float4*>(gp.sh) + 12 * g;
     for (int v = 0; v < vt.n_views; ++v)
-        if (vis_mask & (1u << v)) colour_view(vt.v[v], opt, mu0, mu1, mu2, shq, out, (int64_t)v * n + g);
+        if (vis & (1u << v)) colour_view(vt.v[v], opt, mu0, mu1, mu2, shq, out, slot_base + v * slot_stride);
 }
 
-// Views with their own selections of Gaussians (served requests): slot s
-// belongs to the last segment with slot_start <= s, and maps to Gaussian
-// gstart + (s - slot_start) seen by that segment's view.  One thread per slot.
-__global__ __launch_bounds__(256) void k_project_slots(GaussPtrs gp, int64_t n, ViewTable vt, OptK opt,
-                                                       const SlotSeg* __restrict__ segs, int32_t n_seg,
-                                                       uint32_t n_slots, Projected out) {
-    const uint32_t s = blockIdx.x * 256 + threadIdx.x;
-    if (s >= n_slots) return;
+constexpr int kPF = 256;                 // threads per workgroup
+constexpr int kPFPer = 4;                // items per thread in the pre-test
+constexpr int kPFSpan = kPF * kPFPer;    // items per workgroup
+
+// appends the lanes with cand != 0 to the workgroup's LDS list as
+// (local index | cand << 16)
+__device__ __forceinline__ void list_append(uint32_t cand, int loc, int lane, uint32_t* s_list, uint32_t* s_count) {
+    const uint64_t m = __ballot(cand != 0);
+    if (!m) return;
+    const int below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
+    uint32_t base = 0;
+    if (lane == 0) base = atomicAdd(s_count, (uint32_t)__popcll(m));
+    base = __shfl(base, 0);
+    if (cand) s_list[base + below] = (uint32_t)loc | (cand << 16);
+}
+
+// Every view of the launch sees the same n Gaussians: slot = view * n + g.
+// A workgroup owns 1024 Gaussians.  Pass 1 reads each mean (and, for
+// Gaussians in front of some camera, its scales and opacity), runs the
+// conservative pre-test per view, writes the culled slots' count and key
+// with coalesced stores and lists the rest in LDS; pass 2 runs the FP64 EWA
+// and the colour on full waves of listed Gaussians only (a large scene
+// leaves most lanes culled, which would otherwise idle through the FP64
+// chain of their wave's few visible neighbours).
+__global__ __launch_bounds__(kPF) void k_project_fwd(GaussPtrs gp, int64_t n, ViewTable vt, OptK opt,
+                                                     Projected out) {
+    __shared__ uint32_t s_list[kPFSpan];
+    __shared__ uint32_t s_count;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int64_t g0 = (int64_t)blockIdx.x * kPFSpan;
+    if (tid == 0) s_count = 0;
+    __syncthreads();
+    for (int i = 0; i < kPFPer; ++i) {
+        const int loc = i * kPF + tid;
+        const int64_t g = g0 + loc;
+        uint32_t cand = 0;
+        if (g < n) {
+            const double mu0 = gp.means[g], mu1 = gp.means[n + g], mu2 = gp.means[2 * n + g];
+            double smax = -1.0;
+            float o = 0.0f;
+            for (int v = 0; v < vt.n_views; ++v) {
+                const ViewK& V = vt.v[v];
+                double tx, ty, tz;
+                view_point(V, mu0, mu1, mu2, tx, ty, tz);
+                if (tz >= (double)V.znear && tz <= (double)V.zfar) {
+                    if (smax < 0.0) {
+                        smax = fmax(fabs((double)gp.scales[g]),
+                                    fmax(fabs((double)gp.scales[n + g]), fabs((double)gp.scales[2 * n + g])));
+                        o = gp.opac[g];
+                    }
+                    if (may_cover(V, opt, tx, ty, tz, smax, o)) cand |= 1u << v;
+                }
+                if (!(cand & (1u << v))) {
+                    const int64_t slot = (int64_t)v * n + g;
+                    out.tiles[slot] = 0u;
+                    out.dkey[slot] = 0xFFFFFFFFu;
+                }
+            }
+        }
+        list_append(cand, loc, lane, s_list, &s_count);
+    }
+    __syncthreads();
+    const uint32_t cnt = s_count;
+    for (uint32_t j = tid; j < cnt; j += kPF) {
+        const uint32_t e = s_list[j];
+        const int64_t g = g0 + (e & 0xFFFFu);
+        project_candidate(gp, n, vt, opt, out, g, e >> 16, g, n);
+    }
+}
+
+// slot s of a segment table: the last segment with slot_start <= s
+__device__ __forceinline__ int segment_of(const SlotSeg* __restrict__ segs, int32_t n_seg, uint32_t s) {
     int lo = 0, hi = n_seg;      // invariant: segs[lo].slot_start <= s, answer in [lo, hi)
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
         if (segs[mid].slot_start <= s) lo = mid; else hi = mid;
     }
-    const SlotSeg sg = segs[lo];
-    const int64_t g = sg.gstart + (int64_t)(s - sg.slot_start);
-    const ViewK& V = vt.v[sg.view];
-    const double mu0 = gp.means[g], mu1 = gp.means[n + g], mu2 = gp.means[2 * n + g];
-    double tx, ty, tz;
-    view_point(V, mu0, mu1, mu2, tx, ty, tz);
-    uint32_t ntiles = 0;
-    if (tz >= (double)V.znear && tz <= (double)V.zfar) {
-        double M[9], opac;
-        if (load_shape(gp, n, g, M, opac)) ntiles = project_view(V, opt, tx, ty, tz, M, opac, out, s);
+    return lo;
+}
+
+// Views with their own selections of Gaussians (served requests): slot s
+// maps to Gaussian gstart + (s - slot_start) of its segment, seen by the
+// segment's view.  Same two passes as k_project_fwd, over 1024 slots.
+__global__ __launch_bounds__(kPF) void k_project_slots(GaussPtrs gp, int64_t n, ViewTable vt, OptK opt,
+                                                       const SlotSeg* __restrict__ segs, int32_t n_seg,
+                                                       uint32_t n_slots, Projected out) {
+    __shared__ uint32_t s_list[kPFSpan];
+    __shared__ uint32_t s_count;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const uint32_t s0 = blockIdx.x * kPFSpan;
+    if (tid == 0) s_count = 0;
+    __syncthreads();
+    for (int i = 0; i < kPFPer; ++i) {
+        const int loc = i * kPF + tid;
+        const uint32_t s = s0 + loc;
+        uint32_t cand = 0;
+        if (s < n_slots) {
+            const SlotSeg sg = segs[segment_of(segs, n_seg, s)];
+            const int64_t g = sg.gstart + (int64_t)(s - sg.slot_start);
+            const ViewK& V = vt.v[sg.view];
+            double tx, ty, tz;
+            view_point(V, gp.means[g], gp.means[n + g], gp.means[2 * n + g], tx, ty, tz);
+            if (tz >= (double)V.znear && tz <= (double)V.zfar) {
+                const double smax = fmax(fabs((double)gp.scales[g]),
+                                         fmax(fabs((double)gp.scales[n + g]), fabs((double)gp.scales[2 * n + g])));
+                if (may_cover(V, opt, tx, ty, tz, smax, gp.opac[g])) cand = 1u << sg.view;
+            }
+            if (!cand) {
+                out.tiles[s] = 0u;
+                out.dkey[s] = 0xFFFFFFFFu;
+            }
+        }
+        list_append(cand, loc, lane, s_list, &s_count);
     }
-    out.tiles[s] = ntiles;
-    out.dkey[s] = ntiles ? __float_as_uint((float)tz) : 0xFFFFFFFFu;
-    if (ntiles) colour_view(V, opt, mu0, mu1, mu2, reinterpret_cast<const float4*>(gp.sh) + 12 * g, out, s);
+    __syncthreads();
+    const uint32_t cnt = s_count;
+    for (uint32_t j = tid; j < cnt; j += kPF) {
+        const uint32_t e = s_list[j];
+        const uint32_t s = s0 + (e & 0xFFFFu);
+        const SlotSeg sg = segs[segment_of(segs, n_seg, s)];
+        const int64_t g = sg.gstart + (int64_t)(s - sg.slot_start);
+        // one view bit: the slot is s itself (stride 0)
+        project_candidate(gp, n, vt, opt, out, g, e >> 16, (int64_t)s, 0);
+    }
 }
 
 }  // namespace
 
 hipError_t launch_project_fwd(const GaussPtrs& g, int64_t n, const ViewTable& vt, const OptK& opt,
                               const Projected& out, hipStream_t s) {
-    const unsigned blocks = (unsigned)((n + 255) / 256);
-    hipLaunchKernelGGL(k_project_fwd, dim3(blocks), dim3(256), 0, s, g, n, vt, opt, out);
+    const unsigned blocks = (unsigned)((n + kPFSpan - 1) / kPFSpan);
+    hipLaunchKernelGGL(k_project_fwd, dim3(blocks), dim3(kPF), 0, s, g, n, vt, opt, out);
     return hipGetLastError();
 }
 
@@ -242,8 +351,8 @@ hipError_t launch_project_slots(const GaussPtrs& g, int64_t n, const ViewTable& 
                                 const SlotSeg* segs, int32_t n_seg, uint32_t n_slots, const Projected& out,
                                 hipStream_t s) {
     if (!n_slots) return hipSuccess;
-    hipLaunchKernelGGL(k_project_slots, dim3((n_slots + 255) / 256), dim3(256), 0, s, g, n, vt, opt, segs, n_seg,
-                       n_slots, out);
+    hipLaunchKernelGGL(k_project_slots, dim3((n_slots + kPFSpan - 1) / kPFSpan), dim3(kPF), 0, s, g, n, vt, opt, segs,
+                       n_seg, n_slots, out);
     return hipGetLastError();
 }
 

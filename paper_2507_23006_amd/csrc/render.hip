@@ -102,6 +102,34 @@ __device__ __forceinline__ bool box_hits_quadrant(const float4 g, const float4 r
            fabsf(my - qcy) <= r3.y + 3.5f + 1e-3f + 1e-6f * fabsf(my) && r3.x >= 0.0f;
 }
 
+// Does the entry's alpha reach 1/255 anywhere in the wave's quadrant?  The
+// exponent p(d) = qa dx^2 + qb dx dy + qc dy^2 (d = pixel centre - mean) is a
+// concave quadratic; its maximum over the rectangle spanned by the
+// quadrant's pixel centres is 0 when the mean lies inside, otherwise the
+// largest of the four edges' one-dimensional maxima.  The entry can only be
+// composited where o' 2^p >= 1/255, i.e. p >= log2(1/(255 o')); the test is
+// relaxed by 1e-5 and by 16 float32 ulps of the terms' magnitudes, which
+// covers the rounding of both this test and the kernels' own evaluation of
+// p, so an entry it rejects has alpha < 1/255 at every pixel of the quadrant.
+__device__ __forceinline__ float edge_max(float qa, float qb, float qc, float dx, float lo, float hi) {
+    // max over dy in [lo, hi] of qa dx^2 + qb dx dy + qc dy^2 (qc < 0)
+    const float dy = fminf(fmaxf(-qb * dx / (2.0f * qc), lo), hi);
+    return fmaf(qa, dx * dx, fmaf(qb, dx * dy, qc * (dy * dy)));
+}
+
+__device__ __forceinline__ bool ellipse_hits_quadrant(const float4 g, const float4 r1, float qcx, float qcy) {
+    const float qa = g.z, qb = g.w, qc = r1.x, o = r1.y;
+    const float dx0 = (qcx - 3.5f) - g.x, dx1 = (qcx + 3.5f) - g.x;
+    const float dy0 = (qcy - 3.5f) - g.y, dy1 = (qcy + 3.5f) - g.y;
+    if (dx0 <= 0.0f && dx1 >= 0.0f && dy0 <= 0.0f && dy1 >= 0.0f) return true;
+    float m = fmaxf(edge_max(qa, qb, qc, dx0, dy0, dy1), edge_max(qa, qb, qc, dx1, dy0, dy1));
+    m = fmaxf(m, fmaxf(edge_max(qc, qb, qa, dy0, dx0, dx1), edge_max(qc, qb, qa, dy1, dx0, dx1)));
+    const float DX = fmaxf(fabsf(dx0), fabsf(dx1)), DY = fmaxf(fabsf(dy0), fabsf(dy1));
+    const float mag = fabsf(qa) * DX * DX + fabsf(qb) * DX * DY + fabsf(qc) * DY * DY;
+    const float thr = -__log2f(255.0f * o) - 1e-5f - 16.0f * 5.9604645e-8f * mag;
+    return m >= thr;
+}
+
 __device__ __forceinline__ unsigned long long lanes_below(int lane) {
     return lane ? (~0ull >> (64 - lane)) : 0ull;
 }
@@ -179,7 +207,8 @@ __device__ __forceinline__ Gather load_entry(const float4* __restrict__ rec, uin
 __device__ __forceinline__ int stage_gathered(const Gather& e, int pos, const PixelCoords& pc, int lane,
                                               WaveStage& st) {
     const float4 g = stage_geom(e.r0, e.r1, e.r2, pc.ox, pc.oy);
-    const bool hit = e.slot != kNoSlot && box_hits_quadrant(g, e.r3, pc.qcx, pc.qcy);
+    const bool hit = e.slot != kNoSlot && box_hits_quadrant(g, e.r3, pc.qcx, pc.qcy) &&
+                     ellipse_hits_quadrant(g, e.r1, pc.qcx, pc.qcy);
     const unsigned long long m = __ballot(hit);
     if (hit) {
         const int d = __popcll(m & lanes_below(lane));
@@ -217,6 +246,7 @@ __global__ __launch_bounds__(256) void k_render_fwd(const float4* __restrict__ r
         const int n = stage_gathered(cur, (int)(j0 - rg.x) + lane + 1, pc, lane, st);
         cur = load_entry(rec, s_next);                                   // next chunk's records
         s_next = load_slot(pair_vals, j0 + 2 * kChunk + lane, rg.y);     // and the one after's slots
+#pragma unroll 4
         for (int k = 0; k < n; ++k) {
             const float4 a = st.g[k], b = st.b[k];
             const Eval e = eval_entry(a, b, pc.fpx, pc.fpy);
