@@ -124,8 +124,7 @@ def main():
         for p in params:
             p.grad = None
         rgb, depth, alpha = gs.rasterize(*params, cams, opts, stats)
-        ed = depth / alpha.clamp_min(1e-10)
-        loss = (rgb - tgt_rgb).abs().mean() + 0.5 * (ed - tgt_d).abs().mean()
+        loss = gs.l1_depth_loss(rgb, depth, alpha, tgt_rgb, tgt_d, 0.5)
         loss.backward()
         return loss
 
@@ -273,9 +272,11 @@ def serve_bench(gs, S, torch, fine, opts, n_requests):
     block: levels of 1M, 3M and 6M Gaussians resident in HBM, 30 m render-time
     partitions, thresholds (30, 60, inf) m; Poisson arrivals at 150 req/s,
     resolutions 640x360 / 1280x720 / 1920x1080 and budgets 1M / 3M / 6M
-    drawn uniformly.  Run twice on the same trace: "plain" (one request per
+    drawn uniformly.  Run on the same trace: "plain" (one request per
     launch, one stream, FIFO) and "served" (continuous batching of up to 8
-    views, two worker streams).  Latency = completion - scheduled arrival."""
+    views, two worker streams), then both again with every request arriving
+    at once ("_burst": the saturated throughput).  Latency = completion -
+    scheduled arrival."""
     t_gen = time.time()
     lod = S.lod_scene_c4(fine)
     sc, offsets = lod.combined()
@@ -298,11 +299,14 @@ def serve_bench(gs, S, torch, fine, opts, n_requests):
                                  pair_capacity=96_000_000, pixel_capacity=1 << 24, queue_capacity=n_requests),
     }
     res = {}
-    for name, cfg in modes.items():
+    # the trace as scheduled, then the same requests all at once (saturation)
+    runs = [(name, cfg, False) for name, cfg in modes.items()] + [(name + "_burst", cfg, True)
+                                                                  for name, cfg in modes.items()]
+    for name, cfg, burst in runs:
         srv = gs.Server(params, table, opts, cfg)
         t0 = srv.now() + 0.5
         for r, o in zip(trace, outs):
-            srv.submit(r["camera"], r["budget"], o, t0 + r["t"])
+            srv.submit(r["camera"], r["budget"], o, t0 + (0.0 if burst else r["t"]))
         n_done, n_fail, views, t_print = 0, 0, 0, time.time()
         while n_done < len(trace):
             for c in srv.poll(max_items=512, timeout_us=200_000):

@@ -217,6 +217,20 @@ int gs_project_bwd(const gs_gaussians *g, const gs_camera *cams, int32_t n_views
  * unwritten) -- for inspection and tests. */
 const float *gs_render_bwd_grad2d(void *ws);
 
+/* Training loss and its gradient in one pass: the L1 term of Eq. 3 plus the
+ * depth regulariser of §3.5.3 on the expected depth,
+ *   L = mean_{pix, ch} |rgb - target_rgb|
+ *     + lambda_depth * mean_pix |depth / max(alpha, 1e-10) - target_depth|
+ * over n_pix pixels (rgb, target_rgb [pix][3]; depth, alpha, target_depth
+ * [pix]; target_depth NULL drops the depth term).  Writes loss [1] and the
+ * gradients d_rgb [pix][3], d_depth [pix], d_alpha [pix] (sign(x) as the
+ * derivative of |x|, 0 at 0; no gradient through the clamp below 1e-10) on
+ * the device.  The total is summed in a fixed order (deterministic). */
+size_t gs_loss_workspace_size(int64_t n_pix);
+int gs_loss_l1_depth(const float *rgb, const float *depth, const float *alpha, const float *target_rgb,
+                     const float *target_depth, int64_t n_pix, float lambda_depth, float *loss, float *d_rgb,
+                     float *d_depth, float *d_alpha, void *ws, size_t ws_bytes, void *stream);
+
 /* ------------------------------------------------------------------------
  * Level-of-detail selection and serving (§3.4.2 "Detail Level Selection",
  * Fig. 3b; distance thresholds as in Tab. 13).

@@ -309,6 +309,29 @@ int gs_render_count(const gs_projected* proj, const uint32_t* pair_vals, const u
     }
 }
 
+size_t gs_loss_workspace_size(int64_t n_pix) {
+    if (n_pix < 1) n_pix = 1;
+    return align_up(loss_partials(n_pix) * sizeof(double));
+}
+
+int gs_loss_l1_depth(const float* rgb, const float* depth, const float* alpha, const float* target_rgb,
+                     const float* target_depth, int64_t n_pix, float lambda_depth, float* loss, float* d_rgb,
+                     float* d_depth, float* d_alpha, void* ws, size_t ws_bytes, void* stream) {
+    try {
+        GS_REQUIRE(n_pix >= 1 && n_pix <= (1LL << 34), "n_pix=%lld out of range", (long long)n_pix);
+        GS_REQUIRE(rgb && target_rgb && loss && d_rgb && d_depth && d_alpha && ws, "NULL buffer");
+        GS_REQUIRE(!target_depth || (depth && alpha), "the depth term needs depth and alpha");
+        GS_REQUIRE(std::isfinite(lambda_depth), "lambda_depth not finite");
+        GS_REQUIRE(((uintptr_t)ws & 7) == 0, "workspace must be 8-byte aligned");
+        GS_REQUIRE(ws_bytes >= gs_loss_workspace_size(n_pix), "workspace too small");
+        GS_HIP(launch_loss(rgb, depth, alpha, target_rgb, target_depth, n_pix, lambda_depth, loss, d_rgb, d_depth,
+                           d_alpha, static_cast<double*>(ws), (hipStream_t)stream));
+        return GS_OK;
+    } catch (...) {
+        return fail(GS_ERR_INTERNAL, "unexpected exception in gs_loss_l1_depth");
+    }
+}
+
 size_t gs_render_bwd_workspace_size(int64_t n_slots) {
     if (n_slots < 1) n_slots = 1;
     return align_up((size_t)n_slots * GS_GRAD2D_FLOATS * sizeof(float));

@@ -180,6 +180,12 @@ hipError_t launch_render_bwd(const Projected& proj, const uint32_t* pair_vals, c
                              const float* d_rgb, const float* d_depth, const float* d_alpha, float* grad2d,
                              hipStream_t s);
 
+// training loss (loss.hip): per-workgroup partial sums, then a fixed-order total
+size_t loss_partials(int64_t n_pix);
+hipError_t launch_loss(const float* rgb, const float* depth, const float* alpha, const float* t_rgb,
+                       const float* t_depth, int64_t n_pix, float lambda, float* loss, float* d_rgb, float* d_depth,
+                       float* d_alpha, double* partial, hipStream_t s);
+
 // projection backward (project_bwd.hip)
 hipError_t launch_project_bwd(const GaussPtrs& g, int64_t n, const ViewTable& vt, const OptK& opt,
                               const Projected& proj, const float* grad2d, const GradPtrs& out,

@@ -263,8 +263,8 @@ class GsRasterize(torch.autograd.Function):
         _mark("bin_sort")
         out = render_fwd(proj, pair_vals, ranges, cams, opts)
         _mark("render_fwd")
-        ctx.save_for_backward(*params, proj.rec, proj.rect, proj.tiles, proj.depth_key, pair_vals, ranges,
-                              out["T"], out["last"])
+        ctx.save_for_backward(*params, proj.rec, proj.rect, proj.tiles, proj.depth_key, proj.tile_order, pair_vals,
+                              ranges, out["T"], out["last"])
         ctx.cams, ctx.opts, ctx.stats = list(cams), opts, stats
         if stats is not None:
             stats.n_pairs = P
@@ -272,8 +272,9 @@ class GsRasterize(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, d_rgb, d_depth, d_alpha):
-        (means, scales, quats, opacities, sh, rec, rect, tiles, dkey, pair_vals, ranges, T, last) = ctx.saved_tensors
-        proj = Projected(rec, rect, tiles, dkey)
+        (means, scales, quats, opacities, sh, rec, rect, tiles, dkey, order, pair_vals, ranges, T,
+         last) = ctx.saved_tensors
+        proj = Projected(rec, rect, tiles, dkey, order)
         g = render_bwd((means, scales, quats, opacities, sh), ctx.cams, ctx.opts, proj, pair_vals, ranges, T, last,
                        d_rgb, d_depth, d_alpha)
         if ctx.stats is not None:
@@ -286,6 +287,47 @@ def rasterize(means, scales, quats, opacities, sh, cams, opts: RenderOptions | N
               stats: RenderStats | None = None):
     """Autograd entry point; returns flat (rgb, depth, alpha) over all views."""
     return GsRasterize.apply(means, scales, quats, opacities, sh, list(cams), opts or RenderOptions(), stats)
+
+
+class L1DepthLoss(torch.autograd.Function):
+    """Training loss of the library's fused kernel: mean |rgb - target_rgb|
+    + lambda * mean |depth / max(alpha, 1e-10) - target_depth| (the depth
+    term is dropped when target_depth is None).  The forward computes the
+    loss and its gradient in one pass; the backward scales the gradient."""
+
+    @staticmethod
+    def forward(ctx, rgb, depth, alpha, target_rgb, target_depth, lambda_depth: float):
+        lib = L.load()
+        n_pix = rgb.shape[0]
+        rgb, target_rgb = rgb.detach().contiguous(), target_rgb.detach().contiguous()
+        if rgb.shape != (n_pix, 3) or target_rgb.shape != (n_pix, 3):
+            raise ValueError("rgb and target_rgb must be [n_pix, 3]")
+        has_d = target_depth is not None
+        depth, alpha = depth.detach().contiguous(), alpha.detach().contiguous()
+        td = target_depth.detach().contiguous() if has_d else None
+        for t in (rgb, target_rgb, depth, alpha) + ((td,) if has_d else ()):
+            if not (t.is_cuda and t.dtype == torch.float32):
+                raise ValueError("loss inputs must be float32 CUDA tensors")
+        if depth.numel() != n_pix or alpha.numel() != n_pix or (has_d and td.numel() != n_pix):
+            raise ValueError("depth, alpha and target_depth need one value per pixel")
+        loss = torch.empty((1,), dtype=torch.float32, device=rgb.device)
+        d_rgb, d_depth, d_alpha = torch.empty_like(rgb), torch.empty_like(depth), torch.empty_like(alpha)
+        wsz = lib.gs_loss_workspace_size(n_pix)
+        ws = _default_ws.get("loss", wsz + 256, rgb.device)
+        L.check(lib.gs_loss_l1_depth(_ptr(rgb), _ptr(depth), _ptr(alpha), _ptr(target_rgb), _ptr(td), n_pix,
+                                     float(lambda_depth), _ptr(loss), _ptr(d_rgb), _ptr(d_depth), _ptr(d_alpha),
+                                     C.c_void_p(Workspace.aligned(ws)), wsz, _stream()))
+        ctx.save_for_backward(d_rgb, d_depth, d_alpha)
+        return loss[0]
+
+    @staticmethod
+    def backward(ctx, g):
+        d_rgb, d_depth, d_alpha = ctx.saved_tensors
+        return d_rgb * g, d_depth * g, d_alpha * g, None, None, None
+
+
+def l1_depth_loss(rgb, depth, alpha, target_rgb, target_depth=None, lambda_depth: float = 0.5):
+    return L1DepthLoss.apply(rgb, depth, alpha, target_rgb, target_depth, lambda_depth)
 
 
 def split_views(flat: torch.Tensor, cams) -> list:

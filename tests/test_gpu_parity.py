@@ -373,3 +373,26 @@ def test_invalid_arguments_raise(gpu_lib):
         gpu_lib.project(*params, [small_cam(10, 10, 10.0)] * 17, opts)
     with pytest.raises(gpu_lib.GsError):
         gpu_lib.project(*params, [small_cam(10, 10, 10.0)], gpu_lib.RenderOptions(sh_degree=4))
+
+
+@pytest.mark.parametrize("n_pix,with_depth", [(1, True), (160 * 120, True), (1920 * 1080, True), (5000, False)])
+def test_loss_kernel_matches_oracle(gpu_lib, n_pix, with_depth):
+    from oracle import loss as OL
+    rng = np.random.default_rng(n_pix)
+    rgb, t_rgb = rng.random((n_pix, 3)).astype(np.float32), rng.random((n_pix, 3)).astype(np.float32)
+    D = rng.uniform(0, 40, n_pix).astype(np.float32)
+    a = rng.uniform(0, 1, n_pix).astype(np.float32)
+    a[::97] = 0.0                                    # below the clamp
+    td = rng.uniform(20, 45, n_pix).astype(np.float32) if with_depth else None
+    dev = [torch.from_numpy(x).cuda().requires_grad_(True) for x in (rgb, D, a)]
+    tt = [torch.from_numpy(t_rgb).cuda(), torch.from_numpy(td).cuda() if with_depth else None]
+    loss = gpu_lib.l1_depth_loss(dev[0], dev[1], dev[2], tt[0], tt[1], 0.5)
+    (2.0 * loss).backward()
+    L, dr, dd, da = OL.l1_depth(rgb, D, a, t_rgb, td, 0.5)
+    assert abs(loss.item() - L) <= 1e-6 * abs(L)
+    np.testing.assert_allclose(dev[0].grad.cpu().numpy(), 2 * dr, rtol=1e-6, atol=0)
+    np.testing.assert_allclose(dev[1].grad.cpu().numpy(), 2 * dd, rtol=2e-6, atol=0)
+    np.testing.assert_allclose(dev[2].grad.cpu().numpy(), 2 * da, rtol=4e-6, atol=0)
+    # the loss is summed in a fixed order
+    again = gpu_lib.l1_depth_loss(dev[0], dev[1], dev[2], tt[0], tt[1], 0.5)
+    assert torch.equal(loss, again)

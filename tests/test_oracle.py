@@ -546,3 +546,38 @@ def test_float32_and_float64_inputs_give_identical_results():
     assert np.array_equal(res[0][0], res[1][0])
     for k in GROUPS:      # the OpenMP backward sums in varying order: equal up to rounding
         np.testing.assert_allclose(res[0][1][k], res[1][1][k], rtol=1e-10, atol=1e-14, err_msg=k)
+
+
+# --------------------------------------------------------------- loss
+
+def test_loss_fixture_by_hand():
+    from oracle import loss as OL
+    # one pixel: |(0.5, 0.2, 0.9) - 0.4| = (0.1, 0.2, 0.5) -> 0.8 / 3; expected depth 2 / 0.5 = 4 vs 3 -> 0.5 * 1
+    L, dr, dd, da = OL.l1_depth([[0.5, 0.2, 0.9]], [2.0], [0.5], [[0.4, 0.4, 0.4]], [3.0], 0.5)
+    assert abs(L - (0.8 / 3 + 0.5)) < 1e-15
+    np.testing.assert_allclose(dr, [[1 / 3, -1 / 3, 1 / 3]], rtol=1e-15)
+    np.testing.assert_allclose(dd, [0.5 / 0.5], rtol=1e-15)           # lambda * sign / alpha
+    np.testing.assert_allclose(da, [-0.5 * 2.0 / 0.25], rtol=1e-15)   # -lambda * sign * D / alpha^2
+    # alpha below the clamp: expected depth D / 1e-10, no gradient to alpha
+    L, dr, dd, da = OL.l1_depth([[0.0, 0.0, 0.0]], [1e-12], [0.0], [[0.0, 0.0, 0.0]], [0.0], 0.5)
+    assert abs(L - 0.5 * 1e-2) < 1e-15 and da[0] == 0.0 and abs(dd[0] - 0.5 / 1e-10) < 1e-3
+
+
+def test_loss_gradient_by_finite_differences():
+    from oracle import loss as OL
+    rng = np.random.default_rng(4)
+    n = 50
+    rgb, t_rgb = rng.random((n, 3)), rng.random((n, 3))
+    D, a, td = rng.uniform(1, 5, n), rng.uniform(0.2, 1, n), rng.uniform(1, 20, n)
+    L0, dr, dd, da = OL.l1_depth(rgb, D, a, t_rgb, td, 0.7)
+    h = 1e-7
+    for arr, grad in ((rgb, dr), (D, dd), (a, da)):
+        for _ in range(10):
+            i = tuple(int(rng.integers(0, s)) for s in arr.shape)
+            old = arr[i]
+            arr[i] = old + h
+            lp = OL.l1_depth(rgb, D, a, t_rgb, td, 0.7)[0]
+            arr[i] = old - h
+            lm = OL.l1_depth(rgb, D, a, t_rgb, td, 0.7)[0]
+            arr[i] = old
+            assert abs((lp - lm) / (2 * h) - grad[i]) <= 1e-6 * max(1.0, abs(grad[i]))
