@@ -182,7 +182,17 @@ int gs_render_fwd(const gs_projected *proj, const uint32_t *pair_vals, const uin
 int gs_render_count(const gs_projected *proj, const uint32_t *pair_vals, const uint32_t *tile_ranges,
                     const gs_camera *cams, int32_t n_views, int32_t *n_eval, void *stream);
 
+/* Workspace of the backward: gs_render_bwd_workspace_size(n_slots) bytes of
+ * per-slot 2D gradients, optionally followed (gs_render_bwd) or given
+ * separately (gs_composite_bwd's seg_ws) by gs_seg_workspace_size(n_tiles,
+ * n_pairs) bytes for the segmented walk: tile lists longer than 512
+ * positions are then walked in 512-position segments by separate
+ * workgroups, each starting from the transmittance and colour behind it
+ * (folded from per-segment states a pre-pass computes), so the longest
+ * lists no longer serialise the launch.  A smaller or absent segment area
+ * walks every list whole; results agree to float rounding either way. */
 size_t gs_render_bwd_workspace_size(int64_t n_slots);
+size_t gs_seg_workspace_size(int64_t n_tiles, int64_t n_pairs);
 
 /* Backward of compositing and projection.  Transmittance is recovered back
  * to front from T_final and last instead of stored per-pixel lists.  Inputs
@@ -206,7 +216,7 @@ int gs_render_bwd(const gs_gaussians *g, const gs_camera *cams, int32_t n_views,
 int gs_composite_bwd(const gs_projected *proj, const uint32_t *pair_vals, const uint32_t *tile_ranges,
                      const gs_camera *cams, int32_t n_views, const gs_options *opt, const float *T_final,
                      const int32_t *last, const float *d_rgb, const float *d_depth, const float *d_alpha,
-                     int64_t n_slots, float *grad2d, void *stream);
+                     int64_t n_slots, float *grad2d, void *seg_ws, size_t seg_ws_bytes, void *stream);
 int gs_project_bwd(const gs_gaussians *g, const gs_camera *cams, int32_t n_views, const gs_options *opt,
                    const gs_projected *proj, const float *grad2d, const gs_gaussians_grad *out,
                    float *mean2d_grad_norm, float *absgrad, void *stream);

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 
 #include "gs.h"
@@ -339,6 +340,39 @@ size_t gs_render_bwd_workspace_size(int64_t n_slots) {
 
 const float* gs_render_bwd_grad2d(void* ws) { return static_cast<const float*>(ws); }
 
+namespace {
+
+// segment area: work_off [T + 1] | state_off [T + 1] | states [capacity][kSegFields][256]
+size_t seg_fixed_bytes(int64_t n_tiles) {
+    Carver c(nullptr);
+    c.take<uint32_t>((size_t)n_tiles + 1);
+    c.take<uint32_t>((size_t)n_tiles + 1);
+    return c.off;
+}
+
+constexpr size_t kSegStateBytes = (size_t)kSegFields * 256 * sizeof(float);
+
+// a plan over `base` (NULL or too small: no segments)
+void seg_layout(void* base, size_t bytes, int64_t n_tiles, SegPlan* plan, uint32_t* capacity) {
+    *plan = SegPlan{nullptr, nullptr, nullptr, (uint32_t)n_tiles};
+    *capacity = 0;
+    const size_t fixed = seg_fixed_bytes(n_tiles);
+    if (!base || bytes < fixed) return;
+    Carver c(base);
+    plan->work_off = c.take<uint32_t>((size_t)n_tiles + 1);
+    plan->state_off = c.take<uint32_t>((size_t)n_tiles + 1);
+    plan->state = reinterpret_cast<float*>(static_cast<char*>(base) + fixed);
+    *capacity = (uint32_t)std::min<size_t>((bytes - fixed) / kSegStateBytes, 1u << 24);
+}
+
+}  // namespace
+
+size_t gs_seg_workspace_size(int64_t n_tiles, int64_t n_pairs) {
+    if (n_tiles < 1) n_tiles = 1;
+    if (n_pairs < 0) n_pairs = 0;
+    return seg_fixed_bytes(n_tiles) + ((size_t)n_pairs / kSegLen + 1) * kSegStateBytes;
+}
+
 int gs_render_bwd(const gs_gaussians* g, const gs_camera* cams, int32_t n_views, const gs_options* opt,
                   const gs_projected* proj, const uint32_t* pair_vals, const uint32_t* tile_ranges,
                   const float* T_final, const int32_t* last, const float* d_rgb, const float* d_depth,
@@ -355,13 +389,20 @@ int gs_render_bwd(const gs_gaussians* g, const gs_camera* cams, int32_t n_views,
         GS_REQUIRE(out->d_means && out->d_scales && out->d_quats && out->d_opacities && out->d_sh,
                    "NULL gradient output");
         const int64_t n_slots = g->n * n_views;
-        GS_REQUIRE(ws_bytes >= gs_render_bwd_workspace_size(n_slots), "workspace too small");
+        const size_t g2_bytes = gs_render_bwd_workspace_size(n_slots);
+        GS_REQUIRE(ws_bytes >= g2_bytes, "workspace too small");
+        GS_REQUIRE(((uintptr_t)ws & (kAlign - 1)) == 0, "workspace must be 256-byte aligned");
         hipStream_t s = (hipStream_t)stream;
         float* grad2d = static_cast<float*>(ws);
+        SegPlan plan;
+        uint32_t cap;
+        seg_layout(static_cast<char*>(ws) + g2_bytes, ws_bytes - g2_bytes, vt.total_tiles, &plan, &cap);
         GS_HIP(zero_seen_grad2d(proj->tiles, grad2d, n_slots, s));
         const Projected pr = to_proj(proj);
-        GS_HIP(launch_render_bwd(pr, pair_vals, reinterpret_cast<const uint2*>(tile_ranges), vt, ok, T_final, last,
-                                 d_rgb, d_depth, d_alpha, grad2d, s));
+        const uint2* rg = reinterpret_cast<const uint2*>(tile_ranges);
+        if (plan.work_off) GS_HIP(launch_seg_prepare(pr, pair_vals, rg, vt, last, cap, plan, s));
+        GS_HIP(launch_render_bwd(pr, pair_vals, rg, vt, ok, T_final, last, d_rgb, d_depth, d_alpha, grad2d, plan, cap,
+                                 s));
         GaussPtrs gp{g->means, g->scales, g->quats, g->opacities, g->sh};
         GradPtrs go{out->d_means, out->d_scales, out->d_quats, out->d_opacities, out->d_sh};
         GS_HIP(launch_project_bwd(gp, g->n, vt, ok, pr, grad2d, go, mean2d_grad_norm, absgrad, s));
@@ -374,7 +415,7 @@ int gs_render_bwd(const gs_gaussians* g, const gs_camera* cams, int32_t n_views,
 int gs_composite_bwd(const gs_projected* proj, const uint32_t* pair_vals, const uint32_t* tile_ranges,
                      const gs_camera* cams, int32_t n_views, const gs_options* opt, const float* T_final,
                      const int32_t* last, const float* d_rgb, const float* d_depth, const float* d_alpha,
-                     int64_t n_slots, float* grad2d, void* stream) {
+                     int64_t n_slots, float* grad2d, void* seg_ws, size_t seg_ws_bytes, void* stream) {
     try {
         ViewTable vt;
         OptK ok;
@@ -383,10 +424,17 @@ int gs_composite_bwd(const gs_projected* proj, const uint32_t* pair_vals, const 
             return rc;
         GS_REQUIRE(pair_vals && tile_ranges && T_final && last && grad2d, "NULL buffer");
         GS_REQUIRE(n_slots >= 1 && n_slots <= 0xFFFFFF00LL, "bad n_slots");
+        GS_REQUIRE(((uintptr_t)seg_ws & (kAlign - 1)) == 0, "segment workspace must be 256-byte aligned");
         hipStream_t s = (hipStream_t)stream;
+        SegPlan plan;
+        uint32_t cap;
+        seg_layout(seg_ws, seg_ws_bytes, vt.total_tiles, &plan, &cap);
         GS_HIP(zero_seen_grad2d(proj->tiles, grad2d, n_slots, s));
-        GS_HIP(launch_render_bwd(to_proj(proj), pair_vals, reinterpret_cast<const uint2*>(tile_ranges), vt, ok, T_final,
-                                 last, d_rgb, d_depth, d_alpha, grad2d, s));
+        const Projected pr = to_proj(proj);
+        const uint2* rg = reinterpret_cast<const uint2*>(tile_ranges);
+        if (plan.work_off) GS_HIP(launch_seg_prepare(pr, pair_vals, rg, vt, last, cap, plan, s));
+        GS_HIP(launch_render_bwd(pr, pair_vals, rg, vt, ok, T_final, last, d_rgb, d_depth, d_alpha, grad2d, plan, cap,
+                                 s));
         return GS_OK;
     } catch (...) {
         return fail(GS_ERR_INTERNAL, "unexpected exception in gs_composite_bwd");

@@ -169,6 +169,26 @@ hipError_t launch_tile_ranges(const uint32_t* sorted_keys, uint32_t n_pairs, uin
 // tile launch order for compositing, longest lists first
 hipError_t launch_tile_order(const uint32_t* ranges, uint32_t n_tiles, uint32_t* order, hipStream_t s);
 
+// Segmented backward: lists longer than kSegLen positions are walked in
+// segments of kSegLen by separate workgroups.  work_off [T + 1] and
+// state_off [T + 1] are exclusive prefix sums, over the tiles in launch
+// order, of the work items (segments) and of the stored segment states
+// (segments 1 .. n - 1 of a segmented tile); state holds kSegFields planes
+// of 256 pixels per stored segment: T_seg, C_seg (r, g, b), D_seg.
+constexpr int kSegLen = 512;
+constexpr int kSegFields = 5;
+struct SegPlan {
+    uint32_t* work_off;    // null: one work item per tile, no segments
+    uint32_t* state_off;
+    float* state;
+    uint32_t n_tiles;
+};
+// plans the segments of every tile (segments disabled when they need more
+// than `capacity` stored states) and writes their states
+hipError_t launch_seg_prepare(const Projected& proj, const uint32_t* pair_vals, const uint2* ranges,
+                              const ViewTable& vt, const int32_t* last, uint32_t capacity, const SegPlan& plan,
+                              hipStream_t s);
+
 // compositing (render.hip)
 hipError_t launch_render_fwd(const Projected& proj, const uint32_t* pair_vals, const uint2* ranges,
                              const ViewTable& vt, const OptK& opt, float* rgb, float* depth, float* alpha,
@@ -178,7 +198,7 @@ hipError_t launch_render_count(const Projected& proj, const uint32_t* pair_vals,
 hipError_t launch_render_bwd(const Projected& proj, const uint32_t* pair_vals, const uint2* ranges,
                              const ViewTable& vt, const OptK& opt, const float* T_final, const int32_t* last,
                              const float* d_rgb, const float* d_depth, const float* d_alpha, float* grad2d,
-                             hipStream_t s);
+                             const SegPlan& plan, uint32_t capacity, hipStream_t s);
 
 // training loss (loss.hip): per-workgroup partial sums, then a fixed-order total
 size_t loss_partials(int64_t n_pix);

@@ -73,6 +73,7 @@ struct PixelCoords {
     float qcx, qcy;        // centre of the wave's quadrant (pixel-centre span +-3.5)
     bool inside;
     int64_t pix;
+    int lx, ly;            // pixel within the tile
 };
 
 __device__ __forceinline__ PixelCoords pixel_coords(const ViewTable& vt, int tile, int wave, int lane) {
@@ -92,6 +93,8 @@ __device__ __forceinline__ PixelCoords pixel_coords(const ViewTable& vt, int til
     const int px = tx * kTile + lx, py = ty * kTile + ly;
     c.inside = px < V.W && py < V.H;
     c.pix = V.pix_off + (int64_t)py * V.W + px;
+    c.lx = lx;
+    c.ly = ly;
     return c;
 }
 
@@ -172,6 +175,22 @@ __device__ __forceinline__ int stage_chunk(const float4* __restrict__ rec, const
     }
     __builtin_amdgcn_wave_barrier();
     return __popcll(m);
+}
+
+// largest i in [0, n] with a[i] <= v (a non-decreasing, a[0] <= v)
+__device__ __forceinline__ uint32_t last_le(const uint32_t* __restrict__ a, uint32_t n, uint32_t v) {
+    uint32_t lo = 0, hi = n + 1;      // invariant: a[lo] <= v, answer in [lo, hi)
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (a[mid] <= v) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// tile at launch position i (the order, when valid, else the position)
+__device__ __forceinline__ int order_tile(const uint32_t* __restrict__ tile_order, const ViewTable& vt, uint32_t i) {
+    const uint32_t t = tile_order ? tile_order[i] : i;
+    return t < (uint32_t)vt.total_tiles ? (int)t : (int)i;
 }
 
 // One lane's list entry, loaded a chunk ahead of its use so that the two
@@ -368,11 +387,25 @@ __global__ __launch_bounds__(256) void k_render_bwd(const float4* __restrict__ r
                                                     const float* __restrict__ T_final,
                                                     const int32_t* __restrict__ last_in,
                                                     const float* __restrict__ d_rgb, const float* __restrict__ d_depth,
-                                                    const float* __restrict__ d_alpha, float* __restrict__ grad2d) {
+                                                    const float* __restrict__ d_alpha, float* __restrict__ grad2d,
+                                                    SegPlan plan) {
     __shared__ WaveStage stage[kWaves];
     __shared__ float s_red[kWaves][kChunk][kG2];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int tile = launch_tile(tile_order, vt);
+    int tile, seg = 0, nseg = 1;
+    uint32_t st0 = 0;
+    if (plan.work_off) {
+        // work item -> (launch position, segment)
+        const uint32_t b = blockIdx.x;
+        if (b >= plan.work_off[plan.n_tiles]) return;
+        const uint32_t i = last_le(plan.work_off, plan.n_tiles, b);
+        seg = (int)(b - plan.work_off[i]);
+        nseg = (int)(plan.work_off[i + 1] - plan.work_off[i]);
+        st0 = plan.state_off[i];
+        tile = order_tile(tile_order, vt, i);
+    } else {
+        tile = launch_tile(tile_order, vt);
+    }
     const PixelCoords pc = pixel_coords(vt, tile, wave, lane);
     WaveStage& st = stage[wave];
     const uint2 rg = ranges[tile];
@@ -399,16 +432,39 @@ __global__ __launch_bounds__(256) void k_render_bwd(const float4* __restrict__ r
     float R0 = opt.bg[0], R1 = opt.bg[1], R2 = opt.bg[2], RD = 0.0f, Q = 1.0f;
     const float ln2 = kLn2;
 
-    // chunk [b_end - 64, b_end) of positions, clipped at 0, walked from the
+    // A segmented list: this workgroup walks segment `seg` (positions
+    // (seg S, (seg + 1) S]); the state behind it comes from folding the later
+    // segments' transmittance and local colour, written by k_seg_prepass:
+    // R <- C_j + T_j R, T <- T / T_j, Q <- Q T_j (segments starting at or
+    // after the pixel's last composited entry are the identity).
+    int lo = 0, hi = maxlast;
+    if (nseg > 1) {
+        const int px = pc.ly * kTile + pc.lx;
+        for (int j = nseg - 1; j > seg; --j) {
+            if (j * kSegLen >= last) continue;
+            const float* sj = plan.state + (size_t)(st0 + (uint32_t)(j - 1)) * kSegFields * 256;
+            const float Ts = sj[0 * 256 + px];
+            R0 = fmaf(Ts, R0, sj[1 * 256 + px]);
+            R1 = fmaf(Ts, R1, sj[2 * 256 + px]);
+            R2 = fmaf(Ts, R2, sj[3 * 256 + px]);
+            RD = fmaf(Ts, RD, sj[4 * 256 + px]);
+            T = T / Ts;
+            Q = Q * Ts;
+        }
+        lo = seg * kSegLen;
+        hi = min((seg + 1) * kSegLen, maxlast);
+    }
+
+    // chunk [b_end - 64, b_end) of positions, clipped at lo, walked from the
     // back; lane l of a chunk gathers position b_start + l
     auto chunk_slot = [&](int b_end_) {
-        const int b_start_ = max(0, b_end_ - kChunk);
-        return b_end_ > 0 ? load_slot(pair_vals, rg.x + (uint32_t)(b_start_ + lane), rg.x + (uint32_t)b_end_) : kNoSlot;
+        const int b_start_ = max(lo, b_end_ - kChunk);
+        return b_end_ > lo ? load_slot(pair_vals, rg.x + (uint32_t)(b_start_ + lane), rg.x + (uint32_t)b_end_) : kNoSlot;
     };
-    Gather cur = load_entry(rec, chunk_slot(maxlast));
-    uint32_t s_next = chunk_slot(maxlast - kChunk);
-    for (int b_end = maxlast; b_end > 0; b_end -= kChunk) {
-        const int b_start = max(0, b_end - kChunk);
+    Gather cur = load_entry(rec, chunk_slot(hi));
+    uint32_t s_next = chunk_slot(hi - kChunk);
+    for (int b_end = hi; b_end > lo; b_end -= kChunk) {
+        const int b_start = max(lo, b_end - kChunk);
         const int n = stage_gathered(cur, b_start + lane + 1, pc, lane, st);
         cur = load_entry(rec, s_next);
         s_next = chunk_slot(b_end - 2 * kChunk);
@@ -467,6 +523,127 @@ __global__ __launch_bounds__(256) void k_render_bwd(const float4* __restrict__ r
     }
 }
 
+// exclusive scan of v over the 1024 threads of the workgroup; *total gets the sum
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* s_wave, uint32_t* total) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) s_wave[wave] = x;
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+    for (int w = 0; w < 16; ++w) {
+        const uint32_t t = s_wave[w];
+        before += w < wave ? t : 0u;
+        all += t;
+    }
+    __syncthreads();
+    *total = all;
+    return before + x - v;
+}
+
+// One workgroup: segments per tile in launch order (ceil(L / kSegLen) for a
+// list of L > kSegLen positions, else 1) and the stored states (segments
+// 1 .. n - 1); exclusive prefix sums into work_off / state_off.  When the
+// states would exceed `capacity`, every tile keeps a single segment.
+__global__ __launch_bounds__(1024) void k_seg_plan(const uint2* __restrict__ ranges,
+                                                   const uint32_t* __restrict__ tile_order, ViewTable vt,
+                                                   uint32_t capacity, uint32_t* __restrict__ work_off,
+                                                   uint32_t* __restrict__ state_off) {
+    __shared__ uint32_t s_wave[16];
+    __shared__ uint32_t s_flag;
+    const uint32_t n_tiles = (uint32_t)vt.total_tiles;
+    auto nseg_of = [&](uint32_t i) -> uint32_t {
+        const uint2 r = ranges[order_tile(tile_order, vt, i)];
+        const uint32_t L = r.y - r.x;
+        return L > (uint32_t)kSegLen ? (L + kSegLen - 1) / kSegLen : 1u;
+    };
+    // pass 1: do the states fit?
+    uint32_t need = 0;
+    for (uint32_t i = threadIdx.x; i < n_tiles; i += 1024) need += nseg_of(i) - 1u;
+    uint32_t total_need = 0;
+    (void)block_excl_scan(need, s_wave, &total_need);
+    const bool on = total_need <= capacity;
+    // pass 2: prefix sums
+    if (threadIdx.x == 0) s_flag = 0;
+    uint32_t base_w = 0, base_s = 0;
+    for (uint32_t c0 = 0; c0 < n_tiles; c0 += 1024) {
+        const uint32_t i = c0 + threadIdx.x;
+        uint32_t nw = 0, ns = 0;
+        if (i < n_tiles) {
+            nw = on ? nseg_of(i) : 1u;
+            ns = nw - 1u;
+        }
+        uint32_t tw = 0, ts = 0;
+        const uint32_t ew = block_excl_scan(nw, s_wave, &tw);
+        const uint32_t es = block_excl_scan(ns, s_wave, &ts);
+        if (i < n_tiles) {
+            work_off[i] = base_w + ew;
+            state_off[i] = base_s + es;
+        }
+        base_w += tw;
+        base_s += ts;
+    }
+    if (threadIdx.x == 0) {
+        work_off[n_tiles] = base_w;
+        state_off[n_tiles] = base_s;
+    }
+}
+
+// State of one stored segment (tile at launch position i, segment j >= 1):
+// per pixel, front to back over the segment's composited entries (position
+// <= last and not skipped), T_seg = prod (1 - alpha) and the colour and
+// depth sums with T restarted at 1: C_seg = sum c alpha T_local.  The
+// alpha values are the forward's and the backward's bit for bit.
+__global__ __launch_bounds__(256) void k_seg_prepass(const float4* __restrict__ rec,
+                                                     const uint32_t* __restrict__ pair_vals,
+                                                     const uint2* __restrict__ ranges,
+                                                     const uint32_t* __restrict__ tile_order, ViewTable vt,
+                                                     const int32_t* __restrict__ last_in, SegPlan plan) {
+    __shared__ WaveStage stage[kWaves];
+    const uint32_t b = blockIdx.x;
+    if (b >= plan.state_off[plan.n_tiles]) return;
+    const uint32_t i = last_le(plan.state_off, plan.n_tiles, b);
+    const int j = (int)(b - plan.state_off[i]) + 1;
+    const int tile = order_tile(tile_order, vt, i);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const PixelCoords pc = pixel_coords(vt, tile, wave, lane);
+    WaveStage& st = stage[wave];
+    const uint2 rg = ranges[tile];
+    const int last = pc.inside ? last_in[pc.pix] : 0;
+    int maxlast = last;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) maxlast = max(maxlast, __shfl_xor(maxlast, off, 64));
+    const int lo = j * kSegLen, hi = min((j + 1) * kSegLen, maxlast);
+    float T = 1.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f, D = 0.0f;
+    for (int b0 = lo; b0 < hi; b0 += kChunk) {
+        const Gather e = load_entry(rec, load_slot(pair_vals, rg.x + (uint32_t)(b0 + lane), rg.x + (uint32_t)hi));
+        const int n = stage_gathered(e, b0 + lane + 1, pc, lane, st);
+        for (int k = 0; k < n; ++k) {
+            const float4 a = st.g[k], bb = st.b[k], c = st.c[k];
+            const Eval ev = eval_entry(a, bb, pc.fpx, pc.fpy);
+            const bool con = st.pos[k] <= last && ev.keep;
+            const float w = con ? ev.alpha * T : 0.0f;
+            c0 = fmaf(c.x, w, c0);
+            c1 = fmaf(c.y, w, c1);
+            c2 = fmaf(c.z, w, c2);
+            D = fmaf(bb.z, w, D);
+            T = con ? T * (1.0f - ev.alpha) : T;
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+    float* out = plan.state + (size_t)b * kSegFields * 256;
+    const int px = pc.ly * kTile + pc.lx;
+    out[0 * 256 + px] = T;
+    out[1 * 256 + px] = c0;
+    out[2 * 256 + px] = c1;
+    out[3 * 256 + px] = c2;
+    out[4 * 256 + px] = D;
+}
+
 // 2D-gradient rows of the slots that some tile lists (tiles > 0): the only
 // rows the compositing backward accumulates into and the only ones read
 __global__ __launch_bounds__(256) void k_zero_seen_rows(const uint32_t* __restrict__ tiles, float4* __restrict__ grad2d,
@@ -498,13 +675,25 @@ hipError_t launch_render_count(const Projected& proj, const uint32_t* pair_vals,
     return hipGetLastError();
 }
 
+hipError_t launch_seg_prepare(const Projected& proj, const uint32_t* pair_vals, const uint2* ranges,
+                              const ViewTable& vt, const int32_t* last, uint32_t capacity, const SegPlan& plan,
+                              hipStream_t s) {
+    hipLaunchKernelGGL(k_seg_plan, dim3(1), dim3(1024), 0, s, ranges, proj.tile_order, vt, capacity, plan.work_off,
+                       plan.state_off);
+    if (capacity)
+        hipLaunchKernelGGL(k_seg_prepass, dim3(capacity), dim3(256), 0, s, proj.rec, pair_vals, ranges, proj.tile_order,
+                           vt, last, plan);
+    return hipGetLastError();
+}
+
 hipError_t launch_render_bwd(const Projected& proj, const uint32_t* pair_vals, const uint2* ranges,
                              const ViewTable& vt, const OptK& opt, const float* T_final, const int32_t* last,
                              const float* d_rgb, const float* d_depth, const float* d_alpha, float* grad2d,
-                             hipStream_t s) {
-    if (vt.total_tiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_render_bwd, dim3(vt.total_tiles), dim3(256), 0, s, proj.rec, pair_vals, ranges,
-                       proj.tile_order, vt, opt, T_final, last, d_rgb, d_depth, d_alpha, grad2d);
+                             const SegPlan& plan, uint32_t capacity, hipStream_t s) {
+    // with a plan, blocks beyond the planned work items exit at once
+    const unsigned blocks = (unsigned)vt.total_tiles + (plan.work_off ? capacity : 0u);
+    hipLaunchKernelGGL(k_render_bwd, dim3(blocks), dim3(256), 0, s, proj.rec, pair_vals, ranges,
+                       proj.tile_order, vt, opt, T_final, last, d_rgb, d_depth, d_alpha, grad2d, plan);
     return hipGetLastError();
 }
 

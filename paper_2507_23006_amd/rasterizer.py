@@ -217,12 +217,16 @@ def render_bwd(params, cams, opts: RenderOptions, proj: Projected, pair_vals, ra
     wsz = lib.gs_render_bwd_workspace_size(n * V)
     wbuf = ws.get("bwd", wsz + 256, dev)
     g2 = C.c_void_p(Workspace.aligned(wbuf))
+    n_tiles, _ = views_extent(cams)
+    ssz = lib.gs_seg_workspace_size(n_tiles, int(pair_vals.numel()))
+    sbuf = ws.get("seg", ssz + 256, dev)
     cont = lambda t: t.contiguous() if t is not None else None
     d_rgb, d_depth, d_alpha = cont(d_rgb), cont(d_depth), cont(d_alpha)
     cams_c, opt_c, proj_c = L.make_cameras(cams), opts.c(), proj.c()
     _mark("bwd_begin")
     L.check(lib.gs_composite_bwd(C.byref(proj_c), _ptr(pair_vals), _ptr(ranges), cams_c, V, C.byref(opt_c), _ptr(T),
-                                 _ptr(last), _ptr(d_rgb), _ptr(d_depth), _ptr(d_alpha), n * V, g2, _stream()))
+                                 _ptr(last), _ptr(d_rgb), _ptr(d_depth), _ptr(d_alpha), n * V, g2,
+                                 C.c_void_p(Workspace.aligned(sbuf)), ssz, _stream()))
     _mark("composite_bwd")
     L.check(lib.gs_project_bwd(C.byref(g), cams_c, V, C.byref(opt_c), C.byref(proj_c), g2, C.byref(go), _ptr(norm),
                                _ptr(absg), _stream()))

@@ -396,3 +396,37 @@ def test_loss_kernel_matches_oracle(gpu_lib, n_pix, with_depth):
     # the loss is summed in a fixed order
     again = gpu_lib.l1_depth_loss(dev[0], dev[1], dev[2], tt[0], tt[1], 0.5)
     assert torch.equal(loss, again)
+
+
+def test_segmented_backward_matches_whole_lists(gpu_lib):
+    """Lists longer than 512 positions are walked in segments by separate
+    workgroups (state behind each segment folded from a pre-pass); the 2D
+    gradients must equal those of whole-list walks to float rounding."""
+    import ctypes as C
+    from paper_2507_23006_amd import _lib as L
+    cam = S.Camera(60.0, 60.0, 24.0, 20.0, S.look_at((0.3, -0.2, -3.0), (0.0, 0.0, 0.0)), 48, 40)
+    scene = S.random_scene(6000, seed=3, log_scale_mu=-3.2)
+    opts = gpu_lib.RenderOptions(aa=True, bg=(0.1, 0.2, 0.3))
+    _, proj, pairs, ranges, P, out = gpu_forward(gpu_lib, scene, [cam], opts)
+    rg = ranges.cpu().numpy().view(np.uint32).astype(np.int64)
+    assert (rg[:, 1] - rg[:, 0]).max() > 1024          # several segments per long list
+    lib = L.load()
+    n_slots, npx = scene.n, cam.n_pixels
+    gen = torch.Generator(device="cuda").manual_seed(1)
+    d = [torch.randn(s, device="cuda", generator=gen) for s in ((npx, 3), (npx,), (npx,))]
+    res = []
+    for seg in (False, True):
+        g2 = torch.zeros((n_slots, 12), device="cuda")
+        ssz = lib.gs_seg_workspace_size(cam.n_tiles, P) if seg else 0
+        sbuf = torch.empty(ssz + 512, dtype=torch.uint8, device="cuda")
+        sp = C.c_void_p((sbuf.data_ptr() + 255) & ~255) if seg else None
+        L.check(lib.gs_composite_bwd(C.byref(proj.c()), C.c_void_p(pairs.data_ptr()), C.c_void_p(ranges.data_ptr()),
+                                     L.make_cameras([cam]), 1, C.byref(opts.c()), C.c_void_p(out["T"].data_ptr()),
+                                     C.c_void_p(out["last"].data_ptr()), *[C.c_void_p(t.data_ptr()) for t in d],
+                                     n_slots, C.c_void_p(g2.data_ptr()), sp, ssz,
+                                     C.c_void_p(torch.cuda.current_stream().cuda_stream)))
+        torch.cuda.synchronize()
+        res.append(g2.cpu().numpy().astype(np.float64) * (proj.tiles.cpu().numpy()[:, None] > 0))
+    a, b = res
+    rel = np.linalg.norm(a - b, axis=0) / np.maximum(np.linalg.norm(a, axis=0), 1e-30)
+    assert rel.max() < 1e-5, rel
