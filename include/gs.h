@@ -241,6 +241,16 @@ int gs_loss_l1_depth(const float *rgb, const float *depth, const float *alpha, c
                      const float *target_depth, int64_t n_pix, float lambda_depth, float *loss, float *d_rgb,
                      float *d_depth, float *d_alpha, void *ws, size_t ws_bytes, void *stream);
 
+/* D-SSIM term of Eq. 3 and its gradient: weight * (1 - mean SSIM) over the
+ * 3 width * height values of rgb against target (both [H][W][3] float32),
+ * SSIM per pixel and channel with an 11x11 Gaussian window (sigma 1.5,
+ * normalised), zero outside the image, C1 = 0.01^2, C2 = 0.03^2.  Writes
+ * loss [1] and d_rgb [H][W][3] (the term's gradient) on the device; the
+ * mean is summed in a fixed order. */
+size_t gs_dssim_workspace_size(int32_t width, int32_t height);
+int gs_dssim(const float *rgb, const float *target, int32_t width, int32_t height, float weight, float *loss,
+             float *d_rgb, void *ws, size_t ws_bytes, void *stream);
+
 /* ------------------------------------------------------------------------
  * Level-of-detail selection and serving (§3.4.2 "Detail Level Selection",
  * Fig. 3b; distance thresholds as in Tab. 13).

@@ -9,7 +9,7 @@ the batching server for rendering requests.  This package only marshals torch te
 from ._lib import GsError, load, LIB_PATH
 from .rasterizer import (RenderOptions, RenderStats, Projected, Workspace, GsRasterize, rasterize, project,
                          bin_sort, render_fwd, render_bwd, split_views, views_extent, grad2d_view, check_params, set_stage_hook, render_count,
-                         L1DepthLoss, l1_depth_loss)
+                         L1DepthLoss, l1_depth_loss, DSSIMLoss, dssim_loss)
 from .serving import LodTable, lod_select, ServeConfig, Server
 
 
@@ -20,5 +20,5 @@ def build(verbose: bool = False) -> str:
 
 __all__ = ["GsError", "load", "LIB_PATH", "RenderOptions", "RenderStats", "Projected", "Workspace", "GsRasterize",
            "rasterize", "project", "bin_sort", "render_fwd", "render_bwd", "split_views", "views_extent",
-           "grad2d_view", "check_params", "set_stage_hook", "render_count", "build", "L1DepthLoss", "l1_depth_loss", "LodTable", "lod_select",
+           "grad2d_view", "check_params", "set_stage_hook", "render_count", "build", "L1DepthLoss", "l1_depth_loss", "DSSIMLoss", "dssim_loss", "LodTable", "lod_select",
            "ServeConfig", "Server"]

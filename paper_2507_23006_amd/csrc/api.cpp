@@ -333,6 +333,35 @@ int gs_loss_l1_depth(const float* rgb, const float* depth, const float* alpha, c
     }
 }
 
+size_t gs_dssim_workspace_size(int32_t width, int32_t height) {
+    if (width < 1 || height < 1) return 0;
+    Carver c(nullptr);
+    for (int i = 0; i < 3; ++i) c.take<float>((size_t)width * height * 3);
+    c.take<double>(ssim_partials(width, height));
+    return c.off;
+}
+
+int gs_dssim(const float* rgb, const float* target, int32_t width, int32_t height, float weight, float* loss,
+             float* d_rgb, void* ws, size_t ws_bytes, void* stream) {
+    try {
+        GS_REQUIRE(width >= 1 && width <= 16384 && height >= 1 && height <= 16384, "image %dx%d outside 1..16384",
+                   width, height);
+        GS_REQUIRE(rgb && target && loss && d_rgb && ws, "NULL buffer");
+        GS_REQUIRE(std::isfinite(weight), "weight not finite");
+        GS_REQUIRE(((uintptr_t)ws & (kAlign - 1)) == 0, "workspace must be 256-byte aligned");
+        GS_REQUIRE(ws_bytes >= gs_dssim_workspace_size(width, height), "workspace too small");
+        Carver c(ws);
+        float* Pa = c.take<float>((size_t)width * height * 3);
+        float* Pb = c.take<float>((size_t)width * height * 3);
+        float* Pc = c.take<float>((size_t)width * height * 3);
+        double* partial = c.take<double>(ssim_partials(width, height));
+        GS_HIP(launch_dssim(rgb, target, width, height, weight, loss, d_rgb, Pa, Pb, Pc, partial, (hipStream_t)stream));
+        return GS_OK;
+    } catch (...) {
+        return fail(GS_ERR_INTERNAL, "unexpected exception in gs_dssim");
+    }
+}
+
 size_t gs_render_bwd_workspace_size(int64_t n_slots) {
     if (n_slots < 1) n_slots = 1;
     return align_up((size_t)n_slots * GS_GRAD2D_FLOATS * sizeof(float));

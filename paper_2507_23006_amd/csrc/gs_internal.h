@@ -206,6 +206,11 @@ hipError_t launch_loss(const float* rgb, const float* depth, const float* alpha,
                        const float* t_depth, int64_t n_pix, float lambda, float* loss, float* d_rgb, float* d_depth,
                        float* d_alpha, double* partial, hipStream_t s);
 
+// D-SSIM term (ssim.hip)
+size_t ssim_partials(int W, int H);
+hipError_t launch_dssim(const float* x, const float* y, int W, int H, float weight, float* loss, float* dx, float* Pa,
+                        float* Pb, float* Pc, double* partial, hipStream_t s);
+
 // projection backward (project_bwd.hip)
 hipError_t launch_project_bwd(const GaussPtrs& g, int64_t n, const ViewTable& vt, const OptK& opt,
                               const Projected& proj, const float* grad2d, const GradPtrs& out,

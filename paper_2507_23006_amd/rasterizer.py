@@ -334,6 +334,40 @@ def l1_depth_loss(rgb, depth, alpha, target_rgb, target_depth=None, lambda_depth
     return L1DepthLoss.apply(rgb, depth, alpha, target_rgb, target_depth, lambda_depth)
 
 
+class DSSIMLoss(torch.autograd.Function):
+    """weight * (1 - mean SSIM) of one image [H, W, 3] against a target
+    (11x11 Gaussian window, sigma 1.5), value and gradient in the library's
+    kernels; the backward scales the gradient."""
+
+    @staticmethod
+    def forward(ctx, rgb, target, weight: float):
+        lib = L.load()
+        if rgb.dim() != 3 or rgb.shape[-1] != 3 or tuple(target.shape) != tuple(rgb.shape):
+            raise ValueError("rgb and target must be [H, W, 3]")
+        rgb, target = rgb.detach().contiguous(), target.detach().contiguous()
+        for t in (rgb, target):
+            if not (t.is_cuda and t.dtype == torch.float32):
+                raise ValueError("D-SSIM inputs must be float32 CUDA tensors")
+        H, W = int(rgb.shape[0]), int(rgb.shape[1])
+        loss = torch.empty((1,), dtype=torch.float32, device=rgb.device)
+        d_rgb = torch.empty_like(rgb)
+        wsz = lib.gs_dssim_workspace_size(W, H)
+        ws = _default_ws.get("dssim", wsz + 256, rgb.device)
+        L.check(lib.gs_dssim(_ptr(rgb), _ptr(target), W, H, float(weight), _ptr(loss), _ptr(d_rgb),
+                             C.c_void_p(Workspace.aligned(ws)), wsz, _stream()))
+        ctx.save_for_backward(d_rgb)
+        return loss[0]
+
+    @staticmethod
+    def backward(ctx, g):
+        (d_rgb,) = ctx.saved_tensors
+        return d_rgb * g, None, None
+
+
+def dssim_loss(rgb, target, weight: float = 0.2):
+    return DSSIMLoss.apply(rgb, target, weight)
+
+
 def split_views(flat: torch.Tensor, cams) -> list:
     """Per-view [H, W, ...] views of a flat per-pixel tensor."""
     sizes = [int(c.width) * int(c.height) for c in cams]

@@ -430,3 +430,21 @@ def test_segmented_backward_matches_whole_lists(gpu_lib):
     a, b = res
     rel = np.linalg.norm(a - b, axis=0) / np.maximum(np.linalg.norm(a, axis=0), 1e-30)
     assert rel.max() < 1e-5, rel
+
+
+@pytest.mark.parametrize("W,H", [(1, 1), (16, 16), (37, 23), (1920, 1080)])
+def test_dssim_kernel_matches_oracle(gpu_lib, W, H):
+    from oracle import ssim as OS
+    rng = np.random.default_rng(W * 7 + H)
+    x = rng.random((H, W, 3)).astype(np.float32)
+    y = np.clip(x + 0.1 * rng.standard_normal((H, W, 3)), 0, 1).astype(np.float32)
+    xt = torch.from_numpy(x).cuda().requires_grad_(True)
+    loss = gpu_lib.dssim_loss(xt, torch.from_numpy(y).cuda(), 0.2)
+    (3.0 * loss).backward()
+    L, g = OS.dssim(x, y, 0.2)
+    assert abs(loss.item() - L) <= 1e-5 * max(abs(L), 1e-3)
+    got = xt.grad.cpu().numpy().astype(np.float64)
+    scale = np.abs(3 * g).max()
+    assert np.abs(got - 3 * g).max() <= 1e-4 * scale
+    again = gpu_lib.dssim_loss(xt, torch.from_numpy(y).cuda(), 0.2)
+    assert torch.equal(loss, again)

@@ -581,3 +581,41 @@ def test_loss_gradient_by_finite_differences():
             lm = OL.l1_depth(rgb, D, a, t_rgb, td, 0.7)[0]
             arr[i] = old
             assert abs((lp - lm) / (2 * h) - grad[i]) <= 1e-6 * max(1.0, abs(grad[i]))
+
+
+# --------------------------------------------------------------- D-SSIM
+
+def test_ssim_window_and_identity():
+    from oracle import ssim as OS
+    w = OS.window()
+    assert len(w) == 11 and abs(w.sum() - 1.0) < 1e-15 and np.allclose(w, w[::-1])
+    assert abs(w[6] / w[5] - np.exp(-1.0 / (2 * 1.5 ** 2))) < 1e-14      # Gaussian, sigma 1.5
+    x = np.random.default_rng(0).random((20, 17, 3))
+    loss, g = OS.dssim(x, x, 0.2)
+    assert abs(loss) < 1e-12 and np.abs(g).max() < 1e-12                  # SSIM(x, x) = 1 is a maximum
+
+
+def test_ssim_of_constant_images_closed_form():
+    from oracle import ssim as OS
+    a, b = 0.3, 0.7
+    s, _ = OS.ssim_map(np.full((31, 31, 3), a), np.full((31, 31, 3), b))
+    # away from the border the window sees only constants: zero variances
+    want = (2 * a * b + OS.C1) / (a * a + b * b + OS.C1)      # the C2 factors cancel
+    np.testing.assert_allclose(s[10:21, 10:21], want, rtol=1e-12)
+
+
+def test_dssim_gradient_by_finite_differences():
+    from oracle import ssim as OS
+    rng = np.random.default_rng(1)
+    x, y = rng.random((13, 12, 3)), rng.random((13, 12, 3))
+    L0, g = OS.dssim(x, y, 0.2)
+    h = 1e-6
+    for _ in range(25):
+        i = tuple(int(rng.integers(0, s)) for s in x.shape)
+        old = x[i]
+        x[i] = old + h
+        lp = OS.dssim(x, y, 0.2)[0]
+        x[i] = old - h
+        lm = OS.dssim(x, y, 0.2)[0]
+        x[i] = old
+        assert abs((lp - lm) / (2 * h) - g[i]) <= 1e-7 + 1e-5 * abs(g[i]), i
