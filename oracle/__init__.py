@@ -121,8 +121,10 @@ def sh_basis(dirs: np.ndarray) -> np.ndarray:
     return out
 
 
-def project(scene, cam, **opt) -> dict:
-    """Per-Gaussian FP64 projection of one view (EWA, colour, rectangle)."""
+def project(scene, cam, opac=None, cbase=None, **opt) -> dict:
+    """Per-Gaussian FP64 projection of one view (EWA, colour, rectangle).
+    opac replaces the scene's opacities and cbase [n][3] the colour
+    constant 1/2 (both for appearance offsets)."""
     lib = _load()
     n = scene.n
     out = {
@@ -134,9 +136,10 @@ def project(scene, cam, **opt) -> dict:
     }
     pr = _Proj(*[out[k].ctypes.data for k, _ in _Proj._fields_])
     means, scales, quats = _c64(scene.means), _c64(scene.scales), _c64(scene.quats)
-    opac, sh = _c64(scene.opacities), _c64(scene.sh)
+    opac, sh = _c64(scene.opacities if opac is None else opac), _c64(scene.sh)
+    cb = None if cbase is None else _c64(cbase).reshape(n, 3)
     c, o = make_cam(cam), make_opt(**opt)
-    lib.orc_project(C.c_int64(n), _ptr(means), _ptr(scales), _ptr(quats), _ptr(opac), _ptr(sh),
+    lib.orc_project(C.c_int64(n), _ptr(means), _ptr(scales), _ptr(quats), _ptr(opac), _ptr(sh), _ptr(cb),
                     C.byref(c), C.byref(o), C.byref(pr))
     return out
 
@@ -223,34 +226,45 @@ def render_bwd_view(cam, opt: dict, tile_off: int, twod, pair_slot, ranges, g_rg
                        _ptr(mask), _ptr(g_rgb), _ptr(g_depth), _ptr(g_alpha), _ptr(d2), _ptr(absg))
 
 
-def project_bwd(scene, cam, opt: dict, d2_view, grads: dict):
+def project_bwd(scene, cam, opt: dict, d2_view, grads: dict, opac=None, cbase=None):
     """Adds one view's parameter gradients into ``grads`` (float64 arrays in
-    the parameter layouts); returns |d mean2d| per Gaussian."""
+    the parameter layouts; with cbase also grads["cbase"] [n][3]); returns
+    |d mean2d| per Gaussian.  ``grads["opacities"]`` is the gradient with
+    respect to the opacity used (``opac`` when given)."""
     lib = _load()
     n = scene.n
     norm = np.zeros(n)
     # converted copies are held in locals so they outlive the call
     means, scales, quats = _c64(scene.means), _c64(scene.scales), _c64(scene.quats)
-    opac, sh = _c64(scene.opacities), _c64(scene.sh)
+    opac, sh = _c64(scene.opacities if opac is None else opac), _c64(scene.sh)
+    cb = None if cbase is None else _c64(cbase).reshape(n, 3)
     d2 = np.ascontiguousarray(d2_view, np.float64)
-    for k in ("means", "scales", "quats", "opacities", "sh"):
+    keys = ("means", "scales", "quats", "opacities", "sh") + (("cbase",) if cb is not None else ())
+    for k in keys:
         assert grads[k].dtype == np.float64 and grads[k].flags.c_contiguous
     c, o = make_cam(cam), make_opt(**opt)
-    lib.orc_project_bwd(C.c_int64(n), _ptr(means), _ptr(scales), _ptr(quats), _ptr(opac), _ptr(sh), C.byref(c),
-                        C.byref(o), _ptr(d2), _ptr(grads["means"]), _ptr(grads["scales"]), _ptr(grads["quats"]),
-                        _ptr(grads["opacities"]), _ptr(grads["sh"]), _ptr(norm))
+    lib.orc_project_bwd(C.c_int64(n), _ptr(means), _ptr(scales), _ptr(quats), _ptr(opac), _ptr(sh), _ptr(cb),
+                        C.byref(c), C.byref(o), _ptr(d2), _ptr(grads["means"]), _ptr(grads["scales"]),
+                        _ptr(grads["quats"]), _ptr(grads["opacities"]), _ptr(grads["sh"]),
+                        _ptr(grads["cbase"]) if cb is not None else None, _ptr(norm))
     return norm
 
 
-def forward(scene, cams, opt: dict | None = None, guard_eps=DEFAULT_GUARD, depth_keys=None) -> dict:
+def forward(scene, cams, opt: dict | None = None, guard_eps=DEFAULT_GUARD, depth_keys=None, app=None) -> dict:
     """Full FP64 forward over one or more views of the same Gaussians.
 
-    Returns per-view images (rgb, depth, alpha, T, last, guard) and the
-    intermediate stages (projections, pairs, ranges)."""
+    ``app`` [n][4]: appearance offsets (dc, do), applied as in
+    oracle.appearance.apply_offsets.  Returns per-view images (rgb, depth,
+    alpha, T, last, guard) and the intermediate stages (projections, pairs,
+    ranges)."""
     opt = dict(opt or {})
     if not isinstance(cams, (list, tuple)):
         cams = [cams]
-    projs = [project(scene, c, **opt) for c in cams]
+    opac = cbase = None
+    if app is not None:
+        from .appearance import apply_offsets
+        opac, cbase = apply_offsets(scene.opacities, app)
+    projs = [project(scene, c, opac=opac, cbase=cbase, **opt) for c in cams]
     n = scene.n
     rect = np.concatenate([p["rect"] for p in projs], 0)
     tiles = np.concatenate([p["tiles"] for p in projs], 0)
@@ -260,7 +274,9 @@ def forward(scene, cams, opt: dict | None = None, guard_eps=DEFAULT_GUARD, depth
     twod = _twod(projs)
     images = [render_view(c, opt, int(bins["tile_off"][v]), twod, bins["pair_slot"], bins["ranges"],
                           guard_eps=guard_eps) for v, c in enumerate(cams)]
-    return {"proj": projs, "bins": bins, "twod": twod, "images": images, "cams": list(cams), "opt": opt}
+    return {"proj": projs, "bins": bins, "twod": twod, "images": images, "cams": list(cams), "opt": opt,
+            "app": None if app is None else np.asarray(app, np.float64).reshape(n, 4), "opac": opac,
+            "cbase": cbase}
 
 
 def backward(scene, fwd: dict, g_images: list, absgrad: bool = True) -> dict:
@@ -277,9 +293,17 @@ def backward(scene, fwd: dict, g_images: list, absgrad: bool = True) -> dict:
                         d2, absg)
     grads = {"means": np.zeros((3, n)), "scales": np.zeros((3, n)), "quats": np.zeros((4, n)),
              "opacities": np.zeros(n), "sh": np.zeros((16, 3, n))}
+    app = fwd.get("app")
+    if app is not None:
+        grads["cbase"] = np.zeros((n, 3))
     norms = np.zeros((V, n))
     for v, c in enumerate(cams):
-        norms[v] = project_bwd(scene, c, opt, d2[v * n:(v + 1) * n], grads)
+        norms[v] = project_bwd(scene, c, opt, d2[v * n:(v + 1) * n], grads, opac=fwd.get("opac"),
+                               cbase=fwd.get("cbase"))
+    if app is not None:
+        from .appearance import apply_offsets_bwd
+        grads["opacities"], grads["app"] = apply_offsets_bwd(scene.opacities, app, grads["opacities"],
+                                                             grads.pop("cbase"))
     grads["mean2d_norm"] = norms
     grads["d2"] = d2
     if absg is not None:

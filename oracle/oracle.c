@@ -221,8 +221,11 @@ typedef struct {
     int tiles;
 } proj1_t;
 
+/* cbase: the constant of the colour polynomial per channel (NULL: 0.5, the
+ * plain 3DGS offset; with appearance offsets it is their colour part) */
 static void project_one(const ocam_t *cam, const oopt_t *opt, const double mu[3], const double s[3],
-                        const double q[4], double o, const double *sh, int64_t sh_stride, proj1_t *P) {
+                        const double q[4], double o, const double *sh, int64_t sh_stride, const double *cbase,
+                        proj1_t *P) {
     memset(P, 0, sizeof(*P));
     /* camera-space mean */
     for (int i = 0; i < 3; i++)
@@ -346,7 +349,7 @@ static void project_one(const ocam_t *cam, const oopt_t *opt, const double mu[3]
     for (int ch = 0; ch < 3; ch++) {
         double acc = 0.0;
         for (int k = 0; k < nb; k++) acc += sh[(k * 3 + ch) * sh_stride] * P->Y[k];
-        P->raw[ch] = acc + 0.5;
+        P->raw[ch] = acc + (cbase ? cbase[ch] : 0.5);
         P->clamped[ch] = P->raw[ch] < 0.0;
         P->rgb[ch] = P->clamped[ch] ? 0.0 : P->raw[ch];
     }
@@ -360,13 +363,14 @@ static void load_params(int64_t n, int64_t i, const double *means, const double 
 }
 
 int orc_project(int64_t n, const double *means, const double *scales, const double *quats, const double *opac,
-                const double *sh, const ocam_t *cam, const oopt_t *opt, oproj_t *out) {
+                const double *sh, const double *cbase /* [n][3] or NULL */, const ocam_t *cam, const oopt_t *opt,
+                oproj_t *out) {
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; i++) {
         double mu[3], s[3], q[4];
         load_params(n, i, means, scales, quats, mu, s, q);
         proj1_t P;
-        project_one(cam, opt, mu, s, q, opac[i], sh + i, n, &P);
+        project_one(cam, opt, mu, s, q, opac[i], sh + i, n, cbase ? cbase + 3 * i : NULL, &P);
         out->visible[i] = P.visible;
         for (int k = 0; k < 3; k++) out->tcam[3 * i + k] = P.t[k];
         out->cov2d[3 * i] = P.a; out->cov2d[3 * i + 1] = P.b; out->cov2d[3 * i + 2] = P.c;
@@ -643,25 +647,29 @@ int orc_render_bwd(const ocam_t *cam, const oopt_t *opt, int64_t tile_off, const
 /* ------------------------------------------------------------------------ */
 
 /* Adds this view's parameter gradients to d_means[3][n], d_scales[3][n],
- * d_quats[4][n], d_opac[n], d_sh[16][3][n]; writes |d mean2d| per slot. */
+ * d_quats[4][n], d_opac[n], d_sh[16][3][n] and, when given, d_cbase[n][3]
+ * (the colour constant); writes |d mean2d| per slot. */
 int orc_project_bwd(int64_t n, const double *means, const double *scales, const double *quats, const double *opac,
-                    const double *sh, const ocam_t *cam, const oopt_t *opt, const double *d2, double *d_means,
-                    double *d_scales, double *d_quats, double *d_opac, double *d_sh, double *mean2d_norm) {
+                    const double *sh, const double *cbase, const ocam_t *cam, const oopt_t *opt, const double *d2,
+                    double *d_means, double *d_scales, double *d_quats, double *d_opac, double *d_sh,
+                    double *d_cbase, double *mean2d_norm) {
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; i++) {
         double mu[3], s[3], q[4];
         load_params(n, i, means, scales, quats, mu, s, q);
         proj1_t P;
-        project_one(cam, opt, mu, s, q, opac[i], sh + i, n, &P);
+        project_one(cam, opt, mu, s, q, opac[i], sh + i, n, cbase ? cbase + 3 * i : NULL, &P);
         const double *g = d2 + 10 * i;
         mean2d_norm[i] = sqrt(g[0] * g[0] + g[1] * g[1]);
         if (!P.visible) continue;
         double dmu[3] = {0.0, 0.0, 0.0}, dt[3] = {0.0, 0.0, 0.0};
 
-        /* colour: raw = sum_k sh_k Y_k(dhat) + 0.5, clamped at 0 */
+        /* colour: raw = sum_k sh_k Y_k(dhat) + cbase, clamped at 0 */
         int nb = (opt->sh_degree + 1) * (opt->sh_degree + 1);
         double graw[3];
         for (int ch = 0; ch < 3; ch++) graw[ch] = P.clamped[ch] ? 0.0 : g[6 + ch];
+        if (d_cbase)
+            for (int ch = 0; ch < 3; ch++) d_cbase[3 * i + ch] += graw[ch];
         for (int k = 0; k < nb; k++)
             for (int ch = 0; ch < 3; ch++) d_sh[(k * 3 + ch) * n + i] += graw[ch] * P.Y[k];
         double dY[16][3];

@@ -619,3 +619,127 @@ def test_dssim_gradient_by_finite_differences():
         lm = OS.dssim(x, y, 0.2)[0]
         x[i] = old
         assert abs((lp - lm) / (2 * h) - g[i]) <= 1e-7 + 1e-5 * abs(g[i]), i
+
+
+# --------------------------------------------------------------- appearance transform
+
+def _mlp_inputs(rng, n):
+    from oracle import appearance as OA
+    return (rng.normal(0, 1, (n, OA.GAUSS_DIM)), rng.normal(0, 1, OA.IMAGE_DIM),
+            rng.normal(0, 0.4, (OA.HIDDEN, OA.GAUSS_DIM + OA.IMAGE_DIM)), rng.normal(0, 0.2, OA.HIDDEN),
+            rng.normal(0, 0.5, (OA.OUT, OA.HIDDEN)), rng.normal(0, 0.2, OA.OUT))
+
+
+def test_appearance_mlp_worked_example():
+    """A hand-built MLP: g = (3, 4, 0...) normalises to (0.6, 0.8, 0...),
+    the image embedding 2 e_31 to e_31; hidden unit 0 sees 0.6 + 0.8 = 1.4,
+    unit 1 sees -2 + 0.5 < 0 and is cut by the ReLU; output 3 gets
+    ln(3) / 1.4 * 1.4 = ln 3, so its sigmoid is 3/4; the others are sigmoid(0)."""
+    from oracle import appearance as OA
+    g = np.zeros((1, 16)); g[0, 0], g[0, 1] = 3.0, 4.0
+    e = np.zeros(32); e[31] = 2.0
+    w1 = np.zeros((32, 48)); w1[0, 0] = w1[0, 1] = 1.0; w1[1, 47] = -2.0
+    b1 = np.zeros(32); b1[1] = 0.5
+    w2 = np.zeros((4, 32)); w2[3, 0] = math.log(3.0) / 1.4; w2[2, 1] = 100.0
+    f = OA.mlp_forward(g, e, w1, b1, w2, np.zeros(4))
+    np.testing.assert_allclose(f["y"][0], [0.5, 0.5, 0.5, 0.75], rtol=0, atol=1e-15)
+    assert f["h"][0, 1] == 0.0
+
+
+def test_appearance_mlp_gradient_by_finite_differences():
+    from oracle import appearance as OA
+    rng = np.random.default_rng(11)
+    ins = list(_mlp_inputs(rng, 7))
+    dy = rng.normal(0, 1, (7, 4))
+    lam = 0.3
+
+    def loss(args):
+        f = OA.mlp_forward(*args)
+        return float((f["y"] * dy).sum()) + OA.opacity_reg(f["y"], lam), f
+
+    L0, f0 = loss(ins)
+    assert np.abs(f0["a"]).min() > 1e-3          # no ReLU kink within the step
+    g = OA.mlp_backward(f0, dy, lam)
+    names = ("gemb", "iemb", "w1", "b1", "w2", "b2")
+    h = 1e-6
+    for k, name in enumerate(names):
+        arr = ins[k]
+        for _ in range(6):
+            i = tuple(int(rng.integers(0, s)) for s in arr.shape)
+            old = arr[i]
+            arr[i] = old + h
+            lp = loss(ins)[0]
+            arr[i] = old - h
+            lm = loss(ins)[0]
+            arr[i] = old
+            fd = (lp - lm) / (2 * h)
+            assert abs(fd - g[name][i]) <= 1e-7 + 1e-6 * abs(fd), (name, i, fd, g[name][i])
+
+
+def test_appearance_mlp_scale_invariance_of_normalised_embeddings():
+    """The MLP sees only directions of both embeddings: outputs are invariant
+    under positive scaling and each embedding gradient is orthogonal to it."""
+    from oracle import appearance as OA
+    rng = np.random.default_rng(12)
+    gemb, iemb, w1, b1, w2, b2 = _mlp_inputs(rng, 9)
+    f = OA.mlp_forward(gemb, iemb, w1, b1, w2, b2)
+    scale = rng.uniform(0.1, 10.0, (9, 1))
+    f2 = OA.mlp_forward(gemb * scale, iemb * 3.7, w1, b1, w2, b2)
+    np.testing.assert_allclose(f2["y"], f["y"], rtol=1e-13, atol=0)
+    g = OA.mlp_backward(f, rng.normal(0, 1, (9, 4)), 0.0)
+    np.testing.assert_allclose((g["gemb"] * gemb).sum(1), 0.0, atol=1e-13)
+    assert abs(float(g["iemb"] @ iemb)) < 1e-12
+    # a zero embedding stays finite (the 1e-12 floor of the norm)
+    f3 = OA.mlp_forward(np.zeros((1, 16)), iemb, w1, b1, w2, b2)
+    assert np.isfinite(f3["y"]).all()
+
+
+def test_appearance_identity_offsets_leave_the_render_unchanged():
+    """dc = 1/2, do = 0 is the identity of the offset rule; do = 1 makes
+    every Gaussian transparent."""
+    sc, cam = S.random_scene(512, 0), S.camera_c1()
+    opt = {"sh_degree": 3}
+    base = oracle.forward(sc, cam, opt)["images"][0]
+    ident = np.tile([0.5, 0.5, 0.5, 0.0], (sc.n, 1))
+    im = oracle.forward(sc, cam, opt, app=ident)["images"][0]
+    for k in ("rgb", "depth", "alpha", "T", "last"):
+        assert np.array_equal(im[k], base[k]), k
+    clear = np.tile([0.5, 0.5, 0.5, 1.0], (sc.n, 1))
+    im = oracle.forward(sc, cam, opt, app=clear)["images"][0]
+    assert (im["T"] == 1.0).all() and (im["rgb"] == 0.0).all()
+
+
+def test_appearance_offset_gradients_by_finite_differences():
+    """Render gradients with respect to the offsets (through o (1 - do) and
+    the colour constant) against FP64 central differences."""
+    sc, cam = S.random_scene(256, 3), S.camera_c1()
+    opt = {"sh_degree": 3, "aa": True}
+    rng = np.random.default_rng(5)
+    app = np.column_stack([rng.uniform(0.2, 0.8, (sc.n, 3)), rng.uniform(0.0, 0.5, sc.n)])
+    f = oracle.forward(sc, cam, opt, app=app)
+    H, W = cam.height, cam.width
+    w = (rng.normal(0, 1, (H, W, 3)), rng.normal(0, 1, (H, W)), rng.normal(0, 1, (H, W)))
+    g = oracle.backward(sc, f, [w])
+
+    def lin(a):
+        im = oracle.forward(sc, cam, opt, app=a)["images"][0]
+        return float((im["rgb"] * w[0]).sum() + (im["depth"] * w[1]).sum() + (im["alpha"] * w[2]).sum()), im
+
+    seen = np.nonzero(f["proj"][0]["tiles"] > 0)[0]
+    h = 1e-7
+    checked = 0
+    for i in rng.permutation(seen)[:12]:
+        for c in range(4):
+            a = app.copy(); a[i, c] += h
+            lp, ip = lin(a)
+            a[i, c] -= 2 * h
+            lm, im_ = lin(a)
+            if not (np.array_equal(ip["last"], im_["last"]) and np.array_equal(ip["last"], f["images"][0]["last"])):
+                continue                     # the skip/stop set moved inside the step
+            fd = (lp - lm) / (2 * h)
+            assert abs(fd - g["app"][i, c]) <= 1e-5 * max(1.0, abs(fd)), (i, c, fd, g["app"][i, c])
+            checked += 1
+    assert checked >= 30
+    # the opacity gradient is chained through o (1 - do)
+    f0 = oracle.forward(sc, cam, opt, app=None)
+    assert np.isfinite(g["opacities"]).all() and f0["app"] is None
