@@ -743,3 +743,131 @@ def test_appearance_offset_gradients_by_finite_differences():
     # the opacity gradient is chained through o (1 - do)
     f0 = oracle.forward(sc, cam, opt, app=None)
     assert np.isfinite(g["opacities"]).all() and f0["app"] is None
+
+
+# --------------------------------------------------------------- densification bookkeeping
+
+def test_densify_accumulate_worked_example():
+    """Two views, three Gaussians: Gaussian 1 unseen in view 0; AbsGS mode
+    takes the length of the per-axis sums (3-4-5)."""
+    from oracle import densify as OD
+    tiles = np.array([[2, 0, 1], [1, 1, 0]])
+    gn = np.array([[0.5, 9.0, 1.0], [0.25, 2.0, 7.0]])
+    acc, cnt = OD.accumulate(tiles, grad_norm=gn, view_scale=[2.0, 4.0])
+    np.testing.assert_array_equal(cnt, [2, 1, 1])
+    np.testing.assert_allclose(acc, [0.5 * 2 + 0.25 * 4, 2.0 * 4, 1.0 * 2], rtol=0, atol=0)
+    ab = np.zeros((2, 3, 2)); ab[0, 0] = (3.0, 4.0); ab[1, 0] = (6.0, 8.0)
+    acc2, cnt2 = OD.accumulate(tiles, absgrad=ab, accum=acc, count=cnt)
+    assert acc2[0] == acc[0] + 5.0 + 10.0 and cnt2[0] == 4
+
+
+def test_densify_threshold_eq4_worked_example():
+    """tau_min inside the partition, eta tau_min beyond d_max, linear between:
+    d = 30 of d_max = 60 with eta = 4 gives tau_min (0.5 * 3 + 1)."""
+    from oracle import densify as OD
+    means = np.array([[5.0, 40.0, 200.0, 10.0], [5.0, 5.0, 5.0, -20.0], [0.0, 0.0, 0.0, 40.0]])
+    tau, d = OD.thresholds(means, (0.0, 0.0, -100.0), (10.0, 10.0, 100.0), 2e-4, 4.0, 60.0)
+    np.testing.assert_allclose(d, [0.0, 30.0, 190.0, 20.0], rtol=1e-15)
+    np.testing.assert_allclose(tau, [2e-4, 2.5 * 2e-4, 4 * 2e-4, 2e-4 * (20 / 60 * 3 + 1)], rtol=1e-15)
+
+
+def test_densify_box_distance_by_dense_sampling():
+    from oracle import densify as OD
+    rng = np.random.default_rng(3)
+    lo, hi = np.array([-2.0, 1.0, 0.0]), np.array([3.0, 2.0, 5.0])
+    g = [np.linspace(lo[k], hi[k], 41) for k in range(3)]
+    box = np.stack(np.meshgrid(*g, indexing="ij"), -1).reshape(-1, 3)
+    pts = rng.uniform(-8, 10, (40, 3))
+    d = OD.box_distance(pts.T, lo, hi)
+    brute = np.sqrt(((pts[:, None, :] - box[None, :, :]) ** 2).sum(-1)).min(1)
+    assert np.all(d <= brute + 1e-12) and np.all(brute - d <= 0.2)   # grid step 0.125 at most
+
+
+def test_densify_select_worked_example():
+    """Six Gaussians, budget for 2 new ones after pruning one: the two
+    largest mean / tau win; the larger-scaled of them is split."""
+    from oracle import densify as OD
+    means = np.zeros((3, 6)); means[0, 5] = 70.0          # Gaussian 5 is 60 m outside: tau = 4 tau_min
+    acc = np.array([3.0, 6.0, 1.0, 9.0, 5.0, 12.0]) * 1e-4
+    cnt = np.array([1, 2, 1, 3, 1, 1])                    # means 3, 3, 1, 3, 5, 12 (x 1e-4)
+    scales = np.full((3, 6), 0.01); scales[1, 4] = 0.5
+    opac = np.array([0.5, 0.5, 0.5, 0.001, 0.5, 0.5])      # Gaussian 3 is pruned
+    r = OD.select(acc, cnt, means, scales, opac, (-10, -10, -10), (10, 10, 10), 2e-4, 4.0, 60.0, 0.005, 0.1,
+                  budget=7)
+    # candidates: 0 (1.5), 1 (1.5), 4 (2.5), 5 (12 / 8 = 1.5); 2 is below tau; K = 7 - 5 = 2
+    assert r["k"] == 2
+    assert list(r["candidates"]) == [0, 1, 4, 5]
+    assert list(r["action"]) == [OD.CLONE, OD.KEEP, OD.KEEP, OD.PRUNE, OD.SPLIT, OD.KEEP]
+
+
+def test_densify_select_invariants():
+    from oracle import densify as OD
+    rng = np.random.default_rng(4)
+    n = 3000
+    means = rng.uniform(-50, 50, (3, n))
+    acc = rng.exponential(4e-4, n)
+    cnt = rng.integers(0, 5, n)
+    scales = rng.uniform(0.001, 0.2, (3, n))
+    opac = rng.uniform(0, 1, n)
+    for budget in (0, n - 50, n + 100, 10 * n):
+        r = OD.select(acc, cnt, means, scales, opac, (-10, -10, -5), (10, 10, 5), 2e-4, 4.0, 40.0, 0.01, 0.1, budget)
+        a = r["action"]
+        assert ((a == OD.PRUNE) == (opac < 0.01)).all()
+        kept = np.isin(a, (OD.CLONE, OD.SPLIT))
+        assert kept.sum() == min(r["k"], len(r["candidates"]))
+        cand = np.zeros(n, bool); cand[r["candidates"]] = True
+        assert not (kept & ~cand).any()
+        if kept.any() and (cand & ~kept).any():
+            assert r["score"][kept].min() >= r["score"][cand & ~kept].max()
+        assert ((a == OD.SPLIT) == (kept & (scales.max(0) > 0.1))).all()
+
+
+def test_filter3d_is_an_isotropic_covariance_addition():
+    """R diag(s'^2) R^T = R diag(s^2) R^T + sigma^2 I, and the opacity factor
+    is sqrt(det Sigma / det Sigma') (numpy determinants)."""
+    from oracle import densify as OD
+    rng = np.random.default_rng(5)
+    for _ in range(10):
+        q = rng.normal(size=4); s = rng.uniform(0.01, 0.5, 3); rate = rng.uniform(50, 500)
+        s2, o2 = OD.filter_apply(s[:, None], np.array([0.8]), np.array([rate]), 0.45)
+        sig2 = (0.45 / rate) ** 2
+        S0 = oracle.cov3d(q, s)
+        S1 = oracle.cov3d(q, s2[:, 0])
+        np.testing.assert_allclose(S1, S0 + sig2 * np.eye(3), rtol=1e-12, atol=1e-15)
+        np.testing.assert_allclose(o2[0], 0.8 * np.sqrt(np.linalg.det(S0) / np.linalg.det(S1)), rtol=1e-10)
+    s2, o2 = OD.filter_apply(np.full((3, 1), 0.1), np.array([0.7]), np.array([0.0]), 0.45)
+    assert s2[0, 0] == 0.1 and o2[0] == 0.7                   # unseen: no filter
+
+
+def test_filter3d_gradient_by_finite_differences():
+    from oracle import densify as OD
+    rng = np.random.default_rng(6)
+    n = 20
+    s, o, r = rng.uniform(0.01, 0.3, (3, n)), rng.uniform(0.1, 1, n), rng.uniform(20, 300, n)
+    r[3] = 0.0
+    ws, wo = rng.normal(size=(3, n)), rng.normal(size=n)
+    f = lambda s_, o_: float((OD.filter_apply(s_, o_, r, 0.45)[0] * ws).sum() + (OD.filter_apply(s_, o_, r, 0.45)[1] * wo).sum())
+    ds, do = OD.filter_bwd(s, o, r, 0.45, ws, wo)
+    h = 1e-7
+    for k in range(3):
+        for i in range(n):
+            sp, sm = s.copy(), s.copy(); sp[k, i] += h; sm[k, i] -= h
+            assert abs((f(sp, o) - f(sm, o)) / (2 * h) - ds[k, i]) <= 1e-6 * max(1, abs(ds[k, i]))
+    for i in range(n):
+        op, om = o.copy(), o.copy(); op[i] += h; om[i] -= h
+        assert abs((f(s, op) - f(s, om)) / (2 * h) - do[i]) <= 1e-7
+
+
+def test_filter3d_rate_closed_forms():
+    """On the optical axis at depth z the rate is f / z; behind the camera or
+    outside the widened image it is 0; with two cameras the larger wins."""
+    from oracle import densify as OD
+    cam = S.camera_c1()                                       # f = 150, centre at z = -4 looking +z
+    means = np.array([[0.0, 0.0, 0.0, 0.0, 5.0], [0.0, 0.0, 0.0, 0.0, 0.0], [0.0, 2.0, -6.0, 1.0, 0.0]])
+    r = OD.filter_rate(means, [cam])
+    np.testing.assert_allclose(r[:4], [150 / 4.0, 150 / 6.0, 0.0, 150 / 5.0], rtol=1e-12)
+    assert r[4] == 0.0                                        # x / z = 5 / 4 beyond (80 + 24) / 150
+    vm = np.array(cam.viewmat, np.float32).copy(); vm[2, 3] = 2.0
+    near = S.Camera(cam.fx, cam.fy, cam.cx, cam.cy, vm, cam.width, cam.height)
+    r2 = OD.filter_rate(means, [cam, near])
+    np.testing.assert_allclose(r2[:2], [150 / 2.0, 150 / 4.0], rtol=1e-12)
