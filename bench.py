@@ -201,6 +201,8 @@ def main():
             roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None}
 
+    nxt = next_rows_bench(gs, torch, scene.n, W, H, dev, max(5, args.steps))
+
     serve = None
     if not args.no_serve:
         del params, stats, proj, pv, rg, out
@@ -239,8 +241,108 @@ def main():
         "workload_stats": {"visible": n_vis, "in_front": n_front, "pairs": P, "evals_fwd": e_fwd, "evals_bwd": e_bwd},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "next_rows": nxt,
     }
     print(json.dumps(rec), flush=True)
+
+
+# Algorithmic HBM bytes per unit of the kernels measured beside the step
+APP_FWD_BYTES = 64 + 16            # per Gaussian: embedding in, offsets out
+APP_BWD_BYTES = 64 + 16 + 16 + 64  # embedding, offsets and their gradient in; embedding gradient out
+APP_FWD_MFMA, APP_BWD_MFMA = 64, 104          # v_mfma_f32_16x16x4_f32 per 64 Gaussians
+MFMA_F32_FLOPS = 16 * 16 * 4 * 2
+# D-SSIM per pixel (3 channels, float32): forward reads x, y and writes 3
+# partials; backward reads the partials, x and y and writes dx
+DSSIM_BYTES = (12 + 12 + 36) + (36 + 12 + 12 + 12)
+
+
+# per Gaussian, one view: tiles + statistic read, sum and count read and written
+DENS_ACC_BYTES = 4 + 4 + 8 + 8
+# scales, opacity and rate read; filtered scales and opacity written
+FILTER_FWD_BYTES = 12 + 4 + 4 + 12 + 4
+
+
+class _Ctx:
+    """Stand-in autograd context for timing a Function's forward alone."""
+
+    def save_for_backward(self, *a):
+        pass
+
+
+def S_cam_ring(k):
+    import synthetic as S
+    import numpy as np
+    eye = (120.0 * np.cos(k * 0.4), 120.0 * np.sin(k * 0.4), 1.7)
+    return S.Camera(1371.1, 1371.1, 960.0, 540.0, S.look_at(eye, (0.0, 0.0, 1.7), up=(0, 0, 1)), 1920, 1080)
+
+
+def next_rows_bench(gs, torch, n, W, H, dev, reps):
+    """Appearance MLP (forward, backward) over the scene's n Gaussians and
+    D-SSIM (value + gradient) over the W x H image, timed with events on the
+    stream the library launches on; HBM fraction of the algorithmic bytes."""
+    g = torch.Generator(device="cpu").manual_seed(5)
+    gemb = torch.randn(n, 16, generator=g).to(dev)
+    iemb = torch.randn(32, generator=g).to(dev)
+    p = gs.AppearanceParams.init(dev, seed=6)
+    dy = torch.randn(n, 4, generator=g).to(dev)
+    d_reg = torch.ones(1, device=dev)
+
+    def timed(fn):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        a, b = _ev(torch), None
+        for _ in range(reps):
+            fn()
+        b = _ev(torch)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    ms_f = timed(lambda: gs.appearance_mlp_fwd(gemb, iemb, p.w1, p.b1, p.w2, p.b2, 0.1))
+    off, _ = gs.appearance_mlp_fwd(gemb, iemb, p.w1, p.b1, p.w2, p.b2, 0.1)
+    ms_b = timed(lambda: gs.appearance_mlp_bwd(gemb, iemb, p.w1, p.b1, p.w2, p.b2, off, dy, d_reg, 0.1))
+    # densification bookkeeping over one step's statistics and the 3D filter
+    D = gs.densify
+    st = D.DensifyStats(n, dev)
+    tiles = (torch.rand(n, generator=g) < 0.16).to(torch.int32).to(dev)
+    gn = (torch.rand(1, n, generator=g) * 6e-4).to(dev)
+    ms_acc = timed(lambda: D.accumulate(st, tiles, grad_norm=gn))
+    box = (-25.0, -25.0, -5.0), (25.0, 25.0, 45.0)
+    means = (torch.rand(3, n, generator=g) * 300 - 150).to(dev)
+    scl = torch.exp(torch.randn(3, n, generator=g) * 0.7 - 2.5).to(dev)
+    opac = torch.rand(n, generator=g).to(dev)
+    st.accum.copy_((torch.rand(n, generator=g) * 1e-3).to(dev))
+    st.count.fill_(1)
+    prm = D.DensifyParams(box[0], box[1], tau_min=2e-4, eta=4.0, d_max=50.0, budget=n + n // 50)
+    ms_sel = timed(lambda: D.select(st, means, scl, opac, prm))
+    cams16 = [S_cam_ring(k) for k in range(16)]
+    ms_rate = timed(lambda: D.filter3d_rate(means, cams16))
+    rate = D.filter3d_rate(means, cams16)
+    ms_ff = timed(lambda: D.Filter3D.forward(_Ctx(), scl, opac, rate, 0.45))
+    del st, tiles, gn, means, opac, rate
+    img = torch.rand(H, W, 3, generator=g).to(dev)
+    tgt = torch.rand(H, W, 3, generator=g).to(dev)
+    ms_s = timed(lambda: gs.dssim_loss(img, tgt, 0.2))
+    del gemb, dy, off
+
+    def hbm(nbytes, ms):
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        return {"achieved_GB_s": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+
+    def mfma(n_mfma, ms):
+        tf = n * n_mfma / 64 * MFMA_F32_FLOPS / (ms * 1e-3) / 1e12
+        return {"achieved_TFLOP_s": round(tf, 2), "peak": 157.3, "frac": round(tf / 157.3, 4)}
+
+    return {
+        "appearance_mlp": {"n_gaussians": n, "fwd_ms": round(ms_f, 4), "bwd_ms": round(ms_b, 4),
+                           "fwd_hbm": hbm(n * APP_FWD_BYTES, ms_f), "bwd_hbm": hbm(n * APP_BWD_BYTES, ms_b),
+                           "fwd_mfma_f32": mfma(APP_FWD_MFMA, ms_f), "bwd_mfma_f32": mfma(APP_BWD_MFMA, ms_b)},
+        "dssim": {"pixels": W * H, "ms": round(ms_s, 4), "hbm": hbm(W * H * DSSIM_BYTES, ms_s)},
+        "densify": {"n_gaussians": n, "accumulate_ms": round(ms_acc, 4),
+                    "accumulate_hbm": hbm(n * DENS_ACC_BYTES, ms_acc), "select_ms": round(ms_sel, 4),
+                    "filter3d_rate_16cams_ms": round(ms_rate, 4), "filter3d_rate_hbm": hbm(n * 16, ms_rate),
+                    "filter3d_fwd_ms": round(ms_ff, 4), "filter3d_fwd_hbm": hbm(n * FILTER_FWD_BYTES, ms_ff)},
+    }
 
 
 STAGE_KERNEL = {"render_fwd": "k_render_fwd", "composite_bwd": "k_render_bwd", "project": "k_project_fwd",

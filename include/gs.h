@@ -92,15 +92,23 @@ typedef struct gs_options {
     float bg[3];            /* background colour added as T_final * bg */
 } gs_options;
 
+/* app (nullable): appearance offsets [n][4] = (dc_r, dc_g, dc_b, do) from
+ * gs_appearance_fwd (§3.5.1).  When set, the colour constant 1/2 becomes dc
+ * (colour = max(0, sum_lm sh_lm Y_lm(d) + dc)) and the opacity becomes
+ * o (1 - do); dc = 1/2, do = 0 is the plain rasterizer.  16-byte aligned. */
 typedef struct gs_gaussians {
     const float *means, *scales, *quats, *opacities, *sh;
     int64_t n;
+    const float *app;
 } gs_gaussians;
 
 /* Parameter gradients, same layouts as gs_gaussians; written (not added to),
- * summed over the views of the call. */
+ * summed over the views of the call.  d_app [n][4] (nullable; used only when
+ * gs_gaussians.app is set) receives the gradient with respect to the
+ * appearance offsets. */
 typedef struct gs_gaussians_grad {
     float *d_means, *d_scales, *d_quats, *d_opacities, *d_sh;
+    float *d_app;
 } gs_gaussians_grad;
 
 /* Projected per-slot records (n_views * n slots).
@@ -250,6 +258,124 @@ int gs_loss_l1_depth(const float *rgb, const float *depth, const float *alpha, c
 size_t gs_dssim_workspace_size(int32_t width, int32_t height);
 int gs_dssim(const float *rgb, const float *target, int32_t width, int32_t height, float weight, float *loss,
              float *d_rgb, void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Appearance transform module (§3.5.1; sizes from the implementation
+ * details of the appendix).  Every Gaussian has an embedding (16 values),
+ * every image one (32 values); a small MLP maps both to per-Gaussian colour
+ * and opacity offsets:
+ *   x = (g / max(|g|, 1e-12), e / max(|e|, 1e-12))       (48)
+ *   h = ReLU(W1 x + b1)                                   (32)
+ *   y = sigmoid(W2 h + b2) = (dc_r, dc_g, dc_b, do)       (4)
+ * W1 [32][48] (Gaussian-embedding columns first), b1 [32], W2 [4][32],
+ * b2 [4], row-major float32 device arrays.  The offsets y feed the
+ * rasterizer through gs_gaussians.app; they only change when the image
+ * embedding or the weights do, so rendering reuses them at no cost.
+ * The opacity-offset regulariser is reg_weight * mean_i do_i.
+ * ---------------------------------------------------------------------- */
+#define GS_APP_GAUSS_DIM 16
+#define GS_APP_IMAGE_DIM 32
+#define GS_APP_HIDDEN 32
+#define GS_APP_OUT 4
+
+typedef struct gs_appearance_mlp {
+    const float *w1, *b1, *w2, *b2;
+} gs_appearance_mlp;
+
+/* Gradients of the MLP's weights and of the image embedding, written (not
+ * added to); d_image_emb may be NULL. */
+typedef struct gs_appearance_grad {
+    float *d_w1, *d_b1, *d_w2, *d_b2, *d_image_emb;
+} gs_appearance_grad;
+
+/* Scratch bytes of gs_appearance_fwd / gs_appearance_bwd (about 5.5 MB of
+ * workgroup partials, whatever n). */
+size_t gs_appearance_workspace_size(int64_t n);
+
+/* Offsets y [n][4] of n Gaussians (gauss_emb [n][16], 16-byte aligned) for
+ * one image embedding image_emb [32].  reg_value (nullable, device [1])
+ * receives reg_weight * mean do, summed in a fixed order.  n = 0 writes
+ * only reg_value = 0.  Errors: GS_ERR_INVALID_ARG for n < 0, null or
+ * misaligned pointers, a workspace smaller than the size above. */
+int gs_appearance_fwd(const float *gauss_emb, int64_t n, const float *image_emb, const gs_appearance_mlp *mlp,
+                      float reg_weight, float *offsets, float *reg_value, void *ws, size_t ws_bytes, void *stream);
+
+/* Backward of gs_appearance_fwd for the upstream gradient d_offsets [n][4]
+ * plus, when d_reg (device [1], nullable) is given, d_reg times the
+ * regulariser's gradient reg_weight / n on every do.  offsets are the
+ * forward's outputs.  Writes d_gauss_emb [n][16] and every pointer of
+ * `out`; the weight gradients are sums over all Gaussians, added in a fixed
+ * order (deterministic). */
+int gs_appearance_bwd(const float *gauss_emb, int64_t n, const float *image_emb, const gs_appearance_mlp *mlp,
+                      const float *offsets, const float *d_offsets, const float *d_reg, float reg_weight,
+                      float *d_gauss_emb, const gs_appearance_grad *out, void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Densification bookkeeping (consumers of the backward's statistics between
+ * training steps) and the 3D smoothing filter.
+ *   - the statistic 3DGS densification thresholds is a Gaussian's mean
+ *     image-space gradient over the views that rasterized it (§3.1, after
+ *     Eq. 2); AbsGS (§3.5.4) uses the per-axis absolute sums instead;
+ *   - in-partition prioritized densification (§3.3, Eq. 4): Gaussian i is a
+ *     candidate only if its mean exceeds
+ *       tau_i = tau_min (min(d_i, d_max) / d_max (eta - 1) + 1),
+ *     d_i = distance from its mean to the partition's box (0 inside);
+ *   - a Gaussian budget B caps the model (§3.4.1, the steerable
+ *     densification each detail level trains under): after pruning, at most
+ *     B - (n - pruned) candidates grow, those with the largest mean / tau_i
+ *     (ties: lower index); a grown Gaussian is split when its largest scale
+ *     exceeds split_scale, else cloned;
+ *   - the Mip-Splatting 3D smoothing filter (§3.5.4): rate_i = max over the
+ *     cameras holding the mean (depth in [near, far], projection inside the
+ *     image widened by 15 % per side) of fx / depth; the filter adds
+ *     (s_f / rate_i)^2 to every axis of Sigma, i.e. scales become
+ *     sqrt(s^2 + (s_f / rate)^2) and the opacity is scaled by prod s / s'
+ *     (= sqrt(det Sigma / det Sigma')); rate 0 (unseen) means no filter.
+ * ---------------------------------------------------------------------- */
+#define GS_DENSIFY_KEEP 0
+#define GS_DENSIFY_CLONE 1
+#define GS_DENSIFY_SPLIT 2
+#define GS_DENSIFY_PRUNE 3
+
+/* Adds one step's views to the running statistic: for every view v and
+ * Gaussian i with tiles[v][i] > 0, accum[i] += value * view_scale[v] and
+ * count[i] += 1 (views in order), where value = grad_norm[v][i] or, when
+ * absgrad ([n_views][n][2]) is given instead, the length of absgrad[v][i].
+ * view_scale is a host array [n_views] (NULL: all 1), e.g. (W/2, H/2)-style
+ * unit changes folded into one factor.  n_views 1..GS_MAX_VIEWS. */
+int gs_densify_accumulate(const uint32_t *tiles, const float *grad_norm, const float *absgrad, int32_t n_views,
+                          int64_t n, const float *view_scale, float *accum, int32_t *count, void *stream);
+
+typedef struct gs_densify_params {
+    float box_min[3], box_max[3];  /* partition box */
+    float tau_min, eta, d_max;     /* Eq. 4 */
+    float prune_opacity;           /* opacity below this prunes */
+    float split_scale;             /* largest scale above this splits, else clones */
+    int64_t budget;                /* Gaussians allowed after this densification */
+} gs_densify_params;
+
+size_t gs_densify_workspace_size(int64_t n);
+
+/* Writes action[n] (GS_DENSIFY_*) from the statistic (mean = accum / count
+ * in float32, 0 when count is 0) and the parameters (means [3][n], scales
+ * [3][n], opacities [n]).  counts (host [4]) receives: candidates, pruned,
+ * grown, and the budget's room K.  Synchronises `stream` (the candidate and
+ * pruned totals decide the selection).  n < 2^32 - 256. */
+int gs_densify_select(const float *accum, const int32_t *count, const float *means, const float *scales,
+                      const float *opacities, int64_t n, const gs_densify_params *p, uint8_t *action,
+                      int64_t *counts, void *ws, size_t ws_bytes, void *stream);
+
+/* rate[n] of the 3D filter over n_cams cameras (any number; taken 16 per
+ * launch). */
+int gs_filter3d_rate(const float *means, int64_t n, const gs_camera *cams, int32_t n_cams, float *rate, void *stream);
+
+/* Filtered scales_out [3][n] and opacities_out [n], and the backward that
+ * chains their gradients to d_scales [3][n] and d_opacities [n]. */
+int gs_filter3d_fwd(const float *scales, const float *opacities, const float *rate, int64_t n, float s_f,
+                    float *scales_out, float *opacities_out, void *stream);
+int gs_filter3d_bwd(const float *scales, const float *opacities, const float *rate, int64_t n, float s_f,
+                    const float *d_scales_out, const float *d_opacities_out, float *d_scales, float *d_opacities,
+                    void *stream);
 
 /* ------------------------------------------------------------------------
  * Level-of-detail selection and serving (§3.4.2 "Detail Level Selection",

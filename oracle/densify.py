@@ -14,7 +14,9 @@ Readings where the text is silent (the same in the kernels):
 * statistic per view where the Gaussian was rasterized (tiles > 0):
   |dL/d mean2d| times a per-view scale (pixel -> NDC units, or 1), or, in the
   AbsGS mode, |(sum_p |dL_p/dx|, sum_p |dL_p/dy|)| times that scale; summed
-  over views and iterations with a count of views; mean = sum / count;
+  over views and iterations with a count of views; mean = sum / count,
+  formed in float32 (the statistic's storage precision, so that the
+  threshold decision is taken on the same value the kernels hold);
 * d_i = Euclidean distance from the mean to the partition's axis-aligned box
   (0 inside); tau_i = tau_min (min(d_i, d_max) / d_max (eta - 1) + 1) (Eq. 4);
   a Gaussian is a candidate when its mean exceeds tau_i;
@@ -76,10 +78,10 @@ def thresholds(means, box_min, box_max, tau_min, eta, d_max):
 def select(accum, count, means, scales, opacities, box_min, box_max, tau_min, eta, d_max, prune_opacity,
            split_scale, budget):
     """Actions [n] (KEEP/CLONE/SPLIT/PRUNE) and the intermediate values."""
-    acc = np.asarray(accum, np.float64)
+    acc = np.asarray(accum, np.float32)
     cnt = np.asarray(count, np.int64)
     n = acc.shape[0]
-    mean = np.where(cnt > 0, acc / np.maximum(cnt, 1), 0.0)
+    mean = np.where(cnt > 0, (acc / np.maximum(cnt, 1).astype(np.float32)).astype(np.float64), 0.0)
     tau, d = thresholds(means, box_min, box_max, tau_min, eta, d_max)
     prune = np.asarray(opacities, np.float64) < prune_opacity
     cand = (mean > tau) & ~prune

@@ -44,12 +44,27 @@ class GsOptions(C.Structure):
 
 class GsGaussians(C.Structure):
     _fields_ = [("means", C.c_void_p), ("scales", C.c_void_p), ("quats", C.c_void_p),
-                ("opacities", C.c_void_p), ("sh", C.c_void_p), ("n", C.c_int64)]
+                ("opacities", C.c_void_p), ("sh", C.c_void_p), ("n", C.c_int64), ("app", C.c_void_p)]
 
 
 class GsGaussiansGrad(C.Structure):
     _fields_ = [("d_means", C.c_void_p), ("d_scales", C.c_void_p), ("d_quats", C.c_void_p),
-                ("d_opacities", C.c_void_p), ("d_sh", C.c_void_p)]
+                ("d_opacities", C.c_void_p), ("d_sh", C.c_void_p), ("d_app", C.c_void_p)]
+
+
+class GsDensifyParams(C.Structure):
+    _fields_ = [("box_min", C.c_float * 3), ("box_max", C.c_float * 3), ("tau_min", C.c_float), ("eta", C.c_float),
+                ("d_max", C.c_float), ("prune_opacity", C.c_float), ("split_scale", C.c_float),
+                ("budget", C.c_int64)]
+
+
+class GsAppearanceMlp(C.Structure):
+    _fields_ = [("w1", C.c_void_p), ("b1", C.c_void_p), ("w2", C.c_void_p), ("b2", C.c_void_p)]
+
+
+class GsAppearanceGrad(C.Structure):
+    _fields_ = [("d_w1", C.c_void_p), ("d_b1", C.c_void_p), ("d_w2", C.c_void_p), ("d_b2", C.c_void_p),
+                ("d_image_emb", C.c_void_p)]
 
 
 class GsProjected(C.Structure):
@@ -105,6 +120,15 @@ SIGNATURES = {
     "gs_loss_l1_depth": (C.c_int, [_P, _P, _P, _P, _P, _I64, C.c_float, _P, _P, _P, _P, _P, _SZ, _P]),
     "gs_dssim_workspace_size": (_SZ, [_I32, _I32]),
     "gs_dssim": (C.c_int, [_P, _P, _I32, _I32, C.c_float, _P, _P, _P, _SZ, _P]),
+    "gs_densify_accumulate": (C.c_int, [_P, _P, _P, _I32, _I64, _P, _P, _P, _P]),
+    "gs_densify_workspace_size": (_SZ, [_I64]),
+    "gs_densify_select": (C.c_int, [_P, _P, _P, _P, _P, _I64, _P, _P, _P, _P, _SZ, _P]),
+    "gs_filter3d_rate": (C.c_int, [_P, _I64, _P, _I32, _P, _P]),
+    "gs_filter3d_fwd": (C.c_int, [_P, _P, _P, _I64, C.c_float, _P, _P, _P]),
+    "gs_filter3d_bwd": (C.c_int, [_P, _P, _P, _I64, C.c_float, _P, _P, _P, _P, _P]),
+    "gs_appearance_workspace_size": (_SZ, [_I64]),
+    "gs_appearance_fwd": (C.c_int, [_P, _I64, _P, _P, C.c_float, _P, _P, _P, _SZ, _P]),
+    "gs_appearance_bwd": (C.c_int, [_P, _I64, _P, _P, _P, _P, _P, C.c_float, _P, _P, _P, _SZ, _P]),
     "gs_lod_select": (C.c_int, [_P, _P, _I64, _P, _P]),
     "gs_serve_create": (C.c_int, [_P, _P, _P, _P, _I32, _P]),
     "gs_serve_now": (C.c_double, [_P]),

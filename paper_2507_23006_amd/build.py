@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgs.so")
-SOURCES = ["project.hip", "sort.hip", "bin.hip", "render.hip", "project_bwd.hip", "loss.hip", "ssim.hip", "api.cpp", "serve.cpp"]
+SOURCES = ["project.hip", "sort.hip", "bin.hip", "render.hip", "project_bwd.hip", "loss.hip", "ssim.hip", "appearance.hip", "densify.hip", "api.cpp", "serve.cpp", "densify_api.cpp"]
 ARCH = "gfx950"
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-munsafe-fp-atomics",

@@ -91,7 +91,18 @@ int check_gaussians(const gs_gaussians* g, int32_t n_views) {
     GS_REQUIRE(g->means && g->scales && g->quats && g->opacities && g->sh, "a Gaussian parameter pointer is NULL");
     GS_REQUIRE(g->n * (int64_t)n_views <= 0xFFFFFF00LL, "n * n_views = %lld exceeds 32-bit slot ids",
                (long long)(g->n * n_views));
+    GS_REQUIRE(((uintptr_t)g->app & 15) == 0, "appearance offsets must be 16-byte aligned");
     return GS_OK;
+}
+
+GaussPtrs gauss_ptrs(const gs_gaussians* g) {
+    return GaussPtrs{g->means, g->scales, g->quats, g->opacities, g->sh, g->app};
+}
+
+// the offsets' gradient is produced only when the offsets are in use
+GradPtrs grad_ptrs(const gs_gaussians* g, const gs_gaussians_grad* out) {
+    return GradPtrs{out->d_means, out->d_scales, out->d_quats, out->d_opacities, out->d_sh,
+                    g->app ? out->d_app : nullptr};
 }
 
 int check_proj(const gs_projected* p) {
@@ -247,7 +258,7 @@ int gs_project(const gs_gaussians* g, const gs_camera* cams, int32_t n_views, co
         if ((rc = build_views(cams, n_views, &vt)) || (rc = build_opt(opt, &ok)) ||
             (rc = check_gaussians(g, n_views)) || (rc = check_proj(out)))
             return rc;
-        GaussPtrs gp{g->means, g->scales, g->quats, g->opacities, g->sh};
+        GaussPtrs gp = gauss_ptrs(g);
         GS_HIP(launch_project_fwd(gp, g->n, vt, ok, to_proj(out), (hipStream_t)stream));
         return GS_OK;
     } catch (...) {
@@ -432,8 +443,9 @@ int gs_render_bwd(const gs_gaussians* g, const gs_camera* cams, int32_t n_views,
         if (plan.work_off) GS_HIP(launch_seg_prepare(pr, pair_vals, rg, vt, last, cap, plan, s));
         GS_HIP(launch_render_bwd(pr, pair_vals, rg, vt, ok, T_final, last, d_rgb, d_depth, d_alpha, grad2d, plan, cap,
                                  s));
-        GaussPtrs gp{g->means, g->scales, g->quats, g->opacities, g->sh};
-        GradPtrs go{out->d_means, out->d_scales, out->d_quats, out->d_opacities, out->d_sh};
+        GaussPtrs gp = gauss_ptrs(g);
+        GradPtrs go = grad_ptrs(g, out);
+        GS_REQUIRE(((uintptr_t)go.app & 15) == 0, "d_app must be 16-byte aligned");
         GS_HIP(launch_project_bwd(gp, g->n, vt, ok, pr, grad2d, go, mean2d_grad_norm, absgrad, s));
         return GS_OK;
     } catch (...) {
@@ -483,13 +495,54 @@ int gs_project_bwd(const gs_gaussians* g, const gs_camera* cams, int32_t n_views
         GS_REQUIRE(grad2d && out && mean2d_grad_norm, "NULL buffer");
         GS_REQUIRE(out->d_means && out->d_scales && out->d_quats && out->d_opacities && out->d_sh,
                    "NULL gradient output");
-        GaussPtrs gp{g->means, g->scales, g->quats, g->opacities, g->sh};
-        GradPtrs go{out->d_means, out->d_scales, out->d_quats, out->d_opacities, out->d_sh};
+        GaussPtrs gp = gauss_ptrs(g);
+        GradPtrs go = grad_ptrs(g, out);
+        GS_REQUIRE(((uintptr_t)go.app & 15) == 0, "d_app must be 16-byte aligned");
         GS_HIP(launch_project_bwd(gp, g->n, vt, ok, to_proj(proj), grad2d, go, mean2d_grad_norm, absgrad,
                                   (hipStream_t)stream));
         return GS_OK;
     } catch (...) {
         return fail(GS_ERR_INTERNAL, "unexpected exception in gs_project_bwd");
+    }
+}
+
+size_t gs_appearance_workspace_size(int64_t n) { return app_workspace_bytes(n < 0 ? 0 : n); }
+
+int gs_appearance_fwd(const float* gauss_emb, int64_t n, const float* image_emb, const gs_appearance_mlp* mlp,
+                      float reg_weight, float* offsets, float* reg_value, void* ws, size_t ws_bytes, void* stream) {
+    try {
+        GS_REQUIRE(n >= 0, "n=%lld must be >= 0", (long long)n);
+        GS_REQUIRE(image_emb && mlp && mlp->w1 && mlp->b1 && mlp->w2 && mlp->b2 && ws, "NULL argument");
+        GS_REQUIRE(n == 0 || (gauss_emb && offsets), "NULL embedding or offset buffer");
+        GS_REQUIRE(((uintptr_t)gauss_emb & 15) == 0 && ((uintptr_t)offsets & 15) == 0,
+                   "embeddings and offsets must be 16-byte aligned");
+        GS_REQUIRE(ws_bytes >= app_workspace_bytes(n), "workspace too small");
+        const AppMlp w{mlp->w1, mlp->b1, mlp->w2, mlp->b2};
+        GS_HIP(launch_app_fwd(gauss_emb, n, image_emb, w, reg_weight, offsets, reg_value, ws, (hipStream_t)stream));
+        return GS_OK;
+    } catch (...) {
+        return fail(GS_ERR_INTERNAL, "unexpected exception in gs_appearance_fwd");
+    }
+}
+
+int gs_appearance_bwd(const float* gauss_emb, int64_t n, const float* image_emb, const gs_appearance_mlp* mlp,
+                      const float* offsets, const float* d_offsets, const float* d_reg, float reg_weight,
+                      float* d_gauss_emb, const gs_appearance_grad* out, void* ws, size_t ws_bytes, void* stream) {
+    try {
+        GS_REQUIRE(n >= 0, "n=%lld must be >= 0", (long long)n);
+        GS_REQUIRE(image_emb && mlp && mlp->w1 && mlp->b1 && mlp->w2 && mlp->b2 && ws && out, "NULL argument");
+        GS_REQUIRE(out->d_w1 && out->d_b1 && out->d_w2 && out->d_b2, "NULL weight gradient");
+        GS_REQUIRE(n == 0 || (gauss_emb && offsets && d_offsets && d_gauss_emb), "NULL per-Gaussian buffer");
+        GS_REQUIRE(((uintptr_t)gauss_emb & 15) == 0 && ((uintptr_t)d_gauss_emb & 15) == 0,
+                   "embeddings and their gradient must be 16-byte aligned");
+        GS_REQUIRE(ws_bytes >= app_workspace_bytes(n), "workspace too small");
+        const AppMlp w{mlp->w1, mlp->b1, mlp->w2, mlp->b2};
+        const AppGrad g{out->d_w1, out->d_b1, out->d_w2, out->d_b2, out->d_image_emb};
+        GS_HIP(launch_app_bwd(gauss_emb, n, image_emb, w, offsets, d_offsets, d_reg, reg_weight, d_gauss_emb, g, ws,
+                              (hipStream_t)stream));
+        return GS_OK;
+    } catch (...) {
+        return fail(GS_ERR_INTERNAL, "unexpected exception in gs_appearance_bwd");
     }
 }
 

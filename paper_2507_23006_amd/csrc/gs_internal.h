@@ -116,12 +116,15 @@ struct Projected {
     uint32_t* tile_order; // [tiles] compositing launch order, or null for tile index order
 };
 
+// app: appearance offsets [n][4] (dc, do) or null
 struct GaussPtrs {
     const float *means, *scales, *quats, *opac, *sh;
+    const float *app;
 };
 
 struct GradPtrs {
     float *means, *scales, *quats, *opac, *sh;
+    float *app;
 };
 
 hipError_t launch_project_fwd(const GaussPtrs& g, int64_t n, const ViewTable& vt, const OptK& opt,
@@ -215,5 +218,45 @@ hipError_t launch_dssim(const float* x, const float* y, int W, int H, float weig
 hipError_t launch_project_bwd(const GaussPtrs& g, int64_t n, const ViewTable& vt, const OptK& opt,
                               const Projected& proj, const float* grad2d, const GradPtrs& out,
                               float* mean2d_norm, float* absgrad, hipStream_t s);
+
+// appearance transform MLP (appearance.hip)
+struct AppMlp {
+    const float *w1, *b1, *w2, *b2;
+};
+struct AppGrad {
+    float *d_w1, *d_b1, *d_w2, *d_b2, *d_iemb;
+};
+size_t app_workspace_bytes(int64_t n);
+
+// densification bookkeeping and the 3D filter (densify.hip)
+struct DensViewScale {
+    float s[GS_MAX_VIEWS];
+};
+struct DensParams {
+    double box_min[3], box_max[3];
+    float tau_min, eta, d_max, prune_opacity;
+};
+hipError_t launch_dens_accumulate(const uint32_t* tiles, const float* grad_norm, const float* absgrad,
+                                  int32_t n_views, int64_t n, const DensViewScale& sc, float* accum, int32_t* count,
+                                  hipStream_t s);
+hipError_t launch_dens_classify(const float* accum, const int32_t* count, const float* means, const float* opac,
+                                int64_t n, const DensParams& p, uint8_t* action, uint32_t* cand, uint32_t* pruned,
+                                uint32_t* key, hipStream_t s);
+hipError_t launch_dens_compact(const uint32_t* cand, const uint32_t* pos, const uint32_t* key, int64_t n,
+                               uint32_t* ckey, uint32_t* cidx, hipStream_t s);
+hipError_t launch_dens_mark(const uint32_t* sidx, uint32_t k, const uint32_t* cand, bool all, const float* scales,
+                            int64_t n, float split_scale, uint8_t* action, hipStream_t s);
+hipError_t launch_filter_rate(const float* means, int64_t n, const ViewTable& vt, bool accumulate, float* rate,
+                              hipStream_t s);
+hipError_t launch_filter_fwd(const float* scales, const float* opac, const float* rate, int64_t n, float s_f,
+                             float* scales_out, float* opac_out, hipStream_t s);
+hipError_t launch_filter_bwd(const float* scales, const float* opac, const float* rate, int64_t n, float s_f,
+                             const float* d_scales_out, const float* d_opac_out, float* d_scales, float* d_opac,
+                             hipStream_t s);
+hipError_t launch_app_fwd(const float* gemb, int64_t n, const float* iemb, const AppMlp& w, float reg_weight,
+                          float* offsets, float* reg_value, void* ws, hipStream_t s);
+hipError_t launch_app_bwd(const float* gemb, int64_t n, const float* iemb, const AppMlp& w, const float* offsets,
+                          const float* d_offsets, const float* d_reg, float reg_weight, float* d_gemb,
+                          const AppGrad& g, void* ws, hipStream_t s);
 
 }  // namespace gs

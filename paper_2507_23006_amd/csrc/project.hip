@@ -39,7 +39,8 @@ __device__ __forceinline__ void view_point(const ViewK& V, double mu0, double mu
     tz = (double)V.R[6] * mu0 + (double)V.R[7] * mu1 + (double)V.R[8] * mu2 + (double)V.t[2];
 }
 
-// M = R(q) diag(s) and the opacity of Gaussian g; false for a zero quaternion
+// M = R(q) diag(s) and the opacity of Gaussian g (times 1 - do under
+// appearance offsets); false for a zero quaternion
 __device__ __forceinline__ bool load_shape(const GaussPtrs& gp, int64_t n, int64_t g, double M[9], double& opac) {
     const double s0 = gp.scales[g], s1 = gp.scales[n + g], s2 = gp.scales[2 * n + g];
     double qw = gp.quats[g], qx = gp.quats[n + g], qy = gp.quats[2 * n + g], qz = gp.quats[3 * n + g];
@@ -52,6 +53,7 @@ __device__ __forceinline__ bool load_shape(const GaussPtrs& gp, int64_t n, int64
     M[3] = Rq[3] * s0; M[4] = Rq[4] * s1; M[5] = Rq[5] * s2;
     M[6] = Rq[6] * s0; M[7] = Rq[7] * s1; M[8] = Rq[8] * s2;
     opac = gp.opac[g];
+    if (gp.app) opac *= 1.0 - (double)gp.app[4 * g + 3];
     return true;
 }
 
@@ -133,9 +135,11 @@ __device__ __forceinline__ uint32_t project_view(const ViewK& V, const OptK& opt
 }
 
 // view-dependent colour of a mean seen by V into the record's .xyz of
-// float4 2; the coefficient row is read as 16-byte vectors
+// float4 2; the coefficient row is read as 16-byte vectors; cb is the
+// constant of the polynomial (1/2, or the appearance colour offset)
 __device__ __forceinline__ void colour_view(const ViewK& V, const OptK& opt, double mu0, double mu1, double mu2,
-                                            const float4* __restrict__ shq, const Projected& out, int64_t slot) {
+                                            const float4* __restrict__ shq, float4 cb, const Projected& out,
+                                            int64_t slot) {
     const int nb = (opt.sh_degree + 1) * (opt.sh_degree + 1);
     const int nq = (3 * nb + 3) >> 2;    // float4s that hold the used coefficients
     // direction in FP64 (mu and the camera centre are large numbers), the
@@ -150,7 +154,7 @@ __device__ __forceinline__ void colour_view(const ViewK& V, const OptK& opt, dou
         const float4 t = q < nq ? shq[q] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         shv[4 * q + 0] = t.x; shv[4 * q + 1] = t.y; shv[4 * q + 2] = t.z; shv[4 * q + 3] = t.w;
     }
-    float c[3] = {0.5f, 0.5f, 0.5f};
+    float c[3] = {cb.x, cb.y, cb.z};
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
         if (k < nb) {
@@ -208,8 +212,9 @@ __device__ __forceinline__ void project_candidate(const GaussPtrs& gp, int64_t n
         out.dkey[slot] = ntiles ? __float_as_uint((float)tz) : 0xFFFFFFFFu;
     }
     const float4* shq = reinterpret_cast<const float4*>(gp.sh) + 12 * g;
+    const float4 cb = gp.app ? reinterpret_cast<const float4*>(gp.app)[g] : make_float4(0.5f, 0.5f, 0.5f, 0.0f);
     for (int v = 0; v < vt.n_views; ++v)
-        if (vis & (1u << v)) colour_view(vt.v[v], opt, mu0, mu1, mu2, shq, out, slot_base + v * slot_stride);
+        if (vis & (1u << v)) colour_view(vt.v[v], opt, mu0, mu1, mu2, shq, cb, out, slot_base + v * slot_stride);
 }
 
 constexpr int kPF = 256;                 // threads per workgroup

@@ -75,7 +75,11 @@ __device__ __forceinline__ void project_bwd_one(const GaussPtrs& gp, int64_t n, 
     M[0] = (1.0 - 2.0 * (y * y + z * z)) * s0; M[1] = 2.0 * (x * y - w * z) * s1; M[2] = 2.0 * (x * z + w * y) * s2;
     M[3] = 2.0 * (x * y + w * z) * s0; M[4] = (1.0 - 2.0 * (x * x + z * z)) * s1; M[5] = 2.0 * (y * z - w * x) * s2;
     M[6] = 2.0 * (x * z - w * y) * s0; M[7] = 2.0 * (y * z + w * x) * s1; M[8] = (1.0 - 2.0 * (x * x + y * y)) * s2;
-    const double o = gp.opac[g];
+    // appearance offsets: colour constant dc (else 1/2), opacity o (1 - do)
+    const float4 app = gp.app ? reinterpret_cast<const float4*>(gp.app)[g] : make_float4(0.5f, 0.5f, 0.5f, 0.0f);
+    const double o_raw = gp.opac[g];
+    const double o = o_raw * (gp.app ? 1.0 - (double)app.w : 1.0);
+    float dcb0 = 0.0f, dcb1 = 0.0f, dcb2 = 0.0f;
 
     double dmu[3] = {0.0, 0.0, 0.0};
     double dM[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
@@ -97,7 +101,7 @@ __device__ __forceinline__ void project_bwd_one(const GaussPtrs& gp, int64_t n, 
         const double tz = W[6] * mu0 + W[7] * mu1 + W[8] * mu2 + (double)V.t[2];
         const double fx = V.fx, fy = V.fy;
 
-        // ---- colour: raw = sum_k sh_k Y_k(dhat) + 0.5, clamped at 0 (SH in FP32)
+        // ---- colour: raw = sum_k sh_k Y_k(dhat) + dc, clamped at 0 (SH in FP32)
         {
             const double e0d = mu0 - V.campos[0], e1d = mu1 - V.campos[1], e2d = mu2 - V.campos[2];
             const double dn = sqrt(e0d * e0d + e1d * e1d + e2d * e2d);
@@ -111,7 +115,7 @@ __device__ __forceinline__ void project_bwd_one(const GaussPtrs& gp, int64_t n, 
                 const float4 t = q < nq ? shq[q] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
                 shv[4 * q + 0] = t.x; shv[4 * q + 1] = t.y; shv[4 * q + 2] = t.z; shv[4 * q + 3] = t.w;
             }
-            float raw0 = 0.5f, raw1 = 0.5f, raw2 = 0.5f;
+            float raw0 = app.x, raw1 = app.y, raw2 = app.z;
 #pragma unroll
             for (int k = 0; k < 16; ++k) {
                 if (k < nb) {
@@ -123,6 +127,7 @@ __device__ __forceinline__ void project_bwd_one(const GaussPtrs& gp, int64_t n, 
             const float gr0 = raw0 < 0.0f ? 0.0f : g2[6];
             const float gr1 = raw1 < 0.0f ? 0.0f : g2[7];
             const float gr2 = raw2 < 0.0f ? 0.0f : g2[8];
+            dcb0 += gr0; dcb1 += gr1; dcb2 += gr2;
             float e0 = 0.0f, e1 = 0.0f, e2 = 0.0f;
             float dsh[48];
 #pragma unroll
@@ -257,7 +262,9 @@ __device__ __forceinline__ void project_bwd_one(const GaussPtrs& gp, int64_t n, 
     for (int c = 0; c < 3; ++c) out.means[c * n + g] = (float)dmu[c];
     for (int c = 0; c < 3; ++c) out.scales[c * n + g] = (float)ds[c];
     for (int c = 0; c < 4; ++c) out.quats[c * n + g] = (float)((dq[c] - qh[c] * dot) / qn);
-    out.opac[g] = (float)dop;
+    // dop is the gradient with respect to o (1 - do)
+    out.opac[g] = (float)(gp.app ? dop * (1.0 - (double)app.w) : dop);
+    if (out.app) reinterpret_cast<float4*>(out.app)[g] = make_float4(dcb0, dcb1, dcb2, (float)(-dop * o_raw));
 }
 
 
@@ -298,6 +305,7 @@ __global__ __launch_bounds__(kPB) void k_project_bwd(GaussPtrs gp, int64_t n, Vi
                 for (int c = 0; c < 3; ++c) out.scales[c * n + g] = 0.0f;
                 for (int c = 0; c < 4; ++c) out.quats[c * n + g] = 0.0f;
                 out.opac[g] = 0.0f;
+                if (out.app) reinterpret_cast<float4*>(out.app)[g] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
             }
         }
         s_seen[loc] = vis ? 1 : 0;

@@ -440,6 +440,7 @@ int gs_serve_create(const gs_gaussians* scene, const gs_lod_table* table, const 
         GS_REQUIRE(cfg->pair_capacity >= 1 && cfg->pair_capacity <= 0xFFFFFF00LL, "pair_capacity out of range");
         GS_REQUIRE(cfg->pixel_capacity >= 256 && cfg->pixel_capacity <= (1LL << 31), "pixel_capacity out of range");
         GS_REQUIRE(cfg->queue_capacity >= 1, "queue_capacity must be >= 1");
+        GS_REQUIRE(((uintptr_t)scene->app & 15) == 0, "appearance offsets must be 16-byte aligned");
         s = new gs_server();
         int rc;
         if ((rc = copy_table(table, &s->lod)) || (rc = build_opt(opt, &s->opt))) {
@@ -452,7 +453,7 @@ int gs_serve_create(const gs_gaussians* scene, const gs_lod_table* table, const 
                 return fail(GS_ERR_INVALID_ARG, "lod range %zu exceeds the scene's %lld Gaussians", i,
                             (long long)scene->n);
             }
-        s->gp = GaussPtrs{scene->means, scene->scales, scene->quats, scene->opacities, scene->sh};
+        s->gp = GaussPtrs{scene->means, scene->scales, scene->quats, scene->opacities, scene->sh, scene->app};
         s->n = scene->n;
         s->cfg = *cfg;
         s->tile_cap = cfg->pixel_capacity / 16 + 1024;

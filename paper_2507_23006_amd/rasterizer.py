@@ -3,7 +3,8 @@ every computation runs in the library's gfx950 kernels.
 
 Parameter layout (structure-of-arrays, float32, on the GPU):
   means [3, N], scales [3, N] (positive), quats [4, N] as (w, x, y, z),
-  opacities [N] in (0, 1), sh [16, 3, N].
+  opacities [N] in (0, 1), sh [N, 16, 3]; optional appearance offsets
+  app [N, 4] (see appearance.py).
 Outputs of several views are concatenated per pixel (view-major, each view
 row-major); ``split_views`` reshapes them into per-view images.
 """
@@ -54,10 +55,16 @@ def check_params(means, scales, quats, opacities, sh) -> int:
     return n
 
 
-def gaussians_struct(means, scales, quats, opacities, sh) -> L.GsGaussians:
+def check_app(app, n: int) -> None:
+    if app is not None:
+        _check_param(app, "app", (n, 4))
+
+
+def gaussians_struct(means, scales, quats, opacities, sh, app=None) -> L.GsGaussians:
     g = L.GsGaussians()
     g.means, g.scales, g.quats = means.data_ptr(), scales.data_ptr(), quats.data_ptr()
     g.opacities, g.sh, g.n = opacities.data_ptr(), sh.data_ptr(), means.shape[-1]
+    g.app = app.data_ptr() if app is not None else None
     return g
 
 
@@ -108,9 +115,10 @@ def views_extent(cams) -> tuple:
     return nt.value, npx.value
 
 
-def project(means, scales, quats, opacities, sh, cams, opts: RenderOptions) -> Projected:
+def project(means, scales, quats, opacities, sh, cams, opts: RenderOptions, app=None) -> Projected:
     lib = L.load()
     n = check_params(means, scales, quats, opacities, sh)
+    check_app(app, n)
     S = n * len(cams)
     dev = means.device
     n_tiles, _ = views_extent(cams)
@@ -119,7 +127,7 @@ def project(means, scales, quats, opacities, sh, cams, opts: RenderOptions) -> P
                     torch.empty((S,), dtype=torch.int32, device=dev),
                     torch.empty((S,), dtype=torch.int32, device=dev),
                     torch.empty((n_tiles,), dtype=torch.int32, device=dev))
-    g = gaussians_struct(means, scales, quats, opacities, sh)
+    g = gaussians_struct(means, scales, quats, opacities, sh, app)
     L.check(lib.gs_project(C.byref(g), L.make_cameras(cams), len(cams), C.byref(opts.c()), C.byref(out.c()),
                            _stream()))
     return out
@@ -200,20 +208,24 @@ def _mark(name: str) -> None:
 
 
 def render_bwd(params, cams, opts: RenderOptions, proj: Projected, pair_vals, ranges, T, last, d_rgb, d_depth,
-               d_alpha, ws: Workspace | None = None) -> dict:
+               d_alpha, ws: Workspace | None = None, app=None) -> dict:
     lib = L.load()
     ws = ws or _default_ws
     means, scales, quats, opacities, sh = params
     n = check_params(means, scales, quats, opacities, sh)
+    check_app(app, n)
     V = len(cams)
     dev = means.device
     grads = {k: torch.empty_like(t) for k, t in zip(("means", "scales", "quats", "opacities", "sh"), params)}
     norm = torch.empty((V, n), dtype=torch.float32, device=dev)
     absg = torch.empty((V, n, 2), dtype=torch.float32, device=dev) if opts.absgrad else None
-    g = gaussians_struct(*params)
+    g = gaussians_struct(*params, app)
     go = L.GsGaussiansGrad()
     go.d_means, go.d_scales, go.d_quats = grads["means"].data_ptr(), grads["scales"].data_ptr(), grads["quats"].data_ptr()
     go.d_opacities, go.d_sh = grads["opacities"].data_ptr(), grads["sh"].data_ptr()
+    if app is not None:
+        grads["app"] = torch.empty_like(app)
+        go.d_app = grads["app"].data_ptr()
     wsz = lib.gs_render_bwd_workspace_size(n * V)
     wbuf = ws.get("bwd", wsz + 256, dev)
     g2 = C.c_void_p(Workspace.aligned(wbuf))
@@ -258,17 +270,18 @@ class GsRasterize(torch.autograd.Function):
     z * alpha * T) and alpha [Npix]."""
 
     @staticmethod
-    def forward(ctx, means, scales, quats, opacities, sh, cams, opts: RenderOptions, stats: RenderStats):
+    def forward(ctx, means, scales, quats, opacities, sh, app, cams, opts: RenderOptions, stats: RenderStats):
         params = tuple(t.detach().contiguous() for t in (means, scales, quats, opacities, sh))
+        app = app.detach().contiguous() if app is not None else None
         n = params[0].shape[-1]
-        proj = project(*params, cams, opts)
+        proj = project(*params, cams, opts, app=app)
         _mark("project")
         pair_vals, ranges, P = bin_sort(proj, cams, n)
         _mark("bin_sort")
         out = render_fwd(proj, pair_vals, ranges, cams, opts)
         _mark("render_fwd")
         ctx.save_for_backward(*params, proj.rec, proj.rect, proj.tiles, proj.depth_key, proj.tile_order, pair_vals,
-                              ranges, out["T"], out["last"])
+                              ranges, out["T"], out["last"], app)
         ctx.cams, ctx.opts, ctx.stats = list(cams), opts, stats
         if stats is not None:
             stats.n_pairs = P
@@ -277,20 +290,21 @@ class GsRasterize(torch.autograd.Function):
     @staticmethod
     def backward(ctx, d_rgb, d_depth, d_alpha):
         (means, scales, quats, opacities, sh, rec, rect, tiles, dkey, order, pair_vals, ranges, T,
-         last) = ctx.saved_tensors
+         last, app) = ctx.saved_tensors
         proj = Projected(rec, rect, tiles, dkey, order)
         g = render_bwd((means, scales, quats, opacities, sh), ctx.cams, ctx.opts, proj, pair_vals, ranges, T, last,
-                       d_rgb, d_depth, d_alpha)
+                       d_rgb, d_depth, d_alpha, app=app)
         if ctx.stats is not None:
             ctx.stats.mean2d_grad_norm = g["mean2d_grad_norm"]
             ctx.stats.absgrad = g["absgrad"]
-        return g["means"], g["scales"], g["quats"], g["opacities"], g["sh"], None, None, None
+        return g["means"], g["scales"], g["quats"], g["opacities"], g["sh"], g.get("app"), None, None, None
 
 
 def rasterize(means, scales, quats, opacities, sh, cams, opts: RenderOptions | None = None,
-              stats: RenderStats | None = None):
-    """Autograd entry point; returns flat (rgb, depth, alpha) over all views."""
-    return GsRasterize.apply(means, scales, quats, opacities, sh, list(cams), opts or RenderOptions(), stats)
+              stats: RenderStats | None = None, app=None):
+    """Autograd entry point; returns flat (rgb, depth, alpha) over all views.
+    ``app`` [N, 4]: appearance offsets (dc, do), differentiable."""
+    return GsRasterize.apply(means, scales, quats, opacities, sh, app, list(cams), opts or RenderOptions(), stats)
 
 
 class L1DepthLoss(torch.autograd.Function):
