@@ -458,7 +458,7 @@ def cpu_baseline(scene, cam, crop: int):
     t["project"] = time.perf_counter() - a
     a = time.perf_counter()
     keys = oracle.depth_key(proj["depth"])
-    bins = oracle.bin_pairs(proj["rect"], proj["tiles"], keys, np.zeros(scene.n, np.int32), [sub])
+    bins = oracle.bin_pairs(proj["rect"], proj["tiles"], keys, np.zeros(scene.n, np.int32), [sub], mask=proj["mask"])
     t["bin"] = time.perf_counter() - a
     twod = oracle._twod([proj])
     a = time.perf_counter()

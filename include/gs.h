@@ -126,13 +126,21 @@ typedef struct gs_gaussians_grad {
  *        pixels, which leaves every result unchanged.
  *   rect [slots][2] uint32: global id of the first tile of the rectangle;
  *        rectangle width in tiles | (tiles per image row << 16).
- *   tiles[slots] uint32: tiles in the rectangle, 0 if culled.
+ *   tiles[slots] uint32: tiles covered, 0 if culled.
  *   depth_key[slots] uint32: bit pattern of the float32 view depth
  *        (0xFFFFFFFF if culled); the primary sort key inside a tile.
  *   tile_order [tiles of all views] uint32, optional (NULL = tile index
  *        order): gs_bin_sort writes a launch order of the tiles, longest
  *        lists first, and the compositing calls launch their workgroups in
  *        that order.  Scheduling only: results do not depend on it.
+ *   tile_mask [slots] uint64, optional (NULL = every tile of the
+ *        rectangle): exact tile culling.  For rectangles of at most 64
+ *        tiles, bit (ty - y0) * width + (tx - x0) is set for the tiles whose
+ *        pixel centres the alpha ellipse d^T Sigma'^-1 d <= 2 tau reaches
+ *        (its minimum over the tile's pixel-centre rectangle widened by
+ *        1e-3 px, within 2 tau (1 + 4e-6)); tiles counts those, and binning
+ *        emits only them.  0 for larger rectangles (all tiles kept);
+ *        unwritten for culled slots.
  * Records of culled slots are left unwritten. */
 typedef struct gs_projected {
     float *rec;
@@ -140,6 +148,7 @@ typedef struct gs_projected {
     uint32_t *tiles;
     uint32_t *depth_key;
     uint32_t *tile_order;
+    uint64_t *tile_mask;
 } gs_projected;
 
 const char *gs_last_error(void);

@@ -56,7 +56,7 @@ _P = C.c_void_p
 
 class _Proj(C.Structure):
     _fields_ = [(name, _P) for name in ("visible", "tcam", "cov2d", "rho", "conic", "mean2d", "depth",
-                                        "opac", "rgb", "clamped", "extent", "radius", "rect", "tiles")]
+                                        "opac", "rgb", "clamped", "extent", "radius", "rect", "tiles", "mask")]
 
 
 def _load():
@@ -98,11 +98,13 @@ def make_cam(cam) -> _Cam:
 
 
 def make_opt(sh_degree=3, dilation=0.3, aa=False, bg=(0.0, 0.0, 0.0), tile_cull=True) -> _Opt:
+    """tile_cull: False/0 the 3-sigma rectangle; 1 narrowed to the alpha box;
+    True/2 also per tile by the alpha ellipse (rectangles of <= 64 tiles)."""
     o = _Opt()
     o.sh_degree = int(sh_degree)
     o.dilation = float(np.float32(dilation))
     o.aa = int(bool(aa))
-    o.tile_cull = int(bool(tile_cull))
+    o.tile_cull = 2 if tile_cull is True else int(tile_cull)
     for k in range(3):
         o.bg[k] = float(np.float32(bg[k]))
     return o
@@ -132,7 +134,7 @@ def project(scene, cam, opac=None, cbase=None, **opt) -> dict:
         "rho": np.zeros(n), "conic": np.zeros((n, 3)), "mean2d": np.zeros((n, 2)), "depth": np.zeros(n),
         "opac": np.zeros(n), "rgb": np.zeros((n, 3)), "clamped": np.zeros((n, 3), np.int32),
         "extent": np.zeros(n), "radius": np.zeros(n, np.int32), "rect": np.zeros((n, 4), np.int32),
-        "tiles": np.zeros(n, np.int32),
+        "tiles": np.zeros(n, np.int32), "mask": np.zeros(n, np.uint64),
     }
     pr = _Proj(*[out[k].ctypes.data for k, _ in _Proj._fields_])
     means, scales, quats = _c64(scene.means), _c64(scene.scales), _c64(scene.quats)
@@ -150,12 +152,14 @@ def depth_key(depth: np.ndarray) -> np.ndarray:
     return np.ascontiguousarray(np.asarray(depth, np.float64).astype(np.float32)).view(np.uint32)
 
 
-def bin_pairs(rect, tiles, depth_keys, slot_view, cams) -> dict:
+def bin_pairs(rect, tiles, depth_keys, slot_view, cams, mask=None) -> dict:
     """Pairs (global tile, slot) sorted by (tile, depth key, slot) and the
-    [start, end) range of every global tile; views are concatenated."""
+    [start, end) range of every global tile; views are concatenated.  mask
+    [slots] (uint64, optional) selects covered tiles of each rectangle."""
     lib = _load()
     rect = np.ascontiguousarray(rect, np.int32)
     tiles = np.ascontiguousarray(tiles, np.int32)
+    mask = np.ascontiguousarray(mask, np.uint64) if mask is not None else None
     depth_keys = np.ascontiguousarray(depth_keys, np.uint32)
     slot_view = np.ascontiguousarray(slot_view, np.int32)
     tx = np.array([c.tiles_x for c in cams], np.int32)
@@ -166,7 +170,7 @@ def bin_pairs(rect, tiles, depth_keys, slot_view, cams) -> dict:
     pair_tile = np.zeros(max(P, 1), np.uint32)
     pair_slot = np.zeros(max(P, 1), np.uint32)
     ranges = np.zeros((n_tiles, 2), np.uint32)
-    got = lib.orc_bin(C.c_int64(len(tiles)), _ptr(rect), _ptr(tiles), _ptr(depth_keys), _ptr(slot_view),
+    got = lib.orc_bin(C.c_int64(len(tiles)), _ptr(rect), _ptr(tiles), _ptr(mask), _ptr(depth_keys), _ptr(slot_view),
                       _ptr(tx), _ptr(toff), C.c_int64(n_tiles), C.c_int64(P), _ptr(pair_tile),
                       _ptr(pair_slot), _ptr(ranges))
     assert got == P, (got, P)
@@ -270,7 +274,8 @@ def forward(scene, cams, opt: dict | None = None, guard_eps=DEFAULT_GUARD, depth
     tiles = np.concatenate([p["tiles"] for p in projs], 0)
     keys = depth_key(np.concatenate([p["depth"] for p in projs], 0)) if depth_keys is None else depth_keys
     slot_view = np.repeat(np.arange(len(cams), dtype=np.int32), n)
-    bins = bin_pairs(rect, tiles, keys, slot_view, cams)
+    mask = np.concatenate([p["mask"] for p in projs], 0)
+    bins = bin_pairs(rect, tiles, keys, slot_view, cams, mask=mask)
     twod = _twod(projs)
     images = [render_view(c, opt, int(bins["tile_off"][v]), twod, bins["pair_slot"], bins["ranges"],
                           guard_eps=guard_eps) for v, c in enumerate(cams)]

@@ -57,7 +57,8 @@ typedef struct {
     double dilation;         /* px^2 added to the 2D covariance diagonal */
     int32_t aa;              /* 1: opacity compensation by rho */
     double bg[3];
-    int32_t tile_cull;       /* 1: tile rectangle narrowed to the alpha box (project_one) */
+    int32_t tile_cull;       /* 1: tile rectangle narrowed to the alpha box; 2: and, for rectangles
+                                of at most 64 tiles, only tiles the alpha ellipse reaches (project_one) */
 } oopt_t;
 
 /* per-slot projection outputs (arrays of n entries times the component count) */
@@ -75,7 +76,9 @@ typedef struct {
     double *extent;          /* [n] 3 sqrt(lambda_max), before rounding up */
     int32_t *radius;         /* [n] */
     int32_t *rect;           /* [n][4] tile x0, y0, x1, y1 (inclusive) */
-    int32_t *tiles;          /* [n] number of tiles in the rectangle, 0 if culled */
+    int32_t *tiles;          /* [n] number of tiles covered, 0 if culled */
+    uint64_t *mask;          /* [n] covered tiles of the rectangle, bit (ty - y0) w + (tx - x0);
+                                0 = every tile of the rectangle (nullable) */
 } oproj_t;
 
 /* ------------------------------------------------------------------------ */
@@ -219,6 +222,7 @@ typedef struct {
     int radius;
     int rect[4];
     int tiles;
+    uint64_t mask;
 } proj1_t;
 
 /* cbase: the constant of the colour polynomial per channel (NULL: 0.5, the
@@ -336,6 +340,50 @@ static void project_one(const ocam_t *cam, const oopt_t *opt, const double mu[3]
     P->radius = (int)(r < 2e9 ? r : 2e9);
     P->rect[0] = (int)fx0; P->rect[1] = (int)fy0; P->rect[2] = (int)fx1; P->rect[3] = (int)fy1;
     P->tiles = (P->rect[2] - P->rect[0] + 1) * (P->rect[3] - P->rect[1] + 1);
+    P->mask = 0;
+    if (opt->tile_cull >= 2 && P->tiles <= 64) {
+        /* Exact tile culling: keep a tile only if the alpha ellipse
+         * q(d) = d^T Sigma'^-1 d <= L, L = 2 tau (1 + 4e-6) (tau as for the
+         * box), reaches the rectangle of its pixel centres (widened by
+         * 1e-3 px).  Row by row: the ellipse within a row's strip
+         * [ylo, yhi] is convex, so it meets a tile of the row iff its
+         * x-extent over the strip meets the tile's column range.  For fixed
+         * y the ellipse spans x = (-B y -+ sqrt(A L - det y^2)) / A; the upper
+         * end is concave in y with its maximum at the ellipse's rightmost
+         * point (X, -B X / C), X = sqrt(L C / det), and the lower end convex
+         * with its minimum at (-X, B X / C): over the strip (clipped to the
+         * ellipse's y-extent +-sqrt(L A / det)) both are taken at those y
+         * clamped into the strip. */
+        double tau = log(255.0 * P->opac) + 1e-5;
+        double L = 2.0 * tau * (1.0 + 4e-6);
+        double A = P->conic[0], B = P->conic[1], C = P->conic[2];
+        double det = A * C - B * B;
+        double X = sqrt(L * C / det), Y = sqrt(L * A / det), yr = -B / C * X;
+        int w = P->rect[2] - P->rect[0] + 1, cnt = 0;
+        for (int ty = P->rect[1]; ty <= P->rect[3]; ty++) {
+            int py1 = ty * ORC_TILE + ORC_TILE - 1;
+            if (py1 > cam->H - 1) py1 = cam->H - 1;
+            double ylo = ty * ORC_TILE + 0.5 - 1e-3 - P->mean2d[1], yhi = py1 + 0.5 + 1e-3 - P->mean2d[1];
+            double a = ylo > -Y ? ylo : -Y, b = yhi < Y ? yhi : Y;
+            if (a > b) continue;
+            double y1 = yr < a ? a : (yr > b ? b : yr);
+            double y2 = -yr < a ? a : (-yr > b ? b : -yr);
+            double r1 = A * L - det * y1 * y1, r2 = A * L - det * y2 * y2;
+            double xhi_e = (-B * y1 + sqrt(r1 > 0.0 ? r1 : 0.0)) / A;
+            double xlo_e = (-B * y2 - sqrt(r2 > 0.0 ? r2 : 0.0)) / A;
+            for (int tx = P->rect[0]; tx <= P->rect[2]; tx++) {
+                int px1 = tx * ORC_TILE + ORC_TILE - 1;
+                if (px1 > cam->W - 1) px1 = cam->W - 1;
+                double xlo = tx * ORC_TILE + 0.5 - 1e-3 - P->mean2d[0], xhi = px1 + 0.5 + 1e-3 - P->mean2d[0];
+                if (xlo <= xhi_e && xhi >= xlo_e) {
+                    P->mask |= 1ull << ((ty - P->rect[1]) * w + (tx - P->rect[0]));
+                    cnt++;
+                }
+            }
+        }
+        if (cnt == 0) return;
+        P->tiles = cnt;
+    }
 
     /* view-dependent colour from the world-space viewing direction */
     double campos[3];
@@ -384,6 +432,7 @@ int orc_project(int64_t n, const double *means, const double *scales, const doub
         out->radius[i] = P.radius;
         for (int k = 0; k < 4; k++) out->rect[4 * i + k] = P.visible ? P.rect[k] : 0;
         out->tiles[i] = P.visible ? P.tiles : 0;
+        if (out->mask) out->mask[i] = P.visible ? P.mask : 0;
     }
     return 0;
 }
@@ -402,15 +451,17 @@ static int pair_cmp(const void *pa, const void *pb) {
     return 0;
 }
 
-/* Enumerates one pair per (slot, tile in the slot's rectangle), sorts the
+/* Enumerates one pair per (slot, covered tile: a tile of the slot's
+ * rectangle whose bit is set in mask[s], every tile when mask is NULL or
+ * mask[s] is 0), sorts the
  * pairs by (global tile id, depth key, slot) -- "processed in depth order"
  * of §3.1, ties by input index -- and writes [start, end) per global tile.
  * slot_view[s] selects the view of a slot; its tiles are numbered
  * view_tile_off[v] + ty * view_tiles_x[v] + tx. */
-int64_t orc_bin(int64_t n_slots, const int32_t *rect, const int32_t *tiles, const uint32_t *depth_key,
-                const int32_t *slot_view, const int32_t *view_tiles_x, const int32_t *view_tile_off,
-                int64_t n_tiles_total, int64_t capacity, uint32_t *pair_tile, uint32_t *pair_slot,
-                uint32_t *ranges /* [n_tiles_total][2] */) {
+int64_t orc_bin(int64_t n_slots, const int32_t *rect, const int32_t *tiles, const uint64_t *mask,
+                const uint32_t *depth_key, const int32_t *slot_view, const int32_t *view_tiles_x,
+                const int32_t *view_tile_off, int64_t n_tiles_total, int64_t capacity, uint32_t *pair_tile,
+                uint32_t *pair_slot, uint32_t *ranges /* [n_tiles_total][2] */) {
     int64_t P = 0;
     for (int64_t s = 0; s < n_slots; s++) P += tiles[s];
     if (P > capacity) return -P;
@@ -420,8 +471,11 @@ int64_t orc_bin(int64_t n_slots, const int32_t *rect, const int32_t *tiles, cons
     for (int64_t s = 0; s < n_slots; s++) {
         if (tiles[s] <= 0) continue;
         int v = slot_view[s];
+        uint64_t m = mask ? mask[s] : 0;
+        int w = rect[4 * s + 2] - rect[4 * s] + 1;
         for (int ty = rect[4 * s + 1]; ty <= rect[4 * s + 3]; ty++)
             for (int tx = rect[4 * s]; tx <= rect[4 * s + 2]; tx++) {
+                if (m && !((m >> ((ty - rect[4 * s + 1]) * w + (tx - rect[4 * s]))) & 1)) continue;
                 pairs[k].tile = (uint32_t)(view_tile_off[v] + ty * view_tiles_x[v] + tx);
                 pairs[k].key = depth_key[s];
                 pairs[k].slot = (uint32_t)s;

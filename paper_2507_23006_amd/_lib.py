@@ -69,7 +69,7 @@ class GsAppearanceGrad(C.Structure):
 
 class GsProjected(C.Structure):
     _fields_ = [("rec", C.c_void_p), ("rect", C.c_void_p), ("tiles", C.c_void_p), ("depth_key", C.c_void_p),
-                ("tile_order", C.c_void_p)]
+                ("tile_order", C.c_void_p), ("tile_mask", C.c_void_p)]
 
 
 GS_MAX_LEVELS = 8

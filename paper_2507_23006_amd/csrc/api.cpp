@@ -107,12 +107,13 @@ GradPtrs grad_ptrs(const gs_gaussians* g, const gs_gaussians_grad* out) {
 
 int check_proj(const gs_projected* p) {
     GS_REQUIRE(p != nullptr && p->rec && p->rect && p->tiles && p->depth_key, "projected buffers missing");
+    GS_REQUIRE(((uintptr_t)p->tile_mask & 7) == 0, "tile_mask must be 8-byte aligned");
     return GS_OK;
 }
 
 Projected to_proj(const gs_projected* p) {
     return Projected{reinterpret_cast<float4*>(p->rec), reinterpret_cast<uint2*>(p->rect), p->tiles, p->depth_key,
-                     p->tile_order};
+                     p->tile_order, p->tile_mask};
 }
 
 int tile_bits(int64_t n_tiles) {
@@ -128,6 +129,7 @@ struct BinWs {
     uint32_t* hist;
     uint32_t *tiles_s, *offsets;
     uint2* rect_s;
+    uint64_t* mask_s;
     uint32_t* scan_tmp;
     unsigned long long* total;
     uint32_t *pkeys, *pkeys_alt, *pvals_alt;
@@ -144,6 +146,7 @@ size_t bin_layout(int64_t n_slots, int64_t cap, void* base, BinWs* w) {
     w->tiles_s = c.take<uint32_t>(N);
     w->offsets = c.take<uint32_t>(N);
     w->rect_s = c.take<uint2>(N);
+    w->mask_s = c.take<uint64_t>(N);
     w->scan_tmp = c.take<uint32_t>(scan_tmp_elems((uint32_t)N));
     w->total = c.take<unsigned long long>(kTotals);   // [0] visible, [8] offsets total, [16 + 16k] pair parts
     w->pkeys = c.take<uint32_t>(Pc);
@@ -206,7 +209,7 @@ int bin_sort_slots(const Projected& pr, const ViewTable& vt, int64_t n_slots, in
     GS_HIP(radix_sort_pairs(w.dkeys, w.dvals, w.dkeys_alt, w.dvals_alt, NV, 0, 32, w.hist, s, &alt));
     const uint32_t* sorted_slot = alt ? w.dvals_alt : w.dvals;
     if (NV) {
-        GS_HIP(launch_gather_sorted(sorted_slot, pr, NV, w.tiles_s, w.rect_s, s));
+        GS_HIP(launch_gather_sorted(sorted_slot, pr, NV, w.tiles_s, w.rect_s, w.mask_s, s));
         GS_HIP(exclusive_scan_u32(w.tiles_s, w.offsets, NV, w.scan_tmp, w.total + 8, s));
     }
     // 3. expand into (tile, slot) pairs in depth order, then stable sort by tile id
@@ -214,7 +217,8 @@ int bin_sort_slots(const Projected& pr, const ViewTable& vt, int64_t n_slots, in
     const int passes = P <= 1 ? 0 : (bits + 7) / 8;   // radix_sort_pairs runs no pass for P <= 1
     uint32_t* vals_primary = (passes % 2 == 0) ? pair_vals : w.pvals_alt;
     uint32_t* vals_alt = (passes % 2 == 0) ? w.pvals_alt : pair_vals;
-    GS_HIP(launch_emit_pairs(w.offsets, w.rect_s, sorted_slot, NV, (uint32_t)P, w.pkeys, vals_primary, s));
+    GS_HIP(launch_emit_pairs(w.offsets, w.rect_s, pr.tile_mask ? w.mask_s : nullptr, sorted_slot, NV, (uint32_t)P,
+                             w.pkeys, vals_primary, s));
     bool palt = false;
     GS_HIP(radix_sort_pairs(w.pkeys, vals_primary, w.pkeys_alt, vals_alt, (uint32_t)P, 0, bits, w.hist, s, &palt));
     const uint32_t* sorted_keys = palt ? w.pkeys_alt : w.pkeys;

@@ -51,15 +51,36 @@ __global__ __launch_bounds__(256) void k_compact_visible(const uint32_t* __restr
 }
 
 // per depth rank: tiles covered and the emission descriptor of its slot
+// (rectangle and, with exact tile culling, its mask of covered tiles)
 __global__ void k_gather_sorted(const uint32_t* __restrict__ sorted_slot, const uint32_t* __restrict__ tiles,
-                                const uint2* __restrict__ rect, uint32_t n, uint32_t* __restrict__ tiles_s,
-                                uint2* __restrict__ rect_s) {
+                                const uint2* __restrict__ rect, const uint64_t* __restrict__ mask, uint32_t n,
+                                uint32_t* __restrict__ tiles_s, uint2* __restrict__ rect_s,
+                                uint64_t* __restrict__ mask_s) {
     const uint32_t d = blockIdx.x * 256 + threadIdx.x;
     if (d >= n) return;
     const uint32_t s = sorted_slot[d];
     const uint32_t t = tiles[s];
     tiles_s[d] = t;
     rect_s[d] = t ? rect[s] : make_uint2(0u, 1u);
+    if (mask_s) mask_s[d] = (t && mask) ? mask[s] : 0ull;
+}
+
+// index of the k-th set bit (k < popcount(m)) of m, by halving
+__device__ __forceinline__ uint32_t nth_set_bit(uint64_t m, uint32_t k) {
+    uint32_t base = 0;
+#pragma unroll
+    for (int width = 32; width >= 1; width >>= 1) {
+        const uint64_t low = m & ((1ull << width) - 1ull);
+        const uint32_t c = (uint32_t)__popcll(low);
+        if (k >= c) {
+            k -= c;
+            m >>= width;
+            base += width;
+        } else {
+            m = low;
+        }
+    }
+    return base;
 }
 
 constexpr int kEmitThreads = 256;
@@ -73,6 +94,7 @@ constexpr int kEmitChunk = kEmitThreads * kEmitPer;   // pairs per workgroup
 // each pair binary-searches there.  Writes are fully coalesced.
 __global__ __launch_bounds__(kEmitThreads) void k_emit_pairs(const uint32_t* __restrict__ offsets,
                                                              const uint2* __restrict__ rect_s,
+                                                             const uint64_t* __restrict__ mask_s,
                                                              const uint32_t* __restrict__ sorted_slot, uint32_t n,
                                                              uint32_t n_pairs, uint32_t* __restrict__ pair_key,
                                                              uint32_t* __restrict__ pair_val) {
@@ -104,9 +126,14 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit_pairs(const uint32_t* __r
             if (s_off[mid] <= p) lo = mid; else hi = mid;
         }
         const uint32_t d = d0 + lo;
-        const uint32_t local = p - s_off[lo];
+        uint32_t local = p - s_off[lo];
         const uint2 rs = rect_s[d];
         const uint32_t w = rs.y & 0xFFFFu, tw = rs.y >> 16;
+        if (mask_s) {
+            // the local-th covered tile of the rectangle (row-major bits)
+            const uint64_t m = mask_s[d];
+            if (m) local = nth_set_bit(m, local);
+        }
         const uint32_t row = local / w, col = local - row * w;
         pair_key[p] = rs.x + row * tw + col;
         pair_val[p] = sorted_slot[d];
@@ -185,19 +212,19 @@ hipError_t launch_compact_visible(const Projected& proj, const uint32_t* pos, ui
 }
 
 hipError_t launch_gather_sorted(const uint32_t* sorted_slot, const Projected& proj, uint32_t n_slots,
-                                uint32_t* tiles_s, uint2* rect_s, hipStream_t s) {
+                                uint32_t* tiles_s, uint2* rect_s, uint64_t* mask_s, hipStream_t s) {
     hipLaunchKernelGGL(k_gather_sorted, dim3((n_slots + 255) / 256), dim3(256), 0, s, sorted_slot, proj.tiles,
-                       proj.rect, n_slots, tiles_s, rect_s);
+                       proj.rect, proj.tile_mask, n_slots, tiles_s, rect_s, proj.tile_mask ? mask_s : nullptr);
     return hipGetLastError();
 }
 
-hipError_t launch_emit_pairs(const uint32_t* offsets, const uint2* rect_s, const uint32_t* sorted_slot,
-                             uint32_t n_slots, uint32_t n_pairs, uint32_t* pair_key, uint32_t* pair_val,
-                             hipStream_t s) {
+hipError_t launch_emit_pairs(const uint32_t* offsets, const uint2* rect_s, const uint64_t* mask_s,
+                             const uint32_t* sorted_slot, uint32_t n_slots, uint32_t n_pairs, uint32_t* pair_key,
+                             uint32_t* pair_val, hipStream_t s) {
     if (!n_pairs) return hipSuccess;
     const uint32_t blocks = (n_pairs + kEmitChunk - 1) / kEmitChunk;
-    hipLaunchKernelGGL(k_emit_pairs, dim3(blocks), dim3(kEmitThreads), 0, s, offsets, rect_s, sorted_slot, n_slots,
-                       n_pairs, pair_key, pair_val);
+    hipLaunchKernelGGL(k_emit_pairs, dim3(blocks), dim3(kEmitThreads), 0, s, offsets, rect_s, mask_s, sorted_slot,
+                       n_slots, n_pairs, pair_key, pair_val);
     return hipGetLastError();
 }
 

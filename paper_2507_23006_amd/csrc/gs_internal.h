@@ -114,6 +114,7 @@ struct Projected {
     uint32_t* tiles;      // [slots]
     uint32_t* dkey;       // [slots]
     uint32_t* tile_order; // [tiles] compositing launch order, or null for tile index order
+    uint64_t* tile_mask;  // [slots] covered tiles of rectangles of <= 64 tiles (0: all), or null
 };
 
 // app: appearance offsets [n][4] (dc, do) or null
@@ -163,10 +164,10 @@ hipError_t launch_visible_flags(const Projected& proj, uint32_t n_slots, uint32_
 hipError_t launch_compact_visible(const Projected& proj, const uint32_t* pos, uint32_t n_slots, uint32_t* keys,
                                   uint32_t* slots, hipStream_t s);
 hipError_t launch_gather_sorted(const uint32_t* sorted_slot, const Projected& proj, uint32_t n_slots,
-                                uint32_t* tiles_s, uint2* rect_s, hipStream_t s);
-hipError_t launch_emit_pairs(const uint32_t* offsets, const uint2* rect_s, const uint32_t* sorted_slot,
-                             uint32_t n_slots, uint32_t n_pairs, uint32_t* pair_key, uint32_t* pair_val,
-                             hipStream_t s);
+                                uint32_t* tiles_s, uint2* rect_s, uint64_t* mask_s, hipStream_t s);
+hipError_t launch_emit_pairs(const uint32_t* offsets, const uint2* rect_s, const uint64_t* mask_s,
+                             const uint32_t* sorted_slot, uint32_t n_slots, uint32_t n_pairs, uint32_t* pair_key,
+                             uint32_t* pair_val, hipStream_t s);
 hipError_t launch_tile_ranges(const uint32_t* sorted_keys, uint32_t n_pairs, uint32_t* ranges, uint32_t n_tiles,
                               hipStream_t s);
 // tile launch order for compositing, longest lists first

@@ -57,6 +57,49 @@ __device__ __forceinline__ bool load_shape(const GaussPtrs& gp, int64_t n, int64
     return true;
 }
 
+// Exact tile culling of a rectangle of w x h <= 64 tiles at (ix0, iy0): bit
+// (ty - iy0) w + (tx - ix0) is set when the alpha ellipse
+// q(d) = A dx^2 + 2 B dx dy + C dy^2 <= L, L = 2 tau (1 + 4e-6), reaches the
+// tile's pixel-centre rectangle widened by 1e-3 px.  Row by row: the ellipse
+// within a row's strip is convex, so it meets a tile iff its x-extent over the
+// strip meets the tile's columns.  For fixed y the ellipse spans
+// x = (-B y -+ sqrt(A L - det y^2)) / A; the upper end is concave in y and
+// peaks at the rightmost point (X, -B X / C), X = sqrt(L C / det), the lower
+// end is convex with its minimum at (-X, B X / C), so over a strip (clipped
+// to the ellipse's y-extent +-sqrt(L A / det)) both come from those y clamped
+// into it.  O(rows) square roots per Gaussian instead of work per tile, so a
+// wave is not held by its widest lane.  Plain IEEE operations in a fixed
+// order (no contraction).
+__device__ uint64_t covered_tiles(const ViewK& V, double mx, double my, double A, double B, double C, double tau,
+                                  int ix0, int iy0, int w, int h) {
+#pragma clang fp contract(off)
+    const double L = 2.0 * tau * (1.0 + 4e-6);
+    const double det = A * C - B * B;
+    const double X = sqrt(L * C / det), Y = sqrt(L * A / det), yr = -B / C * X;
+    uint64_t m = 0;
+    for (int j = 0; j < h; ++j) {
+        const int ty = iy0 + j;
+        int py1 = ty * kTile + kTile - 1;
+        if (py1 > V.H - 1) py1 = V.H - 1;
+        const double ylo = (double)(ty * kTile) + 0.5 - 1e-3 - my, yhi = (double)py1 + 0.5 + 1e-3 - my;
+        const double a = ylo > -Y ? ylo : -Y, b = yhi < Y ? yhi : Y;
+        if (a > b) continue;
+        const double y1 = yr < a ? a : (yr > b ? b : yr);
+        const double y2 = -yr < a ? a : (-yr > b ? b : -yr);
+        const double r1 = A * L - det * y1 * y1, r2 = A * L - det * y2 * y2;
+        const double xhi_e = (-B * y1 + sqrt(r1 > 0.0 ? r1 : 0.0)) / A;
+        const double xlo_e = (-B * y2 - sqrt(r2 > 0.0 ? r2 : 0.0)) / A;
+        for (int i = 0; i < w; ++i) {
+            const int tx = ix0 + i;
+            int px1 = tx * kTile + kTile - 1;
+            if (px1 > V.W - 1) px1 = V.W - 1;
+            const double xlo = (double)(tx * kTile) + 0.5 - 1e-3 - mx, xhi = (double)px1 + 0.5 + 1e-3 - mx;
+            if (xlo <= xhi_e && xhi >= xlo_e) m |= 1ull << (j * w + i);
+        }
+    }
+    return m;
+}
+
 // 2D Gaussian of (t, M, opac) in view V: writes the record's geometry words
 // (float4s 0, 1, 3 and the .w of 2) and the rectangle of `slot`; returns the
 // number of tiles covered, 0 when culled
@@ -120,6 +163,16 @@ __device__ __forceinline__ uint32_t project_view(const ViewK& V, const OptK& opt
     if (!(x0t <= x1t && y0t <= y1t)) return 0;
     const int ix0 = (int)x0t, iy0 = (int)y0t, ix1 = (int)x1t, iy1 = (int)y1t;
     const int w = ix1 - ix0 + 1, h = iy1 - iy0 + 1;
+    uint32_t covered = (uint32_t)(w * h);
+    if (out.tile_mask) {
+        uint64_t m = 0;
+        if (w * h <= 64) {
+            m = covered_tiles(V, mx, my, cd / detd, -cb / detd, ad / detd, tau, ix0, iy0, w, h);
+            if (!m) return 0;     // the ellipse reaches no pixel centre of the image
+            covered = (uint32_t)__popcll(m);
+        }
+        out.tile_mask[slot] = m;
+    }
     const double invd = 1.0 / detd;
     const double A = cd * invd, B = -cb * invd, C = ad * invd;
     // mean = integer part (exact in float32) + fraction, so that the
@@ -131,7 +184,7 @@ __device__ __forceinline__ uint32_t project_view(const ViewK& V, const OptK& opt
     out.rec[4 * slot + 2].w = (float)(my - fmy);
     out.rec[4 * slot + 3] = make_float4((float)hxd, (float)hyd, 0.0f, 0.0f);
     out.rect[slot] = make_uint2((uint32_t)(V.tile_off + iy0 * TW + ix0), (uint32_t)w | ((uint32_t)TW << 16));
-    return (uint32_t)(w * h);
+    return covered;
 }
 
 // view-dependent colour of a mean seen by V into the record's .xyz of

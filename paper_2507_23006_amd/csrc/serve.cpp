@@ -240,8 +240,9 @@ namespace {
 
 void free_worker(Worker* w) {
     if (!w) return;
-    void* dev[] = {w->proj.rec, w->proj.rect, w->proj.tiles, w->proj.dkey, w->proj.tile_order, w->segs_dev, w->pairs, w->ranges,
-                   w->bin_ws, w->rgb, w->depth, w->alpha, w->T, w->last};
+    void* dev[] = {w->proj.rec,  w->proj.rect, w->proj.tiles, w->proj.dkey, w->proj.tile_order, w->proj.tile_mask,
+                   w->segs_dev,  w->pairs,     w->ranges,     w->bin_ws,    w->rgb,             w->depth,
+                   w->alpha,     w->T,         w->last};
     for (void* p : dev)
         if (p) (void)hipFree(p);
     if (w->segs_host) (void)hipHostFree(w->segs_host);
@@ -261,6 +262,7 @@ int alloc_worker(gs_server* s, Worker* w) {
     GS_HIP(dev_alloc(&w->proj.rect, (size_t)S));
     GS_HIP(dev_alloc(&w->proj.tiles, (size_t)S));
     GS_HIP(dev_alloc(&w->proj.dkey, (size_t)S));
+    GS_HIP(dev_alloc(&w->proj.tile_mask, (size_t)S));
     GS_HIP(dev_alloc(&w->segs_dev, (size_t)s->seg_cap));
     GS_HIP(hipHostMalloc(reinterpret_cast<void**>(&w->segs_host), (size_t)s->seg_cap * sizeof(SlotSeg),
                          hipHostMallocDefault));

@@ -98,12 +98,14 @@ class Projected:
     tiles: torch.Tensor      # [S] int32
     depth_key: torch.Tensor  # [S] int32 (bit patterns of uint32)
     tile_order: torch.Tensor | None = None   # [T] int32, written by bin_sort
+    tile_mask: torch.Tensor | None = None    # [S] int64 (bit patterns of uint64): exact tile culling
 
     def c(self) -> L.GsProjected:
         p = L.GsProjected()
         p.rec, p.rect = self.rec.data_ptr(), self.rect.data_ptr()
         p.tiles, p.depth_key = self.tiles.data_ptr(), self.depth_key.data_ptr()
         p.tile_order = self.tile_order.data_ptr() if self.tile_order is not None else None
+        p.tile_mask = self.tile_mask.data_ptr() if self.tile_mask is not None else None
         return p
 
 
@@ -115,7 +117,10 @@ def views_extent(cams) -> tuple:
     return nt.value, npx.value
 
 
-def project(means, scales, quats, opacities, sh, cams, opts: RenderOptions, app=None) -> Projected:
+def project(means, scales, quats, opacities, sh, cams, opts: RenderOptions, app=None,
+            exact_cull: bool = True) -> Projected:
+    """exact_cull: per-tile ellipse culling (tile_mask); False keeps every
+    tile of the alpha box's rectangle."""
     lib = L.load()
     n = check_params(means, scales, quats, opacities, sh)
     check_app(app, n)
@@ -126,7 +131,8 @@ def project(means, scales, quats, opacities, sh, cams, opts: RenderOptions, app=
                     torch.empty((S, 2), dtype=torch.int32, device=dev),
                     torch.empty((S,), dtype=torch.int32, device=dev),
                     torch.empty((S,), dtype=torch.int32, device=dev),
-                    torch.empty((n_tiles,), dtype=torch.int32, device=dev))
+                    torch.empty((n_tiles,), dtype=torch.int32, device=dev),
+                    torch.empty((S,), dtype=torch.int64, device=dev) if exact_cull else None)
     g = gaussians_struct(means, scales, quats, opacities, sh, app)
     L.check(lib.gs_project(C.byref(g), L.make_cameras(cams), len(cams), C.byref(opts.c()), C.byref(out.c()),
                            _stream()))

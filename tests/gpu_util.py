@@ -38,8 +38,28 @@ def decode_records(rec: np.ndarray):
     return mean2d, conic, rec[:, 5].copy(), rec[:, 8:11].copy(), rec[:, 6].copy()
 
 
-def decode_rect(rect: np.ndarray, tiles: np.ndarray, cams, n):
-    """GPU rect words -> (tile x0, y0, x1, y1) per slot, view-local."""
+def mask_rows(mask: np.ndarray, w: np.ndarray) -> np.ndarray:
+    """Rows of a rectangle of width w spanned by the covered-tile bits of
+    mask (0 where mask is 0)."""
+    mask = np.asarray(mask).view(np.uint64)
+    hi, lo = (mask >> np.uint64(32)).astype(np.float64), (mask & np.uint64(0xFFFFFFFF)).astype(np.float64)
+    # highest set bit: frexp's exponent is exact for integers below 2^53
+    top = np.where(hi > 0, 31 + np.frexp(hi)[1], np.frexp(lo)[1] - 1).astype(np.int64)
+    return np.where(mask != 0, top // np.maximum(w, 1) + 1, 0)
+
+
+def mask_covers(mask, w, x0, y0, tx, ty) -> np.ndarray:
+    """For slots with a covered-tile mask (0 = every tile of the rectangle):
+    whether tile (tx, ty) is covered, given it lies in the rectangle."""
+    mask = np.asarray(mask).view(np.uint64)
+    bit = np.clip((ty - y0) * w + (tx - x0), 0, 63).astype(np.uint64)
+    return (mask == 0) | (((mask >> bit) & np.uint64(1)) == 1)
+
+
+def decode_rect(rect: np.ndarray, tiles: np.ndarray, cams, n, mask=None):
+    """GPU rect words -> (tile x0, y0, x1, y1) per slot, view-local.  With
+    exact tile culling (mask != 0) the height is the last row holding a
+    covered tile (rows below hold none)."""
     rect = rect.view(np.uint32).astype(np.int64)
     tiles = tiles.astype(np.int64)
     out = np.zeros((len(tiles), 4), np.int64)
@@ -53,6 +73,9 @@ def decode_rect(rect: np.ndarray, tiles: np.ndarray, cams, n):
         x0 = np.where(vis, base % c.tiles_x, 0)
         y0 = np.where(vis, base // c.tiles_x, 0)
         h = np.where(vis, tiles[sl] // np.maximum(w, 1), 0)
+        if mask is not None:
+            mv = np.asarray(mask).view(np.uint64)[sl]
+            h = np.where(vis & (mv != 0), mask_rows(mv, w), h)
         out[sl] = np.stack([x0, y0, x0 + w - 1, y0 + h - 1], 1) * vis[:, None]
         assert np.all(tw[vis] == c.tiles_x)
     return out

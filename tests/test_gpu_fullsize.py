@@ -16,7 +16,8 @@ import torch
 
 import oracle
 import synthetic as S
-from gpu_util import decode_records, decode_rect, gpu_forward, grads_oracle_layout, oracle_opt, to_dev, view_images
+from gpu_util import (decode_records, decode_rect, gpu_forward, grads_oracle_layout, mask_covers, mask_rows,
+                      oracle_opt, to_dev, view_images)
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
@@ -32,13 +33,19 @@ def test_c3_forward_and_binning(gpu_lib, c3):
     opts = gpu_lib.RenderOptions(sh_degree=3, aa=True)
     _, proj, pairs, ranges, P, out = gpu_forward(gpu_lib, scene, cams, opts)
     tiles = proj.tiles.cpu().numpy()
-    rect = decode_rect(proj.rect.cpu().numpy(), tiles, cams, scene.n)
+    mask = proj.tile_mask.cpu().numpy().view(np.uint64)
+    rect = decode_rect(proj.rect.cpu().numpy(), tiles, cams, scene.n, mask=mask)
     keys = proj.depth_key.cpu().numpy().view(np.uint32)
     f = oracle.forward(scene, cam, oracle_opt(opts), guard_eps=oracle.DEFAULT_GUARD)
     p = f["proj"][0]
-    # projection-level integer agreement (rectangles from FP64 on both sides)
+    # projection-level integer agreement (rectangles and covered-tile masks
+    # from FP64 on both sides)
     assert np.array_equal(tiles, p["tiles"])
-    assert np.array_equal(rect, p["rect"])
+    vis = tiles > 0                       # masks of culled slots are left unwritten
+    assert np.array_equal(mask[vis], p["mask"][vis])
+    assert np.array_equal(rect[vis][:, :3], p["rect"][vis][:, :3])
+    full = vis & (p["mask"] == 0)
+    assert np.array_equal(rect[full], p["rect"][full])
     assert np.array_equal(keys[tiles > 0], oracle.depth_key(p["depth"])[tiles > 0])
     # binning: bit-exact against the oracle's own sort of the same keys
     assert P == f["bins"]["n_pairs"]
@@ -131,6 +138,7 @@ def test_c5_multiview_sampled(gpu_lib):
     keys_all = proj.depth_key.cpu().numpy().view(np.uint32)
     tiles_all = proj.tiles.cpu().numpy().astype(np.int64)
     words = proj.rect.cpu().numpy().view(np.uint32).astype(np.int64)
+    masks_all = proj.tile_mask.cpu().numpy().view(np.uint64)
     picked = []
     for v, cam in enumerate(cams):
         nt = cam.n_tiles
@@ -141,10 +149,13 @@ def test_c5_multiview_sampled(gpu_lib):
         seen = tl > 0
         x0 = np.where(seen, base % cam.tiles_x, 0)
         y0 = np.where(seen, base // cam.tiles_x, 0)
+        mv = np.where(seen, masks_all[sl], np.uint64(0))
         h = np.where(seen, tl // np.maximum(w, 1), 0)
+        h = np.where(mv != 0, mask_rows(mv, w), h)
         for t in (int(np.argmax(lens)), int(rng.choice(nonempty))):
             tx, ty = t % cam.tiles_x, t // cam.tiles_x
             cover = seen & (x0 <= tx) & (tx < x0 + w) & (y0 <= ty) & (ty < y0 + h)
+            cover &= mask_covers(mv, w, x0, y0, tx, ty)
             slots = np.nonzero(cover)[0] + v * n
             want = slots[np.lexsort((slots, keys_all[slots]))].astype(np.uint32)
             got = pv[rg[toff[v] + t, 0]:rg[toff[v] + t, 1]]
@@ -153,6 +164,7 @@ def test_c5_multiview_sampled(gpu_lib):
 
     # compositing of the sampled tiles by the oracle from the GPU's records
     imgs = {k: view_images(out[k].cpu().numpy(), cams) for k in ("rgb", "depth", "alpha")}
+    guarded = sampled = 0
     for v, cam in enumerate(cams):
         ts = [t for (vv, t) in picked if vv == v]
         lists = [pv[rg[toff[v] + t, 0]:rg[toff[v] + t, 1]] for t in ts]
@@ -172,8 +184,12 @@ def test_c5_multiview_sampled(gpu_lib):
             ys = slice((t // cam.tiles_x) * 16, min(cam.height, (t // cam.tiles_x + 1) * 16))
             xs = slice((t % cam.tiles_x) * 16, min(cam.width, (t % cam.tiles_x + 1) * 16))
             ok = ref["guard"][ys, xs] == 0
-            assert (~ok).sum() <= 2, (v, t)
+            guarded += int((~ok).sum())
+            sampled += ok.size
             assert np.abs(imgs["rgb"][v][ys, xs] - ref["rgb"][ys, xs]).max(-1)[ok].max(initial=0) <= 1e-4
             assert np.abs(imgs["alpha"][v][ys, xs] - ref["alpha"][ys, xs])[ok].max(initial=0) <= 1e-4
             d = np.abs(imgs["depth"][v][ys, xs] - ref["depth"][ys, xs]) / np.maximum(1.0, ref["depth"][ys, xs])
             assert d[ok].max(initial=0) <= 1e-4
+    # the sampled tiles include each view's longest list, where decisions
+    # near the skip / stop thresholds concentrate
+    assert guarded <= max(4, 0.01 * sampled), (guarded, sampled)

@@ -60,7 +60,8 @@ def test_projection_matches_oracle(gpu_lib, case):
     torch.cuda.synchronize()
     rec = proj.rec.cpu().numpy()
     tiles = proj.tiles.cpu().numpy()
-    rect = decode_rect(proj.rect.cpu().numpy(), tiles, cams, scene.n)
+    mask = proj.tile_mask.cpu().numpy().view(np.uint64)
+    rect = decode_rect(proj.rect.cpu().numpy(), tiles, cams, scene.n, mask=mask)
     n = scene.n
     for v, c in enumerate(cams):
         p = oracle.project(scene, c, **oracle_opt(opts))
@@ -69,8 +70,13 @@ def test_projection_matches_oracle(gpu_lib, case):
                                      np.any(np.abs(p["mean2d"] - np.round(p["mean2d"])) < 1e-9, axis=1))
         ok = ~border
         np.testing.assert_array_equal(tiles[sl][ok], p["tiles"][ok])
-        np.testing.assert_array_equal(rect[sl][ok], p["rect"][ok])
         vis = (p["tiles"] > 0) & ok
+        # exact tile culling: the same covered-tile masks; rectangles agree in
+        # origin and width (the height of a masked one is its last covered row)
+        np.testing.assert_array_equal(mask[sl][vis], p["mask"][vis])
+        np.testing.assert_array_equal(rect[sl][ok][:, :3], p["rect"][ok][:, :3])
+        full = ok & (p["mask"] == 0)
+        np.testing.assert_array_equal(rect[sl][full], p["rect"][full])
         assert vis.sum() > 10
         m2, con, op, rgb, dep = decode_records(rec[sl])
         np.testing.assert_allclose(m2[vis], p["mean2d"][vis], atol=1e-4, rtol=0)
@@ -90,10 +96,11 @@ def test_binning_bit_exact_stage_chained(gpu_lib, case):
     opts = _opts(gpu_lib, od)
     params, proj, pairs, ranges, P, _ = gpu_forward(gpu_lib, scene, cams, opts)
     tiles = proj.tiles.cpu().numpy()
-    rect = decode_rect(proj.rect.cpu().numpy(), tiles, cams, scene.n)
+    mask = proj.tile_mask.cpu().numpy().view(np.uint64)
+    rect = decode_rect(proj.rect.cpu().numpy(), tiles, cams, scene.n, mask=mask)
     keys = proj.depth_key.cpu().numpy().view(np.uint32)
     slot_view = np.repeat(np.arange(len(cams), dtype=np.int32), scene.n)
-    ref = oracle.bin_pairs(rect, tiles, keys, slot_view, cams)
+    ref = oracle.bin_pairs(rect, tiles, keys, slot_view, cams, mask=mask)
     assert P == ref["n_pairs"] and P > 0
     np.testing.assert_array_equal(pairs.cpu().numpy().view(np.uint32), ref["pair_slot"])
     np.testing.assert_array_equal(ranges.cpu().numpy().view(np.uint32), ref["ranges"])

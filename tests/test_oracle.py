@@ -206,8 +206,13 @@ def test_tile_culling_keeps_every_reachable_tile(which):
             assert not need, i
             dropped += 1
             continue
-        x0, y0, x1, y1 = q["rect"][i]
+        x0, y0, x1, y1 = (int(v) for v in q["rect"][i])
         assert all(x0 <= tx <= x1 and y0 <= ty <= y1 for tx, ty in need), i
+        m = int(q["mask"][i])
+        if m:
+            w = x1 - x0 + 1
+            assert all((m >> ((ty - y0) * w + (tx - x0))) & 1 for tx, ty in need), i
+            assert bin(m).count("1") == q["tiles"][i]
     assert q["tiles"].sum() < p["tiles"].sum()
     if which == "oblique_aa":
         assert dropped > 0
@@ -219,11 +224,53 @@ def test_tile_culling_leaves_images_unchanged(aa):
     cams = [S.camera_c1(), S.Camera(90.0, 90.0, 50.0, 35.0, S.look_at((1.0, 1.5, -3.0), (0.0, 0.0, 0.0)), 100, 70)]
     opt = dict(aa=aa, bg=(0.1, 0.2, 0.3))
     f0 = oracle.forward(sc, cams, dict(opt, tile_cull=False), guard_eps=None)
+    fb = oracle.forward(sc, cams, dict(opt, tile_cull=1), guard_eps=None)
     f1 = oracle.forward(sc, cams, opt, guard_eps=None)
-    assert f1["bins"]["n_pairs"] < f0["bins"]["n_pairs"]
-    for a, b in zip(f0["images"], f1["images"]):
-        for k in ("rgb", "depth", "alpha", "T"):
-            assert np.array_equal(a[k], b[k]), k
+    assert f1["bins"]["n_pairs"] < fb["bins"]["n_pairs"] < f0["bins"]["n_pairs"]
+    for f in (fb, f1):
+        for a, b in zip(f0["images"], f["images"]):
+            for k in ("rgb", "depth", "alpha", "T"):
+                assert np.array_equal(a[k], b[k]), k
+
+
+def test_exact_tile_culling_matches_dense_minimum():
+    """The per-tile test keeps a tile exactly when the quadratic form of the
+    alpha ellipse, minimised over the tile's widened pixel-centre rectangle,
+    is within 2 tau (1 + 4e-6): checked against a dense grid minimum (the
+    grid can only overestimate the minimum, by at most its resolution)."""
+    sc = S.random_scene(600, seed=23, log_scale_mu=-2.3)
+    cam = S.Camera(110.0, 110.0, 70.0, 45.0, S.look_at((1.4, -1.3, -3.1), (0.0, 0.1, 0.0)), 140, 90)
+    p = oracle.project(sc, cam, aa=True, tile_cull=1)
+    q = oracle.project(sc, cam, aa=True)
+    g = np.linspace(0.0, 1.0, 121)
+    checked = culled = 0
+    for i in np.nonzero(q["visible"])[0]:
+        m = int(q["mask"][i])
+        x0, y0, x1, y1 = (int(v) for v in q["rect"][i])
+        assert tuple(p["rect"][i]) == (x0, y0, x1, y1)
+        w, h = x1 - x0 + 1, y1 - y0 + 1
+        if w * h > 64:
+            assert m == 0 and q["tiles"][i] == w * h
+            continue
+        A, B, C = q["conic"][i]
+        mx, my = q["mean2d"][i]
+        lim = 2.0 * (np.log(255.0 * q["opac"][i]) + 1e-5) * (1.0 + 4e-6)
+        for ty in range(y0, y1 + 1):
+            for tx in range(x0, x1 + 1):
+                xa, xb = tx * 16 + 0.5 - 1e-3 - mx, min(tx * 16 + 15, cam.width - 1) + 0.5 + 1e-3 - mx
+                ya, yb = ty * 16 + 0.5 - 1e-3 - my, min(ty * 16 + 15, cam.height - 1) + 0.5 + 1e-3 - my
+                X, Y = np.meshgrid(xa + (xb - xa) * g, ya + (yb - ya) * g)
+                qq = A * X * X + 2 * B * X * Y + C * Y * Y
+                grid_min = qq.min()
+                slack = 2.0 * np.abs(np.gradient(qq)).max()            # one grid step of change
+                kept = (m >> ((ty - y0) * w + (tx - x0))) & 1
+                if grid_min <= lim:
+                    assert kept, (i, tx, ty)
+                elif grid_min - slack > lim:
+                    assert not kept, (i, tx, ty)
+                    culled += 1
+                checked += 1
+    assert checked > 1000 and culled > 50
 
 def test_near_plane_culls():
     cam = small_cam(tz=0.0)
@@ -241,20 +288,25 @@ def test_bin_matches_lexsort_enumeration():
     projs = [oracle.project(sc, c) for c in cams]
     rect = np.concatenate([p["rect"] for p in projs])
     tiles = np.concatenate([p["tiles"] for p in projs])
+    mask = np.concatenate([p["mask"] for p in projs])
+    assert (mask != 0).any()
     keys = oracle.depth_key(np.concatenate([p["depth"] for p in projs]))
     # force some exact depth ties so the index tie-break is exercised
     keys[10:20] = keys[10]
     slot_view = np.repeat(np.arange(2, dtype=np.int32), sc.n)
-    b = oracle.bin_pairs(rect, tiles, keys, slot_view, cams)
+    b = oracle.bin_pairs(rect, tiles, keys, slot_view, cams, mask=mask)
     toff = [0, cams[0].n_tiles]
     rows = []
     for s_ in range(len(tiles)):
         if tiles[s_] == 0:
             continue
         v = slot_view[s_]
-        x0, y0, x1, y1 = rect[s_]
+        x0, y0, x1, y1 = (int(v) for v in rect[s_])
+        m = int(mask[s_])
         for ty in range(y0, y1 + 1):
             for tx in range(x0, x1 + 1):
+                if m and not (m >> ((ty - y0) * (x1 - x0 + 1) + (tx - x0))) & 1:
+                    continue
                 rows.append((toff[v] + ty * cams[v].tiles_x + tx, keys[s_], s_))
     rows = np.array(rows, np.int64)
     order = np.lexsort((rows[:, 2], rows[:, 1], rows[:, 0]))
