@@ -73,18 +73,23 @@ def n_tiles_of(n_pix):
 
 
 def stage_bytes(n, n_front, n_vis, n_pairs, n_pix, n_views=1):
-    """Algorithmic HBM bytes of each memory-bound stage for one launch."""
+    """Algorithmic HBM bytes of each memory-bound stage for one launch
+    (S = slots = n * views, V = visible slots, P = pairs)."""
+    S = n * n_views
+    tile_passes = max(1, math.ceil(math.log2(max(2, n_tiles_of(n_pix))) / 8))
     return {
         # means of all (12) + scales, quats, opacity of those in front (32) + SH row of
-        # visible (192); writes: tiles + depth key of all (8) + record 64 + rect 8 of visible
-        "project": 12 * n + 32 * n_front + 192 * n_vis + 8 * n * n_views + 72 * n_vis,
-        # depth sort: 4 passes x (read key 4 + read key+val 8 + write 8) on all slots,
-        # gather + scan (4 + 8 + 4 + 8), emission (8 per pair + 12 per visible),
-        # tile sort passes x (4 + 8 + 8) per pair, ranges (4 per pair)
-        "bin_sort": (4 * 20 * n * n_views + 24 * n * n_views + 8 * n_pairs + 12 * n_vis
-                     + max(1, math.ceil(math.log2(max(2, n_tiles_of(n_pix))) / 8)) * 20 * n_pairs + 4 * n_pairs),
+        # visible (192); writes: tiles + depth key of all (8) + record 64, rect 8, tile mask 8 of visible
+        "project": 12 * n + 32 * n_front + 192 * n_vis + 8 * S + 80 * n_vis,
+        # visible flags (tiles in, flag out) and their scan (12) over all slots; compaction
+        # (tiles, position, key in; key, slot out of visible); depth sort of the visible, 4 passes
+        # of (key 4 + key, value 8 in; 8 out); gather by depth rank (slot, tiles, rectangle,
+        # mask in; tiles, rectangle, mask out: 44) and the scan of tiles (12); emission (8 per
+        # pair, 20 per rank); tile sort passes of 20 per pair; ranges (4 per pair)
+        "bin_sort": (8 * S + 12 * S + 12 * S + 8 * n_vis + 4 * 20 * n_vis + 44 * n_vis + 12 * n_vis
+                     + 8 * n_pairs + 20 * n_vis + tile_passes * 20 * n_pairs + 4 * n_pairs),
         # tiles of all (4); params 236 + 2D grads 48 of visible; gradients 236 + norm 4 of all
-        "project_bwd": 4 * n * n_views + (236 + 48) * n_vis + 236 * n + 4 * n * n_views,
+        "project_bwd": 4 * S + (236 + 48) * n_vis + 236 * n + 4 * S,
     }
 
 
@@ -203,6 +208,19 @@ def main():
 
     nxt = next_rows_bench(gs, torch, scene.n, W, H, dev, max(5, args.steps))
 
+    # HBM fraction of every memory-bound stage, ALU fraction of compositing
+    sb = stage_bytes(scene.n, n_front, n_vis, P, npix)
+    stage_roof = {}
+    for k, b in sb.items():
+        if k in stage_ms:
+            gbs = b / (stage_ms[k] * 1e-3) / 1e9
+            stage_roof[k] = {"bound": "hbm", "bytes": int(b), "GB_s": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    for k, f in stage_flops.items():
+        if k in stage_ms:
+            tf = f / (stage_ms[k] * 1e-3) / 1e12
+            stage_roof[k] = {"bound": "alu", "flops": int(f), "TFLOP_s": round(tf, 2),
+                             "frac": round(tf / FP32_PEAK_TFLOPS, 4)}
+
     serve = None
     if not args.no_serve:
         del params, stats, proj, pv, rg, out
@@ -240,6 +258,7 @@ def main():
         "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
         "workload_stats": {"visible": n_vis, "in_front": n_front, "pairs": P, "evals_fwd": e_fwd, "evals_bwd": e_bwd},
         "roofline": roof,
+        "stage_roofline": stage_roof,
         "cpu_baseline": cpu,
         "next_rows": nxt,
     }

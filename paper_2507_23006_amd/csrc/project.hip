@@ -302,25 +302,53 @@ __global__ __launch_bounds__(kPF) void k_project_fwd(GaussPtrs gp, int64_t n, Vi
     const int64_t g0 = (int64_t)blockIdx.x * kPFSpan;
     if (tid == 0) s_count = 0;
     __syncthreads();
+    // the thread's kPFPer Gaussians move through each phase together, so
+    // their independent loads are in flight at once: means; depths and the
+    // views each lies in; scales and opacity of those in front of a view;
+    // the conservative test
+    float mu[kPFPer][3];
+#pragma unroll
+    for (int i = 0; i < kPFPer; ++i) {
+        const int64_t g = g0 + i * kPF + tid;
+        const bool ok = g < n;
+        mu[i][0] = ok ? gp.means[g] : 0.0f;
+        mu[i][1] = ok ? gp.means[n + g] : 0.0f;
+        mu[i][2] = ok ? gp.means[2 * n + g] : 0.0f;
+    }
+    uint32_t front[kPFPer];
+#pragma unroll
+    for (int i = 0; i < kPFPer; ++i) {
+        front[i] = 0;
+        if (g0 + i * kPF + tid >= n) continue;
+        for (int v = 0; v < vt.n_views; ++v) {
+            const ViewK& V = vt.v[v];
+            double tx, ty, tz;
+            view_point(V, mu[i][0], mu[i][1], mu[i][2], tx, ty, tz);
+            if (tz >= (double)V.znear && tz <= (double)V.zfar) front[i] |= 1u << v;
+        }
+    }
+    float sm[kPFPer], op[kPFPer];
+#pragma unroll
+    for (int i = 0; i < kPFPer; ++i) {
+        const int64_t g = g0 + i * kPF + tid;
+        sm[i] = 0.0f;
+        op[i] = 0.0f;
+        if (front[i]) {
+            sm[i] = fmaxf(fabsf(gp.scales[g]), fmaxf(fabsf(gp.scales[n + g]), fabsf(gp.scales[2 * n + g])));
+            op[i] = gp.opac[g];
+        }
+    }
     for (int i = 0; i < kPFPer; ++i) {
         const int loc = i * kPF + tid;
         const int64_t g = g0 + loc;
         uint32_t cand = 0;
         if (g < n) {
-            const double mu0 = gp.means[g], mu1 = gp.means[n + g], mu2 = gp.means[2 * n + g];
-            double smax = -1.0;
-            float o = 0.0f;
             for (int v = 0; v < vt.n_views; ++v) {
                 const ViewK& V = vt.v[v];
-                double tx, ty, tz;
-                view_point(V, mu0, mu1, mu2, tx, ty, tz);
-                if (tz >= (double)V.znear && tz <= (double)V.zfar) {
-                    if (smax < 0.0) {
-                        smax = fmax(fabs((double)gp.scales[g]),
-                                    fmax(fabs((double)gp.scales[n + g]), fabs((double)gp.scales[2 * n + g])));
-                        o = gp.opac[g];
-                    }
-                    if (may_cover(V, opt, tx, ty, tz, smax, o)) cand |= 1u << v;
+                if (front[i] & (1u << v)) {
+                    double tx, ty, tz;
+                    view_point(V, mu[i][0], mu[i][1], mu[i][2], tx, ty, tz);
+                    if (may_cover(V, opt, tx, ty, tz, (double)sm[i], op[i])) cand |= 1u << v;
                 }
                 if (!(cand & (1u << v))) {
                     const int64_t slot = (int64_t)v * n + g;
