@@ -53,6 +53,8 @@ __device__ __forceinline__ void sh_basis_grad(float x, float y, float z, int k, 
     }
 }
 
+typedef float F4 __attribute__((ext_vector_type(4)));
+
 constexpr int kG2 = GS_GRAD2D_FLOATS;
 constexpr int kPB = 256;                  // threads per workgroup
 constexpr int kSpanPer = 4;               // Gaussians per thread in the scan
@@ -301,11 +303,12 @@ __global__ __launch_bounds__(kPB) void k_project_bwd(GaussPtrs gp, int64_t n, Vi
                 if (absgrad) reinterpret_cast<float2*>(absgrad)[slot] = make_float2(ax, ay);
             }
             if (!vis) {
-                for (int c = 0; c < 3; ++c) out.means[c * n + g] = 0.0f;
-                for (int c = 0; c < 3; ++c) out.scales[c * n + g] = 0.0f;
-                for (int c = 0; c < 4; ++c) out.quats[c * n + g] = 0.0f;
-                out.opac[g] = 0.0f;
-                if (out.app) reinterpret_cast<float4*>(out.app)[g] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                // streaming stores: the zero rows are not read again here
+                for (int c = 0; c < 3; ++c) __builtin_nontemporal_store(0.0f, out.means + c * n + g);
+                for (int c = 0; c < 3; ++c) __builtin_nontemporal_store(0.0f, out.scales + c * n + g);
+                for (int c = 0; c < 4; ++c) __builtin_nontemporal_store(0.0f, out.quats + c * n + g);
+                __builtin_nontemporal_store(0.0f, out.opac + g);
+                if (out.app) __builtin_nontemporal_store(F4{0.0f, 0.0f, 0.0f, 0.0f}, reinterpret_cast<F4*>(out.app) + g);
             }
         }
         s_seen[loc] = vis ? 1 : 0;
@@ -322,9 +325,9 @@ __global__ __launch_bounds__(kPB) void k_project_bwd(GaussPtrs gp, int64_t n, Vi
 
     // zero coefficient rows of unseen Gaussians: coalesced 16-byte stores
     const int64_t rows = n - g0 < kSpan ? n - g0 : kSpan;
-    float4* dsh = reinterpret_cast<float4*>(out.sh) + 12 * g0;
+    F4* dsh = reinterpret_cast<F4*>(out.sh) + 12 * g0;
     for (int q = tid; q < 12 * rows; q += kPB)
-        if (!s_seen[q / 12]) dsh[q] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (!s_seen[q / 12]) __builtin_nontemporal_store(F4{0.0f, 0.0f, 0.0f, 0.0f}, dsh + q);
 
     // pass 2: the chain, one thread per seen Gaussian
     const uint32_t cnt = s_count;
