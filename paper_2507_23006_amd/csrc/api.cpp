@@ -130,6 +130,8 @@ struct BinWs {
     uint32_t *tiles_s, *offsets;
     uint2* rect_s;
     uint64_t* mask_s;
+    uint32_t* slot_s;
+    uint4* desc;
     uint32_t* scan_tmp;
     unsigned long long* total;
     uint32_t *pkeys, *pkeys_alt, *pvals_alt;
@@ -147,6 +149,8 @@ size_t bin_layout(int64_t n_slots, int64_t cap, void* base, BinWs* w) {
     w->offsets = c.take<uint32_t>(N);
     w->rect_s = c.take<uint2>(N);
     w->mask_s = c.take<uint64_t>(N);
+    w->slot_s = c.take<uint32_t>(N);
+    w->desc = c.take<uint4>(2 * N);
     w->scan_tmp = c.take<uint32_t>(scan_tmp_elems((uint32_t)N));
     w->total = c.take<unsigned long long>(kTotals);   // [0] visible, [8] offsets total, [16 + 16k] pair parts
     w->pkeys = c.take<uint32_t>(Pc);
@@ -189,7 +193,7 @@ int bin_sort_slots(const Projected& pr, const ViewTable& vt, int64_t n_slots, in
     GS_HIP(fill_u32(reinterpret_cast<uint32_t*>(w.total), 0u, 2 * kTotals, s));
     GS_HIP(launch_visible_flags(pr, N, w.tiles_s, w.total + 16, s));
     GS_HIP(exclusive_scan_u32(w.tiles_s, w.offsets, N, w.scan_tmp, w.total, s));
-    GS_HIP(launch_compact_visible(pr, w.offsets, N, w.dkeys, w.dvals, s));
+    GS_HIP(launch_compact_visible(pr, w.offsets, N, w.dkeys, w.dvals, w.desc, s));
     unsigned long long* host = pinned_scalar();
     if (!host) return fail(GS_ERR_HIP, "pinned host buffer unavailable");
     GS_HIP(hipMemcpyAsync(host, w.total, kTotals * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
@@ -203,13 +207,15 @@ int bin_sort_slots(const Projected& pr, const ViewTable& vt, int64_t n_slots, in
         return fail(GS_ERR_CAPACITY, "pair count %llu exceeds capacity %lld", P, (long long)pair_capacity);
     if (V > N || (V == 0) != (P == 0)) return fail(GS_ERR_INTERNAL, "inconsistent counts (%llu visible, %llu pairs)", V, P);
     const uint32_t NV = (uint32_t)V;
-    // 2. depth order of the visible slots (stable: ties stay in slot order);
-    //    per depth rank its tile count and rectangle; exclusive scan -> pair offsets
+    // 2. depth order of the visible slots (stable: ties stay in slot order,
+    //    which is compaction order); per depth rank its tile count, rectangle,
+    //    mask and slot; exclusive scan -> pair offsets
     bool alt = false;
     GS_HIP(radix_sort_pairs(w.dkeys, w.dvals, w.dkeys_alt, w.dvals_alt, NV, 0, 32, w.hist, s, &alt));
-    const uint32_t* sorted_slot = alt ? w.dvals_alt : w.dvals;
+    const uint32_t* sorted_pos = alt ? w.dvals_alt : w.dvals;
+    const uint32_t* sorted_slot = w.slot_s;
     if (NV) {
-        GS_HIP(launch_gather_sorted(sorted_slot, pr, NV, w.tiles_s, w.rect_s, w.mask_s, s));
+        GS_HIP(launch_gather_sorted(sorted_pos, w.desc, NV, w.tiles_s, w.rect_s, w.mask_s, w.slot_s, s));
         GS_HIP(exclusive_scan_u32(w.tiles_s, w.offsets, NV, w.scan_tmp, w.total + 8, s));
     }
     // 3. expand into (tile, slot) pairs in depth order, then stable sort by tile id

@@ -36,33 +36,44 @@ __global__ __launch_bounds__(256) void k_visible_flags(const uint32_t* __restric
     }
 }
 
-// visible slots, in slot order, with their depth keys: the input of the
-// depth sort (culled slots never enter it)
+// Visible slots, in slot order, with their depth keys: the input of the
+// depth sort (culled slots never enter it), whose values are the compaction
+// positions.  Each visible slot also leaves a 32-byte descriptor there
+// (rectangle, tile mask, tile count, slot) so that the gather after the sort
+// fetches one line per depth rank instead of one per array.
 __global__ __launch_bounds__(256) void k_compact_visible(const uint32_t* __restrict__ tiles,
                                                          const uint32_t* __restrict__ pos,
-                                                         const uint32_t* __restrict__ dkey, uint32_t n,
-                                                         uint32_t* __restrict__ keys, uint32_t* __restrict__ slots) {
+                                                         const uint32_t* __restrict__ dkey,
+                                                         const uint2* __restrict__ rect,
+                                                         const uint64_t* __restrict__ mask, uint32_t n,
+                                                         uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
+                                                         uint4* __restrict__ desc) {
     const uint32_t i = blockIdx.x * 256 + threadIdx.x;
-    if (i < n && tiles[i]) {
-        const uint32_t d = pos[i];
-        keys[d] = dkey[i];
-        slots[d] = i;
-    }
+    if (i >= n) return;
+    const uint32_t t = tiles[i];
+    if (!t) return;
+    const uint32_t d = pos[i];
+    keys[d] = dkey[i];
+    vals[d] = d;
+    const uint2 r = rect[i];
+    const uint64_t m = mask ? mask[i] : 0ull;
+    desc[2 * d] = make_uint4(r.x, r.y, (uint32_t)m, (uint32_t)(m >> 32));
+    desc[2 * d + 1] = make_uint4(t, i, 0u, 0u);
 }
 
 // per depth rank: tiles covered and the emission descriptor of its slot
-// (rectangle and, with exact tile culling, its mask of covered tiles)
-__global__ void k_gather_sorted(const uint32_t* __restrict__ sorted_slot, const uint32_t* __restrict__ tiles,
-                                const uint2* __restrict__ rect, const uint64_t* __restrict__ mask, uint32_t n,
+// (rectangle, covered-tile mask, slot), from its compaction descriptor
+__global__ void k_gather_sorted(const uint32_t* __restrict__ sorted_pos, const uint4* __restrict__ desc, uint32_t n,
                                 uint32_t* __restrict__ tiles_s, uint2* __restrict__ rect_s,
-                                uint64_t* __restrict__ mask_s) {
+                                uint64_t* __restrict__ mask_s, uint32_t* __restrict__ slot_s) {
     const uint32_t d = blockIdx.x * 256 + threadIdx.x;
     if (d >= n) return;
-    const uint32_t s = sorted_slot[d];
-    const uint32_t t = tiles[s];
-    tiles_s[d] = t;
-    rect_s[d] = t ? rect[s] : make_uint2(0u, 1u);
-    if (mask_s) mask_s[d] = (t && mask) ? mask[s] : 0ull;
+    const uint32_t c = sorted_pos[d];
+    const uint4 a = desc[2 * c], b = desc[2 * c + 1];
+    tiles_s[d] = b.x;
+    rect_s[d] = make_uint2(a.x, a.y);
+    mask_s[d] = (uint64_t)a.z | ((uint64_t)a.w << 32);
+    slot_s[d] = b.y;
 }
 
 // index of the k-th set bit (k < popcount(m)) of m, by halving
@@ -205,16 +216,16 @@ hipError_t launch_visible_flags(const Projected& proj, uint32_t n_slots, uint32_
 }
 
 hipError_t launch_compact_visible(const Projected& proj, const uint32_t* pos, uint32_t n_slots, uint32_t* keys,
-                                  uint32_t* slots, hipStream_t s) {
+                                  uint32_t* vals, uint4* desc, hipStream_t s) {
     hipLaunchKernelGGL(k_compact_visible, dim3((n_slots + 255) / 256), dim3(256), 0, s, proj.tiles, pos, proj.dkey,
-                       n_slots, keys, slots);
+                       proj.rect, proj.tile_mask, n_slots, keys, vals, desc);
     return hipGetLastError();
 }
 
-hipError_t launch_gather_sorted(const uint32_t* sorted_slot, const Projected& proj, uint32_t n_slots,
-                                uint32_t* tiles_s, uint2* rect_s, uint64_t* mask_s, hipStream_t s) {
-    hipLaunchKernelGGL(k_gather_sorted, dim3((n_slots + 255) / 256), dim3(256), 0, s, sorted_slot, proj.tiles,
-                       proj.rect, proj.tile_mask, n_slots, tiles_s, rect_s, proj.tile_mask ? mask_s : nullptr);
+hipError_t launch_gather_sorted(const uint32_t* sorted_pos, const uint4* desc, uint32_t n_visible, uint32_t* tiles_s,
+                                uint2* rect_s, uint64_t* mask_s, uint32_t* slot_s, hipStream_t s) {
+    hipLaunchKernelGGL(k_gather_sorted, dim3((n_visible + 255) / 256), dim3(256), 0, s, sorted_pos, desc, n_visible,
+                       tiles_s, rect_s, mask_s, slot_s);
     return hipGetLastError();
 }
 

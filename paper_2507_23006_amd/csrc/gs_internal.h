@@ -161,10 +161,13 @@ hipError_t zero_seen_grad2d(const uint32_t* tiles, float* grad2d, int64_t n_slot
 constexpr int kBinPairParts = 64;
 hipError_t launch_visible_flags(const Projected& proj, uint32_t n_slots, uint32_t* flags,
                                 unsigned long long* pair_parts, hipStream_t s);
+// compaction of the visible slots: depth keys, their positions as sort
+// values, and per position a 32-byte descriptor (uint4 pair: rect.x, rect.y,
+// mask lo, mask hi; tiles, slot, 0, 0)
 hipError_t launch_compact_visible(const Projected& proj, const uint32_t* pos, uint32_t n_slots, uint32_t* keys,
-                                  uint32_t* slots, hipStream_t s);
-hipError_t launch_gather_sorted(const uint32_t* sorted_slot, const Projected& proj, uint32_t n_slots,
-                                uint32_t* tiles_s, uint2* rect_s, uint64_t* mask_s, hipStream_t s);
+                                  uint32_t* vals, uint4* desc, hipStream_t s);
+hipError_t launch_gather_sorted(const uint32_t* sorted_pos, const uint4* desc, uint32_t n_visible, uint32_t* tiles_s,
+                                uint2* rect_s, uint64_t* mask_s, uint32_t* slot_s, hipStream_t s);
 hipError_t launch_emit_pairs(const uint32_t* offsets, const uint2* rect_s, const uint64_t* mask_s,
                              const uint32_t* sorted_slot, uint32_t n_slots, uint32_t n_pairs, uint32_t* pair_key,
                              uint32_t* pair_val, hipStream_t s);
