@@ -54,7 +54,8 @@ __device__ __forceinline__ f4v mfma(float a, float b, f4v c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-__device__ __forceinline__ float sigmoid(float z) { return 1.0f / (1.0f + expf(-z)); }
+// fast exp and divide: a few ulp, far inside the offsets' float32 bar
+__device__ __forceinline__ float sigmoid(float z) { return __fdividef(1.0f, 1.0f + __expf(-z)); }
 
 // normalised image embedding (s_eh) and u = b1 + W1[:, 16:] e_hat (s_u);
 // wave 0 computes, the workgroup waits
@@ -86,9 +87,8 @@ __device__ __forceinline__ float load_unit(const float* __restrict__ gemb, int64
     float ss = e.x * e.x + e.y * e.y + e.z * e.z + e.w * e.w;
     ss += __shfl_xor(ss, 16, 64);
     ss += __shfl_xor(ss, 32, 64);
-    const float nrm = sqrtf(ss);
-    above = nrm > kNormEps;
-    const float inv = 1.0f / fmaxf(nrm, kNormEps);
+    above = ss > kNormEps * kNormEps;
+    const float inv = rsqrtf(fmaxf(ss, kNormEps * kNormEps));    // 1 / max(|g|, eps)
     eh[0] = e.x * inv; eh[1] = e.y * inv; eh[2] = e.z * inv; eh[3] = e.w * inv;
     return inv;
 }
@@ -114,10 +114,11 @@ __global__ __launch_bounds__(kAT) void k_app_fwd(const float* __restrict__ gemb,
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             aw1[mi][r] = w.w1[(16 * mi + j) * kIn + 4 * q + r];                    // W1g[16mi + j][4q + r]
-            aw2[mi][r] = j < kOut ? w.w2[j * kHid + 16 * mi + 4 * q + r] : 0.0f;  // W2[j][16mi + 4q + r]
+            // output o goes to row 4 o of the product, i.e. register 0 of lane group o
+            aw2[mi][r] = (j & 3) == 0 ? w.w2[(j >> 2) * kHid + 16 * mi + 4 * q + r] : 0.0f;
             ub[mi][r] = s_u[16 * mi + 4 * q + r];
         }
-    const float b20 = w.b2[0], b21 = w.b2[1], b22 = w.b2[2], b23 = w.b2[3];
+    const float b2q = w.b2[q];
     float sum_do = 0.0f;
     const int64_t n_chunks = (n + 63) / 64;
     for (int64_t c = (int64_t)blockIdx.x * 4 + wv; c < n_chunks; c += (int64_t)gridDim.x * 4) {
@@ -140,16 +141,12 @@ __global__ __launch_bounds__(kAT) void k_app_fwd(const float* __restrict__ gemb,
                 z0 = mfma(aw2[0][r], fmaxf(h0[r] + ub[0][r], 0.0f), z0);
                 z1 = mfma(aw2[1][r], fmaxf(h1[r] + ub[1][r], 0.0f), z1);
             }
-            const f4v z = z0 + z1;
-            // outputs 0..3 of Gaussian j sit in lane group q = 0
-            if (q == 0 && gi < n) {
-                float4 y;
-                y.x = sigmoid(z[0] + b20);
-                y.y = sigmoid(z[1] + b21);
-                y.z = sigmoid(z[2] + b22);
-                y.w = sigmoid(z[3] + b23);
-                out[gi] = y;
-                sum_do += y.w;
+            // output q of Gaussian j sits in register 0 of lane (q, j): one
+            // sigmoid per lane, and the wave stores 16 rows of 16 bytes
+            if (gi < n) {
+                const float y = sigmoid(z0[0] + z1[0] + b2q);
+                reinterpret_cast<float*>(out)[gi * 4 + q] = y;
+                if (q == 3) sum_do += y;
             }
         }
     }

@@ -352,8 +352,8 @@ __global__ __launch_bounds__(kPF) void k_project_fwd(GaussPtrs gp, int64_t n, Vi
                 }
                 if (!(cand & (1u << v))) {
                     const int64_t slot = (int64_t)v * n + g;
-                    out.tiles[slot] = 0u;
-                    out.dkey[slot] = 0xFFFFFFFFu;
+                    __builtin_nontemporal_store(0u, out.tiles + slot);
+                    __builtin_nontemporal_store(0xFFFFFFFFu, out.dkey + slot);
                 }
             }
         }

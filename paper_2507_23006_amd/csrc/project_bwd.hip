@@ -261,11 +261,11 @@ __device__ __forceinline__ void project_bwd_one(const GaussPtrs& gp, int64_t n, 
     // normalisation q / |q|
     const double dot = dq[0] * w + dq[1] * x + dq[2] * y + dq[3] * z;
     const double qh[4] = {w, x, y, z};
-    for (int c = 0; c < 3; ++c) out.means[c * n + g] = (float)dmu[c];
-    for (int c = 0; c < 3; ++c) out.scales[c * n + g] = (float)ds[c];
-    for (int c = 0; c < 4; ++c) out.quats[c * n + g] = (float)((dq[c] - qh[c] * dot) / qn);
+    for (int c = 0; c < 3; ++c) __builtin_nontemporal_store((float)dmu[c], out.means + c * n + g);
+    for (int c = 0; c < 3; ++c) __builtin_nontemporal_store((float)ds[c], out.scales + c * n + g);
+    for (int c = 0; c < 4; ++c) __builtin_nontemporal_store((float)((dq[c] - qh[c] * dot) / qn), out.quats + c * n + g);
     // dop is the gradient with respect to o (1 - do)
-    out.opac[g] = (float)(gp.app ? dop * (1.0 - (double)app.w) : dop);
+    __builtin_nontemporal_store((float)(gp.app ? dop * (1.0 - (double)app.w) : dop), out.opac + g);
     if (out.app) reinterpret_cast<float4*>(out.app)[g] = make_float4(dcb0, dcb1, dcb2, (float)(-dop * o_raw));
 }
 
@@ -299,8 +299,11 @@ __global__ __launch_bounds__(kPB) void k_project_bwd(GaussPtrs gp, int64_t n, Vi
                     ay = g2[11];
                     vis |= 1u << v;
                 }
-                mean2d_norm[slot] = nrm;
-                if (absgrad) reinterpret_cast<float2*>(absgrad)[slot] = make_float2(ax, ay);
+                __builtin_nontemporal_store(nrm, mean2d_norm + slot);
+                if (absgrad) {
+                    __builtin_nontemporal_store(ax, absgrad + 2 * slot);
+                    __builtin_nontemporal_store(ay, absgrad + 2 * slot + 1);
+                }
             }
             if (!vis) {
                 // streaming stores: the zero rows are not read again here
