@@ -28,7 +28,7 @@ METRIC = "train fwd+bwd iters/s & render Mpix/s, 6M Gaussians 1080p; p50/p99 ser
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3     # MI355X vector FP32 (2 flops per FMA lane, dual issue)
 
-# Algorithmic cost models (documented in the design doc):
+# Algorithmic cost models:
 # FP32 flops per compositing evaluation (an FMA counts 2, exp2 counts 1):
 #   forward: dx, dy (2) + 3 products (3) + 2 FMA (4) + exp2 (1) + o'G (1)
 #            + T(1 - a) (2) + a T (1) + 4 FMA blends (8)              = 22
@@ -96,8 +96,8 @@ def stage_bytes(n, n_front, n_vis, n_pairs, n_pix, n_views=1):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path. "
-              "How the path would shard is described in DESIGN.md.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the library has no multi-GPU path.",
+              file=sys.stderr)
         sys.exit(2)
 
     if args.copy_probe:

@@ -1,6 +1,6 @@
 """Parity of the HIP path (through the C ABI) with the FP64 oracle.
 
-Tolerances (derived in the design doc):
+Tolerances (from the float32 arithmetic of each stage):
   projection: mean2d |d| <= 1e-4 px; conic, opacity', depth, rgb relative
       <= 2e-6 (FP64 arithmetic rounded once to FP32);
   tile rectangles and counts: equal, except Gaussians whose extent or mean
