@@ -34,9 +34,10 @@ __global__ __launch_bounds__(kLossThreads) void k_loss_partial(const float* __re
     const float g_rgb = (float)inv3, g_d = (float)(lambda * inv1);
     double acc = 0.0;
     const int64_t p0 = (int64_t)blockIdx.x * kLossSpan;
+#pragma unroll
     for (int i = 0; i < kLossPerThread; ++i) {
         const int64_t p = p0 + i * kLossThreads + threadIdx.x;
-        if (p >= n_pix) break;
+        if (p >= n_pix) continue;     // predicated: the items' loads are independent
         float l_rgb = 0.0f;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
