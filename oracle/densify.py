@@ -110,10 +110,10 @@ def filter_rate(means, cams):
         cx, cy = float(np.float32(c.cx)), float(np.float32(c.cy))
         W, H = c.width, c.height
         with np.errstate(divide="ignore", invalid="ignore"):
-            u, v = t[0] / z, t[1] / z
+            # x / z within the widened image, compared as products (z > 0 there)
             ok = (z >= float(np.float32(c.near))) & (z <= float(np.float32(c.far)))
-            ok &= (u >= (-cx - 0.15 * W) / fx) & (u <= (W - cx + 0.15 * W) / fx)
-            ok &= (v >= (-cy - 0.15 * H) / fy) & (v <= (H - cy + 0.15 * H) / fy)
+            ok &= (t[0] >= -(cx + 0.15 * W) / fx * z) & (t[0] <= (W - cx + 0.15 * W) / fx * z)
+            ok &= (t[1] >= -(cy + 0.15 * H) / fy * z) & (t[1] <= (H - cy + 0.15 * H) / fy * z)
             r = np.where(ok, fx / z, 0.0)
         rate = np.maximum(rate, r)
     return rate

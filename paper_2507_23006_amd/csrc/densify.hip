@@ -128,8 +128,9 @@ __global__ __launch_bounds__(kDT) void k_filter_rate(const float* __restrict__ m
         if (!(tz >= (double)V.znear && tz <= (double)V.zfar)) continue;
         const double tx = (double)V.R[0] * m0 + (double)V.R[1] * m1 + (double)V.R[2] * m2 + (double)V.t[0];
         const double ty = (double)V.R[3] * m0 + (double)V.R[4] * m1 + (double)V.R[5] * m2 + (double)V.t[1];
-        const double u = tx / tz, w = ty / tz;
-        if (u >= V.ulo && u <= V.uhi && w >= V.vlo && w <= V.vhi) best = fmax(best, (double)V.fx / tz);
+        // x / z within [ulo, uhi] as products (z >= near > 0): one division per camera
+        if (tx >= V.ulo * tz && tx <= V.uhi * tz && ty >= V.vlo * tz && ty <= V.vhi * tz)
+            best = fmax(best, (double)V.fx / tz);
     }
     const float r = (float)best;
     rate[i] = accumulate ? fmaxf(rate[i], r) : r;
