@@ -3,11 +3,12 @@
 //
 // Radix pass = three launches (reduce-then-scan, no inter-workgroup
 // waiting, so no kernel can hang on a missing predecessor):
-//   1. upsweep: each workgroup counts the digits of its 4096-key tile;
+//   1. upsweep: each workgroup counts the digits of its tile (1024 or 2048
+//      keys);
 //      counts go to a digit-major table hist[digit][tile];
 //   2. the table is exclusive-scanned in digit-major order, which yields
 //      the global output offset of every (digit, tile);
-//   3. downsweep: each wave64 ranks its 1024 keys in 16 rounds of 64 with
+//   3. downsweep: each wave64 ranks its keys in rounds of 64 with
 //      ballot-based digit matching (lanes with equal digits find each other
 //      through one __ballot per digit bit; rank = popcount of lower peers),
 //      keeping per-wave running digit counters in LDS.  Keys and values are
@@ -22,10 +23,12 @@ namespace gs {
 namespace {
 
 constexpr int kSortThreads = 256;
-constexpr int kSortIpt = 16;                        // items per thread
-constexpr int kSortTile = kSortThreads * kSortIpt;  // 4096 keys per workgroup
-constexpr int kWaveItems = 64 * kSortIpt;           // 1024 keys per wave
 constexpr int kMaxRadixBits = 8;
+// Keys per workgroup: small sorts take 4 per thread (1024 per workgroup),
+// so that a sort of ~1M keys still spreads over ~1000 workgroups; larger
+// ones take 8 (fewer digit-table entries to scan).
+constexpr uint32_t kSmallSortMax = 1u << 21;
+constexpr int kMinSortTile = kSortThreads * 4;      // digit tables are sized for this
 
 __device__ __forceinline__ unsigned long long lanemask_lt() {
     const unsigned lane = __lane_id();
@@ -44,9 +47,11 @@ __device__ __forceinline__ unsigned long long match_digit(uint32_t digit, bool v
     return m;
 }
 
+template <int kSortIpt>
 __global__ __launch_bounds__(kSortThreads) void k_radix_upsweep(const uint32_t* __restrict__ keys, uint32_t n,
                                                                 int shift, int bits, uint32_t* __restrict__ hist,
                                                                 uint32_t n_tiles) {
+    constexpr int kSortTile = kSortThreads * kSortIpt, kWaveItems = 64 * kSortIpt;
     __shared__ uint32_t cnt[4][1 << kMaxRadixBits];
     const int radix = 1 << bits;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -67,10 +72,12 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_upsweep(const uint32_t* 
         hist[(size_t)d * n_tiles + blockIdx.x] = cnt[0][d] + cnt[1][d] + cnt[2][d] + cnt[3][d];
 }
 
+template <int kSortIpt>
 __global__ __launch_bounds__(kSortThreads) void k_radix_downsweep(
     const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
     uint32_t* __restrict__ vout, uint32_t n, int shift, int bits, const uint32_t* __restrict__ hist_scan,
     uint32_t n_tiles) {
+    constexpr int kSortTile = kSortThreads * kSortIpt, kWaveItems = 64 * kSortIpt;
     __shared__ uint32_t s_keys[kSortTile];
     __shared__ uint32_t s_vals[kSortTile];
     __shared__ uint32_t s_wcnt[4][1 << kMaxRadixBits];
@@ -272,7 +279,8 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t v, size_t n) {
 }  // namespace
 
 size_t radix_hist_elems(uint32_t n) {
-    const size_t tiles = (n + kSortTile - 1) / kSortTile;
+    // sized for the smallest tile, so that the size grows with n
+    const size_t tiles = (n + kMinSortTile - 1) / kMinSortTile;
     return (tiles ? tiles : 1) * (size_t)(1 << kMaxRadixBits) + scan_tmp_elems((uint32_t)(tiles * 256));
 }
 
@@ -314,7 +322,9 @@ hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, 
     if (n <= 1 || end_bit <= begin_bit) return hipSuccess;
     const int total_bits = end_bit - begin_bit;
     const int passes = (total_bits + kMaxRadixBits - 1) / kMaxRadixBits;
-    const uint32_t tiles = (n + kSortTile - 1) / kSortTile;
+    const bool small = n <= kSmallSortMax;
+    const uint32_t sort_tile = (uint32_t)kSortThreads * (small ? 4u : 8u);
+    const uint32_t tiles = (n + sort_tile - 1) / sort_tile;
     const size_t hist_elems = (size_t)tiles * (1 << kMaxRadixBits);
     uint32_t* scan_tmp = hist + hist_elems;
     unsigned long long* total = reinterpret_cast<unsigned long long*>(scan_tmp + scan_sums_elems((uint32_t)hist_elems));
@@ -324,11 +334,20 @@ hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, 
         const int remaining = end_bit - shift;
         const int bits = (remaining + (passes - p) - 1) / (passes - p);
         const uint32_t radix_elems = (uint32_t)tiles << bits;
-        hipLaunchKernelGGL(k_radix_upsweep, dim3(tiles), dim3(kSortThreads), 0, s, ki, n, shift, bits, hist, tiles);
+        if (small)
+            hipLaunchKernelGGL(k_radix_upsweep<4>, dim3(tiles), dim3(kSortThreads), 0, s, ki, n, shift, bits, hist,
+                               tiles);
+        else
+            hipLaunchKernelGGL(k_radix_upsweep<8>, dim3(tiles), dim3(kSortThreads), 0, s, ki, n, shift, bits, hist,
+                               tiles);
         hipError_t e = exclusive_scan_u32(hist, hist, radix_elems, scan_tmp, total, s);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_radix_downsweep, dim3(tiles), dim3(kSortThreads), 0, s, ki, vi, ko, vo, n, shift, bits,
-                           hist, tiles);
+        if (small)
+            hipLaunchKernelGGL(k_radix_downsweep<4>, dim3(tiles), dim3(kSortThreads), 0, s, ki, vi, ko, vo, n, shift,
+                               bits, hist, tiles);
+        else
+            hipLaunchKernelGGL(k_radix_downsweep<8>, dim3(tiles), dim3(kSortThreads), 0, s, ki, vi, ko, vo, n, shift,
+                               bits, hist, tiles);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
         shift += bits;
