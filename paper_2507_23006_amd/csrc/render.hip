@@ -139,8 +139,8 @@ __device__ __forceinline__ unsigned long long lanes_below(int lane) {
 
 struct WaveStage {
     float4 g[kChunk];      // tile-relative mean, qa, qb
-    float4 b[kChunk];      // qc, opacity', depth, -
-    float4 c[kChunk];      // r, g, b, -
+    float4 b[kChunk];      // qc, opacity', depth, 2 qc
+    float4 c[kChunk];      // r, g, b, 2 qa
     int pos[kChunk];       // 1-based position in the tile list
     uint32_t slot[kChunk];
 };
@@ -232,8 +232,8 @@ __device__ __forceinline__ int stage_gathered(const Gather& e, int pos, const Pi
     if (hit) {
         const int d = __popcll(m & lanes_below(lane));
         st.g[d] = g;
-        st.b[d] = e.r1;
-        st.c[d] = e.r2;
+        st.b[d] = make_float4(e.r1.x, e.r1.y, e.r1.z, 2.0f * e.r1.x);
+        st.c[d] = make_float4(e.r2.x, e.r2.y, e.r2.z, 2.0f * g.z);
         st.pos[d] = pos;
         st.slot[d] = e.slot;
     }
@@ -345,7 +345,10 @@ __device__ __forceinline__ float row_total_lane15(float x) {
     x += __builtin_amdgcn_update_dpp(0.0f, x, 0x111, 0xf, 0xf, false);   // row_shr:1
     x += __builtin_amdgcn_update_dpp(0.0f, x, 0x112, 0xf, 0xf, false);   // row_shr:2
     x += __builtin_amdgcn_update_dpp(0.0f, x, 0x114, 0xf, 0xf, false);   // row_shr:4
-    x += __builtin_amdgcn_update_dpp(0.0f, x, 0x118, 0xf, 0xf, false);   // row_shr:8
+    x += __builtin_amdgcn_update_dpp(0.0f, x, 0x128, 0xf, 0xf, false);   // row_ror:8 (lane 15 + lane 7)
+    // keeps the last add beside its DPP move (one v_add_f32_dpp) rather than
+    // sunk into the caller's lane-15 branch; emits no instruction
+    __asm__ volatile("" : "+v"(x));
     return x;
 }
 
@@ -375,11 +378,24 @@ __device__ __forceinline__ void wave_sum12(const float v[12], float out[3]) {
 
 constexpr int kG2 = GS_GRAD2D_FLOATS;   // per-slot 2D gradient fields
 
+// Per-field factors applied once per entry, after the wave sum: the lanes
+// sum dp (2 qa dx + qb dy), dp (qb dx + 2 qc dy), dp dx^2, dp dx dy, dp dy^2
+// and the absolute values of the first two (dp = dL/d of the exponent in
+// natural-log units), whose products with -ln2, -ln2, -1/2, -1, -1/2, ln2,
+// ln2 are the gradients of the mean, of the conic (A, B, C) and the AbsGS
+// sums.
+__device__ __forceinline__ float grad2d_field_scale(int f) {
+    return f < 2 ? -kLn2 : (f == 2 || f == 4) ? -0.5f : f == 3 ? -1.0f : f >= 10 ? kLn2 : 1.0f;
+}
+
 // Backward: each wave walks its quadrant's list back to front from the
 // deepest `last` of its pixels, in chunks staged and culled as in the
 // forward.  Per surviving entry the lanes' gradients are summed by
 // wave_sum12 into a per-wave LDS row; after each chunk the wave adds the rows to the
 // per-slot 2D gradient buffer with float atomics (zeros skipped).
+// The colour and depth behind an entry enter the gradient only through
+// their dot product with the pixel's upstream gradient, so the walk carries
+// that one scalar, S = g_rgb . R_rgb + g_depth R_depth, instead of R itself.
 __global__ __launch_bounds__(256) void k_render_bwd(const float4* __restrict__ rec,
                                                     const uint32_t* __restrict__ pair_vals,
                                                     const uint2* __restrict__ ranges,
@@ -428,15 +444,16 @@ __global__ __launch_bounds__(256) void k_render_bwd(const float4* __restrict__ r
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) maxlast = max(maxlast, __shfl_xor(maxlast, off, 64));
 
-    // R = remaining colour behind the entry divided by T after it; starts at bg
-    float R0 = opt.bg[0], R1 = opt.bg[1], R2 = opt.bg[2], RD = 0.0f, Q = 1.0f;
-    const float ln2 = kLn2;
+    // R = remaining colour behind the entry divided by T after it (starts at
+    // bg); the walk keeps S = g . R
+    float S = fmaf(gC0, opt.bg[0], fmaf(gC1, opt.bg[1], gC2 * opt.bg[2])), Q = 1.0f;
 
     // A segmented list: this workgroup walks segment `seg` (positions
     // (seg S, (seg + 1) S]); the state behind it comes from folding the later
     // segments' transmittance and local colour, written by k_seg_prepass:
-    // R <- C_j + T_j R, T <- T / T_j, Q <- Q T_j (segments starting at or
-    // after the pixel's last composited entry are the identity).
+    // R <- C_j + T_j R (so S <- g . C_j + T_j S), T <- T / T_j, Q <- Q T_j
+    // (segments starting at or after the pixel's last composited entry are
+    // the identity).
     int lo = 0, hi = maxlast;
     if (nseg > 1) {
         const int px = pc.ly * kTile + pc.lx;
@@ -444,10 +461,9 @@ __global__ __launch_bounds__(256) void k_render_bwd(const float4* __restrict__ r
             if (j * kSegLen >= last) continue;
             const float* sj = plan.state + (size_t)(st0 + (uint32_t)(j - 1)) * kSegFields * 256;
             const float Ts = sj[0 * 256 + px];
-            R0 = fmaf(Ts, R0, sj[1 * 256 + px]);
-            R1 = fmaf(Ts, R1, sj[2 * 256 + px]);
-            R2 = fmaf(Ts, R2, sj[3 * 256 + px]);
-            RD = fmaf(Ts, RD, sj[4 * 256 + px]);
+            const float gcs = fmaf(gC0, sj[1 * 256 + px],
+                                   fmaf(gC1, sj[2 * 256 + px], fmaf(gC2, sj[3 * 256 + px], gD * sj[4 * 256 + px])));
+            S = fmaf(Ts, S, gcs);
             T = T / Ts;
             Q = Q * Ts;
         }
@@ -473,31 +489,32 @@ __global__ __launch_bounds__(256) void k_render_bwd(const float4* __restrict__ r
             const int pos = st.pos[k];        // 1-based
             const Eval e = eval_entry(a, b, pc.fpx, pc.fpy);
             const bool con = pos <= last && e.keep;
-            const float one_m = 1.0f - e.alpha;
+            // an entry the pixel did not composite takes alpha = 0, which
+            // leaves S and Q unchanged exactly (x 1, + 0)
+            const float al = con ? e.alpha : 0.0f;
+            const float one_m = 1.0f - al;
             const float Ti = T * __builtin_amdgcn_rcpf(one_m);
+            const float gc = fmaf(gC0, c.x, fmaf(gC1, c.y, fmaf(gC2, c.z, gD * b.z)));   // g . (colour, depth)
+            const float dal = Ti * fmaf(gA, Q, gc - S);
+            const float w = al * Ti;
             float g[kG2];
-            const float w = con ? e.alpha * Ti : 0.0f;
-            const float dal = Ti * (gC0 * (c.x - R0) + gC1 * (c.y - R1) + gC2 * (c.z - R2) + gD * (b.z - RD) + gA * Q);
             g[6] = gC0 * w;
             g[7] = gC1 * w;
             g[8] = gC2 * w;
             g[9] = gD * w;
             const float dal_u = (con && e.raw < kAlphaMax) ? dal : 0.0f;
             g[5] = dal_u * e.G;
-            const float dp = dal_u * e.alpha;          // dL/d power
-            // conic (A, B, C) = -ln2 (2 qa, qb, 2 qc)
-            g[0] = -dp * ln2 * (2.0f * a.z * e.dx + a.w * e.dy);
-            g[1] = -dp * ln2 * (a.w * e.dx + 2.0f * b.x * e.dy);
-            g[2] = -0.5f * e.dx * e.dx * dp;
-            g[3] = -e.dx * e.dy * dp;
-            g[4] = -0.5f * e.dy * e.dy * dp;
+            const float dp = dal_u * al;               // dL/d power (natural-log units)
+            const float dpx = dp * e.dx, dpy = dp * e.dy;
+            g[0] = fmaf(c.w, dpx, a.w * dpy);         // dp (2 qa dx + qb dy)
+            g[1] = fmaf(a.w, dpx, b.w * dpy);         // dp (qb dx + 2 qc dy)
+            g[2] = dpx * e.dx;
+            g[3] = dpx * e.dy;
+            g[4] = dpy * e.dy;
             g[10] = fabsf(g[0]);
             g[11] = fabsf(g[1]);
-            R0 = con ? fmaf(R0, one_m, c.x * e.alpha) : R0;
-            R1 = con ? fmaf(R1, one_m, c.y * e.alpha) : R1;
-            R2 = con ? fmaf(R2, one_m, c.z * e.alpha) : R2;
-            RD = con ? fmaf(RD, one_m, b.z * e.alpha) : RD;
-            Q = con ? Q * one_m : Q;
+            S = fmaf(S, one_m, gc * al);
+            Q *= one_m;
             T = con ? Ti : T;
             if (__ballot(con)) {
                 float tot[3];
@@ -517,7 +534,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(const float4* __restrict__ r
         for (int i = lane; i < n * kG2; i += 64) {
             const int k = i / kG2, f = i - k * kG2;
             const float sum = s_red[wave][k][f];
-            if (sum != 0.0f) atomicAdd(&grad2d[(size_t)st.slot[k] * kG2 + f], sum);
+            if (sum != 0.0f) atomicAdd(&grad2d[(size_t)st.slot[k] * kG2 + f], sum * grad2d_field_scale(f));
         }
         __builtin_amdgcn_wave_barrier();
     }
