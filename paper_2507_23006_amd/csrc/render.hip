@@ -195,7 +195,10 @@ __device__ __forceinline__ int order_tile(const uint32_t* __restrict__ tile_orde
 
 // One lane's list entry, loaded a chunk ahead of its use so that the two
 // dependent gathers (pair value, then record) overlap the evaluation of the
-// previous chunk instead of stalling the wave.
+// previous chunk instead of stalling the wave.  Staging marks the fourth
+// record's unused lanes (z, w) as read: registers of a pending load that
+// the compiler sees as dead get reused as temporaries, which makes the wave
+// wait for the load at once.
 struct Gather {
     float4 r0, r1, r2, r3;
     uint32_t slot;
@@ -225,6 +228,7 @@ __device__ __forceinline__ Gather load_entry(const float4* __restrict__ rec, uin
 // pos = the lane's 1-based position in the tile list.  Wave-uniform result.
 __device__ __forceinline__ int stage_gathered(const Gather& e, int pos, const PixelCoords& pc, int lane,
                                               WaveStage& st) {
+    __asm__ volatile("" ::"v"(e.r3.z), "v"(e.r3.w));   // emits no instruction
     const float4 g = stage_geom(e.r0, e.r1, e.r2, pc.ox, pc.oy);
     const bool hit = e.slot != kNoSlot && box_hits_quadrant(g, e.r3, pc.qcx, pc.qcy) &&
                      ellipse_hits_quadrant(g, e.r1, pc.qcx, pc.qcy);
@@ -477,11 +481,27 @@ __global__ __launch_bounds__(256) void k_render_bwd(const float4* __restrict__ r
         const int b_start_ = max(lo, b_end_ - kChunk);
         return b_end_ > lo ? load_slot(pair_vals, rg.x + (uint32_t)(b_start_ + lane), rg.x + (uint32_t)b_end_) : kNoSlot;
     };
+    // adds chunk sums of the last staged chunk (n entries) to grad2d
+    auto flush = [&](int n_) {
+        for (int i = lane; i < n_ * kG2; i += 64) {
+            const int k = i / kG2, f = i - k * kG2;
+            const float sum = s_red[wave][k][f];
+            if (sum != 0.0f) atomicAdd(&grad2d[(size_t)st.slot[k] * kG2 + f], sum * grad2d_field_scale(f));
+        }
+        __builtin_amdgcn_wave_barrier();
+    };
     Gather cur = load_entry(rec, chunk_slot(hi));
     uint32_t s_next = chunk_slot(hi - kChunk);
+    int n_prev = 0;
     for (int b_end = hi; b_end > lo; b_end -= kChunk) {
         const int b_start = max(lo, b_end - kChunk);
+        // Wait for this chunk's records here, then issue the previous
+        // chunk's atomics: loads and atomics share one in-order counter, so
+        // atomics issued before the wait would be waited for as well.
+        __asm__ volatile("" ::"v"(cur.r0.x), "v"(cur.r1.x), "v"(cur.r2.x), "v"(cur.r3.x), "v"(s_next));
+        flush(n_prev);
         const int n = stage_gathered(cur, b_start + lane + 1, pc, lane, st);
+        n_prev = n;
         cur = load_entry(rec, s_next);
         s_next = chunk_slot(b_end - 2 * kChunk);
         for (int k = n - 1; k >= 0; --k) {
@@ -531,13 +551,8 @@ __global__ __launch_bounds__(256) void k_render_bwd(const float4* __restrict__ r
             }
         }
         __builtin_amdgcn_wave_barrier();
-        for (int i = lane; i < n * kG2; i += 64) {
-            const int k = i / kG2, f = i - k * kG2;
-            const float sum = s_red[wave][k][f];
-            if (sum != 0.0f) atomicAdd(&grad2d[(size_t)st.slot[k] * kG2 + f], sum * grad2d_field_scale(f));
-        }
-        __builtin_amdgcn_wave_barrier();
     }
+    flush(n_prev);
 }
 
 // exclusive scan of v over the 1024 threads of the workgroup; *total gets the sum
