@@ -269,24 +269,32 @@ __global__ __launch_bounds__(256) void k_render_fwd(const float4* __restrict__ r
         const int n = stage_gathered(cur, (int)(j0 - rg.x) + lane + 1, pc, lane, st);
         cur = load_entry(rec, s_next);                                   // next chunk's records
         s_next = load_slot(pair_vals, j0 + 2 * kChunk + lane, rg.y);     // and the one after's slots
-#pragma unroll 4
+        // entry k + 1 is read from LDS while entry k is evaluated; the
+        // position of the pixel's last composited entry is read once per chunk
+        int last_k = -1;
+        float4 an = st.g[0], bn = st.b[0], cn = st.c[0];
+#pragma unroll 2
         for (int k = 0; k < n; ++k) {
-            const float4 a = st.g[k], b = st.b[k];
+            const float4 a = an, b = bn, c = cn;
+            const int kn = k + 1 < n ? k + 1 : k;
+            an = st.g[kn];
+            bn = st.b[kn];
+            cn = st.c[kn];
             const Eval e = eval_entry(a, b, pc.fpx, pc.fpy);
             const float Tn = T * (1.0f - e.alpha);
             const bool keep = alive && e.keep;
             const bool stop = keep && Tn < kTMin;
             const bool use = keep && !stop;
             const float w = use ? e.alpha * T : 0.0f;
-            const float4 c = st.c[k];
             c0 = fmaf(c.x, w, c0);
             c1 = fmaf(c.y, w, c1);
             c2 = fmaf(c.z, w, c2);
             D = fmaf(b.z, w, D);
             T = use ? Tn : T;
-            last = use ? st.pos[k] : last;
+            last_k = use ? k : last_k;
             alive = alive && !stop;
         }
+        if (last_k >= 0) last = st.pos[last_k];
         __builtin_amdgcn_wave_barrier();     // the chunk is consumed before the next one is staged
     }
     if (!pc.inside) return;
