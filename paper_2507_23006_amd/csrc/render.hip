@@ -141,8 +141,8 @@ struct WaveStage {
     float4 g[kChunk];      // tile-relative mean, qa, qb
     float4 b[kChunk];      // qc, opacity', depth, 2 qc
     float4 c[kChunk];      // r, g, b, 2 qa
-    int pos[kChunk];       // 1-based position in the tile list
-    uint32_t slot[kChunk];
+    int4 ps[kChunk];       // 1-based position in the tile list, slot, -, - (16-byte stride like the
+                           // records, so one address register serves every per-entry read)
 };
 
 // Gathers list entries [j0, j0 + 64) of the tile (clipped to `end`), keeps
@@ -170,8 +170,7 @@ __device__ __forceinline__ int stage_chunk(const float4* __restrict__ rec, const
         st.g[d] = g;
         st.b[d] = r1;
         st.c[d] = r2;
-        st.pos[d] = (int)(j - list0) + 1;
-        st.slot[d] = s;
+        st.ps[d] = make_int4((int)(j - list0) + 1, (int)s, 0, 0);
     }
     __builtin_amdgcn_wave_barrier();
     return __popcll(m);
@@ -238,8 +237,7 @@ __device__ __forceinline__ int stage_gathered(const Gather& e, int pos, const Pi
         st.g[d] = g;
         st.b[d] = make_float4(e.r1.x, e.r1.y, e.r1.z, 2.0f * e.r1.x);
         st.c[d] = make_float4(e.r2.x, e.r2.y, e.r2.z, 2.0f * g.z);
-        st.pos[d] = pos;
-        st.slot[d] = e.slot;
+        st.ps[d] = make_int4(pos, (int)e.slot, 0, 0);
     }
     __builtin_amdgcn_wave_barrier();
     return __popcll(m);
@@ -294,7 +292,7 @@ __global__ __launch_bounds__(256) void k_render_fwd(const float4* __restrict__ r
             last_k = use ? k : last_k;
             alive = alive && !stop;
         }
-        if (last_k >= 0) last = st.pos[last_k];
+        if (last_k >= 0) last = st.ps[last_k].x;
         __builtin_amdgcn_wave_barrier();     // the chunk is consumed before the next one is staged
     }
     if (!pc.inside) return;
@@ -330,7 +328,7 @@ __global__ __launch_bounds__(256) void k_render_count(const float4* __restrict__
         if (__ballot(alive) == 0) break;
         const int n = stage_chunk(rec, pair_vals, rg.x, j0, rg.y, pc, lane, st);
         if (lane < n) {
-            const float4 r3 = rec[4 * (size_t)st.slot[lane] + 3];
+            const float4 r3 = rec[4 * (size_t)(uint32_t)st.ps[lane].y + 3];
             sbox[wave][lane] = make_float2(r3.x, r3.y);
         }
         __builtin_amdgcn_wave_barrier();
@@ -494,7 +492,8 @@ __global__ __launch_bounds__(256) void k_render_bwd(const float4* __restrict__ r
         for (int i = lane; i < n_ * kG2; i += 64) {
             const int k = i / kG2, f = i - k * kG2;
             const float sum = s_red[wave][k][f];
-            if (sum != 0.0f) atomicAdd(&grad2d[(size_t)st.slot[k] * kG2 + f], sum * grad2d_field_scale(f));
+            if (sum != 0.0f)
+                atomicAdd(&grad2d[(size_t)(uint32_t)st.ps[k].y * kG2 + f], sum * grad2d_field_scale(f));
         }
         __builtin_amdgcn_wave_barrier();
     };
@@ -514,7 +513,10 @@ __global__ __launch_bounds__(256) void k_render_bwd(const float4* __restrict__ r
         s_next = chunk_slot(b_end - 2 * kChunk);
         for (int k = n - 1; k >= 0; --k) {
             const float4 a = st.g[k], b = st.b[k], c = st.c[k];
-            const int pos = st.pos[k];        // 1-based
+            // whole-record reads at the entry's one LDS address (b.w and c.w
+            // are used only under the ballot below); emits no instruction
+            __asm__ volatile("" ::"v"(b.w), "v"(c.w));
+            const int pos = st.ps[k].x;       // 1-based
             const Eval e = eval_entry(a, b, pc.fpx, pc.fpy);
             const bool con = pos <= last && e.keep;
             // an entry the pixel did not composite takes alpha = 0, which
@@ -544,18 +546,18 @@ __global__ __launch_bounds__(256) void k_render_bwd(const float4* __restrict__ r
             S = fmaf(S, one_m, gc * al);
             Q *= one_m;
             T = con ? Ti : T;
+            // lane 16 r + 15 writes fields 3 r .. 3 r + 2 of the entry's row
+            float* row = &s_red[wave][k][3 * (lane >> 4)];
             if (__ballot(con)) {
                 float tot[3];
                 wave_sum12(g, tot);
                 if ((lane & 15) == 15) {
-                    const int f0 = 3 * (lane >> 4);
-                    s_red[wave][k][f0 + 0] = tot[0];
-                    s_red[wave][k][f0 + 1] = tot[1];
-                    s_red[wave][k][f0 + 2] = tot[2];
+                    row[0] = tot[0];
+                    row[1] = tot[1];
+                    row[2] = tot[2];
                 }
-            } else if (lane == 0) {
-#pragma unroll
-                for (int f = 0; f < kG2; ++f) s_red[wave][k][f] = 0.0f;
+            } else if ((lane & 15) == 15) {
+                row[0] = row[1] = row[2] = 0.0f;
             }
         }
         __builtin_amdgcn_wave_barrier();
@@ -665,7 +667,7 @@ __global__ __launch_bounds__(256) void k_seg_prepass(const float4* __restrict__ 
         for (int k = 0; k < n; ++k) {
             const float4 a = st.g[k], bb = st.b[k], c = st.c[k];
             const Eval ev = eval_entry(a, bb, pc.fpx, pc.fpy);
-            const bool con = st.pos[k] <= last && ev.keep;
+            const bool con = st.ps[k].x <= last && ev.keep;
             const float w = con ? ev.alpha * T : 0.0f;
             c0 = fmaf(c.x, w, c0);
             c1 = fmaf(c.y, w, c1);
