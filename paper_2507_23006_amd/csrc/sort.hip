@@ -203,43 +203,27 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint32_t* __
     if (threadIdx.x == 0) tsum[blockIdx.x] = s_w[0] + s_w[1] + s_w[2] + s_w[3];
 }
 
-// exclusive scan of the tile sums in place (one workgroup), 64-bit total
-__global__ __launch_bounds__(1024) void k_scan_top(uint32_t* __restrict__ tsum, uint32_t nt,
-                                                   unsigned long long* __restrict__ total) {
-    __shared__ unsigned long long s_w[16];
-    __shared__ unsigned long long s_carry;
-    if (threadIdx.x == 0) s_carry = 0;
-    __syncthreads();
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (uint32_t c0 = 0; c0 < nt; c0 += 1024) {
-        const uint32_t idx = c0 + threadIdx.x;
-        const unsigned long long x = idx < nt ? tsum[idx] : 0ull;
-        unsigned long long incl = x;
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const unsigned long long y = __shfl_up(incl, off, 64);
-            if (lane >= off) incl += y;
-        }
-        if (lane == 63) s_w[wave] = incl;
-        __syncthreads();
-        unsigned long long pre = s_carry;
-        for (int w = 0; w < wave; ++w) pre += s_w[w];
-        if (idx < nt) tsum[idx] = (uint32_t)(pre + incl - x);
-        __syncthreads();
-        if (threadIdx.x == 1023) s_carry = pre + incl;
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) *total = s_carry;
-}
-
 // per-tile exclusive scan plus the tile's offset; items are blocked per
-// thread (16 consecutive) so that the in-thread prefix is sequential
+// thread (16 consecutive) so that the in-thread prefix is sequential.  The
+// tile's offset is the sum of the earlier tiles' sums, which every
+// workgroup adds up itself (64-bit, at most a few thousand values) rather
+// than waiting for a separate one-workgroup launch; the last workgroup
+// writes the 64-bit total.
 __global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t* __restrict__ in,
                                                             uint32_t* __restrict__ out, uint32_t n,
-                                                            const uint32_t* __restrict__ tsum) {
+                                                            const uint32_t* __restrict__ tsum,
+                                                            unsigned long long* __restrict__ total) {
     __shared__ uint32_t s_buf[kScanTile];
     __shared__ uint32_t s_w[4];
+    __shared__ unsigned long long s_off[4];
     const uint32_t base = blockIdx.x * kScanTile;
+    {
+        unsigned long long acc = 0;
+        for (uint32_t t = threadIdx.x; t < blockIdx.x; t += kScanThreads) acc += tsum[t];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+        if ((threadIdx.x & 63) == 0) s_off[threadIdx.x >> 6] = acc;
+    }
 #pragma unroll
     for (int r = 0; r < kScanIpt; ++r) {
         const uint32_t i = r * kScanThreads + threadIdx.x;
@@ -256,7 +240,9 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t* __re
     const uint32_t incl = wave_incl_scan(acc);
     if ((threadIdx.x & 63) == 63) s_w[threadIdx.x >> 6] = incl;
     __syncthreads();
-    uint32_t pre = tsum[blockIdx.x] + incl - acc;
+    const unsigned long long tile_off = s_off[0] + s_off[1] + s_off[2] + s_off[3];
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *total = tile_off + tsum[blockIdx.x];
+    uint32_t pre = (uint32_t)tile_off + incl - acc;
     for (int w = 0; w < (int)(threadIdx.x >> 6); ++w) pre += s_w[w];
 #pragma unroll
     for (int r = 0; r < kScanIpt; ++r) {
@@ -308,8 +294,7 @@ hipError_t exclusive_scan_u32(const uint32_t* in, uint32_t* out, uint32_t n, uin
         return hipGetLastError();
     }
     hipLaunchKernelGGL(k_scan_reduce, dim3(nt), dim3(kScanThreads), 0, s, in, n, tmp);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, tmp, nt, total);
-    hipLaunchKernelGGL(k_scan_down, dim3(nt), dim3(kScanThreads), 0, s, in, out, n, tmp);
+    hipLaunchKernelGGL(k_scan_down, dim3(nt), dim3(kScanThreads), 0, s, in, out, n, tmp, total);
     return hipGetLastError();
 }
 
