@@ -188,11 +188,10 @@ int bin_sort_slots(const Projected& pr, const ViewTable& vt, int64_t n_slots, in
     GS_REQUIRE(ws_bytes >= need, "workspace too small: %zu < %zu", ws_bytes, need);
     const uint32_t N = (uint32_t)n_slots;
 
-    // 1. visible slots in slot order (flags, scan, scatter) and the pair count
+    // 1. visible slots in slot order (scan of tiles > 0, scatter) and the pair count
     //    (sum of all tile counts); one read-back gives both sizes
     GS_HIP(fill_u32(reinterpret_cast<uint32_t*>(w.total), 0u, 2 * kTotals, s));
-    GS_HIP(launch_visible_flags(pr, N, w.tiles_s, w.total + 16, s));
-    GS_HIP(exclusive_scan_u32(w.tiles_s, w.offsets, N, w.scan_tmp, w.total, s));
+    GS_HIP(exclusive_scan_nonzero_u32(pr.tiles, w.offsets, N, w.scan_tmp, w.total, w.total + 16, s));
     GS_HIP(launch_compact_visible(pr, w.offsets, N, w.dkeys, w.dvals, w.desc, s));
     unsigned long long* host = pinned_scalar();
     if (!host) return fail(GS_ERR_HIP, "pinned host buffer unavailable");

@@ -13,29 +13,6 @@ namespace gs {
 
 namespace {
 
-// 1 for slots that cover a tile; the block sums of tiles add up to the pair
-// count, spread over kPairParts counters (one atomic address would serialise
-// thousands of workgroups from all XCDs); the counters must start at 0
-constexpr int kPairParts = 64;
-
-__global__ __launch_bounds__(256) void k_visible_flags(const uint32_t* __restrict__ tiles, uint32_t n,
-                                                       uint32_t* __restrict__ flags,
-                                                       unsigned long long* __restrict__ pair_parts) {
-    __shared__ unsigned long long s_sum[4];
-    const uint32_t i = blockIdx.x * 256 + threadIdx.x;
-    const uint32_t t = i < n ? tiles[i] : 0u;
-    if (i < n) flags[i] = t ? 1u : 0u;
-    unsigned long long v = t;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    if ((threadIdx.x & 63) == 0) s_sum[threadIdx.x >> 6] = v;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const unsigned long long b = s_sum[0] + s_sum[1] + s_sum[2] + s_sum[3];
-        if (b) atomicAdd(&pair_parts[16 * (blockIdx.x % kPairParts)], b);   // one 128-byte line each
-    }
-}
-
 // Visible slots, in slot order, with their depth keys: the input of the
 // depth sort (culled slots never enter it), whose values are the compaction
 // positions.  Each visible slot also leaves a 32-byte descriptor there
@@ -205,13 +182,6 @@ __global__ __launch_bounds__(kOrderThreads) void k_tile_order(const uint2* __res
 hipError_t launch_tile_order(const uint32_t* ranges, uint32_t n_tiles, uint32_t* order, hipStream_t s) {
     hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(kOrderThreads), 0, s, reinterpret_cast<const uint2*>(ranges),
                        n_tiles, order);
-    return hipGetLastError();
-}
-
-hipError_t launch_visible_flags(const Projected& proj, uint32_t n_slots, uint32_t* flags,
-                                unsigned long long* pair_parts, hipStream_t s) {
-    hipLaunchKernelGGL(k_visible_flags, dim3((n_slots + 255) / 256), dim3(256), 0, s, proj.tiles, n_slots, flags,
-                       pair_parts);
     return hipGetLastError();
 }
 

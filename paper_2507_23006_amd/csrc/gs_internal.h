@@ -152,15 +152,17 @@ hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, 
 size_t scan_tmp_elems(uint32_t n);
 hipError_t exclusive_scan_u32(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* tmp,
                               unsigned long long* total, hipStream_t s);
+// exclusive scan of (in[i] != 0); the sum of in[] itself is added to
+// sum_parts (kBinPairParts partial sums, 16 u64 apart, zeroed by the caller)
+hipError_t exclusive_scan_nonzero_u32(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* tmp,
+                                      unsigned long long* total, unsigned long long* sum_parts, hipStream_t s);
 hipError_t fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s);
 // zero the [12]-float 2D-gradient rows of slots with tiles > 0
 hipError_t zero_seen_grad2d(const uint32_t* tiles, float* grad2d, int64_t n_slots, hipStream_t s);
 
 // binning (bin.hip)
-// pair_parts: kBinPairParts partial pair counts, 16 u64 apart (zeroed by the caller)
+// pair counts are summed into kBinPairParts partial sums, 16 u64 apart
 constexpr int kBinPairParts = 64;
-hipError_t launch_visible_flags(const Projected& proj, uint32_t n_slots, uint32_t* flags,
-                                unsigned long long* pair_parts, hipStream_t s);
 // compaction of the visible slots: depth keys, their positions as sort
 // values, and per position a 32-byte descriptor (uint4 pair: rect.x, rect.y,
 // mask lo, mask hi; tiles, slot, 0, 0)

@@ -173,6 +173,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_downsweep(
 // ---------------------------------------------------------------- scan
 
 constexpr int kScanThreads = 256;
+constexpr int kScanSumParts = kBinPairParts;
 constexpr int kScanIpt = 16;
 constexpr int kScanTile = kScanThreads * kScanIpt;
 
@@ -187,20 +188,46 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
 }
 
 // tile sums
+// The scanned value of element i: in[i], or with kFlags, 1 where in[i] != 0.
+template <bool kFlags>
+__device__ __forceinline__ uint32_t scan_value(uint32_t x) {
+    return kFlags ? (x != 0u ? 1u : 0u) : x;
+}
+
+// Tile sums.  With kFlags the raw values are also summed (64-bit) into
+// kScanSumParts counters 16 apart (one atomic address would serialise
+// thousands of workgroups from all XCDs); the counters must start at 0.
+template <bool kFlags>
 __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint32_t* __restrict__ in, uint32_t n,
-                                                              uint32_t* __restrict__ tsum) {
+                                                              uint32_t* __restrict__ tsum,
+                                                              unsigned long long* __restrict__ raw_parts) {
     __shared__ uint32_t s_w[4];
+    __shared__ unsigned long long s_raw[4];
     const uint32_t base = blockIdx.x * kScanTile;
     uint32_t acc = 0;
+    unsigned long long raw = 0;
 #pragma unroll
     for (int r = 0; r < kScanIpt; ++r) {
         const uint32_t idx = base + r * kScanThreads + threadIdx.x;
-        if (idx < n) acc += in[idx];
+        const uint32_t x = idx < n ? in[idx] : 0u;
+        acc += scan_value<kFlags>(x);
+        if (kFlags) raw += x;
     }
     const uint32_t w = wave_incl_scan(acc);
     if ((threadIdx.x & 63) == 63) s_w[threadIdx.x >> 6] = w;
+    if (kFlags) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) raw += __shfl_xor(raw, off, 64);
+        if ((threadIdx.x & 63) == 0) s_raw[threadIdx.x >> 6] = raw;
+    }
     __syncthreads();
-    if (threadIdx.x == 0) tsum[blockIdx.x] = s_w[0] + s_w[1] + s_w[2] + s_w[3];
+    if (threadIdx.x == 0) {
+        tsum[blockIdx.x] = s_w[0] + s_w[1] + s_w[2] + s_w[3];
+        if (kFlags) {
+            const unsigned long long b = s_raw[0] + s_raw[1] + s_raw[2] + s_raw[3];
+            if (b) atomicAdd(&raw_parts[16 * (blockIdx.x % kScanSumParts)], b);   // one 128-byte line each
+        }
+    }
 }
 
 // per-tile exclusive scan plus the tile's offset; items are blocked per
@@ -209,6 +236,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint32_t* __
 // workgroup adds up itself (64-bit, at most a few thousand values) rather
 // than waiting for a separate one-workgroup launch; the last workgroup
 // writes the 64-bit total.
+template <bool kFlags>
 __global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t* __restrict__ in,
                                                             uint32_t* __restrict__ out, uint32_t n,
                                                             const uint32_t* __restrict__ tsum,
@@ -227,7 +255,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t* __re
 #pragma unroll
     for (int r = 0; r < kScanIpt; ++r) {
         const uint32_t i = r * kScanThreads + threadIdx.x;
-        s_buf[i] = (base + i < n) ? in[base + i] : 0u;
+        s_buf[i] = (base + i < n) ? scan_value<kFlags>(in[base + i]) : 0u;
     }
     __syncthreads();
     uint32_t v[kScanIpt];
@@ -293,8 +321,21 @@ hipError_t exclusive_scan_u32(const uint32_t* in, uint32_t* out, uint32_t n, uin
         hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, (uint32_t*)total, 0u, (size_t)2);
         return hipGetLastError();
     }
-    hipLaunchKernelGGL(k_scan_reduce, dim3(nt), dim3(kScanThreads), 0, s, in, n, tmp);
-    hipLaunchKernelGGL(k_scan_down, dim3(nt), dim3(kScanThreads), 0, s, in, out, n, tmp, total);
+    hipLaunchKernelGGL(k_scan_reduce<false>, dim3(nt), dim3(kScanThreads), 0, s, in, n, tmp,
+                       (unsigned long long*)nullptr);
+    hipLaunchKernelGGL(k_scan_down<false>, dim3(nt), dim3(kScanThreads), 0, s, in, out, n, tmp, total);
+    return hipGetLastError();
+}
+
+hipError_t exclusive_scan_nonzero_u32(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* tmp,
+                                      unsigned long long* total, unsigned long long* sum_parts, hipStream_t s) {
+    const uint32_t nt = (n + kScanTile - 1) / kScanTile;
+    if (n == 0) {
+        hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, (uint32_t*)total, 0u, (size_t)2);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(k_scan_reduce<true>, dim3(nt), dim3(kScanThreads), 0, s, in, n, tmp, sum_parts);
+    hipLaunchKernelGGL(k_scan_down<true>, dim3(nt), dim3(kScanThreads), 0, s, in, out, n, tmp, total);
     return hipGetLastError();
 }
 
