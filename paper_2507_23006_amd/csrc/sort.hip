@@ -1,13 +1,12 @@
 // Device-wide primitives for binning: a stable LSD radix sort of
 // (uint32 key, uint32 value) pairs and an exclusive scan of uint32 -- gfx950.
 //
-// Radix pass = three launches (reduce-then-scan, no inter-workgroup
-// waiting, so no kernel can hang on a missing predecessor):
+// Radix pass = three steps, four launches (reduce-then-scan, no
+// inter-workgroup waiting, so no kernel can hang on a missing predecessor):
 //   1. upsweep: each workgroup counts the digits of its tile (1024 or 2048
-//      keys);
-//      counts go to a digit-major table hist[digit][tile];
-//   2. the table is exclusive-scanned in digit-major order, which yields
-//      the global output offset of every (digit, tile);
+//      keys); counts go to a digit-major table hist[digit][tile];
+//   2. the table is exclusive-scanned in digit-major order (two launches),
+//      which yields the global output offset of every (digit, tile);
 //   3. downsweep: each wave64 ranks its keys in rounds of 64 with
 //      ballot-based digit matching (lanes with equal digits find each other
 //      through one __ballot per digit bit; rank = popcount of lower peers),
