@@ -271,7 +271,7 @@ __global__ __launch_bounds__(256) void k_render_fwd(const float4* __restrict__ r
         // position of the pixel's last composited entry is read once per chunk
         int last_k = -1;
         float4 an = st.g[0], bn = st.b[0], cn = st.c[0];
-#pragma unroll 2
+#pragma unroll 4
         for (int k = 0; k < n; ++k) {
             const float4 a = an, b = bn, c = cn;
             const int kn = k + 1 < n ? k + 1 : k;
