@@ -14,9 +14,10 @@ Readings where the text is silent (the same in the kernels):
 * statistic per view where the Gaussian was rasterized (tiles > 0):
   |dL/d mean2d| times a per-view scale (pixel -> NDC units, or 1), or, in the
   AbsGS mode, |(sum_p |dL_p/dx|, sum_p |dL_p/dy|)| times that scale; summed
-  over views and iterations with a count of views; mean = sum / count,
-  formed in float32 (the statistic's storage precision, so that the
-  threshold decision is taken on the same value the kernels hold);
+  over views and iterations with a count of views; mean = sum / count in
+  double precision (the plain quotient; a compared float32 implementation
+  differs from it only by rounding, which a test absorbs by setting aside
+  decisions within that rounding of their boundary);
 * d_i = Euclidean distance from the mean to the partition's axis-aligned box
   (0 inside); tau_i = tau_min (min(d_i, d_max) / d_max (eta - 1) + 1) (Eq. 4);
   a Gaussian is a candidate when its mean exceeds tau_i;
@@ -78,10 +79,10 @@ def thresholds(means, box_min, box_max, tau_min, eta, d_max):
 def select(accum, count, means, scales, opacities, box_min, box_max, tau_min, eta, d_max, prune_opacity,
            split_scale, budget):
     """Actions [n] (KEEP/CLONE/SPLIT/PRUNE) and the intermediate values."""
-    acc = np.asarray(accum, np.float32)
+    acc = np.asarray(accum, np.float64)
     cnt = np.asarray(count, np.int64)
     n = acc.shape[0]
-    mean = np.where(cnt > 0, (acc / np.maximum(cnt, 1).astype(np.float32)).astype(np.float64), 0.0)
+    mean = np.where(cnt > 0, acc / np.maximum(cnt, 1), 0.0)
     tau, d = thresholds(means, box_min, box_max, tau_min, eta, d_max)
     prune = np.asarray(opacities, np.float64) < prune_opacity
     cand = (mean > tau) & ~prune
@@ -110,13 +111,39 @@ def filter_rate(means, cams):
         cx, cy = float(np.float32(c.cx)), float(np.float32(c.cy))
         W, H = c.width, c.height
         with np.errstate(divide="ignore", invalid="ignore"):
-            # x / z within the widened image, compared as products (z > 0 there)
+            # the mean is in front and its image-plane ratios x / z, y / z lie
+            # within the image extent widened by 15 % of the size per side
+            u, v = t[0] / z, t[1] / z
             ok = (z >= float(np.float32(c.near))) & (z <= float(np.float32(c.far)))
-            ok &= (t[0] >= -(cx + 0.15 * W) / fx * z) & (t[0] <= (W - cx + 0.15 * W) / fx * z)
-            ok &= (t[1] >= -(cy + 0.15 * H) / fy * z) & (t[1] <= (H - cy + 0.15 * H) / fy * z)
+            ok &= (u >= -(cx + 0.15 * W) / fx) & (u <= (W - cx + 0.15 * W) / fx)
+            ok &= (v >= -(cy + 0.15 * H) / fy) & (v <= (H - cy + 0.15 * H) / fy)
             r = np.where(ok, fx / z, 0.0)
         rate = np.maximum(rate, r)
     return rate
+
+
+def filter_rate_margin(means, cams):
+    """Per Gaussian, the smallest relative distance of a camera's view test
+    (depth against near / far, x / z and y / z against the widened image
+    bounds) from its boundary: decisions this close to their boundary can go
+    either way under rounding and are set aside by comparisons."""
+    m = np.asarray(means, np.float64)
+    out = np.full(m.shape[1], np.inf)
+    for c in cams:
+        vm = np.asarray(c.viewmat, np.float32).astype(np.float64)
+        t = vm[:3, :3] @ m + vm[:3, 3:4]
+        z = t[2]
+        fx, fy = float(np.float32(c.fx)), float(np.float32(c.fy))
+        cx, cy = float(np.float32(c.cx)), float(np.float32(c.cy))
+        W, H = c.width, c.height
+        near, far = float(np.float32(c.near)), float(np.float32(c.far))
+        with np.errstate(divide="ignore", invalid="ignore"):
+            u, v = t[0] / z, t[1] / z
+            for val, b in ((z, near), (z, far), (u, -(cx + 0.15 * W) / fx), (u, (W - cx + 0.15 * W) / fx),
+                           (v, -(cy + 0.15 * H) / fy), (v, (H - cy + 0.15 * H) / fy)):
+                d = np.abs(val - b) / max(1.0, abs(b))
+                out = np.minimum(out, np.where(np.isfinite(d), d, np.inf))
+    return out
 
 
 def filter_apply(scales, opacities, rate, s_f):

@@ -3,10 +3,11 @@ the FP64 oracle (oracle/densify.py), on seeded synthetic statistics.
 
 Bars: counts exact and the running sums within 1e-6 relative (float32
 accumulation of <= 8 terms); actions bit-exact except Gaussians whose
-decision lies within float rounding of its boundary (mean within 1e-6 of
-tau_i relative, or a score within 1e-6 of the budget's last kept score),
-which are counted and must be rare; rates, filtered scales / opacities and
-their gradients within 1e-6 relative.
+decision lies within float rounding of its boundary (the oracle's FP64 mean
+within 1e-6 of tau_i relative -- the kernel forms the mean in float32 --, or
+a score within 1e-6 of the budget's last kept score), which are counted and
+must be rare; rates, filtered scales / opacities and their gradients within
+1e-6 relative, with view tests within 1e-9 of their boundary set aside.
 """
 import numpy as np
 import pytest
@@ -66,6 +67,7 @@ def _select_case(gpu_lib, n, seed, budgets, box=(-30.0, 30.0), d_max=60.0):
         if 0 < r["k"] < len(r["candidates"]):
             kth = r["score"][r["kept"][-1]]
             guard |= (r["score"] > 0) & (np.abs(r["score"] / kth - 1.0) < 1e-6)
+        print(f"select n={n} budget={budget}: {int(guard.sum())} decisions within 1e-6 of their boundary")
         assert guard.sum() <= max(2, n // 10000), guard.sum()
         ok = ~guard
         assert np.array_equal(act[ok], r["action"][ok]), (budget, int((act[ok] != r["action"][ok]).sum()))
@@ -109,8 +111,13 @@ def test_filter_rate_and_filter_match_oracle(gpu_lib):
     dm = torch.from_numpy(means).cuda()
     rate = D.filter3d_rate(dm, cams).cpu().numpy()
     rr = OD.filter_rate(means, cams)
-    assert np.array_equal(rate == 0, rr == 0) and (rr > 0).mean() > 0.5
-    np.testing.assert_allclose(rate, rr, rtol=1e-6)
+    # the kernel tests x / z against the bounds as products; the oracle
+    # divides: view tests within rounding of their boundary are set aside
+    ok = OD.filter_rate_margin(means, cams) > 1e-9
+    print(f"filter rate: {int((~ok).sum())} of {n} view tests within 1e-9 of a boundary")
+    assert (~ok).sum() <= 2
+    assert np.array_equal((rate == 0)[ok], (rr == 0)[ok]) and (rr > 0).mean() > 0.5
+    np.testing.assert_allclose(rate[ok], rr[ok], rtol=1e-6)
     scales = np.exp(rng.normal(-3, 1, (3, n))).astype(np.float32)
     opac = rng.uniform(0.01, 1, n).astype(np.float32)
     s_t = torch.from_numpy(scales).cuda().requires_grad_(True)
