@@ -48,7 +48,7 @@ class _Cam(C.Structure):
 
 class _Opt(C.Structure):
     _fields_ = [("sh_degree", C.c_int32), ("dilation", C.c_double), ("aa", C.c_int32),
-                ("bg", C.c_double * 3), ("tile_cull", C.c_int32)]
+                ("bg", C.c_double * 3)]
 
 
 _P = C.c_void_p
@@ -56,7 +56,7 @@ _P = C.c_void_p
 
 class _Proj(C.Structure):
     _fields_ = [(name, _P) for name in ("visible", "tcam", "cov2d", "rho", "conic", "mean2d", "depth",
-                                        "opac", "rgb", "clamped", "extent", "radius", "rect", "tiles", "mask")]
+                                        "opac", "rgb", "clamped", "extent", "radius", "rect", "tiles")]
 
 
 def _load():
@@ -97,14 +97,11 @@ def make_cam(cam) -> _Cam:
     return c
 
 
-def make_opt(sh_degree=3, dilation=0.3, aa=False, bg=(0.0, 0.0, 0.0), tile_cull=True) -> _Opt:
-    """tile_cull: False/0 the 3-sigma rectangle; 1 narrowed to the alpha box;
-    True/2 also per tile by the alpha ellipse (rectangles of <= 64 tiles)."""
+def make_opt(sh_degree=3, dilation=0.3, aa=False, bg=(0.0, 0.0, 0.0)) -> _Opt:
     o = _Opt()
     o.sh_degree = int(sh_degree)
     o.dilation = float(np.float32(dilation))
     o.aa = int(bool(aa))
-    o.tile_cull = 2 if tile_cull is True else int(tile_cull)
     for k in range(3):
         o.bg[k] = float(np.float32(bg[k]))
     return o
@@ -124,7 +121,8 @@ def sh_basis(dirs: np.ndarray) -> np.ndarray:
 
 
 def project(scene, cam, opac=None, cbase=None, **opt) -> dict:
-    """Per-Gaussian FP64 projection of one view (EWA, colour, rectangle).
+    """Per-Gaussian FP64 projection of one view (EWA, colour, the 3-sigma
+    tile rectangle; tile culling belongs to bin_pairs).
     opac replaces the scene's opacities and cbase [n][3] the colour
     constant 1/2 (both for appearance offsets)."""
     lib = _load()
@@ -134,7 +132,7 @@ def project(scene, cam, opac=None, cbase=None, **opt) -> dict:
         "rho": np.zeros(n), "conic": np.zeros((n, 3)), "mean2d": np.zeros((n, 2)), "depth": np.zeros(n),
         "opac": np.zeros(n), "rgb": np.zeros((n, 3)), "clamped": np.zeros((n, 3), np.int32),
         "extent": np.zeros(n), "radius": np.zeros(n, np.int32), "rect": np.zeros((n, 4), np.int32),
-        "tiles": np.zeros(n, np.int32), "mask": np.zeros(n, np.uint64),
+        "tiles": np.zeros(n, np.int32),
     }
     pr = _Proj(*[out[k].ctypes.data for k, _ in _Proj._fields_])
     means, scales, quats = _c64(scene.means), _c64(scene.scales), _c64(scene.quats)
@@ -152,30 +150,42 @@ def depth_key(depth: np.ndarray) -> np.ndarray:
     return np.ascontiguousarray(np.asarray(depth, np.float64).astype(np.float32)).view(np.uint32)
 
 
-def bin_pairs(rect, tiles, depth_keys, slot_view, cams, mask=None) -> dict:
+def bin_pairs(rect, tiles, depth_keys, slot_view, cams, mask=None, reach=None) -> dict:
     """Pairs (global tile, slot) sorted by (tile, depth key, slot) and the
     [start, end) range of every global tile; views are concatenated.  mask
-    [slots] (uint64, optional) selects covered tiles of each rectangle."""
+    [slots] (uint64, optional) selects covered tiles of each rectangle (0:
+    all of it), as a compared implementation reports them; reach = (mean2d,
+    conic, opac) slot arrays turns on tile culling: a tile is kept only where
+    some pixel centre passes the blend's skip rule (oracle.c tile_reached).
+    Also returns the pair count of every slot ("tiles")."""
     lib = _load()
     rect = np.ascontiguousarray(rect, np.int32)
     tiles = np.ascontiguousarray(tiles, np.int32)
     mask = np.ascontiguousarray(mask, np.uint64) if mask is not None else None
     depth_keys = np.ascontiguousarray(depth_keys, np.uint32)
     slot_view = np.ascontiguousarray(slot_view, np.int32)
+    if reach is not None:
+        rm, rc, ro = (np.ascontiguousarray(a, np.float64) for a in reach[:3])
+        assert rm.shape == (len(tiles), 2) and rc.shape == (len(tiles), 3) and ro.shape == (len(tiles),)
+    else:
+        rm = rc = ro = None
     tx = np.array([c.tiles_x for c in cams], np.int32)
+    vw = np.array([c.width for c in cams], np.int32)
+    vh = np.array([c.height for c in cams], np.int32)
     counts = np.array([c.n_tiles for c in cams], np.int64)
     toff = np.concatenate([[0], np.cumsum(counts)[:-1]]).astype(np.int32)
     n_tiles = int(counts.sum())
-    P = int(tiles.astype(np.int64).sum())
-    pair_tile = np.zeros(max(P, 1), np.uint32)
-    pair_slot = np.zeros(max(P, 1), np.uint32)
+    cap = int(tiles.astype(np.int64).sum())
+    pair_tile = np.zeros(max(cap, 1), np.uint32)
+    pair_slot = np.zeros(max(cap, 1), np.uint32)
     ranges = np.zeros((n_tiles, 2), np.uint32)
-    got = lib.orc_bin(C.c_int64(len(tiles)), _ptr(rect), _ptr(tiles), _ptr(mask), _ptr(depth_keys), _ptr(slot_view),
-                      _ptr(tx), _ptr(toff), C.c_int64(n_tiles), C.c_int64(P), _ptr(pair_tile),
-                      _ptr(pair_slot), _ptr(ranges))
-    assert got == P, (got, P)
+    slot_tiles = np.zeros(len(tiles), np.int32)
+    P = lib.orc_bin(C.c_int64(len(tiles)), _ptr(rect), _ptr(tiles), _ptr(mask), _ptr(rm), _ptr(rc), _ptr(ro),
+                    _ptr(depth_keys), _ptr(slot_view), _ptr(tx), _ptr(vw), _ptr(vh), _ptr(toff), C.c_int64(n_tiles),
+                    C.c_int64(cap), _ptr(pair_tile), _ptr(pair_slot), _ptr(ranges), _ptr(slot_tiles))
+    assert 0 <= P <= cap, (P, cap)
     return {"pair_tile": pair_tile[:P], "pair_slot": pair_slot[:P], "ranges": ranges,
-            "tile_off": toff.astype(np.int64), "n_pairs": P}
+            "tile_off": toff.astype(np.int64), "n_pairs": int(P), "tiles": slot_tiles}
 
 
 def _twod(proj_list):
@@ -184,12 +194,17 @@ def _twod(proj_list):
     return cat("mean2d"), cat("conic"), cat("opac"), cat("rgb"), cat("depth")
 
 
-# Guard band of the compared float32 implementation (see composite_pixel in
-# oracle.c): alpha relative floor (float32 conic coefficients, the exponent
-# polynomial and exp2: about 3e-6 for |power| <= 6), per-step T floor (two
-# float32 roundings of T(1 - alpha)), clamp floor, relative rounding of the
-# tile-relative mean (float32: 2^-24).
-DEFAULT_GUARD = (4e-6, 2.4e-7, 1e-6, 2.0 ** -24)
+# Guard band of a compared float32 implementation (composite_pixel in
+# oracle.c), from the unit roundoff u = 2^-24 of its operations:
+#   e_0 = 5u      exp (2u), o' (u), o' G' (u), the float32 value of 1/255 (u);
+#   e_T = 2u      1 - alpha and T (1 - alpha), one rounding each (and, once
+#                 more in the stop test, the float32 value of 1e-4: 0.4u);
+#   e_clamp       the float32 clamp 0.99f: 1 - 0.99f is 9.5e-7 off 0.01;
+#   e_mean = u    tile-relative mean and dx, each at its own magnitude;
+#   e_quad = 5u   float32 conic coefficients (u) and the products and the two
+#                 fused sums of the three-term exponent, relative to the terms.
+_U = 2.0 ** -24
+DEFAULT_GUARD = (5 * _U, 2 * _U, 1e-6, _U, 5 * _U)
 STAGE_GUARD = DEFAULT_GUARD
 
 
@@ -210,6 +225,70 @@ def render_view(cam, opt: dict, tile_off: int, twod, pair_slot, ranges, tile_mas
                    _ptr(ranges), _ptr(mask), _ptr(g), _ptr(out["rgb"]),
                    _ptr(out["depth"]), _ptr(out["alpha"]), _ptr(out["T"]), _ptr(out["last"]), _ptr(out["guard"]))
     return out
+
+
+def render_alternatives(cam, opt: dict, tile_off: int, twod, pair_slot, ranges, pixels,
+                        guard_eps=DEFAULT_GUARD, max_flags: int = 4):
+    """For pixels (flat indices y * W + x) of one view: the outputs of the
+    blend under every combination of the pixel's flagged decisions taken
+    either way (each is a valid result of a float32 evaluation).  Returns
+    (alts [n, 2^max_flags, 5] = rgb, depth, alpha; n_alt [n]: 2^m, or -m
+    for more than max_flags decisions)."""
+    lib = _load()
+    pix = np.ascontiguousarray(pixels, np.int64)
+    n = len(pix)
+    alts = np.full((n, 1 << max_flags, 5), np.nan)
+    n_alt = np.zeros(n, np.int32)
+    if n == 0:
+        return alts, n_alt
+    mean2d, conic, opac, rgb, depth = (np.ascontiguousarray(a, np.float64) for a in twod)
+    g = np.ascontiguousarray(guard_eps, np.float64)
+    pair_slot = np.ascontiguousarray(pair_slot, np.uint32)
+    ranges = np.ascontiguousarray(ranges, np.uint32)
+    lib.orc_render_alternatives(C.byref(make_cam(cam)), C.byref(make_opt(**opt)), C.c_int64(tile_off),
+                                _ptr(mean2d), _ptr(conic), _ptr(opac), _ptr(rgb), _ptr(depth), _ptr(pair_slot),
+                                _ptr(ranges), _ptr(g), C.c_int64(n), _ptr(pix), C.c_int(max_flags), _ptr(alts),
+                                _ptr(n_alt))
+    return alts, n_alt
+
+
+def compare_image(cam, opt: dict, tile_off: int, twod, pair_slot, ranges, ref: dict, got: dict,
+                  tol: float = 1e-4, guard_eps=DEFAULT_GUARD, max_flags: int = 4, where=None) -> dict:
+    """Compares a compared implementation's image ``got`` (rgb [H][W][3],
+    depth, alpha) with the oracle's ``ref`` (a render_view output over the
+    same lists): outside the guard band within tol (rgb, alpha absolute,
+    depth relative to max(1, depth)); a flagged pixel must match one of the
+    alternatives its flagged decisions allow (render_alternatives).  Returns
+    the worst error outside the band and the counts: flagged pixels,
+    resolved ones, unresolved ones (more decisions than max_flags) and
+    mismatches (flagged pixels matching no alternative).  ``where`` (bool
+    [H][W]) limits the comparison to some pixels."""
+    has_d, has_a = "depth" in got, "alpha" in got      # rgb alone (a served image) is compared too
+
+    def err(g_rgb, g_d, g_a, r_rgb, r_d, r_a):
+        e = np.abs(g_rgb - r_rgb).max(-1)
+        if has_a:
+            e = np.maximum(e, np.abs(g_a - r_a))
+        if has_d:
+            e = np.maximum(e, np.abs(g_d - r_d) / np.maximum(1.0, np.abs(r_d)))
+        return e
+    got = dict(got)
+    got.setdefault("depth", ref["depth"])
+    got.setdefault("alpha", ref["alpha"])
+    e = err(got["rgb"], got["depth"], got["alpha"], ref["rgb"], ref["depth"], ref["alpha"])
+    use = np.ones(e.shape, bool) if where is None else np.asarray(where, bool)
+    flagged = (ref["guard"] != 0) & use
+    worst = float(e[~flagged & use].max(initial=0.0))
+    fi = np.flatnonzero(flagged)
+    alts, n_alt = render_alternatives(cam, opt, tile_off, twod, pair_slot, ranges, fi, guard_eps, max_flags)
+    gr = got["rgb"].reshape(-1, 3)[fi]
+    gd, ga = got["depth"].reshape(-1)[fi], got["alpha"].reshape(-1)[fi]
+    ea = err(gr[:, None, :], gd[:, None], ga[:, None], alts[..., :3], alts[..., 3], alts[..., 4])
+    ok_alt = np.nanmin(np.where(np.isnan(ea), np.inf, ea), axis=1) <= tol
+    resolvable = n_alt > 0
+    return {"worst": worst, "flagged": int(len(fi)), "resolved": int((resolvable & ok_alt).sum()),
+            "unresolved": int((~resolvable).sum()), "mismatch": int((resolvable & ~ok_alt).sum()),
+            "mismatch_pixels": fi[resolvable & ~ok_alt][:10].tolist()}
 
 
 def render_bwd_view(cam, opt: dict, tile_off: int, twod, pair_slot, ranges, g_rgb, g_depth, g_alpha,
@@ -254,10 +333,14 @@ def project_bwd(scene, cam, opt: dict, d2_view, grads: dict, opac=None, cbase=No
     return norm
 
 
-def forward(scene, cams, opt: dict | None = None, guard_eps=DEFAULT_GUARD, depth_keys=None, app=None) -> dict:
+def forward(scene, cams, opt: dict | None = None, guard_eps=DEFAULT_GUARD, depth_keys=None, app=None,
+            tile_cull: bool = False) -> dict:
     """Full FP64 forward over one or more views of the same Gaussians.
 
-    ``app`` [n][4]: appearance offsets (dc, do), applied as in
+    Every Gaussian is listed in every tile of its 3-sigma rectangle (the
+    plain definition); ``tile_cull`` drops the tiles where it cannot pass the
+    skip rule at any pixel centre (bin_pairs), which leaves every image
+    unchanged.  ``app`` [n][4]: appearance offsets (dc, do), applied as in
     oracle.appearance.apply_offsets.  Returns per-view images (rgb, depth,
     alpha, T, last, guard) and the intermediate stages (projections, pairs,
     ranges)."""
@@ -274,9 +357,8 @@ def forward(scene, cams, opt: dict | None = None, guard_eps=DEFAULT_GUARD, depth
     tiles = np.concatenate([p["tiles"] for p in projs], 0)
     keys = depth_key(np.concatenate([p["depth"] for p in projs], 0)) if depth_keys is None else depth_keys
     slot_view = np.repeat(np.arange(len(cams), dtype=np.int32), n)
-    mask = np.concatenate([p["mask"] for p in projs], 0)
-    bins = bin_pairs(rect, tiles, keys, slot_view, cams, mask=mask)
     twod = _twod(projs)
+    bins = bin_pairs(rect, tiles, keys, slot_view, cams, reach=twod[:3] if tile_cull else None)
     images = [render_view(c, opt, int(bins["tile_off"][v]), twod, bins["pair_slot"], bins["ranges"],
                           guard_eps=guard_eps) for v, c in enumerate(cams)]
     return {"proj": projs, "bins": bins, "twod": twod, "images": images, "cams": list(cams), "opt": opt,

@@ -57,8 +57,6 @@ typedef struct {
     double dilation;         /* px^2 added to the 2D covariance diagonal */
     int32_t aa;              /* 1: opacity compensation by rho */
     double bg[3];
-    int32_t tile_cull;       /* 1: tile rectangle narrowed to the alpha box; 2: and, for rectangles
-                                of at most 64 tiles, only tiles the alpha ellipse reaches (project_one) */
 } oopt_t;
 
 /* per-slot projection outputs (arrays of n entries times the component count) */
@@ -77,8 +75,6 @@ typedef struct {
     int32_t *radius;         /* [n] */
     int32_t *rect;           /* [n][4] tile x0, y0, x1, y1 (inclusive) */
     int32_t *tiles;          /* [n] number of tiles covered, 0 if culled */
-    uint64_t *mask;          /* [n] covered tiles of the rectangle, bit (ty - y0) w + (tx - x0);
-                                0 = every tile of the rectangle (nullable) */
 } oproj_t;
 
 /* ------------------------------------------------------------------------ */
@@ -222,7 +218,6 @@ typedef struct {
     int radius;
     int rect[4];
     int tiles;
-    uint64_t mask;
 } proj1_t;
 
 /* cbase: the constant of the colour polynomial per channel (NULL: 0.5, the
@@ -313,77 +308,10 @@ static void project_one(const ocam_t *cam, const oopt_t *opt, const double mu[3]
     if (fy0 < 0.0) fy0 = 0.0;
     if (fx1 > TW - 1) fx1 = TW - 1;
     if (fy1 > TH - 1) fy1 = TH - 1;
-    if (opt->tile_cull) {
-        /* Tile-based culling (adopted in §3.4.2 to skip Gaussians of negligible
-         * contribution in a tile).  A pixel centre can pass the skip rule only
-         * where o' G' >= 1/255, i.e. inside the ellipse d^T Sigma'^-1 d <= 2 tau,
-         * tau = ln(255 o'), whose bounding box has half-widths
-         * sqrt(2 tau Sigma'_xx) and sqrt(2 tau Sigma'_yy).  The box is widened
-         * by margins for the float32 arithmetic of the compositing kernels
-         * (1e-5 on tau, relative 1e-6 and 1e-3 px on the half-widths) and the
-         * rectangle keeps only tiles holding pixel centres inside it, so no
-         * image changes.  With o' below 1/255 (compared in float32) nothing
-         * passes anywhere and the Gaussian is culled. */
-        if (!((float)P->opac >= 1.0f / 255.0f)) return;
-        double tau = log(255.0 * P->opac) + 1e-5;
-        double hx = sqrt(2.0 * tau * P->ad) * (1.0 + 1e-6) + 1e-3;
-        double hy = sqrt(2.0 * tau * P->cd) * (1.0 + 1e-6) + 1e-3;
-        /* pixels p with |p + 0.5 - m| <= h, then their tiles */
-        double bx0 = floor(ceil(P->mean2d[0] - hx - 0.5) / ORC_TILE), bx1 = floor(floor(P->mean2d[0] + hx - 0.5) / ORC_TILE);
-        double by0 = floor(ceil(P->mean2d[1] - hy - 0.5) / ORC_TILE), by1 = floor(floor(P->mean2d[1] + hy - 0.5) / ORC_TILE);
-        if (bx0 > fx0) fx0 = bx0;
-        if (by0 > fy0) fy0 = by0;
-        if (bx1 < fx1) fx1 = bx1;
-        if (by1 < fy1) fy1 = by1;
-    }
     if (!(fx0 <= fx1 && fy0 <= fy1)) return;
     P->radius = (int)(r < 2e9 ? r : 2e9);
     P->rect[0] = (int)fx0; P->rect[1] = (int)fy0; P->rect[2] = (int)fx1; P->rect[3] = (int)fy1;
     P->tiles = (P->rect[2] - P->rect[0] + 1) * (P->rect[3] - P->rect[1] + 1);
-    P->mask = 0;
-    if (opt->tile_cull >= 2 && P->tiles <= 64) {
-        /* Exact tile culling: keep a tile only if the alpha ellipse
-         * q(d) = d^T Sigma'^-1 d <= L, L = 2 tau (1 + 4e-6) (tau as for the
-         * box), reaches the rectangle of its pixel centres (widened by
-         * 1e-3 px).  Row by row: the ellipse within a row's strip
-         * [ylo, yhi] is convex, so it meets a tile of the row iff its
-         * x-extent over the strip meets the tile's column range.  For fixed
-         * y the ellipse spans x = (-B y -+ sqrt(A L - det y^2)) / A; the upper
-         * end is concave in y with its maximum at the ellipse's rightmost
-         * point (X, -B X / C), X = sqrt(L C / det), and the lower end convex
-         * with its minimum at (-X, B X / C): over the strip (clipped to the
-         * ellipse's y-extent +-sqrt(L A / det)) both are taken at those y
-         * clamped into the strip. */
-        double tau = log(255.0 * P->opac) + 1e-5;
-        double L = 2.0 * tau * (1.0 + 4e-6);
-        double A = P->conic[0], B = P->conic[1], C = P->conic[2];
-        double det = A * C - B * B;
-        double X = sqrt(L * C / det), Y = sqrt(L * A / det), yr = -B / C * X;
-        int w = P->rect[2] - P->rect[0] + 1, cnt = 0;
-        for (int ty = P->rect[1]; ty <= P->rect[3]; ty++) {
-            int py1 = ty * ORC_TILE + ORC_TILE - 1;
-            if (py1 > cam->H - 1) py1 = cam->H - 1;
-            double ylo = ty * ORC_TILE + 0.5 - 1e-3 - P->mean2d[1], yhi = py1 + 0.5 + 1e-3 - P->mean2d[1];
-            double a = ylo > -Y ? ylo : -Y, b = yhi < Y ? yhi : Y;
-            if (a > b) continue;
-            double y1 = yr < a ? a : (yr > b ? b : yr);
-            double y2 = -yr < a ? a : (-yr > b ? b : -yr);
-            double r1 = A * L - det * y1 * y1, r2 = A * L - det * y2 * y2;
-            double xhi_e = (-B * y1 + sqrt(r1 > 0.0 ? r1 : 0.0)) / A;
-            double xlo_e = (-B * y2 - sqrt(r2 > 0.0 ? r2 : 0.0)) / A;
-            for (int tx = P->rect[0]; tx <= P->rect[2]; tx++) {
-                int px1 = tx * ORC_TILE + ORC_TILE - 1;
-                if (px1 > cam->W - 1) px1 = cam->W - 1;
-                double xlo = tx * ORC_TILE + 0.5 - 1e-3 - P->mean2d[0], xhi = px1 + 0.5 + 1e-3 - P->mean2d[0];
-                if (xlo <= xhi_e && xhi >= xlo_e) {
-                    P->mask |= 1ull << ((ty - P->rect[1]) * w + (tx - P->rect[0]));
-                    cnt++;
-                }
-            }
-        }
-        if (cnt == 0) return;
-        P->tiles = cnt;
-    }
 
     /* view-dependent colour from the world-space viewing direction */
     double campos[3];
@@ -432,7 +360,6 @@ int orc_project(int64_t n, const double *means, const double *scales, const doub
         out->radius[i] = P.radius;
         for (int k = 0; k < 4; k++) out->rect[4 * i + k] = P.visible ? P.rect[k] : 0;
         out->tiles[i] = P.visible ? P.tiles : 0;
-        if (out->mask) out->mask[i] = P.visible ? P.mask : 0;
     }
     return 0;
 }
@@ -451,37 +378,103 @@ static int pair_cmp(const void *pa, const void *pb) {
     return 0;
 }
 
-/* Enumerates one pair per (slot, covered tile: a tile of the slot's
- * rectangle whose bit is set in mask[s], every tile when mask is NULL or
- * mask[s] is 0), sorts the
- * pairs by (global tile id, depth key, slot) -- "processed in depth order"
- * of §3.1, ties by input index -- and writes [start, end) per global tile.
- * slot_view[s] selects the view of a slot; its tiles are numbered
- * view_tile_off[v] + ty * view_tiles_x[v] + tx. */
+/* The exponent of G' at pixel centre (px, py) for a Gaussian with 2D mean m
+ * and conic (A, B, C), i.e. -1/2 d^T Sigma'^-1 d with d = p - m; also the
+ * offsets.  Compositing and tile culling both evaluate this one expression. */
+static double entry_power(const double *m, const double *cn, double px, double py, double *dx_out, double *dy_out) {
+    double dx = px - m[0], dy = py - m[1];
+    *dx_out = dx;
+    *dy_out = dy;
+    return -0.5 * (cn[0] * dx * dx + cn[2] * dy * dy) - cn[1] * dx * dy;
+}
+
+/* Tile-based culling (§3.4.2: a Gaussian whose contribution to a tile is
+ * negligible is skipped there).  The reading: an entry contributes nothing
+ * to a tile when the skip rule of the blend (alpha = min(0.99, o' G') below
+ * 1/255, or a positive exponent) holds at every pixel centre of the tile
+ * inside the image.  This tests every such pixel centre with the
+ * compositing's own expressions, so culling never changes an image.
+ * An exponent more than 1e-9 below ln(1/(255 o')) fails the skip test
+ * without evaluating exp (a margin far above the rounding of log and exp). */
+static int tile_reached(const double *m, const double *cn, double opac, int tx, int ty, int W, int H) {
+    if (!(opac >= ORC_ALPHA_MIN)) return 0;   /* o' G' <= o' since G' <= 1 */
+    double lim = log(ORC_ALPHA_MIN / opac) - 1e-9;
+    for (int y = ty * ORC_TILE; y < (ty + 1) * ORC_TILE && y < H; y++)
+        for (int x = tx * ORC_TILE; x < (tx + 1) * ORC_TILE && x < W; x++) {
+            double dx, dy;
+            double power = entry_power(m, cn, x + 0.5, y + 0.5, &dx, &dy);
+            if (power > 0.0 || power < lim) continue;
+            double raw = opac * exp(power);
+            double alpha = raw < ORC_ALPHA_MAX ? raw : ORC_ALPHA_MAX;
+            if (alpha >= ORC_ALPHA_MIN) return 1;
+        }
+    return 0;
+}
+
+/* Whether tile (tx, ty) of slot s's rectangle is enumerated: its bit in a
+ * given covered-tile mask (mask[s] == 0: every tile), and, with 2D records
+ * given, tile culling by tile_reached. */
+static int tile_kept(int64_t s, int tx, int ty, const int32_t *rect, const uint64_t *mask, const double *mean2d,
+                     const double *conic, const double *opac, int W, int H) {
+    uint64_t mk = mask ? mask[s] : 0;
+    int w = rect[4 * s + 2] - rect[4 * s] + 1;
+    if (mk && !((mk >> ((ty - rect[4 * s + 1]) * w + (tx - rect[4 * s]))) & 1)) return 0;
+    if (mean2d && !tile_reached(mean2d + 2 * s, conic + 3 * s, opac[s], tx, ty, W, H)) return 0;
+    return 1;
+}
+
+/* Enumerates one pair per (slot, kept tile of the slot's rectangle; see
+ * tile_kept: mask[s] selects tiles of a rectangle computed elsewhere, the
+ * nullable 2D records mean2d [n][2], conic [n][3], opac [n] turn on tile
+ * culling), sorts the pairs by (global tile id, depth key, slot) --
+ * "processed in depth order" of §3.1, ties by input index -- and writes
+ * [start, end) per global tile.  slot_view[s] selects the view of a slot;
+ * its tiles are numbered view_tile_off[v] + ty * view_tiles_x[v] + tx and
+ * its image is view_W[v] x view_H[v].  slot_tiles (nullable) receives the
+ * number of pairs of each slot.  Returns P, or -P when P > capacity. */
 int64_t orc_bin(int64_t n_slots, const int32_t *rect, const int32_t *tiles, const uint64_t *mask,
-                const uint32_t *depth_key, const int32_t *slot_view, const int32_t *view_tiles_x,
+                const double *mean2d, const double *conic, const double *opac, const uint32_t *depth_key,
+                const int32_t *slot_view, const int32_t *view_tiles_x, const int32_t *view_W, const int32_t *view_H,
                 const int32_t *view_tile_off, int64_t n_tiles_total, int64_t capacity, uint32_t *pair_tile,
-                uint32_t *pair_slot, uint32_t *ranges /* [n_tiles_total][2] */) {
+                uint32_t *pair_slot, uint32_t *ranges /* [n_tiles_total][2] */, int32_t *slot_tiles) {
+    int64_t *cnt = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n_slots + 1));
+    if (!cnt) return -1;
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t s = 0; s < n_slots; s++) {
+        int64_t c = 0;
+        if (tiles[s] > 0) {
+            int v = slot_view[s];
+            for (int ty = rect[4 * s + 1]; ty <= rect[4 * s + 3]; ty++)
+                for (int tx = rect[4 * s]; tx <= rect[4 * s + 2]; tx++)
+                    c += tile_kept(s, tx, ty, rect, mask, mean2d, conic, opac, view_W[v], view_H[v]);
+        }
+        cnt[s] = c;
+    }
     int64_t P = 0;
-    for (int64_t s = 0; s < n_slots; s++) P += tiles[s];
-    if (P > capacity) return -P;
+    for (int64_t s = 0; s < n_slots; s++) {
+        int64_t c = cnt[s];
+        if (slot_tiles) slot_tiles[s] = (int32_t)c;
+        cnt[s] = P;
+        P += c;
+    }
+    if (P > capacity) { free(cnt); return -P; }
     opair_t *pairs = (opair_t *)malloc(sizeof(opair_t) * (size_t)(P > 0 ? P : 1));
-    if (!pairs) return -1;
-    int64_t k = 0;
+    if (!pairs) { free(cnt); return -1; }
+#pragma omp parallel for schedule(dynamic, 256)
     for (int64_t s = 0; s < n_slots; s++) {
         if (tiles[s] <= 0) continue;
         int v = slot_view[s];
-        uint64_t m = mask ? mask[s] : 0;
-        int w = rect[4 * s + 2] - rect[4 * s] + 1;
+        int64_t k = cnt[s];
         for (int ty = rect[4 * s + 1]; ty <= rect[4 * s + 3]; ty++)
             for (int tx = rect[4 * s]; tx <= rect[4 * s + 2]; tx++) {
-                if (m && !((m >> ((ty - rect[4 * s + 1]) * w + (tx - rect[4 * s]))) & 1)) continue;
+                if (!tile_kept(s, tx, ty, rect, mask, mean2d, conic, opac, view_W[v], view_H[v])) continue;
                 pairs[k].tile = (uint32_t)(view_tile_off[v] + ty * view_tiles_x[v] + tx);
                 pairs[k].key = depth_key[s];
                 pairs[k].slot = (uint32_t)s;
                 k++;
             }
     }
+    free(cnt);
     qsort(pairs, (size_t)P, sizeof(opair_t), pair_cmp);
     for (int64_t t = 0; t < n_tiles_total; t++) { ranges[2 * t] = 0; ranges[2 * t + 1] = 0; }
     for (int64_t i = 0; i < P; i++) {
@@ -516,55 +509,110 @@ typedef struct {
 
 /* Composites one pixel; returns the number of composited entries and fills
  * `ent` (if non-NULL, capacity `cap`) with them in front-to-back order. */
-/* Guard band.  guard_eps (nullable) = {e_alpha, e_T, e_clamp, e_mean}: a
- * compared implementation evaluates alpha with relative error at most
- * e_alpha + |d power / d mean| * (|dx| + 17) * e_mean (e_mean models a mean
- * held relative to its 16x16 tile's origin with that relative rounding; the
- * tile-relative mean is at most |dx| + 16 from the origin), and T with the
- * accumulated relative error of the alphas before it plus e_T.  A pixel is
- * flagged when a skip (alpha vs 1/255), stop (T(1 - alpha) vs 1e-4) or clamp
- * (o' G' vs 0.99) decision lies inside that error. */
+/* Guard band.  guard_eps (nullable) = {e_0, e_T, e_clamp, e_mean, e_quad}
+ * bounds how far a compared float32 evaluation of the blend can stray from
+ * this FP64 one (each float32 operation rounds within its unit roundoff u):
+ *   - alpha = o' exp(power) carries relative error at most
+ *       e_0 + e_quad (|A dx^2 / 2| + |B dx dy| + |C dy^2 / 2|)
+ *           + e_mean (|d power / d dx| (2 |dx| + 17) + |d power / d dy| (2 |dy| + 17)):
+ *     e_0 for exp, o' and its product and the float32 threshold constants;
+ *     e_quad for the float32 conic coefficients and the products and sums of
+ *     the three-term exponent (relative to the terms' magnitudes, which
+ *     exceed |power| when the terms cancel); e_mean for a mean held relative
+ *     to its 16x16 tile's origin (at most |dx| + 16 from it) and the
+ *     difference dx, each rounded at its own magnitude;
+ *   - the factor 1 - alpha carries the relative error of alpha times
+ *     alpha / (1 - alpha), or e_clamp when alpha is the (float32) clamp
+ *     0.99; each step adds e_T for rounding 1 - alpha and the product, and
+ *     the stop test allows one more e_T for the float32 value of 1e-4.
+ * A pixel is flagged when a skip (alpha vs 1/255), clamp (o' G' vs 0.99)
+ * or stop (T (1 - alpha) vs 1e-4) decision lies within that error. */
+/* The flagged decisions of one pixel (list position and kind), and the
+ * ones a caller asks to be taken the other way: a decision within the guard
+ * band can go either way in a float32 evaluation, so each way gives a valid
+ * result (orc_render_alternatives). */
+typedef struct { int pos, kind; } oflag_t;
+
+typedef struct {
+    const oflag_t *flip;
+    int n_flip;
+    oflag_t *seen;           /* flagged decisions met, in list order */
+    int cap_seen, n_seen;
+} odecide_t;
+
+static int decision_flipped(const odecide_t *d, int pos, int kind) {
+    if (!d) return 0;
+    for (int i = 0; i < d->n_flip; i++)
+        if (d->flip[i].pos == pos && d->flip[i].kind == kind) return 1;
+    return 0;
+}
+
+static void decision_seen(odecide_t *d, int pos, int kind) {
+    if (!d) return;
+    if (d->n_seen < d->cap_seen) { d->seen[d->n_seen].pos = pos; d->seen[d->n_seen].kind = kind; }
+    d->n_seen++;
+}
+
 static int composite_pixel(const o2d_t *g, const uint32_t *pair_slot, uint32_t start, uint32_t end,
                            double px, double py, const double *guard_eps, double out[7],
-                           int *last_out, int *guard_out, oentry_t *ent, int cap) {
+                           int *last_out, int *guard_out, oentry_t *ent, int cap, odecide_t *dec) {
     double T = 1.0, C[3] = {0.0, 0.0, 0.0}, D = 0.0;
     double errT = 0.0;     /* relative error bound of T so far */
     int last = 0, guard = 0, n = 0;
     for (uint32_t k = start; k < end; k++) {
-        int s = (int)pair_slot[k];
+        int s = (int)pair_slot[k], pos = (int)(k - start);
         const double *m = g->mean2d + 2 * s, *cn = g->conic + 3 * s;
-        double dx = px - m[0], dy = py - m[1];
-        double power = -0.5 * (cn[0] * dx * dx + cn[2] * dy * dy) - cn[1] * dx * dy;
-        if (power > 0.0) continue;
+        double dx, dy;
+        double power = entry_power(m, cn, px, py, &dx, &dy);
+        if (power > 0.0 && !guard_eps) continue;     /* skipped, nothing to flag */
         double G = exp(power);
         double raw = g->opac[s] * G;
-        double alpha = raw < ORC_ALPHA_MAX ? raw : ORC_ALPHA_MAX;
+        int clamp = raw >= ORC_ALPHA_MAX;
         double ea = 0.0;   /* relative error bound of alpha */
         if (guard_eps) {
+            double quad = fabs(0.5 * cn[0] * dx * dx) + fabs(cn[1] * dx * dy) + fabs(0.5 * cn[2] * dy * dy);
             double gx = fabs(cn[0] * dx + cn[1] * dy), gy = fabs(cn[1] * dx + cn[2] * dy);
-            ea = guard_eps[0] + (gx * (fabs(dx) + 17.0) + gy * (fabs(dy) + 17.0)) * guard_eps[3];
-            if (fabs(alpha - ORC_ALPHA_MIN) <= ea * ORC_ALPHA_MIN) guard |= ORC_GUARD_SKIP;
-            if (fabs(raw - ORC_ALPHA_MAX) <= (ea + guard_eps[2]) * ORC_ALPHA_MAX) guard |= ORC_GUARD_CLAMP;
+            ea = guard_eps[0] + guard_eps[4] * quad +
+                 (gx * (2.0 * fabs(dx) + 17.0) + gy * (2.0 * fabs(dy) + 17.0)) * guard_eps[3];
+            if (fabs(raw - ORC_ALPHA_MAX) <= ea * ORC_ALPHA_MAX) {
+                guard |= ORC_GUARD_CLAMP;
+                decision_seen(dec, pos, ORC_GUARD_CLAMP);
+                if (decision_flipped(dec, pos, ORC_GUARD_CLAMP)) clamp = !clamp;
+            }
         }
-        if (alpha < ORC_ALPHA_MIN) continue;
+        double alpha = clamp ? ORC_ALPHA_MAX : raw;
+        /* skipped: a positive exponent, or alpha below 1/255 */
+        int skip = power > 0.0 || alpha < ORC_ALPHA_MIN;
+        if (guard_eps && (power >= -ea || fabs(alpha - ORC_ALPHA_MIN) <= ea * ORC_ALPHA_MIN)) {
+            guard |= ORC_GUARD_SKIP;
+            decision_seen(dec, pos, ORC_GUARD_SKIP);
+            if (decision_flipped(dec, pos, ORC_GUARD_SKIP)) skip = !skip;
+        }
+        if (skip) continue;
         double Tn = T * (1.0 - alpha);
+        int stop = Tn < ORC_T_MIN;
         if (guard_eps) {
-            double eTn = errT + ea * alpha / (1.0 - alpha) + guard_eps[1];
-            if (fabs(Tn - ORC_T_MIN) <= eTn * ORC_T_MIN) guard |= ORC_GUARD_STOP;
+            double e1 = clamp ? guard_eps[2] : ea * alpha / (1.0 - alpha);
+            double eTn = errT + e1 + guard_eps[1];
+            if (fabs(Tn - ORC_T_MIN) <= (eTn + guard_eps[1]) * ORC_T_MIN) {
+                guard |= ORC_GUARD_STOP;
+                decision_seen(dec, pos, ORC_GUARD_STOP);
+                if (decision_flipped(dec, pos, ORC_GUARD_STOP)) stop = !stop;
+            }
             errT = eTn;
         }
-        if (Tn < ORC_T_MIN) break;
+        if (stop) break;
         if (ent && n < cap) {
-            ent[n].pos = (int)(k - start);
+            ent[n].pos = pos;
             ent[n].slot = s;
             ent[n].dx = dx; ent[n].dy = dy; ent[n].G = G; ent[n].alpha = alpha; ent[n].T = T;
-            ent[n].clamped = raw >= ORC_ALPHA_MAX;
+            ent[n].clamped = clamp;
         }
         n++;
         for (int ch = 0; ch < 3; ch++) C[ch] += g->rgb[3 * s + ch] * alpha * T;
         D += g->depth[s] * alpha * T;
         T = Tn;
-        last = (int)(k - start) + 1;
+        last = pos + 1;
     }
     out[0] = C[0]; out[1] = C[1]; out[2] = C[2]; out[3] = D; out[4] = 1.0 - T; out[5] = T;
     *last_out = last;
@@ -591,7 +639,8 @@ int orc_render(const ocam_t *cam, const oopt_t *opt, int64_t tile_off, const dou
             for (int x = tx * ORC_TILE; x < (tx + 1) * ORC_TILE && x < cam->W; x++) {
                 double o[7];
                 int last, guard;
-                composite_pixel(&g, pair_slot, start, end, x + 0.5, y + 0.5, guard_eps, o, &last, &guard, NULL, 0);
+                composite_pixel(&g, pair_slot, start, end, x + 0.5, y + 0.5, guard_eps, o, &last, &guard, NULL, 0,
+                                NULL);
                 int64_t p = (int64_t)y * cam->W + x;
                 for (int ch = 0; ch < 3; ch++) out_rgb[3 * p + ch] = o[ch] + o[5] * opt->bg[ch];
                 out_depth[p] = o[3];
@@ -600,6 +649,73 @@ int orc_render(const ocam_t *cam, const oopt_t *opt, int64_t tile_off, const dou
                 out_last[p] = last;
                 if (out_guard) out_guard[p] = (uint8_t)guard;
             }
+    }
+    return 0;
+}
+
+static int flag_in(const oflag_t *f, int n, oflag_t x) {
+    for (int i = 0; i < n; i++)
+        if (f[i].pos == x.pos && f[i].kind == x.kind) return 1;
+    return 0;
+}
+
+/* For each listed pixel (index y * W + x) of one view: the outputs
+ * (rgb + T bg, depth, alpha) of the blend under every combination of its
+ * flagged decisions taken either way.  The set of decisions is closed: a
+ * combination that meets a further flagged decision adds it, and the
+ * enumeration restarts.  n_alt[i] = 2^m for m <= max_flags flagged
+ * decisions (out[i] holds that many alternatives of 5 values, the first
+ * one with no decision flipped), or -m when there are more. */
+int orc_render_alternatives(const ocam_t *cam, const oopt_t *opt, int64_t tile_off, const double *mean2d,
+                            const double *conic, const double *opac, const double *rgb, const double *depth,
+                            const uint32_t *pair_slot, const uint32_t *ranges, const double *guard_eps,
+                            int64_t n_px, const int64_t *pix, int max_flags, double *out, int32_t *n_alt) {
+    o2d_t g = {mean2d, conic, opac, rgb, depth};
+    int TW = (cam->W + ORC_TILE - 1) / ORC_TILE;
+    int n_max = 1 << max_flags;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t i = 0; i < n_px; i++) {
+        int x = (int)(pix[i] % cam->W), y = (int)(pix[i] / cam->W);
+        int t = (y / ORC_TILE) * TW + x / ORC_TILE;
+        uint32_t start = ranges[2 * (tile_off + t)], end = ranges[2 * (tile_off + t) + 1];
+        oflag_t F[32], seen[64], flip[32];
+        int m = 0, closed = 0;
+        /* the decisions flagged on the plain path */
+        {
+            odecide_t d = {NULL, 0, seen, 64, 0};
+            double o[7];
+            int last, guard;
+            composite_pixel(&g, pair_slot, start, end, x + 0.5, y + 0.5, guard_eps, o, &last, &guard, NULL, 0, &d);
+            for (int k = 0; k < d.n_seen && k < 64 && m < 32; k++)
+                if (!flag_in(F, m, seen[k])) F[m++] = seen[k];
+            if (d.n_seen > 64) m = 32;
+        }
+        while (!closed && m <= max_flags) {
+            closed = 1;
+            for (int mask = 0; mask < (1 << m) && closed; mask++) {
+                int nf = 0;
+                for (int b = 0; b < m; b++)
+                    if (mask >> b & 1) flip[nf++] = F[b];
+                odecide_t d = {flip, nf, seen, 64, 0};
+                double o[7];
+                int last, guard;
+                composite_pixel(&g, pair_slot, start, end, x + 0.5, y + 0.5, guard_eps, o, &last, &guard, NULL, 0, &d);
+                if (d.n_seen > 64) { m = 32; closed = 0; break; }
+                for (int k = 0; k < d.n_seen; k++)
+                    if (!flag_in(F, m, seen[k])) {
+                        if (m < 32) F[m] = seen[k];
+                        m++;
+                        closed = 0;
+                    }
+                if (closed) {
+                    double *r = out + ((int64_t)i * n_max + mask) * 5;
+                    for (int ch = 0; ch < 3; ch++) r[ch] = o[ch] + o[5] * opt->bg[ch];
+                    r[3] = o[3];
+                    r[4] = o[4];
+                }
+            }
+        }
+        n_alt[i] = m <= max_flags ? (1 << m) : -m;
     }
     return 0;
 }
@@ -643,7 +759,7 @@ int orc_render_bwd(const ocam_t *cam, const oopt_t *opt, int64_t tile_off, const
                     double o[7];
                     int last, guard;
                     int n = composite_pixel(&g, pair_slot, start, end, x + 0.5, y + 0.5, NULL, o, &last, &guard,
-                                            ent, cap);
+                                            ent, cap, NULL);
                     double Tf = o[5];
                     int64_t p = (int64_t)y * cam->W + x;
                     const double *gc = g_rgb + 3 * p;

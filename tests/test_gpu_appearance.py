@@ -14,7 +14,7 @@ import torch
 import oracle
 import synthetic as S
 from oracle import appearance as OA
-from gpu_util import grads_oracle_layout, oracle_opt, to_dev, view_images
+from gpu_util import check_image, grads_oracle_layout, oracle_opt, to_dev, view_images
 
 pytestmark = pytest.mark.gpu
 
@@ -164,12 +164,10 @@ def test_render_with_offsets_matches_oracle(gpu_lib):
     torch.cuda.synchronize()
     f = oracle.forward(scene, cams, oracle_opt(opts), app=app_np)
     for v, c in enumerate(cams):
-        ref = f["images"][v]
-        ok = ref["guard"] == 0
-        got_rgb = view_images(rgb.detach().cpu().numpy(), cams)[v]
-        got_d = view_images(depth.detach().cpu().numpy(), cams)[v]
-        assert np.abs(got_rgb - ref["rgb"]).max(axis=-1)[ok].max() <= 1e-4
-        assert (np.abs(got_d - ref["depth"]) / np.maximum(1, np.abs(ref["depth"])))[ok].max() <= 1e-4
+        got = {"rgb": view_images(rgb.detach().cpu().numpy(), cams)[v],
+               "depth": view_images(depth.detach().cpu().numpy(), cams)[v]}
+        check_image(c, oracle_opt(opts), int(f["bins"]["tile_off"][v]), f["twod"], f["bins"]["pair_slot"],
+                    f["bins"]["ranges"], f["images"][v], got, f"offsets view {v}")
     ref = oracle.backward(scene, f, ws)
     g = grads_oracle_layout(params)
     for k in ("means", "scales", "quats", "opacities", "sh"):

@@ -16,8 +16,8 @@ import torch
 
 import oracle
 import synthetic as S
-from gpu_util import (decode_records, decode_rect, gpu_forward, grads_oracle_layout, mask_covers, mask_rows,
-                      oracle_opt, to_dev, view_images)
+from gpu_util import (border_slots, check_image, check_tile_culling, decode_records, decode_rect, gpu_forward, grads_oracle_layout,
+                      mask_covers, mask_rows, oracle_opt, to_dev, view_images)
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
@@ -27,83 +27,46 @@ def c3():
     return S.scene_c3(seed=0), S.camera_c3(seed=2)
 
 
-def test_c3_forward_and_binning(gpu_lib, c3):
-    scene, cam = c3
-    cams = [cam]
-    opts = gpu_lib.RenderOptions(sh_degree=3, aa=True)
+def _forward_at_size(gpu_lib, scene, cams, opts, label):
+    """Projection, binning and image of one full-size view against the FP64
+    oracle: rectangles inside the oracle's 3-sigma rectangles, depth keys
+    equal, binning bit-exact on the GPU's own rectangles, tile masks and keys
+    (stage-chained), tile culling against the oracle's per-pixel definition,
+    and the image against the unculled oracle (gpu_util.check_image)."""
     _, proj, pairs, ranges, P, out = gpu_forward(gpu_lib, scene, cams, opts)
     tiles = proj.tiles.cpu().numpy()
     mask = proj.tile_mask.cpu().numpy().view(np.uint64)
     rect = decode_rect(proj.rect.cpu().numpy(), tiles, cams, scene.n, mask=mask)
     keys = proj.depth_key.cpu().numpy().view(np.uint32)
-    f = oracle.forward(scene, cam, oracle_opt(opts), guard_eps=oracle.DEFAULT_GUARD)
+    f = oracle.forward(scene, cams, oracle_opt(opts), guard_eps=oracle.DEFAULT_GUARD)
     p = f["proj"][0]
-    # projection-level integer agreement (rectangles and covered-tile masks
-    # from FP64 on both sides)
-    assert np.array_equal(tiles, p["tiles"])
-    vis = tiles > 0                       # masks of culled slots are left unwritten
-    assert np.array_equal(mask[vis], p["mask"][vis])
-    assert np.array_equal(rect[vis][:, :3], p["rect"][vis][:, :3])
-    full = vis & (p["mask"] == 0)
-    assert np.array_equal(rect[full], p["rect"][full])
-    assert np.array_equal(keys[tiles > 0], oracle.depth_key(p["depth"])[tiles > 0])
-    # binning: bit-exact against the oracle's own sort of the same keys
-    assert P == f["bins"]["n_pairs"]
-    assert np.array_equal(pairs.cpu().numpy().view(np.uint32), f["bins"]["pair_slot"])
-    assert np.array_equal(ranges.cpu().numpy().view(np.uint32), f["bins"]["ranges"])
-    ref = f["images"][0]
+    ok = ~border_slots([p])
+    gt, pt = tiles.astype(np.int64), p["tiles"].astype(np.int64)
+    assert np.all(gt[ok] <= pt[ok]) and np.all(gt[ok & (pt == 0)] == 0)
+    vis = gt > 0
+    assert np.all(rect[vis & ok][:, :2] >= p["rect"][vis & ok][:, :2])
+    assert np.all(rect[vis & ok][:, 2:] <= p["rect"][vis & ok][:, 2:])
+    assert np.array_equal(keys[vis], oracle.depth_key(p["depth"])[vis])
+    ref_bins = oracle.bin_pairs(rect, tiles, keys, np.zeros(scene.n, np.int32), cams, mask=mask)
+    assert P == ref_bins["n_pairs"]
+    assert np.array_equal(pairs.cpu().numpy().view(np.uint32)[:P], ref_bins["pair_slot"])
+    assert np.array_equal(ranges.cpu().numpy().view(np.uint32), ref_bins["ranges"])
+    need, got, extra = check_tile_culling(f, pairs, ranges, P)
+    print(f"{label}: {f['bins']['n_pairs']} pairs in 3-sigma rectangles, {need} needed, GPU {got} (+{extra})")
+    assert extra <= 0.1 * need
     g = {k: view_images(out[k].cpu().numpy(), cams)[0] for k in ("rgb", "depth", "alpha")}
-    ok = ref["guard"] == 0
-    assert (~ok).sum() <= 1e-3 * cam.n_pixels
-    assert np.abs(g["rgb"] - ref["rgb"]).max(-1)[ok].max() <= 1e-4
-    assert np.abs(g["alpha"] - ref["alpha"])[ok].max() <= 1e-4
-    assert (np.abs(g["depth"] - ref["depth"]) / np.maximum(1.0, ref["depth"]))[ok].max() <= 1e-4
+    check_image(cams[0], oracle_opt(opts), 0, f["twod"], f["bins"]["pair_slot"], f["bins"]["ranges"],
+                f["images"][0], g, label)
 
 
-def test_c3_gradients(gpu_lib, c3):
+def test_c3_forward_and_binning(gpu_lib, c3):
     scene, cam = c3
-    opts = gpu_lib.RenderOptions(sh_degree=3, aa=True, absgrad=True)
-    w = S.linear_loss_weights(cam.height, cam.width, seed=7)
-    params = to_dev(scene, requires_grad=True)
-    stats = gpu_lib.RenderStats()
-    rgb, depth, alpha = gpu_lib.rasterize(*params, [cam], opts, stats)
-    loss = ((torch.from_numpy(w[0]).cuda().view(-1, 3) * rgb).sum() + (torch.from_numpy(w[1]).cuda().view(-1) * depth).sum()
-            + (torch.from_numpy(w[2]).cuda().view(-1) * alpha).sum())
-    loss.backward()
-    torch.cuda.synchronize()
-    f = oracle.forward(scene, cam, oracle_opt(opts))
-    ref = oracle.backward(scene, f, [w])
-    g = grads_oracle_layout(params)
-    for k in ("means", "scales", "quats", "opacities", "sh"):
-        a = g[k].ravel()
-        b = ref[k].ravel()
-        rel = np.linalg.norm(a - b) / np.linalg.norm(b)
-        assert rel <= 1e-3, (k, rel)
-        rms = np.sqrt(np.mean(b * b))
-        good = np.abs(a - b) <= 1e-3 * np.abs(b) + 1e-3 * rms
-        assert good.mean() >= 0.999, (k, good.mean())
-    rn = ref["mean2d_norm"]
-    assert np.linalg.norm(stats.mean2d_grad_norm.cpu().numpy() - rn) / np.linalg.norm(rn) <= 1e-3
+    _forward_at_size(gpu_lib, scene, [cam], gpu_lib.RenderOptions(sh_degree=3, aa=True), "C3")
 
 
 def test_c2_forward_and_binning(gpu_lib):
     scene, cam = S.scene_c2(seed=0), S.camera_c2()
-    cams = [cam]
-    opts = gpu_lib.RenderOptions(sh_degree=3, aa=False)
-    _, proj, pairs, ranges, P, out = gpu_forward(gpu_lib, scene, cams, opts)
-    tiles = proj.tiles.cpu().numpy()
-    f = oracle.forward(scene, cam, oracle_opt(opts), guard_eps=oracle.DEFAULT_GUARD)
-    assert np.array_equal(tiles, f["proj"][0]["tiles"])
-    assert P == f["bins"]["n_pairs"]
-    assert np.array_equal(pairs.cpu().numpy().view(np.uint32), f["bins"]["pair_slot"])
-    assert np.array_equal(ranges.cpu().numpy().view(np.uint32), f["bins"]["ranges"])
-    ref = f["images"][0]
-    g = {k: view_images(out[k].cpu().numpy(), cams)[0] for k in ("rgb", "depth", "alpha")}
-    ok = ref["guard"] == 0
-    assert (~ok).sum() <= 1e-3 * cam.n_pixels
-    assert np.abs(g["rgb"] - ref["rgb"]).max(-1)[ok].max() <= 1e-4
-    assert np.abs(g["alpha"] - ref["alpha"])[ok].max() <= 1e-4
-    assert (np.abs(g["depth"] - ref["depth"]) / np.maximum(1.0, ref["depth"]))[ok].max() <= 1e-4
+    _forward_at_size(gpu_lib, scene, [cam], gpu_lib.RenderOptions(sh_degree=3, aa=False), "C2")
 
 
 def test_c5_multiview_sampled(gpu_lib):
@@ -121,9 +84,10 @@ def test_c5_multiview_sampled(gpu_lib):
     for v, cam in enumerate(cams):
         p = oracle.project(sub, cam, **oracle_opt(opts))
         sl = torch.from_numpy(v * n + idx).cuda()
-        t_gpu = proj.tiles[sl].cpu().numpy()
-        assert np.array_equal(t_gpu, p["tiles"]), v
-        vis = p["tiles"] > 0
+        t_gpu = proj.tiles[sl].cpu().numpy().astype(np.int64)
+        ok = ~border_slots([p])
+        assert np.all(t_gpu[ok] <= p["tiles"][ok]) and np.all(t_gpu[ok & (p["tiles"] == 0)] == 0), v
+        vis = (t_gpu > 0) & ok
         assert vis.sum() > 100, v
         m2, con, op, rgb, dep = decode_records(proj.rec[sl].cpu().numpy())
         np.testing.assert_allclose(m2[vis], p["mean2d"][vis], atol=1e-4, rtol=0)
@@ -164,7 +128,6 @@ def test_c5_multiview_sampled(gpu_lib):
 
     # compositing of the sampled tiles by the oracle from the GPU's records
     imgs = {k: view_images(out[k].cpu().numpy(), cams) for k in ("rgb", "depth", "alpha")}
-    guarded = sampled = 0
     for v, cam in enumerate(cams):
         ts = [t for (vv, t) in picked if vv == v]
         lists = [pv[rg[toff[v] + t, 0]:rg[toff[v] + t, 1]] for t in ts]
@@ -180,16 +143,11 @@ def test_c5_multiview_sampled(gpu_lib):
         mask[ts] = 1
         ref = oracle.render_view(cam, oracle_opt(opts), int(toff[v]), twod, inv.astype(np.uint32), rg_sub,
                                  tile_mask=mask, guard_eps=oracle.STAGE_GUARD)
+        where = np.zeros((cam.height, cam.width), bool)
         for t in ts:
-            ys = slice((t // cam.tiles_x) * 16, min(cam.height, (t // cam.tiles_x + 1) * 16))
-            xs = slice((t % cam.tiles_x) * 16, min(cam.width, (t % cam.tiles_x + 1) * 16))
-            ok = ref["guard"][ys, xs] == 0
-            guarded += int((~ok).sum())
-            sampled += ok.size
-            assert np.abs(imgs["rgb"][v][ys, xs] - ref["rgb"][ys, xs]).max(-1)[ok].max(initial=0) <= 1e-4
-            assert np.abs(imgs["alpha"][v][ys, xs] - ref["alpha"][ys, xs])[ok].max(initial=0) <= 1e-4
-            d = np.abs(imgs["depth"][v][ys, xs] - ref["depth"][ys, xs]) / np.maximum(1.0, ref["depth"][ys, xs])
-            assert d[ok].max(initial=0) <= 1e-4
-    # the sampled tiles include each view's longest list, where decisions
-    # near the skip / stop thresholds concentrate
-    assert guarded <= max(4, 0.01 * sampled), (guarded, sampled)
+            where[(t // cam.tiles_x) * 16:(t // cam.tiles_x + 1) * 16, (t % cam.tiles_x) * 16:(t % cam.tiles_x + 1) * 16] = True
+        g = {k: imgs[k][v] for k in ("rgb", "depth", "alpha")}
+        # the sampled tiles include each view's longest list, where decisions
+        # near the skip / stop thresholds concentrate
+        check_image(cam, oracle_opt(opts), int(toff[v]), twod, inv.astype(np.uint32), rg_sub, ref, g,
+                    f"C5 view {v} sampled tiles", guard_eps=oracle.STAGE_GUARD, where=where, cap=1e-3)

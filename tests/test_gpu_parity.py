@@ -3,12 +3,18 @@
 Tolerances (from the float32 arithmetic of each stage):
   projection: mean2d |d| <= 1e-4 px; conic, opacity', depth, rgb relative
       <= 2e-6 (FP64 arithmetic rounded once to FP32);
-  tile rectangles and counts: equal, except Gaussians whose extent or mean
-      sits within 1e-9 of an integer (none expected);
+  tile rectangles: inside the oracle's 3-sigma rectangles, empty where those
+      are (Gaussians whose extent or mean sits within 1e-9 of an integer
+      aside); tile culling: every (tile, Gaussian) pair where the oracle's
+      FP64 record passes the skip rule at some pixel centre is listed, every
+      listed pair lies in a 3-sigma rectangle, and the listed pairs beyond
+      the needed ones stay below 10 %;
   binning and sort: bit-exact on the GPU's own records (stage-chained);
   compositing: max |d| <= 1e-4 on rgb and alpha, depth <= 1e-4 max(1, depth),
-      outside the guard band (pixels where an evaluated alpha is within a
-      relative eps of 1/255 or T(1 - alpha) within eps of 1e-4);
+      outside the guard band (pixels where a skip, clamp or stop decision
+      lies within the float32 error bound of oracle.DEFAULT_GUARD); a pixel
+      inside it must match one of the results its flagged decisions allow
+      (gpu_util.check_image), at most 1e-4 of the pixels unresolved;
   gradients: per group ||g - g_ref|| / ||g_ref|| <= 1e-3, and elementwise
       |g - g_ref| <= 1e-3 |g_ref| + 1e-3 rms(g_ref) for >= 99.9% of entries.
 """
@@ -20,8 +26,8 @@ import torch
 
 import oracle
 import synthetic as S
-from gpu_util import (decode_records, decode_rect, gpu_forward, grads_oracle_layout, oracle_opt, to_dev,
-                      view_images)
+from gpu_util import (border_slots, check_image, check_tile_culling, decode_records, decode_rect, gpu_forward, grads_oracle_layout,
+                      oracle_opt, to_dev, view_images)
 
 pytestmark = pytest.mark.gpu
 
@@ -66,17 +72,15 @@ def test_projection_matches_oracle(gpu_lib, case):
     for v, c in enumerate(cams):
         p = oracle.project(scene, c, **oracle_opt(opts))
         sl = slice(v * n, (v + 1) * n)
-        border = (p["tiles"] > 0) & ((np.abs(p["extent"] - np.round(p["extent"])) < 1e-9) |
-                                     np.any(np.abs(p["mean2d"] - np.round(p["mean2d"])) < 1e-9, axis=1))
-        ok = ~border
-        np.testing.assert_array_equal(tiles[sl][ok], p["tiles"][ok])
-        vis = (p["tiles"] > 0) & ok
-        # exact tile culling: the same covered-tile masks; rectangles agree in
-        # origin and width (the height of a masked one is its last covered row)
-        np.testing.assert_array_equal(mask[sl][vis], p["mask"][vis])
-        np.testing.assert_array_equal(rect[sl][ok][:, :3], p["rect"][ok][:, :3])
-        full = ok & (p["mask"] == 0)
-        np.testing.assert_array_equal(rect[sl][full], p["rect"][full])
+        ok = ~border_slots([p])
+        # the GPU rectangle is the oracle's 3-sigma rectangle narrowed by tile
+        # culling (whose tiles are checked against the oracle's definition in
+        # the binning tests): inside it, and empty where it is empty
+        gt, pt = tiles[sl].astype(np.int64), p["tiles"].astype(np.int64)
+        assert np.all(gt[ok] <= pt[ok]) and np.all(gt[ok & (pt == 0)] == 0)
+        vis = (gt > 0) & ok
+        r, q = rect[sl][vis], p["rect"][vis]
+        assert np.all(r[:, :2] >= q[:, :2]) and np.all(r[:, 2:] <= q[:, 2:])
         assert vis.sum() > 10
         m2, con, op, rgb, dep = decode_records(rec[sl])
         np.testing.assert_allclose(m2[vis], p["mean2d"][vis], atol=1e-4, rtol=0)
@@ -104,15 +108,11 @@ def test_binning_bit_exact_stage_chained(gpu_lib, case):
     assert P == ref["n_pairs"] and P > 0
     np.testing.assert_array_equal(pairs.cpu().numpy().view(np.uint32), ref["pair_slot"])
     np.testing.assert_array_equal(ranges.cpu().numpy().view(np.uint32), ref["ranges"])
-
-
-def _guarded_compare(gpu_img, ref, guard, tol=1e-4):
-    ok = guard == 0
-    d_rgb = np.abs(gpu_img["rgb"] - ref["rgb"]).max(axis=-1)
-    d_a = np.abs(gpu_img["alpha"] - ref["alpha"])
-    d_d = np.abs(gpu_img["depth"] - ref["depth"]) / np.maximum(1.0, np.abs(ref["depth"]))
-    worst = max(d_rgb[ok].max(initial=0), d_a[ok].max(initial=0), d_d[ok].max(initial=0))
-    return worst, int((~ok).sum())
+    # the GPU's culled tiles against the oracle's per-pixel definition
+    f = oracle.forward(scene, cams, oracle_opt(opts), guard_eps=None)
+    need, got, extra = check_tile_culling(f, pairs, ranges, P)
+    print(f"{case}: {f['bins']['n_pairs']} pairs in 3-sigma rectangles, {need} needed, GPU {got} (+{extra})")
+    assert extra <= 0.1 * need
 
 
 @pytest.mark.parametrize("case", list(CASES))
@@ -130,9 +130,8 @@ def test_compositing_stage_chained(gpu_lib, case):
     for v, c in enumerate(cams):
         ref = oracle.render_view(c, oracle_opt(opts), int(toff[v]), twod, pv, rg, guard_eps=oracle.STAGE_GUARD)
         g = {k: gimgs[k][v] for k in gimgs}
-        worst, guarded = _guarded_compare(g, ref, ref["guard"])
-        assert worst <= 1e-4, (v, worst)
-        assert guarded <= max(2, 1e-3 * c.n_pixels), guarded
+        check_image(c, oracle_opt(opts), int(toff[v]), twod, pv, rg, ref, g, f"{case} view {v} stage-chained",
+                    guard_eps=oracle.STAGE_GUARD)
         same_last = (g["last"] == ref["last"]) | (ref["guard"] != 0)
         assert same_last.all()
 
@@ -145,13 +144,11 @@ def test_forward_end_to_end(gpu_lib, case):
     opts = _opts(gpu_lib, od)
     _, _, _, _, P, out = gpu_forward(gpu_lib, scene, cams, opts)
     f = oracle.forward(scene, cams, oracle_opt(opts), guard_eps=oracle.DEFAULT_GUARD)
-    assert f["bins"]["n_pairs"] == P
+    assert f["bins"]["n_pairs"] >= P
     for v, c in enumerate(cams):
         g = {k: view_images(out[k].cpu().numpy(), cams)[v] for k in ("rgb", "depth", "alpha", "T", "last")}
-        ref = f["images"][v]
-        worst, guarded = _guarded_compare(g, ref, ref["guard"])
-        assert worst <= 1e-4, (v, worst)
-        assert guarded <= max(2, 1e-3 * c.n_pixels), guarded
+        check_image(c, oracle_opt(opts), int(f["bins"]["tile_off"][v]), f["twod"], f["bins"]["pair_slot"],
+                    f["bins"]["ranges"], f["images"][v], g, f"{case} view {v} end to end")
 
 
 @pytest.mark.parametrize("case", ["c1", "ragged_aa"])
@@ -365,7 +362,7 @@ def test_single_gaussian_and_tiny_image(gpu_lib):
         _, _, _, _, P, out = gpu_forward(gpu_lib, scene, [cam], opts)
         f = oracle.forward(scene, cam, oracle_opt(opts))
         ref = f["images"][0]
-        assert P == f["bins"]["n_pairs"]
+        assert 0 < P <= f["bins"]["n_pairs"]
         np.testing.assert_allclose(out["rgb"].cpu().numpy().reshape(H, W, 3), ref["rgb"], atol=1e-5)
 
 
