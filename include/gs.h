@@ -258,6 +258,20 @@ int gs_loss_l1_depth(const float *rgb, const float *depth, const float *alpha, c
                      const float *target_depth, int64_t n_pix, float lambda_depth, float *loss, float *d_rgb,
                      float *d_depth, float *d_alpha, void *ws, size_t ws_bytes, void *stream);
 
+/* gs_loss_l1_depth without a workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving or training
+ * loops, harnesses that forbid allocation).  Same arguments, kernels and
+ * results as gs_loss_l1_depth; its workgroup partials live in a static
+ * 256 KiB array of the library, one copy per GPU (held until the process
+ * ends), whose address is looked up once per device on the first call.  It
+ * allocates nothing and needs no zeroed memory (every partial is written
+ * before it is read).  n_pix above 2^26 (67,108,864 pixels) returns
+ * GS_ERR_CAPACITY.  Calls that overlap in time on one GPU (different
+ * streams or threads) share that array and race: serialise them. */
+int gs_loss_l1_depth_noalloc(const float *rgb, const float *depth, const float *alpha, const float *target_rgb,
+                             const float *target_depth, int64_t n_pix, float lambda_depth, float *loss,
+                             float *d_rgb, float *d_depth, float *d_alpha, void *stream);
+
 /* D-SSIM term of Eq. 3 and its gradient: weight * (1 - mean SSIM) over the
  * 3 width * height values of rgb against target (both [H][W][3] float32),
  * SSIM per pixel and channel with an 11x11 Gaussian window (sigma 1.5,

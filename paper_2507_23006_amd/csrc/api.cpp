@@ -353,6 +353,27 @@ int gs_loss_l1_depth(const float* rgb, const float* depth, const float* alpha, c
     }
 }
 
+int gs_loss_l1_depth_noalloc(const float* rgb, const float* depth, const float* alpha, const float* target_rgb,
+                             const float* target_depth, int64_t n_pix, float lambda_depth, float* loss, float* d_rgb,
+                             float* d_depth, float* d_alpha, void* stream) {
+    try {
+        GS_REQUIRE(n_pix >= 1, "n_pix=%lld out of range", (long long)n_pix);
+        if (n_pix > loss_scratch_max_pixels())
+            return fail(GS_ERR_CAPACITY, "n_pix=%lld exceeds the %lld pixels of the static scratch", (long long)n_pix,
+                        (long long)loss_scratch_max_pixels());
+        GS_REQUIRE(rgb && target_rgb && loss && d_rgb && d_depth && d_alpha, "NULL buffer");
+        GS_REQUIRE(!target_depth || (depth && alpha), "the depth term needs depth and alpha");
+        GS_REQUIRE(std::isfinite(lambda_depth), "lambda_depth not finite");
+        double* scratch = nullptr;
+        GS_HIP(loss_scratch_ptr(&scratch));
+        GS_HIP(launch_loss(rgb, depth, alpha, target_rgb, target_depth, n_pix, lambda_depth, loss, d_rgb, d_depth,
+                           d_alpha, scratch, (hipStream_t)stream));
+        return GS_OK;
+    } catch (...) {
+        return fail(GS_ERR_INTERNAL, "unexpected exception in gs_loss_l1_depth_noalloc");
+    }
+}
+
 size_t gs_dssim_workspace_size(int32_t width, int32_t height) {
     if (width < 1 || height < 1) return 0;
     Carver c(nullptr);

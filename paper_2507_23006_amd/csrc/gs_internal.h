@@ -211,6 +211,10 @@ hipError_t launch_render_bwd(const Projected& proj, const uint32_t* pair_vals, c
 
 // training loss (loss.hip): per-workgroup partial sums, then a fixed-order total
 size_t loss_partials(int64_t n_pix);
+// the allocation-free loss: largest pixel count its file-scope scratch
+// holds, and that scratch's address on the current device
+int64_t loss_scratch_max_pixels();
+hipError_t loss_scratch_ptr(double** out);
 hipError_t launch_loss(const float* rgb, const float* depth, const float* alpha, const float* t_rgb,
                        const float* t_depth, int64_t n_pix, float lambda, float* loss, float* d_rgb, float* d_depth,
                        float* d_alpha, double* partial, hipStream_t s);

@@ -8,6 +8,8 @@
 // gradient below 1e-10), and the workgroup writes its partial sum; one
 // workgroup then adds the partials in a fixed order, so the loss is
 // deterministic.  HBM-bound: 36 bytes read and 20 written per pixel.
+#include <mutex>
+
 #include "gs_internal.h"
 
 namespace gs {
@@ -17,6 +19,10 @@ namespace {
 constexpr int kLossThreads = 256;
 constexpr int kLossPerThread = 8;
 constexpr int kLossSpan = kLossThreads * kLossPerThread;
+// partials of the allocation-free entry point: 32768 doubles (256 KiB) per
+// GPU, enough for 2^26 pixels (eight 3840x2160 views)
+constexpr int kLossScratchPartials = 32768;
+constexpr int kMaxDevices = 64;
 
 __device__ __forceinline__ float sgn(float x) { return x > 0.0f ? 1.0f : (x < 0.0f ? -1.0f : 0.0f); }
 
@@ -88,7 +94,34 @@ __global__ __launch_bounds__(1024) void k_loss_final(const double* __restrict__ 
 
 }  // namespace
 
+// Scratch of the allocation-free entry point: the workgroup partials live
+// in this file-scope array (one copy per GPU, kept until the process ends)
+// instead of a caller workspace.  Host code never passes the array's name
+// to a kernel -- on the host it only stands in for the symbol -- but the
+// address hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) double scratch[kLossScratchPartials];
+
 size_t loss_partials(int64_t n_pix) { return (size_t)((n_pix + kLossSpan - 1) / kLossSpan); }
+
+int64_t loss_scratch_max_pixels() { return (int64_t)kLossScratchPartials * kLossSpan; }
+
+hipError_t loss_scratch_ptr(double** out) {
+    static std::mutex mu;
+    static double* ptr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        ptr[dev] = static_cast<double*>(p);
+    }
+    *out = ptr[dev];
+    return hipSuccess;
+}
 
 hipError_t launch_loss(const float* rgb, const float* depth, const float* alpha, const float* t_rgb,
                        const float* t_depth, int64_t n_pix, float lambda, float* loss, float* d_rgb, float* d_depth,
