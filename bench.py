@@ -28,16 +28,33 @@ METRIC = "train fwd+bwd iters/s & render Mpix/s, 6M Gaussians 1080p; p50/p99 ser
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3     # MI355X vector FP32 (2 flops per FMA lane, dual issue)
 
-# Algorithmic cost models:
-# FP32 flops per compositing evaluation (an FMA counts 2, exp2 counts 1):
-#   forward: dx, dy (2) + 3 products (3) + 2 FMA (4) + exp2 (1) + o'G (1)
-#            + T(1 - a) (2) + a T (1) + 4 FMA blends (8)              = 22
-#   backward (per entry before `last`): recompute (11) + rcp and T_i (2)
-#            + weight (1) + dL/da (13) + colour/depth grads (4)
-#            + d o', d power (2) + d mean (10) + d conic (7)
-#            + recurrences (12) + |d mean| (0)                         = 62
-FLOPS_FWD_EVAL = 22.0
-FLOPS_BWD_EVAL = 62.0
+# Algorithmic cost models per unit of work, on each kernel's own duration:
+# * compositing forward: an evaluation is one (pixel, list entry whose alpha
+#   box holds the pixel centre) up to the pixel's stop; ~14 VALU operations
+#   and one exp (a quarter-rate transcendental, 4 issue slots) = 18 issue
+#   slots per evaluation;
+# * compositing backward: an evaluation is one (pixel, box-covered entry) up
+#   to the pixel's last composited entry; ~40 VALU operations, one exp and
+#   one reciprocal = 42 operations per evaluation;
+# * projection: 16 B per Gaussian (mean, plus the tile count written) and
+#   272 B per visible Gaussian (the other 224 B of parameters read, 48 B of
+#   record written);
+# * binning: 172 B per pair (12 B emitted, 8 B histogram read, 24 B per
+#   8-bit pass of a 45-bit (tile, depth) key sort -- 6 passes --, 8 B range
+#   read), whatever the design does;
+# * projection backward: 536 B per visible Gaussian (236 B parameters, 40 B
+#   2D gradients and 16 B saved values read; 236 B gradients and 8 B
+#   statistics written).
+# ALU work is reported in TFLOP/s of those operations against the 157.3
+# TFLOP/s FP32 vector peak (packed, FMA = 2), and as a fraction of the issue
+# ceiling of 256 CUs x 64 lanes x 2.4 GHz = 39.3e12 lane operations/s (the
+# non-packed rate this build runs at).
+OPS_FWD_EVAL = 18.0
+OPS_BWD_EVAL = 42.0
+ISSUE_PEAK = 256 * 64 * 2.4e9
+BIN_BYTES_PER_PAIR = 172.0
+PROJ_BYTES_ALL, PROJ_BYTES_VIS = 16.0, 272.0
+PROJ_BWD_BYTES_VIS = 536.0
 
 
 def parse():
@@ -48,6 +65,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-crop", type=int, default=16, help="oracle baseline renders 1/crop of the pixels")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving trace")
+    ap.add_argument("--no-configs", action="store_true", help="skip the C1, C2 and C5 lines")
     ap.add_argument("--serve-requests", type=int, default=2000, help="requests of the serving trace")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-MiB device buffer 3 times (reference kernel for HBM byte counters)")
@@ -68,29 +86,110 @@ def copy_probe(mib):
     print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4, "copies": 3}))
 
 
-def n_tiles_of(n_pix):
-    return max(1, n_pix // 256)
+def pct(xs, q):
+    """q-quantile (linear interpolation) of a list of step times."""
+    return float(np.percentile(np.asarray(xs, np.float64), q))
 
 
-def stage_bytes(n, n_front, n_vis, n_pairs, n_pix, n_views=1):
-    """Algorithmic HBM bytes of each memory-bound stage for one launch
-    (S = slots = n * views, V = visible slots, P = pairs)."""
-    S = n * n_views
-    tile_passes = max(1, math.ceil(math.log2(max(2, n_tiles_of(n_pix))) / 8))
-    return {
-        # means of all (12) + scales, quats, opacity of those in front (32) + SH row of
-        # visible (192); writes: tiles + depth key of all (8) + record 64, rect 8, tile mask 8 of visible
-        "project": 12 * n + 32 * n_front + 192 * n_vis + 8 * S + 80 * n_vis,
-        # visible flags (tiles in, flag out) and their scan (12) over all slots; compaction
-        # (tiles, position, key in; key, slot out of visible); depth sort of the visible, 4 passes
-        # of (key 4 + key, value 8 in; 8 out); gather by depth rank (slot, tiles, rectangle,
-        # mask in; tiles, rectangle, mask out: 44) and the scan of tiles (12); emission (8 per
-        # pair, 20 per rank); tile sort passes of 20 per pair; ranges (4 per pair)
-        "bin_sort": (8 * S + 12 * S + 12 * S + 8 * n_vis + 4 * 20 * n_vis + 44 * n_vis + 12 * n_vis
-                     + 8 * n_pairs + 20 * n_vis + tile_passes * 20 * n_pairs + 4 * n_pairs),
-        # tiles of all (4); params 236 + 2D grads 48 of visible; gradients 236 + norm 4 of all
-        "project_bwd": 4 * S + (236 + 48) * n_vis + 236 * n + 4 * S,
-    }
+def step_times(torch, step, steps, warmup):
+    """W untimed steps, then K steps bracketed by a synchronisation on both
+    sides; each step also between two events on the current stream.
+    Returns (wall ms per step over the K steps, per-step event ms)."""
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        evs.append(_ev(torch))
+        step()
+    evs.append(_ev(torch))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    per = [evs[i].elapsed_time(evs[i + 1]) for i in range(steps)]
+    return (t1 - t0) * 1000.0 / steps, per
+
+
+def summary(per):
+    return {"median": round(pct(per, 50), 4), "p10": round(pct(per, 10), 4), "p90": round(pct(per, 90), 4),
+            "mean": round(float(np.mean(per)), 4)}
+
+
+def in_front(torch, params, cams):
+    """Gaussians whose view depth lies in [near, far] of some view."""
+    means = params[0].detach()
+    hit = torch.zeros(means.shape[1], dtype=torch.bool, device=means.device)
+    for c in cams:
+        vm = torch.tensor(np.asarray(c.viewmat, np.float32), device=means.device)
+        z = vm[2, :3] @ means + vm[2, 3]
+        hit |= (z >= c.near) & (z <= c.far)
+    return int(hit.sum().item())
+
+
+def kernel_roofline(name, ms, n, n_vis, P, e_fwd, e_bwd):
+    """The per-unit model of one timed kernel over its own average launch
+    duration `ms`."""
+    t = ms * 1e-3
+    if name in ("k_render_fwd", "k_render_bwd"):
+        ops = (OPS_FWD_EVAL * e_fwd) if name == "k_render_fwd" else (OPS_BWD_EVAL * e_bwd)
+        evals = e_fwd if name == "k_render_fwd" else e_bwd
+        ach = ops / t / 1e12
+        return {"bound": "alu", "kernel": name, "achieved": round(ach, 3), "peak": FP32_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(ach / FP32_PEAK_TFLOPS, 4),
+                "issue_frac": round(ops / t / ISSUE_PEAK, 4), "evals_per_s": round(evals / t, 1),
+                "model": f"{OPS_FWD_EVAL if name == 'k_render_fwd' else OPS_BWD_EVAL:.0f} operations x {evals} "
+                         f"evaluations per launch", "launch_ms": round(ms, 4)}
+    if name == "k_project_fwd":
+        b = PROJ_BYTES_ALL * n + PROJ_BYTES_VIS * n_vis
+        model = f"16 B x {n} Gaussians + 272 B x {n_vis} visible"
+    elif name == "bin_sort":
+        b = BIN_BYTES_PER_PAIR * P
+        model = f"172 B x {P} pairs"
+    else:
+        b = PROJ_BWD_BYTES_VIS * n_vis
+        model = f"536 B x {n_vis} visible"
+    ach = b / t / 1e9
+    return {"bound": "hbm", "kernel": name, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "bytes": int(b), "model": model, "launch_ms": round(ms, 4)}
+
+
+def train_config(gs, torch, S, scene, cams, opts, tgt, steps, warmup, depth_term=True):
+    """One training step (projection, binning, compositing, loss, full
+    backward) on the given views: step times, forward-only render times,
+    pairs and visible counts."""
+    dev = torch.device("cuda:0")
+    params = [torch.from_numpy(a).to(dev).requires_grad_(True) for a in scene.param_arrays()]
+    stats = gs.RenderStats()
+    tgt_rgb, tgt_d = tgt
+
+    def step():
+        for p in params:
+            p.grad = None
+        rgb, depth, alpha = gs.rasterize(*params, cams, opts, stats)
+        loss = gs.l1_depth_loss(rgb, depth, alpha, tgt_rgb, tgt_d if depth_term else None, 0.5)
+        loss.backward()
+
+    wall, per = step_times(torch, step, steps, warmup)
+    pd = [p.detach() for p in params]
+
+    def fwd():
+        proj = gs.project(*pd, cams, opts)
+        pv, rg, P = gs.bin_sort(proj, cams, scene.n)
+        gs.render_fwd(proj, pv, rg, cams, opts)
+
+    with torch.no_grad():
+        _, per_f = step_times(torch, fwd, steps, 3)
+        proj = gs.project(*pd, cams, opts)
+        pv, rg, P = gs.bin_sort(proj, cams, scene.n)
+        n_vis = int((proj.tiles > 0).sum().item())
+    npix = sum(c.width * c.height for c in cams)
+    med, med_f = pct(per, 50), pct(per_f, 50)
+    out = {"iters_per_s": round(1000.0 / med, 2), "step_ms": summary(per), "wall_ms_per_step": round(wall, 4),
+           "render_mpix_s": round(npix / (med_f * 1e-3) / 1e6, 1), "render_ms": summary(per_f),
+           "gaussians": scene.n, "views": len(cams), "pixels": npix, "visible_slots": n_vis, "pairs": int(P)}
+    del params, stats, pd, proj, pv, rg
+    torch.cuda.synchronize()
+    return out
 
 
 def main():
@@ -133,30 +232,40 @@ def main():
         loss.backward()
         return loss
 
-    # stage timing with stream events
+    # stage timing with stream events between the library calls, and the
+    # library's own events around each main kernel
     marks = []
 
     def hook(name):
-        ev = torch.cuda.Event(enable_timing=True)
-        ev.record()
-        marks.append((name, ev))
+        marks.append((name, _ev(torch)))
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
 
-    stage_ms = {}
     gs.set_stage_hook(hook)
+    gs.kernel_timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         marks.append(("start", _ev(torch)))
         step()
+    marks.append(("start", _ev(torch)))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     gs.set_stage_hook(None)
-    prev = None
+    kernel_ms = {}
+    for k in gs.rasterizer.KERNELS_TIMED:
+        tot, cnt = gs.kernel_timing_read(k)
+        if cnt:
+            kernel_ms[k] = tot / cnt
+    gs.kernel_timing(False)
+    stage_ms, per_step, prev, start = {}, [], None, None
     for name, ev in marks:
+        if name == "start":
+            if start is not None:
+                per_step.append(start.elapsed_time(ev))
+            start = ev
         if prev is not None and name != "start":
             stage_ms[name] = stage_ms.get(name, 0.0) + prev.elapsed_time(ev)
         prev = ev
@@ -170,56 +279,31 @@ def main():
     # forward-only render rate
     with torch.no_grad():
         pd = [p.detach() for p in params]
-        for _ in range(3):
+
+        def fwd():
             proj = gs.project(*pd, cams, opts)
             pv, rg, P = gs.bin_sort(proj, cams, scene.n)
             gs.render_fwd(proj, pv, rg, cams, opts)
-        torch.cuda.synchronize()
-        r0 = time.perf_counter()
-        for _ in range(args.steps):
-            proj = gs.project(*pd, cams, opts)
-            pv, rg, P = gs.bin_sort(proj, cams, scene.n)
-            out = gs.render_fwd(proj, pv, rg, cams, opts)
-        torch.cuda.synchronize()
-        r1 = time.perf_counter()
-        ms_fwd = (r1 - r0) * 1000.0 / args.steps
+
+        _, per_fwd = step_times(torch, fwd, args.steps, 3)
+        ms_fwd = pct(per_fwd, 50)
         # workload statistics for the cost models (outside the timed regions)
-        n_front = int((proj.depth_key.view(torch.int32) != -1).sum().item())
-        tiles = proj.tiles
-        n_vis = int((tiles > 0).sum().item())
+        proj = gs.project(*pd, cams, opts)
+        pv, rg, P = gs.bin_sort(proj, cams, scene.n)
+        out = gs.render_fwd(proj, pv, rg, cams, opts)
+        n_front = in_front(torch, params, cams)
+        n_vis = int((proj.tiles > 0).sum().item())
         counts = gs.render_count(proj, pv, rg, cams).to(torch.int64).sum(0).tolist()
         e_fwd, e_bwd = int(counts[0]), int(counts[1])
     npix = W * H
 
-    # roofline of the dominant stage
-    stage_flops = {"render_fwd": FLOPS_FWD_EVAL * e_fwd, "composite_bwd": FLOPS_BWD_EVAL * e_bwd}
-    dom = max((k for k in stage_ms if k != "loss"), key=stage_ms.get)
-    roof = None
-    if dom in stage_flops:
-        ach = stage_flops[dom] / (stage_ms[dom] * 1e-3) / 1e12
-        roof = {"bound": "alu", "kernel": dom, "achieved": round(ach, 3), "peak": FP32_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(ach / FP32_PEAK_TFLOPS, 4), "traffic": None}
-    else:
-        b = stage_bytes(scene.n, n_front, n_vis, P, npix).get(dom)
-        if b:
-            ach = b / (stage_ms[dom] * 1e-3) / 1e9
-            roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None}
+    # every timed kernel against its model; the roofline object is the
+    # longest-running one
+    kroof = {k: kernel_roofline(k, ms, scene.n, n_vis, P, e_fwd, e_bwd) for k, ms in kernel_ms.items()}
+    dom = max(kernel_ms, key=kernel_ms.get) if kernel_ms else None
+    roof = dict(kroof[dom]) if dom else None
 
     nxt = next_rows_bench(gs, torch, scene.n, W, H, dev, max(5, args.steps))
-
-    # HBM fraction of every memory-bound stage, ALU fraction of compositing
-    sb = stage_bytes(scene.n, n_front, n_vis, P, npix)
-    stage_roof = {}
-    for k, b in sb.items():
-        if k in stage_ms:
-            gbs = b / (stage_ms[k] * 1e-3) / 1e9
-            stage_roof[k] = {"bound": "hbm", "bytes": int(b), "GB_s": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
-    for k, f in stage_flops.items():
-        if k in stage_ms:
-            tf = f / (stage_ms[k] * 1e-3) / 1e12
-            stage_roof[k] = {"bound": "alu", "flops": int(f), "TFLOP_s": round(tf, 2),
-                             "frac": round(tf / FP32_PEAK_TFLOPS, 4)}
 
     serve = None
     if not args.no_serve:
@@ -231,7 +315,11 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(scene, cam, args.cpu_crop)
+        cpu = cpu_baseline(scene, [cam], args.cpu_crop)
+
+    configs = None
+    if not args.no_configs:
+        configs = other_configs(gs, torch, S, args, not args.no_cpu)
 
     rec = {
         "metric": METRIC,
@@ -250,26 +338,60 @@ def main():
                                "1920x1080 street-level camera, AA dilation 0.3 + compensation, SH3; "
                                "step = fwd + L1(rgb) + 0.5 L1(expected depth) + bwd to all parameters",
                    "n_gaussians": scene.n, "width": W, "height": H, "views": 1},
+        "step_ms": summary(per_step),
+        "iters_per_s_median": round(1000.0 / pct(per_step, 50), 3),
         "render_mpix_s": round(npix / (ms_fwd * 1e-3) / 1e6, 1),
-        "render_ms": round(ms_fwd, 3),
+        "render_ms": summary(per_fwd),
         "serve_p50_ms": serve["served"]["p50_ms"] if serve else None,
         "serve_p99_ms": serve["served"]["p99_ms"] if serve else None,
         "serve": serve,
         "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
+        "kernel_ms": {k: round(v, 4) for k, v in kernel_ms.items()},
         "workload_stats": {"visible": n_vis, "in_front": n_front, "pairs": P, "evals_fwd": e_fwd, "evals_bwd": e_bwd},
         "roofline": roof,
-        "stage_roofline": stage_roof,
+        "kernel_roofline": kroof,
         "cpu_baseline": cpu,
+        "configs": configs,
         "next_rows": nxt,
     }
     print(json.dumps(rec), flush=True)
 
 
+def other_configs(gs, torch, S, args, with_cpu):
+    """C1 (4096 Gaussians, 160x120), C2 (1M, 1600x1066) and C5 (12M, eight
+    views, 25.57 Mpix per launch): step times on the GPU beside the oracle
+    on the host (C1 whole, C2 and C5 on a cropped sample)."""
+    dev = torch.device("cuda:0")
+    out = {}
+    specs = [
+        ("C1", lambda: (S.scene_c1(), [S.camera_c1()]), False, False, 1),
+        ("C2", lambda: (S.scene_c2(seed=0), [S.camera_c2()]), False, True, 16),
+        ("C5", lambda: (S.scene_urban(12_000_000, 400, seed=0), S.cameras_c5()), True, True, 64),
+    ]
+    for name, make, aa, depth_term, crop in specs:
+        t = time.time()
+        scene, cams = make()
+        tgt_rgb = torch.cat([torch.from_numpy(S.target_rgb(c.height, c.width, seed=1)).view(-1, 3) for c in cams]).to(dev)
+        tgt_d = torch.cat([torch.from_numpy(S.target_depth(c.height, c.width, seed=1)).view(-1) for c in cams]).to(dev)
+        opts = gs.RenderOptions(sh_degree=3, dilation=0.3, aa=aa)
+        rec = train_config(gs, torch, S, scene, cams, opts, (tgt_rgb, tgt_d), args.steps, args.warmup, depth_term)
+        if with_cpu:
+            rec["cpu_baseline"] = cpu_baseline(scene, cams, crop, aa=aa, repeats=5 if crop == 1 else 1)
+        out[name] = rec
+        print(f"# {name}: {rec['iters_per_s']} iters/s, {rec['render_mpix_s']} Mpix/s ({time.time() - t:.1f} s)",
+              file=sys.stderr, flush=True)
+        del scene, tgt_rgb, tgt_d
+    return out
+
+
 # Algorithmic HBM bytes per unit of the kernels measured beside the step
 APP_FWD_BYTES = 64 + 16            # per Gaussian: embedding in, offsets out
 APP_BWD_BYTES = 64 + 16 + 16 + 64  # embedding, offsets and their gradient in; embedding gradient out
-APP_FWD_MFMA, APP_BWD_MFMA = 64, 104          # v_mfma_f32_16x16x4_f32 per 64 Gaussians
-MFMA_F32_FLOPS = 16 * 16 * 4 * 2
+# algorithmic flops per Gaussian (the image-embedding half of the first
+# layer is one bias per image): forward 16x32 + 32x4 products, backward dh,
+# dW2, dW1 (Gaussian half) and dx
+APP_FWD_FLOPS = 2 * (16 * 32 + 32 * 4)
+APP_BWD_FLOPS = 2 * (32 * 4 + 32 * 4 + 16 * 32 + 16 * 32)
 # D-SSIM per pixel (3 channels, float32): forward reads x, y and writes 3
 # partials; backward reads the partials, x and y and writes dx
 DSSIM_BYTES = (12 + 12 + 36) + (36 + 12 + 12 + 12)
@@ -348,14 +470,15 @@ def next_rows_bench(gs, torch, n, W, H, dev, reps):
         gbs = nbytes / (ms * 1e-3) / 1e9
         return {"achieved_GB_s": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
 
-    def mfma(n_mfma, ms):
-        tf = n * n_mfma / 64 * MFMA_F32_FLOPS / (ms * 1e-3) / 1e12
-        return {"achieved_TFLOP_s": round(tf, 2), "peak": 157.3, "frac": round(tf / 157.3, 4)}
+    def mfma(flops, ms):
+        tf = n * flops / (ms * 1e-3) / 1e12
+        return {"achieved_TFLOP_s": round(tf, 2), "peak": 157.3, "frac": round(tf / 157.3, 4),
+                "flops_per_gaussian": flops}
 
     return {
         "appearance_mlp": {"n_gaussians": n, "fwd_ms": round(ms_f, 4), "bwd_ms": round(ms_b, 4),
                            "fwd_hbm": hbm(n * APP_FWD_BYTES, ms_f), "bwd_hbm": hbm(n * APP_BWD_BYTES, ms_b),
-                           "fwd_mfma_f32": mfma(APP_FWD_MFMA, ms_f), "bwd_mfma_f32": mfma(APP_BWD_MFMA, ms_b)},
+                           "fwd_mfma_f32": mfma(APP_FWD_FLOPS, ms_f), "bwd_mfma_f32": mfma(APP_BWD_FLOPS, ms_b)},
         "dssim": {"pixels": W * H, "ms": round(ms_s, 4), "hbm": hbm(W * H * DSSIM_BYTES, ms_s)},
         "densify": {"n_gaussians": n, "accumulate_ms": round(ms_acc, 4),
                     "accumulate_hbm": hbm(n * DENS_ACC_BYTES, ms_acc), "select_ms": round(ms_sel, 4),
@@ -364,25 +487,25 @@ def next_rows_bench(gs, torch, n, W, H, dev, reps):
     }
 
 
-STAGE_KERNEL = {"render_fwd": "k_render_fwd", "composite_bwd": "k_render_bwd", "project": "k_project_fwd",
-                "project_bwd": "k_project_bwd"}
+KERNEL_SOURCE = {"k_render_fwd": "render.hip", "k_render_bwd": "render.hip", "k_project_fwd": "project.hip",
+                 "k_project_bwd": "project_bwd.hip"}
 
 
-def counted_traffic(stage):
-    """HBM bytes per launch of the stage's kernel from the committed
-    rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE scaled by a plain
-    device copy), or None when the summary is missing or the compositing
-    source has changed since the counters were taken."""
+def counted_traffic(kernel):
+    """HBM bytes per launch of a kernel from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE scaled by a plain device copy), or
+    None when the summary is missing or the kernel's source has changed since
+    the counters were taken."""
     import hashlib
     root = os.path.dirname(os.path.abspath(__file__))
     path = os.path.join(root, "profiles", "counters_urban6M_1080p.md")
-    src = os.path.join(root, "paper_2507_23006_amd", "csrc", "render.hip")
     try:
+        src = os.path.join(root, "paper_2507_23006_amd", "csrc", KERNEL_SOURCE[kernel])
         line = next(l for l in open(path) if l.strip().startswith("COUNTERS "))
         rec = json.loads(line.strip()[len("COUNTERS "):])
-        if rec["render_hip_sha256"] != hashlib.sha256(open(src, "rb").read()).hexdigest():
+        if rec["sources_sha256"][KERNEL_SOURCE[kernel]] != hashlib.sha256(open(src, "rb").read()).hexdigest():
             return None
-        k = rec["kernels"][STAGE_KERNEL[stage]]
+        k = rec["kernels"][kernel]
         return int(k["read_bytes"] + k["write_bytes"])
     except (OSError, StopIteration, KeyError, ValueError):
         return None
@@ -395,9 +518,10 @@ def serve_bench(gs, S, torch, fine, opts, n_requests):
     resolutions 640x360 / 1280x720 / 1920x1080 and budgets 1M / 3M / 6M
     drawn uniformly.  Run on the same trace: "plain" (one request per
     launch, one stream, FIFO) and "served" (continuous batching of up to 8
-    views, two worker streams), then both again with every request arriving
-    at once ("_burst": the saturated throughput).  Latency = completion -
-    scheduled arrival."""
+    views, two worker streams); then both with the arrival times compressed
+    to 800 req/s ("_800"), and with every request arriving at once
+    ("_burst": the saturated throughput).  Latency = completion - scheduled
+    arrival."""
     t_gen = time.time()
     lod = S.lod_scene_c4(fine)
     sc, offsets = lod.combined()
@@ -420,14 +544,17 @@ def serve_bench(gs, S, torch, fine, opts, n_requests):
                                  pair_capacity=96_000_000, pixel_capacity=1 << 24, queue_capacity=n_requests),
     }
     res = {}
-    # the trace as scheduled, then the same requests all at once (saturation)
-    runs = [(name, cfg, False) for name, cfg in modes.items()] + [(name + "_burst", cfg, True)
-                                                                  for name, cfg in modes.items()]
-    for name, cfg, burst in runs:
+    # the trace as scheduled (150 req/s), the same requests at 800 req/s
+    # (where batches form), and all at once (saturation)
+    fast = [r["t"] * 150.0 / 800.0 for r in trace]
+    runs = ([(name, cfg, [r["t"] for r in trace]) for name, cfg in modes.items()]
+            + [(name + "_800", cfg, fast) for name, cfg in modes.items()]
+            + [(name + "_burst", cfg, [0.0] * len(trace)) for name, cfg in modes.items()])
+    for name, cfg, arrivals in runs:
         srv = gs.Server(params, table, opts, cfg)
         t0 = srv.now() + 0.5
-        for r, o in zip(trace, outs):
-            srv.submit(r["camera"], r["budget"], o, t0 + (0.0 if burst else r["t"]))
+        for r, o, ta in zip(trace, outs, arrivals):
+            srv.submit(r["camera"], r["budget"], o, t0 + ta)
         n_done, n_fail, views, t_print = 0, 0, 0, time.time()
         while n_done < len(trace):
             for c in srv.poll(max_items=512, timeout_us=200_000):
@@ -455,50 +582,63 @@ def _ev(torch):
     return ev
 
 
-def cpu_baseline(scene, cam, crop: int):
+def cpu_baseline(scene, cams, crop: int, aa: bool = True, repeats: int = 1):
     """The FP64 oracle on a bounded sample of the same workload: every
-    Gaussian is projected and back-projected for a camera that sees a
-    centred 1/crop of the image (same pose and focal length, tile-aligned),
-    and binning, compositing and its backward run on that crop.  The
-    full-image time is extrapolated as projection + projection backward +
-    crop * (binning + compositing + compositing backward)."""
+    Gaussian is projected and back-projected for cameras that see a centred
+    1/crop of each view (same pose and focal length, tile-aligned), and
+    binning, compositing and its backward run on those crops.  The full
+    step is extrapolated as projection + projection backward + crop x
+    (binning + compositing + compositing backward); crop 1 is the whole
+    step, timed `repeats` times (median)."""
     import oracle
     import synthetic as S
-    cw = max(16, int(round(cam.width / math.sqrt(crop) / 16)) * 16)
-    ch = max(16, int(round(cam.height / math.sqrt(crop) / 16)) * 16)
-    x0 = ((cam.width - cw) // 2) // 16 * 16
-    y0 = ((cam.height - ch) // 2) // 16 * 16
-    sub = S.Camera(cam.fx, cam.fy, cam.cx - x0, cam.cy - y0, cam.viewmat, cw, ch)
-    frac = (cw * ch) / (cam.width * cam.height)
-    opt = dict(sh_degree=3, aa=True)
-    t = {}
-    a = time.perf_counter()
-    proj = oracle.project(scene, sub, **opt)
-    t["project"] = time.perf_counter() - a
-    a = time.perf_counter()
-    keys = oracle.depth_key(proj["depth"])
-    bins = oracle.bin_pairs(proj["rect"], proj["tiles"], keys, np.zeros(scene.n, np.int32), [sub], mask=proj["mask"])
-    t["bin"] = time.perf_counter() - a
-    twod = oracle._twod([proj])
-    a = time.perf_counter()
-    img = oracle.render_view(sub, opt, 0, twod, bins["pair_slot"], bins["ranges"], guard_eps=None)
-    t["render"] = time.perf_counter() - a
-    g = (np.sign(img["rgb"]) / img["rgb"].size, np.zeros_like(img["depth"]), np.zeros_like(img["alpha"]))
-    a = time.perf_counter()
-    d2 = np.zeros((scene.n, 10))
-    oracle.render_bwd_view(sub, opt, 0, twod, bins["pair_slot"], bins["ranges"], *g, d2, None)
-    t["render_bwd"] = time.perf_counter() - a
-    grads = {"means": np.zeros((3, scene.n)), "scales": np.zeros((3, scene.n)), "quats": np.zeros((4, scene.n)),
-             "opacities": np.zeros(scene.n), "sh": np.zeros((16, 3, scene.n))}
-    a = time.perf_counter()
-    oracle.project_bwd(scene, sub, opt, d2, grads)
-    t["project_bwd"] = time.perf_counter() - a
-    full = t["project"] + t["project_bwd"] + (t["bin"] + t["render"] + t["render_bwd"]) / frac
+    opt = dict(sh_degree=3, aa=aa)
+    runs = []
+    for _ in range(repeats):
+        t = {"project": 0.0, "bin": 0.0, "render": 0.0, "render_bwd": 0.0, "project_bwd": 0.0}
+        px_sub = px_all = 0
+        for cam in cams:
+            cw = max(16, int(round(cam.width / math.sqrt(crop) / 16)) * 16) if crop > 1 else cam.width
+            ch = max(16, int(round(cam.height / math.sqrt(crop) / 16)) * 16) if crop > 1 else cam.height
+            x0 = ((cam.width - cw) // 2) // 16 * 16
+            y0 = ((cam.height - ch) // 2) // 16 * 16
+            sub = S.Camera(cam.fx, cam.fy, cam.cx - x0, cam.cy - y0, cam.viewmat, cw, ch)
+            px_sub += cw * ch
+            px_all += cam.width * cam.height
+            a = time.perf_counter()
+            proj = oracle.project(scene, sub, **opt)
+            t["project"] += time.perf_counter() - a
+            a = time.perf_counter()
+            keys = oracle.depth_key(proj["depth"])
+            bins = oracle.bin_pairs(proj["rect"], proj["tiles"], keys, np.zeros(scene.n, np.int32), [sub])
+            t["bin"] += time.perf_counter() - a
+            twod = oracle._twod([proj])
+            a = time.perf_counter()
+            img = oracle.render_view(sub, opt, 0, twod, bins["pair_slot"], bins["ranges"], guard_eps=None)
+            t["render"] += time.perf_counter() - a
+            g = (np.sign(img["rgb"]) / img["rgb"].size, np.zeros_like(img["depth"]), np.zeros_like(img["alpha"]))
+            a = time.perf_counter()
+            d2 = np.zeros((scene.n, 10))
+            oracle.render_bwd_view(sub, opt, 0, twod, bins["pair_slot"], bins["ranges"], *g, d2, None)
+            t["render_bwd"] += time.perf_counter() - a
+            grads = {"means": np.zeros((3, scene.n)), "scales": np.zeros((3, scene.n)),
+                     "quats": np.zeros((4, scene.n)), "opacities": np.zeros(scene.n), "sh": np.zeros((16, 3, scene.n))}
+            a = time.perf_counter()
+            oracle.project_bwd(scene, sub, opt, d2, grads)
+            t["project_bwd"] += time.perf_counter() - a
+            del proj, bins, twod, img, d2, grads
+        frac = px_sub / px_all
+        full = t["project"] + t["project_bwd"] + (t["bin"] + t["render"] + t["render_bwd"]) / frac
+        runs.append((full, t, frac))
+    runs.sort(key=lambda r: r[0])
+    full, t, frac = runs[len(runs) // 2]
+    what = ("the whole step" if crop == 1 else
+            f"all {scene.n} Gaussians projected and back-projected (FP64) for centred crops of {frac:.3f} of the "
+            f"pixels of each of the {len(cams)} view(s); binning, compositing and its backward on those crops, "
+            f"scaled by 1/{frac:.3f}")
     return {"value": round(1.0 / full, 5), "unit": "iters/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"all {scene.n} Gaussians projected and back-projected (FP64) for a centred {cw}x{ch} crop "
-                      f"camera ({frac:.3f} of the pixels); binning, compositing and its backward on that crop, "
-                      f"scaled by 1/{frac:.3f}",
-            "seconds": {k: round(v, 2) for k, v in t.items()}, "extrapolated_s_per_iter": round(full, 2)}
+            "sample": what + (f", median of {repeats}" if repeats > 1 else ""),
+            "seconds": {k: round(v, 3) for k, v in t.items()}, "extrapolated_s_per_iter": round(full, 3)}
 
 
 if __name__ == "__main__":

@@ -244,6 +244,22 @@ int gs_project_bwd(const gs_gaussians *g, const gs_camera *cams, int32_t n_views
  * unwritten) -- for inspection and tests. */
 const float *gs_render_bwd_grad2d(void *ws);
 
+/* Measurement.  While timing is enabled, every launch of the kernels below
+ * records a pair of library-owned events around itself on the stream it
+ * is launched on (binning: around the whole gs_bin_sort sequence);
+ * gs_kernel_timing_read waits for the recorded pairs of one kernel, returns
+ * their summed elapsed time and count, and forgets them.  Enabling or
+ * disabling forgets every pending pair.  For benchmarks: the event records
+ * cost about a microsecond per launch. */
+#define GS_KERNEL_PROJECT_FWD 0   /* k_project_fwd */
+#define GS_KERNEL_BIN_SORT 1      /* the binning launches of one gs_bin_sort */
+#define GS_KERNEL_RENDER_FWD 2    /* k_render_fwd */
+#define GS_KERNEL_RENDER_BWD 3    /* k_render_bwd */
+#define GS_KERNEL_PROJECT_BWD 4   /* k_project_bwd */
+#define GS_KERNEL_TIMED 5
+int gs_kernel_timing(int32_t enable);
+int gs_kernel_timing_read(int32_t kernel, double *total_ms, int64_t *launches);
+
 /* Training loss and its gradient in one pass: the L1 term of Eq. 3 plus the
  * depth regulariser of §3.5.3 on the expected depth,
  *   L = mean_{pix, ch} |rgb - target_rgb|

@@ -119,6 +119,8 @@ SIGNATURES = {
     "gs_loss_workspace_size": (_SZ, [_I64]),
     "gs_loss_l1_depth": (C.c_int, [_P, _P, _P, _P, _P, _I64, C.c_float, _P, _P, _P, _P, _P, _SZ, _P]),
     "gs_loss_l1_depth_noalloc": (C.c_int, [_P, _P, _P, _P, _P, _I64, C.c_float, _P, _P, _P, _P, _P]),
+    "gs_kernel_timing": (C.c_int, [C.c_int32]),
+    "gs_kernel_timing_read": (C.c_int, [C.c_int32, _P, _P]),
     "gs_dssim_workspace_size": (_SZ, [_I32, _I32]),
     "gs_dssim": (C.c_int, [_P, _P, _I32, _I32, C.c_float, _P, _P, _P, _SZ, _P]),
     "gs_densify_accumulate": (C.c_int, [_P, _P, _P, _I32, _I64, _P, _P, _P, _P]),

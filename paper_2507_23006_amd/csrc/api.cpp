@@ -3,8 +3,12 @@
 // each stage.  No call here allocates device memory.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
+#include <mutex>
+#include <utility>
+#include <vector>
 #include <cstdio>
 #include <algorithm>
 #include <cstring>
@@ -14,6 +18,41 @@
 #include "host.h"
 
 namespace gs {
+
+namespace {
+// event pairs recorded around timed launches, per timed kernel
+std::atomic<bool> g_timing{false};
+std::mutex g_timer_mu;
+struct TimerPool {
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    size_t used = 0;
+};
+TimerPool g_timers[GS_KERNEL_TIMED];
+}  // namespace
+
+hipEvent_t timer_begin(int kernel, hipStream_t s) {
+    if (!g_timing.load(std::memory_order_relaxed) || kernel < 0 || kernel >= GS_KERNEL_TIMED) return nullptr;
+    std::lock_guard<std::mutex> lk(g_timer_mu);
+    TimerPool& p = g_timers[kernel];
+    if (p.used == p.ev.size()) {
+        hipEvent_t b = nullptr, e = nullptr;
+        if (hipEventCreate(&b) != hipSuccess) return nullptr;
+        if (hipEventCreate(&e) != hipSuccess) {
+            (void)hipEventDestroy(b);
+            return nullptr;
+        }
+        p.ev.emplace_back(b, e);
+    }
+    auto& pr = p.ev[p.used];
+    if (hipEventRecord(pr.first, s) != hipSuccess) return nullptr;
+    ++p.used;
+    return pr.second;
+}
+
+void timer_end(hipEvent_t closing, hipStream_t s) {
+    if (closing) (void)hipEventRecord(closing, s);
+}
+
 namespace host {
 
 namespace {
@@ -187,6 +226,7 @@ int bin_sort_slots(const Projected& pr, const ViewTable& vt, int64_t n_slots, in
     const size_t need = bin_layout(n_slots, pair_capacity, ws, &w);
     GS_REQUIRE(ws_bytes >= need, "workspace too small: %zu < %zu", ws_bytes, need);
     const uint32_t N = (uint32_t)n_slots;
+    const hipEvent_t timed = timer_begin(GS_KERNEL_BIN_SORT, s);
 
     // 1. visible slots in slot order (scan of tiles > 0, scatter) and the pair count
     //    (sum of all tile counts); one read-back gives both sizes
@@ -232,6 +272,7 @@ int bin_sort_slots(const Projected& pr, const ViewTable& vt, int64_t n_slots, in
     // 4. [start, end) per tile, and the compositing launch order
     GS_HIP(launch_tile_ranges(sorted_keys, (uint32_t)P, tile_ranges, (uint32_t)vt.total_tiles, s));
     if (pr.tile_order) GS_HIP(launch_tile_order(tile_ranges, (uint32_t)vt.total_tiles, pr.tile_order, s));
+    timer_end(timed, s);
     return GS_OK;
 }
 
@@ -246,6 +287,35 @@ extern "C" {
 const char* gs_last_error(void) { return last_error(); }
 
 const char* gs_version(void) { return "gsmi-rasterizer 0.1 (gfx950)"; }
+
+int gs_kernel_timing(int32_t enable) {
+    std::lock_guard<std::mutex> lk(g_timer_mu);
+    for (auto& p : g_timers) p.used = 0;
+    g_timing.store(enable != 0);
+    return GS_OK;
+}
+
+int gs_kernel_timing_read(int32_t kernel, double* total_ms, int64_t* launches) {
+    try {
+        GS_REQUIRE(kernel >= 0 && kernel < GS_KERNEL_TIMED, "kernel id %d outside 0..%d", kernel, GS_KERNEL_TIMED - 1);
+        GS_REQUIRE(total_ms && launches, "NULL output");
+        std::lock_guard<std::mutex> lk(g_timer_mu);
+        TimerPool& p = g_timers[kernel];
+        double sum = 0.0;
+        for (size_t i = 0; i < p.used; ++i) {
+            float ms = 0.0f;
+            GS_HIP(hipEventSynchronize(p.ev[i].second));
+            GS_HIP(hipEventElapsedTime(&ms, p.ev[i].first, p.ev[i].second));
+            sum += ms;
+        }
+        *total_ms = sum;
+        *launches = (int64_t)p.used;
+        p.used = 0;
+        return GS_OK;
+    } catch (...) {
+        return fail(GS_ERR_INTERNAL, "unexpected exception in gs_kernel_timing_read");
+    }
+}
 
 int gs_views_extent(const gs_camera* cams, int32_t n_views, int64_t* n_tiles, int64_t* n_pixels) {
     ViewTable vt;

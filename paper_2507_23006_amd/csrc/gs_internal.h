@@ -108,6 +108,15 @@ __device__ __forceinline__ void sh_eval_basis(Real x, Real y, Real z, int degree
 // ---------------------------------------------------------------------------
 namespace gs {
 
+// ---------------------------------------------------------------------------
+// measurement: while enabled (gs_kernel_timing), the launch helpers of the
+// timed kernels bracket their launch with two events on the launch stream;
+// timer_begin returns the closing event (null when disabled)
+// ---------------------------------------------------------------------------
+hipEvent_t timer_begin(int kernel, hipStream_t s);
+void timer_end(hipEvent_t closing, hipStream_t s);
+
+
 struct Projected {
     float4* rec;          // [slots][4]
     uint2* rect;          // [slots]

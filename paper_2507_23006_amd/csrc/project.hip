@@ -429,7 +429,9 @@ __global__ __launch_bounds__(kPF) void k_project_slots(GaussPtrs gp, int64_t n, 
 hipError_t launch_project_fwd(const GaussPtrs& g, int64_t n, const ViewTable& vt, const OptK& opt,
                               const Projected& out, hipStream_t s) {
     const unsigned blocks = (unsigned)((n + kPFSpan - 1) / kPFSpan);
+    const hipEvent_t timed_ = timer_begin(GS_KERNEL_PROJECT_FWD, s);
     hipLaunchKernelGGL(k_project_fwd, dim3(blocks), dim3(kPF), 0, s, g, n, vt, opt, out);
+    timer_end(timed_, s);
     return hipGetLastError();
 }
 

@@ -346,8 +346,10 @@ hipError_t launch_project_bwd(const GaussPtrs& g, int64_t n, const ViewTable& vt
                               const Projected& proj, const float* grad2d, const GradPtrs& out, float* mean2d_norm,
                               float* absgrad, hipStream_t s) {
     const unsigned blocks = (unsigned)((n + kSpan - 1) / kSpan);
+    const hipEvent_t timed_ = timer_begin(GS_KERNEL_PROJECT_BWD, s);
     hipLaunchKernelGGL(k_project_bwd, dim3(blocks), dim3(kPB), 0, s, g, n, vt, opt, proj, grad2d, out, mean2d_norm,
                        absgrad);
+    timer_end(timed_, s);
     return hipGetLastError();
 }
 

@@ -704,8 +704,10 @@ hipError_t launch_render_fwd(const Projected& proj, const uint32_t* pair_vals, c
                              const ViewTable& vt, const OptK& opt, float* rgb, float* depth, float* alpha,
                              float* T_final, int32_t* last, hipStream_t s) {
     if (vt.total_tiles <= 0) return hipSuccess;
+    const hipEvent_t timed_ = timer_begin(GS_KERNEL_RENDER_FWD, s);
     hipLaunchKernelGGL(k_render_fwd, dim3(vt.total_tiles), dim3(256), 0, s, proj.rec, pair_vals, ranges,
                        proj.tile_order, vt, opt, rgb, depth, alpha, T_final, last);
+    timer_end(timed_, s);
     return hipGetLastError();
 }
 
@@ -734,8 +736,10 @@ hipError_t launch_render_bwd(const Projected& proj, const uint32_t* pair_vals, c
                              const SegPlan& plan, uint32_t capacity, hipStream_t s) {
     // with a plan, blocks beyond the planned work items exit at once
     const unsigned blocks = (unsigned)vt.total_tiles + (plan.work_off ? capacity : 0u);
+    const hipEvent_t timed_ = timer_begin(GS_KERNEL_RENDER_BWD, s);
     hipLaunchKernelGGL(k_render_bwd, dim3(blocks), dim3(256), 0, s, proj.rec, pair_vals, ranges,
                        proj.tile_order, vt, opt, T_final, last, d_rgb, d_depth, d_alpha, grad2d, plan);
+    timer_end(timed_, s);
     return hipGetLastError();
 }
 

@@ -197,6 +197,23 @@ def render_count(proj: Projected, pair_vals, ranges, cams) -> torch.Tensor:
     return out
 
 
+KERNELS_TIMED = {"k_project_fwd": 0, "bin_sort": 1, "k_render_fwd": 2, "k_render_bwd": 3, "k_project_bwd": 4}
+
+
+def kernel_timing(enable: bool) -> None:
+    """Turns the library's per-launch event timing of the main kernels on or
+    off (measurement); either way, pending measurements are dropped."""
+    L.check(L.load().gs_kernel_timing(1 if enable else 0))
+
+
+def kernel_timing_read(name: str):
+    """(total ms, launches) of the timed launches of one kernel since the
+    last read, measured with events on its own stream."""
+    ms, k = C.c_double(), C.c_int64()
+    L.check(L.load().gs_kernel_timing_read(KERNELS_TIMED[name], C.byref(ms), C.byref(k)))
+    return ms.value, k.value
+
+
 _stage_hook = None
 
 
