@@ -174,11 +174,13 @@ def train_config(gs, torch, S, scene, cams, opts, tgt, steps, warmup, depth_term
 
     def fwd():
         proj = gs.project(*pd, cams, opts)
-        pv, rg, P = gs.bin_sort(proj, cams, scene.n)
+        pv, rg, P = gs.bin_sort(proj, cams, scene.n, sync=False)
         gs.render_fwd(proj, pv, rg, cams, opts)
+        return P
 
     with torch.no_grad():
         _, per_f = step_times(torch, fwd, steps, 3)
+        assert not fwd().overflowed()
         proj = gs.project(*pd, cams, opts)
         pv, rg, P = gs.bin_sort(proj, cams, scene.n)
         n_vis = int((proj.tiles > 0).sum().item())
@@ -282,10 +284,12 @@ def main():
 
         def fwd():
             proj = gs.project(*pd, cams, opts)
-            pv, rg, P = gs.bin_sort(proj, cams, scene.n)
+            pv, rg, P = gs.bin_sort(proj, cams, scene.n, sync=False)
             gs.render_fwd(proj, pv, rg, cams, opts)
+            return P
 
         _, per_fwd = step_times(torch, fwd, args.steps, 3)
+        assert not fwd().overflowed()
         ms_fwd = pct(per_fwd, 50)
         # workload statistics for the cost models (outside the timed regions)
         proj = gs.project(*pd, cams, opts)

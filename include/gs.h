@@ -36,8 +36,7 @@
  *     size the matching *_workspace_size function returns (256-byte
  *     aligned pointers required).
  *   - `stream` is a hipStream_t (NULL = the null stream).  Work is enqueued
- *     asynchronously; gs_bin_sort is the one call that synchronises the
- *     stream (it reads back the pair count).
+ *     asynchronously; no call of the rendering path synchronises it.
  *   - Return value 0 (GS_OK) or a negative GS_ERR_* code; nothing throws.
  *     gs_last_error() returns the calling thread's last message.
  *   - Gaussian parameters over n Gaussians: means [3][n], scales [3][n]
@@ -169,16 +168,20 @@ int gs_project(const gs_gaussians *g, const gs_camera *cams, int32_t n_views, co
 size_t gs_bin_workspace_size(int64_t n_slots, int64_t pair_capacity);
 
 /* Tile binning and depth order ("processed in depth order", §3.1).
- * Sorts slots by depth key (stable, so ties keep slot order), expands each
- * slot into one pair per covered tile, stably sorts the pairs by global
- * tile id, and writes
+ * Sorts the visible slots by depth key (stable, so ties keep slot order),
+ * expands each into one pair per covered tile, stably sorts the pairs by
+ * global tile id, and writes
  *   pair_vals[P]          slot of each pair, tile-major, depth order inside;
  *   tile_ranges[T][2]     [start, end) of every global tile in pair_vals.
- * *n_pairs receives P.  If P > pair_capacity nothing past the count is
- * written and GS_ERR_CAPACITY is returned with *n_pairs = P, so the caller
- * can grow its buffers and call again.  Synchronises `stream`. */
+ * Asynchronous, with no host read-back: the pair count P is written to the
+ * DEVICE int64 *n_pairs_dev (8-byte aligned) on the stream, and every launch
+ * after the count is sized by slots or pair_capacity and reads the counts on
+ * the device.  If P > pair_capacity (or P > 2^32 - 256), pair_vals is left
+ * unwritten and every tile range is empty (compositing then sees no
+ * Gaussians): the caller reads *n_pairs_dev after the stream and, when it
+ * exceeds pair_capacity, grows its buffers and calls again. */
 int gs_bin_sort(const gs_projected *proj, const gs_camera *cams, int32_t n_views, int64_t n,
-                int64_t pair_capacity, uint32_t *pair_vals, uint32_t *tile_ranges, int64_t *n_pairs,
+                int64_t pair_capacity, uint32_t *pair_vals, uint32_t *tile_ranges, int64_t *n_pairs_dev,
                 void *ws, size_t ws_bytes, void *stream);
 
 /* Front-to-back compositing (Eq. 2), one 256-thread workgroup per 16x16

@@ -165,14 +165,15 @@ constexpr int kTotals = 16 + 16 * kBinPairParts;
 
 struct BinWs {
     uint32_t *dkeys, *dvals, *dkeys_alt, *dvals_alt;
-    uint32_t* hist;
+    uint4* desc;
     uint32_t *tiles_s, *offsets;
     uint2* rect_s;
     uint64_t* mask_s;
     uint32_t* slot_s;
-    uint4* desc;
+    uint32_t* hist;
     uint32_t* scan_tmp;
     unsigned long long* total;
+    uint32_t* cnt;          // effective visible and pair counts on the device
     uint32_t *pkeys, *pkeys_alt, *pvals_alt;
 };
 
@@ -183,28 +184,20 @@ size_t bin_layout(int64_t n_slots, int64_t cap, void* base, BinWs* w) {
     w->dvals = c.take<uint32_t>(N);
     w->dkeys_alt = c.take<uint32_t>(N);
     w->dvals_alt = c.take<uint32_t>(N);
-    w->hist = c.take<uint32_t>(radix_hist_elems((uint32_t)(N > Pc ? N : Pc)));
+    w->desc = c.take<uint4>(2 * N);
     w->tiles_s = c.take<uint32_t>(N);
     w->offsets = c.take<uint32_t>(N);
     w->rect_s = c.take<uint2>(N);
     w->mask_s = c.take<uint64_t>(N);
     w->slot_s = c.take<uint32_t>(N);
-    w->desc = c.take<uint4>(2 * N);
+    w->hist = c.take<uint32_t>(radix_hist_elems((uint32_t)(N > Pc ? N : Pc)));
     w->scan_tmp = c.take<uint32_t>(scan_tmp_elems((uint32_t)N));
     w->total = c.take<unsigned long long>(kTotals);   // [0] visible, [8] offsets total, [16 + 16k] pair parts
+    w->cnt = c.take<uint32_t>(4);
     w->pkeys = c.take<uint32_t>(Pc);
     w->pkeys_alt = c.take<uint32_t>(Pc);
     w->pvals_alt = c.take<uint32_t>(Pc);
     return c.off;
-}
-
-// per-thread pinned read-back buffer of kTotals counters
-unsigned long long* pinned_scalar() {
-    thread_local unsigned long long* p = nullptr;
-    if (!p && hipHostMalloc(reinterpret_cast<void**>(&p), kTotals * sizeof(unsigned long long),
-                            hipHostMallocDefault) != hipSuccess)
-        p = nullptr;
-    return p;
 }
 
 }  // namespace
@@ -216,61 +209,49 @@ size_t bin_workspace_bytes(int64_t n_slots, int64_t pair_capacity) {
 }
 
 int bin_sort_slots(const Projected& pr, const ViewTable& vt, int64_t n_slots, int64_t pair_capacity,
-                   uint32_t* pair_vals, uint32_t* tile_ranges, int64_t* n_pairs, void* ws, size_t ws_bytes,
+                   uint32_t* pair_vals, uint32_t* tile_ranges, int64_t* n_pairs_dev, void* ws, size_t ws_bytes,
                    hipStream_t s) {
     GS_REQUIRE(n_slots >= 1 && n_slots <= 0xFFFFFF00LL, "bad slot count %lld", (long long)n_slots);
-    GS_REQUIRE(pair_vals && tile_ranges && n_pairs && ws, "NULL output or workspace");
+    GS_REQUIRE(pair_vals && tile_ranges && n_pairs_dev && ws, "NULL output or workspace");
     GS_REQUIRE(pair_capacity >= 0 && pair_capacity <= 0xFFFFFF00LL, "pair_capacity out of range");
     GS_REQUIRE(((uintptr_t)ws & (kAlign - 1)) == 0, "workspace must be 256-byte aligned");
+    GS_REQUIRE(((uintptr_t)n_pairs_dev & 7) == 0, "n_pairs must be 8-byte aligned");
     BinWs w;
     const size_t need = bin_layout(n_slots, pair_capacity, ws, &w);
     GS_REQUIRE(ws_bytes >= need, "workspace too small: %zu < %zu", ws_bytes, need);
-    const uint32_t N = (uint32_t)n_slots;
+    const uint32_t N = (uint32_t)n_slots, Pc = (uint32_t)pair_capacity;
     const hipEvent_t timed = timer_begin(GS_KERNEL_BIN_SORT, s);
 
-    // 1. visible slots in slot order (scan of tiles > 0, scatter) and the pair count
-    //    (sum of all tile counts); one read-back gives both sizes
+    // 1. visible slots in slot order (scan of tiles > 0, scatter) with the
+    //    pair count summed in the same pass; the counts stay on the device:
+    //    every later launch is sized by N or the pair capacity and reads
+    //    them there
     GS_HIP(fill_u32(reinterpret_cast<uint32_t*>(w.total), 0u, 2 * kTotals, s));
     GS_HIP(exclusive_scan_nonzero_u32(pr.tiles, w.offsets, N, w.scan_tmp, w.total, w.total + 16, s));
+    GS_HIP(launch_bin_counts(w.total, w.total + 16, Pc, n_pairs_dev, w.cnt, s));
     GS_HIP(launch_compact_visible(pr, w.offsets, N, w.dkeys, w.dvals, w.desc, s));
-    unsigned long long* host = pinned_scalar();
-    if (!host) return fail(GS_ERR_HIP, "pinned host buffer unavailable");
-    GS_HIP(hipMemcpyAsync(host, w.total, kTotals * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
-    GS_HIP(hipStreamSynchronize(s));
-    unsigned long long P = 0;
-    for (int k = 0; k < kBinPairParts; ++k) P += host[16 + 16 * k];
-    const unsigned long long V = host[0];
-    *n_pairs = (int64_t)P;
-    if (P > 0xFFFFFF00ULL) return fail(GS_ERR_CAPACITY, "pair count %llu exceeds 32-bit indices", P);
-    if ((int64_t)P > pair_capacity)
-        return fail(GS_ERR_CAPACITY, "pair count %llu exceeds capacity %lld", P, (long long)pair_capacity);
-    if (V > N || (V == 0) != (P == 0)) return fail(GS_ERR_INTERNAL, "inconsistent counts (%llu visible, %llu pairs)", V, P);
-    const uint32_t NV = (uint32_t)V;
     // 2. depth order of the visible slots (stable: ties stay in slot order,
     //    which is compaction order); per depth rank its tile count, rectangle,
     //    mask and slot; exclusive scan -> pair offsets
     bool alt = false;
-    GS_HIP(radix_sort_pairs(w.dkeys, w.dvals, w.dkeys_alt, w.dvals_alt, NV, 0, 32, w.hist, s, &alt));
+    GS_HIP(radix_sort_pairs(w.dkeys, w.dvals, w.dkeys_alt, w.dvals_alt, N, 0, 32, w.hist, s, &alt, w.cnt));
     const uint32_t* sorted_pos = alt ? w.dvals_alt : w.dvals;
-    const uint32_t* sorted_slot = w.slot_s;
-    if (NV) {
-        GS_HIP(launch_gather_sorted(sorted_pos, w.desc, NV, w.tiles_s, w.rect_s, w.mask_s, w.slot_s, s));
-        GS_HIP(exclusive_scan_u32(w.tiles_s, w.offsets, NV, w.scan_tmp, w.total + 8, s));
-    }
+    GS_HIP(launch_gather_sorted(sorted_pos, w.desc, N, w.cnt, w.tiles_s, w.rect_s, w.mask_s, w.slot_s, s));
+    GS_HIP(exclusive_scan_u32(w.tiles_s, w.offsets, N, w.scan_tmp, w.total + 8, s, w.cnt));
     // 3. expand into (tile, slot) pairs in depth order, then stable sort by tile id
     const int bits = tile_bits(vt.total_tiles);
-    const int passes = P <= 1 ? 0 : (bits + 7) / 8;   // radix_sort_pairs runs no pass for P <= 1
+    const int passes = radix_passes(Pc, 0, bits);
     uint32_t* vals_primary = (passes % 2 == 0) ? pair_vals : w.pvals_alt;
     uint32_t* vals_alt = (passes % 2 == 0) ? w.pvals_alt : pair_vals;
-    GS_HIP(launch_emit_pairs(w.offsets, w.rect_s, pr.tile_mask ? w.mask_s : nullptr, sorted_slot, NV, (uint32_t)P,
-                             w.pkeys, vals_primary, s));
+    GS_HIP(launch_emit_pairs(w.offsets, w.rect_s, pr.tile_mask ? w.mask_s : nullptr, w.slot_s, N, Pc, w.cnt, w.pkeys,
+                             vals_primary, s));
     bool palt = false;
-    GS_HIP(radix_sort_pairs(w.pkeys, vals_primary, w.pkeys_alt, vals_alt, (uint32_t)P, 0, bits, w.hist, s, &palt));
+    GS_HIP(radix_sort_pairs(w.pkeys, vals_primary, w.pkeys_alt, vals_alt, Pc, 0, bits, w.hist, s, &palt, w.cnt + 1));
     const uint32_t* sorted_keys = palt ? w.pkeys_alt : w.pkeys;
     if ((palt ? vals_alt : vals_primary) != pair_vals)
         return fail(GS_ERR_INTERNAL, "tile sort ended in the wrong buffer");
     // 4. [start, end) per tile, and the compositing launch order
-    GS_HIP(launch_tile_ranges(sorted_keys, (uint32_t)P, tile_ranges, (uint32_t)vt.total_tiles, s));
+    GS_HIP(launch_tile_ranges(sorted_keys, Pc, w.cnt, tile_ranges, (uint32_t)vt.total_tiles, s));
     if (pr.tile_order) GS_HIP(launch_tile_order(tile_ranges, (uint32_t)vt.total_tiles, pr.tile_order, s));
     timer_end(timed, s);
     return GS_OK;
@@ -350,17 +331,14 @@ size_t gs_bin_workspace_size(int64_t n_slots, int64_t pair_capacity) {
 }
 
 int gs_bin_sort(const gs_projected* proj, const gs_camera* cams, int32_t n_views, int64_t n, int64_t pair_capacity,
-                uint32_t* pair_vals, uint32_t* tile_ranges, int64_t* n_pairs, void* ws, size_t ws_bytes,
+                uint32_t* pair_vals, uint32_t* tile_ranges, int64_t* n_pairs_dev, void* ws, size_t ws_bytes,
                 void* stream) {
     try {
         ViewTable vt;
         int rc;
         if ((rc = build_views(cams, n_views, &vt)) || (rc = check_proj(proj))) return rc;
         GS_REQUIRE(n >= 1 && n * (int64_t)n_views <= 0xFFFFFF00LL, "bad n=%lld", (long long)n);
-        GS_REQUIRE(pair_vals && tile_ranges && n_pairs && ws, "NULL output or workspace");
-        GS_REQUIRE(pair_capacity >= 0 && pair_capacity <= 0xFFFFFF00LL, "pair_capacity out of range");
-        GS_REQUIRE(((uintptr_t)ws & (kAlign - 1)) == 0, "workspace must be 256-byte aligned");
-        return bin_sort_slots(to_proj(proj), vt, n * n_views, pair_capacity, pair_vals, tile_ranges, n_pairs, ws,
+        return bin_sort_slots(to_proj(proj), vt, n * n_views, pair_capacity, pair_vals, tile_ranges, n_pairs_dev, ws,
                               ws_bytes, (hipStream_t)stream);
     } catch (...) {
         return fail(GS_ERR_INTERNAL, "unexpected exception in gs_bin_sort");

@@ -40,9 +40,11 @@ __global__ __launch_bounds__(256) void k_compact_visible(const uint32_t* __restr
 
 // per depth rank: tiles covered and the emission descriptor of its slot
 // (rectangle, covered-tile mask, slot), from its compaction descriptor
-__global__ void k_gather_sorted(const uint32_t* __restrict__ sorted_pos, const uint4* __restrict__ desc, uint32_t n,
-                                uint32_t* __restrict__ tiles_s, uint2* __restrict__ rect_s,
-                                uint64_t* __restrict__ mask_s, uint32_t* __restrict__ slot_s) {
+__global__ void k_gather_sorted(const uint32_t* __restrict__ sorted_pos, const uint4* __restrict__ desc,
+                                uint32_t n_max, const uint32_t* __restrict__ counts, uint32_t* __restrict__ tiles_s,
+                                uint2* __restrict__ rect_s, uint64_t* __restrict__ mask_s,
+                                uint32_t* __restrict__ slot_s) {
+    const uint32_t n = counts ? min(counts[0], n_max) : n_max;
     const uint32_t d = blockIdx.x * 256 + threadIdx.x;
     if (d >= n) return;
     const uint32_t c = sorted_pos[d];
@@ -83,12 +85,17 @@ constexpr int kEmitChunk = kEmitThreads * kEmitPer;   // pairs per workgroup
 __global__ __launch_bounds__(kEmitThreads) void k_emit_pairs(const uint32_t* __restrict__ offsets,
                                                              const uint2* __restrict__ rect_s,
                                                              const uint64_t* __restrict__ mask_s,
-                                                             const uint32_t* __restrict__ sorted_slot, uint32_t n,
-                                                             uint32_t n_pairs, uint32_t* __restrict__ pair_key,
+                                                             const uint32_t* __restrict__ sorted_slot, uint32_t n_max,
+                                                             uint32_t n_pairs_max, const uint32_t* __restrict__ counts,
+                                                             uint32_t* __restrict__ pair_key,
                                                              uint32_t* __restrict__ pair_val) {
     __shared__ uint32_t s_off[kEmitChunk + 1];
     __shared__ uint32_t s_d0;
+    // depth ranks and pairs: the launch's bounds, or the counts on the device
+    const uint32_t n = counts ? min(counts[0], n_max) : n_max;
+    const uint32_t n_pairs = counts ? min(counts[1], n_pairs_max) : n_pairs_max;
     const uint32_t p0 = blockIdx.x * kEmitChunk;
+    if (p0 >= n_pairs) return;
     if (threadIdx.x == 0) {
         // last d with offsets[d] <= p0 (offsets[0] == 0 <= p0)
         uint32_t lo = 0, hi = n;      // invariant: offsets[lo] <= p0, answer in [lo, hi)
@@ -128,14 +135,34 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit_pairs(const uint32_t* __r
     }
 }
 
-__global__ void k_tile_ranges(const uint32_t* __restrict__ keys, uint32_t n, uint2* __restrict__ ranges,
-                              uint32_t n_tiles) {
+__global__ void k_tile_ranges(const uint32_t* __restrict__ keys, uint32_t n_max, const uint32_t* __restrict__ counts,
+                              uint2* __restrict__ ranges, uint32_t n_tiles) {
+    const uint32_t n = counts ? min(counts[1], n_max) : n_max;
     const uint32_t p = blockIdx.x * 256 + threadIdx.x;
     if (p >= n) return;
     const uint32_t k = keys[p];
     if (k >= n_tiles) return;     // keys are tile ids by construction; guards the write
     if (p == 0 || keys[p - 1] != k) ranges[k].x = p;
     if (p == n - 1 || keys[p + 1] != k) ranges[k].y = p + 1;
+}
+
+// The binning's sizes from the visibility scan: visible slots (total[0]) and
+// pairs (the sum of kBinPairParts partial sums, 16 apart).  The pair count
+// goes to n_pairs_out; the effective counts counts[0] (visible) and
+// counts[1] (pairs), read by the launches after this one, are 0 when the
+// pairs exceed the capacity or 32-bit indexing, so those launches then
+// produce empty lists and the caller learns of it from the count alone.
+__global__ void k_bin_counts(const unsigned long long* __restrict__ total,
+                             const unsigned long long* __restrict__ parts, unsigned long long capacity,
+                             int64_t* __restrict__ n_pairs_out, uint32_t* __restrict__ counts) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    unsigned long long P = 0;
+    for (int k = 0; k < kBinPairParts; ++k) P += parts[16 * k];
+    const unsigned long long V = total[0];
+    const bool ok = P <= capacity && P <= 0xFFFFFF00ull;
+    counts[0] = ok ? (uint32_t)V : 0u;
+    counts[1] = ok ? (uint32_t)P : 0u;
+    *n_pairs_out = (int64_t)P;
 }
 
 // Launch order of the tiles for compositing: longest lists first, so that
@@ -192,29 +219,36 @@ hipError_t launch_compact_visible(const Projected& proj, const uint32_t* pos, ui
     return hipGetLastError();
 }
 
-hipError_t launch_gather_sorted(const uint32_t* sorted_pos, const uint4* desc, uint32_t n_visible, uint32_t* tiles_s,
-                                uint2* rect_s, uint64_t* mask_s, uint32_t* slot_s, hipStream_t s) {
+hipError_t launch_gather_sorted(const uint32_t* sorted_pos, const uint4* desc, uint32_t n_visible, const uint32_t* counts,
+                                uint32_t* tiles_s, uint2* rect_s, uint64_t* mask_s, uint32_t* slot_s, hipStream_t s) {
+    if (!n_visible) return hipSuccess;
     hipLaunchKernelGGL(k_gather_sorted, dim3((n_visible + 255) / 256), dim3(256), 0, s, sorted_pos, desc, n_visible,
-                       tiles_s, rect_s, mask_s, slot_s);
+                       counts, tiles_s, rect_s, mask_s, slot_s);
     return hipGetLastError();
 }
 
 hipError_t launch_emit_pairs(const uint32_t* offsets, const uint2* rect_s, const uint64_t* mask_s,
-                             const uint32_t* sorted_slot, uint32_t n_slots, uint32_t n_pairs, uint32_t* pair_key,
-                             uint32_t* pair_val, hipStream_t s) {
-    if (!n_pairs) return hipSuccess;
+                             const uint32_t* sorted_slot, uint32_t n_slots, uint32_t n_pairs, const uint32_t* counts,
+                             uint32_t* pair_key, uint32_t* pair_val, hipStream_t s) {
+    if (!n_pairs || !n_slots) return hipSuccess;
     const uint32_t blocks = (n_pairs + kEmitChunk - 1) / kEmitChunk;
     hipLaunchKernelGGL(k_emit_pairs, dim3(blocks), dim3(kEmitThreads), 0, s, offsets, rect_s, mask_s, sorted_slot,
-                       n_slots, n_pairs, pair_key, pair_val);
+                       n_slots, n_pairs, counts, pair_key, pair_val);
     return hipGetLastError();
 }
 
-hipError_t launch_tile_ranges(const uint32_t* sorted_keys, uint32_t n_pairs, uint32_t* ranges, uint32_t n_tiles,
-                              hipStream_t s) {
+hipError_t launch_tile_ranges(const uint32_t* sorted_keys, uint32_t n_pairs, const uint32_t* counts, uint32_t* ranges,
+                              uint32_t n_tiles, hipStream_t s) {
     hipError_t e = fill_u32(ranges, 0u, (size_t)n_tiles * 2, s);
     if (e != hipSuccess || !n_pairs) return e;
-    hipLaunchKernelGGL(k_tile_ranges, dim3((n_pairs + 255) / 256), dim3(256), 0, s, sorted_keys, n_pairs,
+    hipLaunchKernelGGL(k_tile_ranges, dim3((n_pairs + 255) / 256), dim3(256), 0, s, sorted_keys, n_pairs, counts,
                        reinterpret_cast<uint2*>(ranges), n_tiles);
+    return hipGetLastError();
+}
+
+hipError_t launch_bin_counts(const unsigned long long* total, const unsigned long long* parts,
+                             unsigned long long capacity, int64_t* n_pairs_out, uint32_t* counts, hipStream_t s) {
+    hipLaunchKernelGGL(k_bin_counts, dim3(1), dim3(64), 0, s, total, parts, capacity, n_pairs_out, counts);
     return hipGetLastError();
 }
 

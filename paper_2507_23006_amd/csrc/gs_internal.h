@@ -154,13 +154,16 @@ hipError_t launch_project_slots(const GaussPtrs& g, int64_t n, const ViewTable& 
                                 hipStream_t s);
 
 // radix sort / scan primitives (sort.hip)
+// n_dev (nullable): the element count on the device, at most n, which sizes
+// the launches (no host read-back needed)
 size_t radix_hist_elems(uint32_t n);        // counters needed per pass
+int radix_passes(uint32_t n, int begin_bit, int end_bit);
 hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt,
                             uint32_t n, int begin_bit, int end_bit, uint32_t* hist, hipStream_t s,
-                            bool* result_in_alt);
+                            bool* result_in_alt, const uint32_t* n_dev = nullptr);
 size_t scan_tmp_elems(uint32_t n);
 hipError_t exclusive_scan_u32(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* tmp,
-                              unsigned long long* total, hipStream_t s);
+                              unsigned long long* total, hipStream_t s, const uint32_t* n_dev = nullptr);
 // exclusive scan of (in[i] != 0); the sum of in[] itself is added to
 // sum_parts (kBinPairParts partial sums, 16 u64 apart, zeroed by the caller)
 hipError_t exclusive_scan_nonzero_u32(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* tmp,
@@ -177,13 +180,21 @@ constexpr int kBinPairParts = 64;
 // mask lo, mask hi; tiles, slot, 0, 0)
 hipError_t launch_compact_visible(const Projected& proj, const uint32_t* pos, uint32_t n_slots, uint32_t* keys,
                                   uint32_t* vals, uint4* desc, hipStream_t s);
-hipError_t launch_gather_sorted(const uint32_t* sorted_pos, const uint4* desc, uint32_t n_visible, uint32_t* tiles_s,
-                                uint2* rect_s, uint64_t* mask_s, uint32_t* slot_s, hipStream_t s);
+hipError_t launch_gather_sorted(const uint32_t* sorted_pos, const uint4* desc, uint32_t n_visible, const uint32_t* counts,
+                                uint32_t* tiles_s, uint2* rect_s, uint64_t* mask_s, uint32_t* slot_s, hipStream_t s);
+// gather, emission and ranges take their counts from the device (counts[0]
+// visible ranks, counts[1] pairs, from launch_bin_counts) when counts is
+// set, within the launch bounds n_visible / n_slots, n_pairs
 hipError_t launch_emit_pairs(const uint32_t* offsets, const uint2* rect_s, const uint64_t* mask_s,
-                             const uint32_t* sorted_slot, uint32_t n_slots, uint32_t n_pairs, uint32_t* pair_key,
-                             uint32_t* pair_val, hipStream_t s);
-hipError_t launch_tile_ranges(const uint32_t* sorted_keys, uint32_t n_pairs, uint32_t* ranges, uint32_t n_tiles,
-                              hipStream_t s);
+                             const uint32_t* sorted_slot, uint32_t n_slots, uint32_t n_pairs, const uint32_t* counts,
+                             uint32_t* pair_key, uint32_t* pair_val, hipStream_t s);
+hipError_t launch_tile_ranges(const uint32_t* sorted_keys, uint32_t n_pairs, const uint32_t* counts, uint32_t* ranges,
+                              uint32_t n_tiles, hipStream_t s);
+// total[0] = visible slots, parts = kBinPairParts pair-count parts (16
+// apart): writes the pair count to n_pairs_out and the effective counts
+// counts[0..1], 0 when the pairs exceed capacity
+hipError_t launch_bin_counts(const unsigned long long* total, const unsigned long long* parts,
+                             unsigned long long capacity, int64_t* n_pairs_out, uint32_t* counts, hipStream_t s);
 // tile launch order for compositing, longest lists first
 hipError_t launch_tile_order(const uint32_t* ranges, uint32_t n_tiles, uint32_t* order, hipStream_t s);
 

@@ -54,9 +54,11 @@ int build_opt(const gs_options* o, OptK* k);
 size_t bin_workspace_bytes(int64_t n_slots, int64_t pair_capacity);
 
 // depth sort of n_slots projected slots, pair emission, tile sort and tile
-// ranges for the views of vt; synchronises `s` to read back the pair count
+// ranges for the views of vt; asynchronous: the pair count is written to
+// the device int64 *n_pairs_dev, and a count above pair_capacity leaves
+// every tile range empty
 int bin_sort_slots(const Projected& pr, const ViewTable& vt, int64_t n_slots, int64_t pair_capacity,
-                   uint32_t* pair_vals, uint32_t* tile_ranges, int64_t* n_pairs, void* ws, size_t ws_bytes,
+                   uint32_t* pair_vals, uint32_t* tile_ranges, int64_t* n_pairs_dev, void* ws, size_t ws_bytes,
                    hipStream_t s);
 
 }  // namespace host

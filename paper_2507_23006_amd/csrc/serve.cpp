@@ -204,6 +204,8 @@ struct Worker {
     size_t bin_ws_bytes = 0;
     float *rgb = nullptr, *depth = nullptr, *alpha = nullptr, *T = nullptr;
     int32_t* last = nullptr;
+    int64_t* npairs_dev = nullptr;      // the binning's pair count (device)
+    int64_t* npairs_host = nullptr;     // its copy after the batch (pinned)
     std::thread th;
 };
 
@@ -242,10 +244,11 @@ void free_worker(Worker* w) {
     if (!w) return;
     void* dev[] = {w->proj.rec,  w->proj.rect, w->proj.tiles, w->proj.dkey, w->proj.tile_order, w->proj.tile_mask,
                    w->segs_dev,  w->pairs,     w->ranges,     w->bin_ws,    w->rgb,             w->depth,
-                   w->alpha,     w->T,         w->last};
+                   w->alpha,     w->T,         w->last,       w->npairs_dev};
     for (void* p : dev)
         if (p) (void)hipFree(p);
     if (w->segs_host) (void)hipHostFree(w->segs_host);
+    if (w->npairs_host) (void)hipHostFree(w->npairs_host);
     if (w->stream) (void)hipStreamDestroy(w->stream);
     delete w;
 }
@@ -276,6 +279,8 @@ int alloc_worker(gs_server* s, Worker* w) {
     GS_HIP(dev_alloc(&w->alpha, (size_t)X));
     GS_HIP(dev_alloc(&w->T, (size_t)X));
     GS_HIP(dev_alloc(&w->last, (size_t)X));
+    GS_HIP(dev_alloc(&w->npairs_dev, 1));
+    GS_HIP(hipHostMalloc(reinterpret_cast<void**>(&w->npairs_host), sizeof(int64_t), hipHostMallocDefault));
     return GS_OK;
 }
 
@@ -306,7 +311,7 @@ int render_batch(Worker* w, Request* r, int nb, int64_t* n_pairs) {
         GS_HIP(hipMemcpyAsync(w->segs_dev, w->segs_host, (size_t)ns * sizeof(SlotSeg), hipMemcpyHostToDevice,
                               w->stream));
         GS_HIP(launch_project_slots(s->gp, s->n, vt, s->opt, w->segs_dev, ns, (uint32_t)slots, w->proj, w->stream));
-        rc = bin_sort_slots(w->proj, vt, slots, s->cfg.pair_capacity, w->pairs, w->ranges, n_pairs, w->bin_ws,
+        rc = bin_sort_slots(w->proj, vt, slots, s->cfg.pair_capacity, w->pairs, w->ranges, w->npairs_dev, w->bin_ws,
                             w->bin_ws_bytes, w->stream);
         if (rc) return rc;
     } else {
@@ -319,7 +324,16 @@ int render_batch(Worker* w, Request* r, int nb, int64_t* n_pairs) {
         GS_HIP(hipMemcpyAsync(r[v].out, w->rgb + 3 * vt.v[v].pix_off,
                               (size_t)r[v].cam.width * r[v].cam.height * 3 * sizeof(float), hipMemcpyDeviceToDevice,
                               w->stream));
+    if (slots > 0)
+        GS_HIP(hipMemcpyAsync(w->npairs_host, w->npairs_dev, sizeof(int64_t), hipMemcpyDeviceToHost, w->stream));
     GS_HIP(hipStreamSynchronize(w->stream));
+    if (slots > 0) {
+        // a batch over the pair buffer rendered empty lists: the caller splits it
+        *n_pairs = *w->npairs_host;
+        if (*n_pairs > s->cfg.pair_capacity)
+            return fail(GS_ERR_CAPACITY, "batch needs %lld pairs (capacity %lld)", (long long)*n_pairs,
+                        (long long)s->cfg.pair_capacity);
+    }
     return GS_OK;
 }
 

@@ -46,12 +46,20 @@ __device__ __forceinline__ unsigned long long match_digit(uint32_t digit, bool v
     return m;
 }
 
+// n_dev (nullable): the key count on the device, at most n (the launch's bound)
+__device__ __forceinline__ uint32_t count_of(uint32_t n, const uint32_t* __restrict__ n_dev) {
+    return n_dev ? min(*n_dev, n) : n;
+}
+
 template <int kSortIpt>
-__global__ __launch_bounds__(kSortThreads) void k_radix_upsweep(const uint32_t* __restrict__ keys, uint32_t n,
-                                                                int shift, int bits, uint32_t* __restrict__ hist,
+__global__ __launch_bounds__(kSortThreads) void k_radix_upsweep(const uint32_t* __restrict__ keys, uint32_t n_max,
+                                                                const uint32_t* __restrict__ n_dev, int shift,
+                                                                int bits, uint32_t* __restrict__ hist,
                                                                 uint32_t n_tiles) {
     constexpr int kSortTile = kSortThreads * kSortIpt, kWaveItems = 64 * kSortIpt;
     __shared__ uint32_t cnt[4][1 << kMaxRadixBits];
+    // every workgroup writes its column of the digit table (zeros past n)
+    const uint32_t n = count_of(n_max, n_dev);
     const int radix = 1 << bits;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     // rows are (1 << kMaxRadixBits) apart: clear the whole table, not 4 * radix entries
@@ -74,9 +82,11 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_upsweep(const uint32_t* 
 template <int kSortIpt>
 __global__ __launch_bounds__(kSortThreads) void k_radix_downsweep(
     const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
-    uint32_t* __restrict__ vout, uint32_t n, int shift, int bits, const uint32_t* __restrict__ hist_scan,
-    uint32_t n_tiles) {
+    uint32_t* __restrict__ vout, uint32_t n_max, const uint32_t* __restrict__ n_dev, int shift, int bits,
+    const uint32_t* __restrict__ hist_scan, uint32_t n_tiles) {
     constexpr int kSortTile = kSortThreads * kSortIpt, kWaveItems = 64 * kSortIpt;
+    const uint32_t n = count_of(n_max, n_dev);
+    if (blockIdx.x * (uint32_t)kSortTile >= n) return;     // no keys in this tile
     __shared__ uint32_t s_keys[kSortTile];
     __shared__ uint32_t s_vals[kSortTile];
     __shared__ uint32_t s_wcnt[4][1 << kMaxRadixBits];
@@ -197,11 +207,13 @@ __device__ __forceinline__ uint32_t scan_value(uint32_t x) {
 // kScanSumParts counters 16 apart (one atomic address would serialise
 // thousands of workgroups from all XCDs); the counters must start at 0.
 template <bool kFlags>
-__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint32_t* __restrict__ in, uint32_t n,
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint32_t* __restrict__ in, uint32_t n_max,
+                                                              const uint32_t* __restrict__ n_dev,
                                                               uint32_t* __restrict__ tsum,
                                                               unsigned long long* __restrict__ raw_parts) {
     __shared__ uint32_t s_w[4];
     __shared__ unsigned long long s_raw[4];
+    const uint32_t n = count_of(n_max, n_dev);
     const uint32_t base = blockIdx.x * kScanTile;
     uint32_t acc = 0;
     unsigned long long raw = 0;
@@ -237,10 +249,12 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint32_t* __
 // writes the 64-bit total.
 template <bool kFlags>
 __global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t* __restrict__ in,
-                                                            uint32_t* __restrict__ out, uint32_t n,
+                                                            uint32_t* __restrict__ out, uint32_t n_max,
+                                                            const uint32_t* __restrict__ n_dev,
                                                             const uint32_t* __restrict__ tsum,
                                                             unsigned long long* __restrict__ total) {
     __shared__ uint32_t s_buf[kScanTile];
+    const uint32_t n = count_of(n_max, n_dev);
     __shared__ uint32_t s_w[4];
     __shared__ unsigned long long s_off[4];
     const uint32_t base = blockIdx.x * kScanTile;
@@ -314,15 +328,15 @@ hipError_t fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s) {
 }
 
 hipError_t exclusive_scan_u32(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* tmp,
-                              unsigned long long* total, hipStream_t s) {
+                              unsigned long long* total, hipStream_t s, const uint32_t* n_dev) {
     const uint32_t nt = (n + kScanTile - 1) / kScanTile;
     if (n == 0) {
         hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, (uint32_t*)total, 0u, (size_t)2);
         return hipGetLastError();
     }
-    hipLaunchKernelGGL(k_scan_reduce<false>, dim3(nt), dim3(kScanThreads), 0, s, in, n, tmp,
+    hipLaunchKernelGGL(k_scan_reduce<false>, dim3(nt), dim3(kScanThreads), 0, s, in, n, n_dev, tmp,
                        (unsigned long long*)nullptr);
-    hipLaunchKernelGGL(k_scan_down<false>, dim3(nt), dim3(kScanThreads), 0, s, in, out, n, tmp, total);
+    hipLaunchKernelGGL(k_scan_down<false>, dim3(nt), dim3(kScanThreads), 0, s, in, out, n, n_dev, tmp, total);
     return hipGetLastError();
 }
 
@@ -333,18 +347,27 @@ hipError_t exclusive_scan_nonzero_u32(const uint32_t* in, uint32_t* out, uint32_
         hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, (uint32_t*)total, 0u, (size_t)2);
         return hipGetLastError();
     }
-    hipLaunchKernelGGL(k_scan_reduce<true>, dim3(nt), dim3(kScanThreads), 0, s, in, n, tmp, sum_parts);
-    hipLaunchKernelGGL(k_scan_down<true>, dim3(nt), dim3(kScanThreads), 0, s, in, out, n, tmp, total);
+    hipLaunchKernelGGL(k_scan_reduce<true>, dim3(nt), dim3(kScanThreads), 0, s, in, n, (const uint32_t*)nullptr,
+                       tmp, sum_parts);
+    hipLaunchKernelGGL(k_scan_down<true>, dim3(nt), dim3(kScanThreads), 0, s, in, out, n, (const uint32_t*)nullptr,
+                       tmp, total);
     return hipGetLastError();
+}
+
+int radix_passes(uint32_t n, int begin_bit, int end_bit) {
+    return (n <= 1 || end_bit <= begin_bit) ? 0 : (end_bit - begin_bit + kMaxRadixBits - 1) / kMaxRadixBits;
 }
 
 // Sorts keys/vals on bits [begin_bit, end_bit) with passes of <= 8 bits of
 // near-equal width.  The result lands in (keys, vals) or in the alternate
 // buffers; *result_in_alt says which.  `hist` needs radix_hist_elems(n).
+// With n_dev the key count is read on the device (at most n, which sizes
+// the launches), so the sort needs no host knowledge of it.
 hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt, uint32_t n,
-                            int begin_bit, int end_bit, uint32_t* hist, hipStream_t s, bool* result_in_alt) {
+                            int begin_bit, int end_bit, uint32_t* hist, hipStream_t s, bool* result_in_alt,
+                            const uint32_t* n_dev) {
     *result_in_alt = false;
-    if (n <= 1 || end_bit <= begin_bit) return hipSuccess;
+    if (radix_passes(n, begin_bit, end_bit) == 0) return hipSuccess;
     const int total_bits = end_bit - begin_bit;
     const int passes = (total_bits + kMaxRadixBits - 1) / kMaxRadixBits;
     const bool small = n <= kSmallSortMax;
@@ -360,19 +383,19 @@ hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, 
         const int bits = (remaining + (passes - p) - 1) / (passes - p);
         const uint32_t radix_elems = (uint32_t)tiles << bits;
         if (small)
-            hipLaunchKernelGGL(k_radix_upsweep<4>, dim3(tiles), dim3(kSortThreads), 0, s, ki, n, shift, bits, hist,
-                               tiles);
+            hipLaunchKernelGGL(k_radix_upsweep<4>, dim3(tiles), dim3(kSortThreads), 0, s, ki, n, n_dev, shift, bits,
+                               hist, tiles);
         else
-            hipLaunchKernelGGL(k_radix_upsweep<8>, dim3(tiles), dim3(kSortThreads), 0, s, ki, n, shift, bits, hist,
-                               tiles);
+            hipLaunchKernelGGL(k_radix_upsweep<8>, dim3(tiles), dim3(kSortThreads), 0, s, ki, n, n_dev, shift, bits,
+                               hist, tiles);
         hipError_t e = exclusive_scan_u32(hist, hist, radix_elems, scan_tmp, total, s);
         if (e != hipSuccess) return e;
         if (small)
-            hipLaunchKernelGGL(k_radix_downsweep<4>, dim3(tiles), dim3(kSortThreads), 0, s, ki, vi, ko, vo, n, shift,
-                               bits, hist, tiles);
+            hipLaunchKernelGGL(k_radix_downsweep<4>, dim3(tiles), dim3(kSortThreads), 0, s, ki, vi, ko, vo, n, n_dev,
+                               shift, bits, hist, tiles);
         else
-            hipLaunchKernelGGL(k_radix_downsweep<8>, dim3(tiles), dim3(kSortThreads), 0, s, ki, vi, ko, vo, n, shift,
-                               bits, hist, tiles);
+            hipLaunchKernelGGL(k_radix_downsweep<8>, dim3(tiles), dim3(kSortThreads), 0, s, ki, vi, ko, vo, n, n_dev,
+                               shift, bits, hist, tiles);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
         shift += bits;

@@ -74,6 +74,7 @@ class Workspace:
 
     def __init__(self):
         self._bufs = {}
+        self.pair_caps = {}      # (slots, tiles) -> pair capacity of gs_bin_sort
 
     def get(self, name: str, nbytes: int, device) -> torch.Tensor:
         b = self._bufs.get(name)
@@ -139,32 +140,68 @@ def project(means, scales, quats, opacities, sh, cams, opts: RenderOptions, app=
     return out
 
 
-def bin_sort(proj: Projected, cams, n: int, ws: Workspace | None = None, capacity_hint: int | None = None):
-    """Returns (pair_vals [P] int32, tile_ranges [T, 2] int32, P).  pair_vals
-    is a fresh tensor (torch's caching allocator), so results of several
-    calls can be alive at once; the capacity guess is remembered.  With P = 0
-    pair_vals has one unused element."""
+class PairCount:
+    """The pair count of an asynchronous binning: the library writes it to
+    device memory; int() waits for that write (a copy to pinned host memory
+    queued behind the binning) and returns it.  A count above `capacity`
+    means the binning produced empty tile lists and must be repeated with a
+    larger pair buffer."""
+
+    def __init__(self, dev_count: torch.Tensor, capacity: int):
+        self.capacity = int(capacity)
+        self._host = torch.empty((1,), dtype=torch.int64, pin_memory=True)
+        self._host.copy_(dev_count, non_blocking=True)
+        self._event = torch.cuda.Event()
+        self._event.record()
+
+    def __int__(self) -> int:
+        self._event.synchronize()
+        return int(self._host[0])
+
+    def overflowed(self) -> bool:
+        return int(self) > self.capacity
+
+
+def _pair_capacity(P: int) -> int:
+    return int(P * 1.25) + 4096
+
+
+def bin_sort(proj: Projected, cams, n: int, ws: Workspace | None = None, capacity_hint: int | None = None,
+             sync: bool = True):
+    """Returns (pair_vals, tile_ranges [T, 2] int32, P).  The library bins
+    without any host read-back.  With sync (default) P is read here as an
+    int -- the call is repeated with a larger pair buffer when P exceeded
+    it -- and pair_vals is [P] (one unused element when P = 0).  With
+    sync=False nothing waits: pair_vals is the whole capacity buffer and P a
+    PairCount to check later.  pair_vals is a fresh tensor (torch's caching
+    allocator), so results of several calls can be alive at once; the
+    workspace remembers, per (slots, tiles), a capacity 25 % above the last
+    count it read."""
     lib = L.load()
     ws = ws or _default_ws
     dev = proj.rec.device
     S = n * len(cams)
     n_tiles, _ = views_extent(cams)
-    cap = int(capacity_hint or max(1 << 20, 4 * S, getattr(ws, "pair_capacity", 0)))
+    key = (S, n_tiles)
+    cap = int(capacity_hint or ws.pair_caps.get(key, 0) or max(1 << 20, 4 * S))
     ranges = torch.empty((n_tiles, 2), dtype=torch.int32, device=dev)
     cams_c = L.make_cameras(cams)
-    for _ in range(2):
-        pairs = torch.empty((cap,), dtype=torch.int32, device=dev)
+    npairs = torch.empty((1,), dtype=torch.int64, device=dev)
+    for _ in range(3):
+        pairs = torch.empty((max(cap, 1),), dtype=torch.int32, device=dev)
         wsz = lib.gs_bin_workspace_size(S, cap)
         wbuf = ws.get("bin", wsz + 256, dev)
-        npairs = C.c_int64()
-        rc = lib.gs_bin_sort(C.byref(proj.c()), cams_c, len(cams), n, cap, _ptr(pairs), _ptr(ranges),
-                             C.byref(npairs), C.c_void_p(Workspace.aligned(wbuf)), wsz, _stream())
-        if rc == L.GS_ERR_CAPACITY and cap < npairs.value < 0xFFFFFF00:
-            cap = int(npairs.value * 1.25) + 1024
-            ws.pair_capacity = cap
+        L.check(lib.gs_bin_sort(C.byref(proj.c()), cams_c, len(cams), n, cap, _ptr(pairs), _ptr(ranges),
+                                C.c_void_p(npairs.data_ptr()), C.c_void_p(Workspace.aligned(wbuf)), wsz, _stream()))
+        if not sync:
+            return pairs, ranges, PairCount(npairs, cap)
+        P = int(npairs.item())
+        if P > 0xFFFFFF00:
+            raise L.GsError(L.GS_ERR_CAPACITY, f"{P} pairs exceed 32-bit indexing")
+        ws.pair_caps[key] = _pair_capacity(P)
+        if P > cap:
+            cap = ws.pair_caps[key]
             continue
-        L.check(rc)
-        P = int(npairs.value)
         # an empty view has a null data pointer in torch; with no pairs hand
         # back one (never read) element so the buffer pointer stays valid
         return (pairs[:P] if P > 0 else pairs[:1]), ranges, P
@@ -281,7 +318,8 @@ def grad2d_view(grads: dict) -> torch.Tensor:
 
 class RenderStats:
     """Filled by the backward: per-view |dL/d mean2d| [V, N] in pixels, and
-    (with absgrad) the per-pixel absolute accumulation [V, N, 2]."""
+    (with absgrad) the per-pixel absolute accumulation [V, N, 2]; by the
+    forward: n_pairs (an int, or a PairCount whose int() waits for it)."""
     mean2d_grad_norm = None
     absgrad = None
     n_pairs = 0
@@ -299,13 +337,17 @@ class GsRasterize(torch.autograd.Function):
         n = params[0].shape[-1]
         proj = project(*params, cams, opts, app=app)
         _mark("project")
-        pair_vals, ranges, P = bin_sort(proj, cams, n)
+        # asynchronous once the workspace knows a pair capacity for this
+        # size (checked at the end of the backward, or by reading
+        # stats.n_pairs)
+        known = (n * len(cams), views_extent(cams)[0]) in _default_ws.pair_caps
+        pair_vals, ranges, P = bin_sort(proj, cams, n, sync=not known)
         _mark("bin_sort")
         out = render_fwd(proj, pair_vals, ranges, cams, opts)
         _mark("render_fwd")
         ctx.save_for_backward(*params, proj.rec, proj.rect, proj.tiles, proj.depth_key, proj.tile_order, pair_vals,
                               ranges, out["T"], out["last"], app)
-        ctx.cams, ctx.opts, ctx.stats = list(cams), opts, stats
+        ctx.cams, ctx.opts, ctx.stats, ctx.n_pairs, ctx.n_slots = list(cams), opts, stats, P, n * len(cams)
         if stats is not None:
             stats.n_pairs = P
         return out["rgb"], out["depth"], out["alpha"]
@@ -320,6 +362,13 @@ class GsRasterize(torch.autograd.Function):
         if ctx.stats is not None:
             ctx.stats.mean2d_grad_norm = g["mean2d_grad_norm"]
             ctx.stats.absgrad = g["absgrad"]
+        # the forward's binning ran without a read-back; its count is known
+        # by now (the whole backward is enqueued behind it)
+        P = ctx.n_pairs
+        if isinstance(P, PairCount) and P.overflowed():
+            _default_ws.pair_caps[(ctx.n_slots, views_extent(ctx.cams)[0])] = _pair_capacity(int(P))
+            raise L.GsError(L.GS_ERR_CAPACITY, f"the forward needed {int(P)} pairs but had room for {P.capacity}; "
+                                               f"the capacity has been grown, repeat the step")
         return g["means"], g["scales"], g["quats"], g["opacities"], g["sh"], g.get("app"), None, None, None
 
 

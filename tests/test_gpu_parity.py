@@ -452,3 +452,37 @@ def test_dssim_kernel_matches_oracle(gpu_lib, W, H):
     assert np.abs(got - 3 * g).max() <= 1e-4 * scale
     again = gpu_lib.dssim_loss(xt, torch.from_numpy(y).cuda(), 0.2)
     assert torch.equal(loss, again)
+
+
+def test_async_binning_matches_and_reports_overflow(gpu_lib):
+    """gs_bin_sort reads nothing back: with sync=False the pair count stays
+    on the device (PairCount), results equal the synchronous call's bit for
+    bit, a pair buffer that is too small shows in the count and leaves every
+    tile list empty, and the autograd path raises at the end of the backward
+    when its forward's binning overflowed (after growing the capacity)."""
+    make, cams, od = CASES["multiview"]
+    scene = make()
+    opts = _opts(gpu_lib, od)
+    proj = gpu_lib.project(*to_dev(scene), cams, opts)
+    pv, rg, P = gpu_lib.bin_sort(proj, cams, scene.n)
+    pv2, rg2, P2 = gpu_lib.bin_sort(proj, cams, scene.n, sync=False, capacity_hint=P + 10)
+    assert int(P2) == P and not P2.overflowed()
+    assert torch.equal(pv2[:P], pv) and torch.equal(rg2, rg)
+    pv3, rg3, P3 = gpu_lib.bin_sort(proj, cams, scene.n, sync=False, capacity_hint=P // 2)
+    assert int(P3) == P and P3.overflowed()
+    assert int(rg3.to(torch.int64).abs().sum()) == 0
+    ws = gpu_lib.rasterizer._default_ws
+    key = (scene.n * len(cams), sum(c.n_tiles for c in cams))
+    saved = ws.pair_caps.get(key)
+    ws.pair_caps[key] = P // 2
+    try:
+        prm = to_dev(scene, requires_grad=True)
+        rgb, depth, alpha = gpu_lib.rasterize(*prm, cams, opts)
+        with pytest.raises(gpu_lib.GsError):
+            rgb.sum().backward()
+        assert ws.pair_caps[key] > P
+    finally:
+        if saved is None:
+            ws.pair_caps.pop(key, None)
+        else:
+            ws.pair_caps[key] = saved
