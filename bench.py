@@ -515,17 +515,30 @@ def counted_traffic(kernel):
         return None
 
 
-def serve_bench(gs, S, torch, fine, opts, n_requests):
+def serve_modes(gs, n_requests):
+    """Server configurations of the serving trace: "plain" (one request per
+    launch, one worker, one batch in flight: FIFO) and "served" (continuous
+    batching of up to 8 views admitted by estimated pairs, two workers, two
+    batches in flight per worker so the next batch's projection and binning
+    overlap the current compositing)."""
+    return {
+        "plain": gs.ServeConfig(max_views_per_batch=1, n_streams=1, pipeline_depth=1, slot_capacity=6_000_000,
+                                pair_capacity=48_000_000, pixel_capacity=1 << 21, queue_capacity=n_requests),
+        "served": gs.ServeConfig(max_views_per_batch=8, n_streams=2, pipeline_depth=2, slot_capacity=24_000_000,
+                                 pair_capacity=96_000_000, pixel_capacity=1 << 24, queue_capacity=n_requests),
+    }
+
+
+def serve_bench(gs, S, torch, fine, opts, n_requests, modes=None, loads=("", "_800", "_burst")):
     """Open-loop serving trace on the level-of-detail stand-in of the urban
     block: levels of 1M, 3M and 6M Gaussians resident in HBM, 30 m render-time
     partitions, thresholds (30, 60, inf) m; Poisson arrivals at 150 req/s,
     resolutions 640x360 / 1280x720 / 1920x1080 and budgets 1M / 3M / 6M
-    drawn uniformly.  Run on the same trace: "plain" (one request per
-    launch, one stream, FIFO) and "served" (continuous batching of up to 8
-    views, two worker streams); then both with the arrival times compressed
-    to 800 req/s ("_800"), and with every request arriving at once
-    ("_burst": the saturated throughput).  Latency = completion - scheduled
-    arrival."""
+    drawn uniformly.  Each configuration of `modes` (default serve_modes)
+    runs the trace as scheduled, with the arrival times compressed to 800
+    req/s ("_800", where batches form), and with every request arriving at
+    once ("_burst": the saturated throughput).  Latency = completion -
+    scheduled arrival."""
     t_gen = time.time()
     lod = S.lod_scene_c4(fine)
     sc, offsets = lod.combined()
@@ -541,23 +554,15 @@ def serve_bench(gs, S, torch, fine, opts, n_requests):
         off += k
     print(f"# serving scene ready in {time.time() - t_gen:.1f} s ({sc.n} Gaussians in {len(lod.levels)} levels, "
           f"{lod.counts.shape[1]} partitions)", file=sys.stderr, flush=True)
-    modes = {
-        "plain": gs.ServeConfig(max_views_per_batch=1, n_streams=1, slot_capacity=6_000_000,
-                                pair_capacity=48_000_000, pixel_capacity=1 << 21, queue_capacity=n_requests),
-        "served": gs.ServeConfig(max_views_per_batch=8, n_streams=2, slot_capacity=24_000_000,
-                                 pair_capacity=96_000_000, pixel_capacity=1 << 24, queue_capacity=n_requests),
-    }
-    res = {}
-    # the trace as scheduled (150 req/s), the same requests at 800 req/s
-    # (where batches form), and all at once (saturation)
+    modes = modes or serve_modes(gs, n_requests)
     fast = [r["t"] * 150.0 / 800.0 for r in trace]
-    runs = ([(name, cfg, [r["t"] for r in trace]) for name, cfg in modes.items()]
-            + [(name + "_800", cfg, fast) for name, cfg in modes.items()]
-            + [(name + "_burst", cfg, [0.0] * len(trace)) for name, cfg in modes.items()])
-    for name, cfg, arrivals in runs:
+    arrivals = {"": [r["t"] for r in trace], "_800": fast, "_burst": [0.0] * len(trace)}
+    runs = [(name + load, cfg, arrivals[load]) for load in loads for name, cfg in modes.items()]
+    res = {}
+    for name, cfg, arr in runs:
         srv = gs.Server(params, table, opts, cfg)
         t0 = srv.now() + 0.5
-        for r, o, ta in zip(trace, outs, arrivals):
+        for r, o, ta in zip(trace, outs, arr):
             srv.submit(r["camera"], r["budget"], o, t0 + ta)
         n_done, n_fail, views, t_print = 0, 0, 0, time.time()
         while n_done < len(trace):
@@ -573,6 +578,7 @@ def serve_bench(gs, S, torch, fine, opts, n_requests):
                      "mean_ms": round(st["mean_ms"], 3), "max_ms": round(st["max_ms"], 3),
                      "req_per_s": round(st["req_per_s"], 2), "mpix_per_s": round(st["mpix_per_s"], 1),
                      "mean_batch_views": round(st["mean_batch_views"], 3), "batches": st["batches"],
+                     "split_batches": st["split_batches"], "est_over_actual": round(st["est_over_actual"], 3),
                      "completed": st["completed"], "failed": st["failed"]}
         print(f"# {name}: {res[name]}", file=sys.stderr, flush=True)
     res["trace"] = (f"{len(trace)} requests, Poisson {len(trace) / trace[-1]['t']:.0f} req/s over "

@@ -462,27 +462,39 @@ typedef struct gs_lod_table {
 int gs_lod_select(const gs_lod_table *table, const gs_camera *cam, int64_t budget, int32_t *level,
                   int64_t *total);
 
-/* Serving: a native request queue with worker threads, one HIP stream and
- * one set of device buffers per worker (allocated by gs_serve_create, the
- * only allocating call).  Each request is a camera, a Gaussian budget and a
- * device output image [H][W][3] float32 owned by the caller.  Requests wait
- * until their arrival time; a free worker takes every arrived request at the
- * head of the queue, in order, while the batch stays within
- * max_views_per_batch and the worker's slot, pixel and tile capacities
- * (admission), projects each view's selected segments, bins all views of the
- * batch in one sort and composites them in one multi-view launch, then
- * copies each image to its request's output.  A batch whose pairs overflow
- * pair_capacity is split in halves and retried; a single request that still
- * overflows completes with GS_ERR_CAPACITY.  The rendered image is the
- * image gs_render_fwd gives for the selected Gaussians alone, whatever the
- * batch. */
+/* Serving: a native request queue with worker threads (allocated by
+ * gs_serve_create, the only allocating call).  Each request is a camera, a
+ * Gaussian budget and a device output image [H][W][3] float32 owned by the
+ * caller.  Requests wait until their arrival time; a worker takes every
+ * arrived request at the head of the queue, in order, while the batch stays
+ * within max_views_per_batch, the slot, pixel and tile capacities, and an
+ * estimate of its (tile, Gaussian) pairs within pair_capacity (admission by
+ * sort-buffer size: a request's estimate is its selected Gaussians times a
+ * pairs-per-Gaussian ratio learned per image size from the batches already
+ * rendered -- raised at once when a batch needs more, lowered gradually --
+ * with 15 % headroom; pairs_per_gaussian seeds sizes not yet seen).  It
+ * projects each view's selected segments, bins all views of the batch in one
+ * sort and composites them in one multi-view launch, then copies each image
+ * to its request's output.  Each worker has two HIP streams and
+ * pipeline_depth sets of device buffers: with a depth of 2 the projection
+ * and binning of the next batch (one stream) overlap the compositing of the
+ * current one (the other), ordered by events, with no host wait in between.
+ * A batch whose pairs still overflow pair_capacity is split in halves and
+ * re-rendered (counted in split_batches); a single request that overflows
+ * completes with GS_ERR_CAPACITY.  The rendered image is the image
+ * gs_render_fwd gives for the selected Gaussians alone, whatever the batch,
+ * the pipeline depth or the compositing mode. */
 typedef struct gs_serve_config {
     int32_t max_views_per_batch;   /* 1..GS_MAX_VIEWS; 1 = one request per launch */
-    int32_t n_streams;             /* worker threads / HIP streams, 1..8 */
+    int32_t n_streams;             /* worker threads, 1..8 */
     int64_t slot_capacity;         /* selected Gaussians per batch, summed over its views */
     int64_t pair_capacity;         /* (tile, Gaussian) pairs per batch */
     int64_t pixel_capacity;        /* pixels per batch */
     int32_t queue_capacity;        /* pending requests; gs_serve_submit returns GS_EAGAIN beyond */
+    int32_t pipeline_depth;        /* batches in flight per worker (buffer sets), 1..4 */
+    int32_t persistent_ctas;       /* 0: one workgroup per tile; > 0: persistent compositing with at most
+                                      this many workgroups taking tiles from a counter */
+    double pairs_per_gaussian;     /* admission ratio for image sizes not yet rendered; 0 = 8 */
 } gs_serve_config;
 
 typedef struct gs_completion {
@@ -500,6 +512,8 @@ typedef struct gs_serve_stats {
     double p50_ms, p99_ms, mean_ms, max_ms;   /* latency = t_done - t_arrival, completed requests */
     double span_s;                 /* first arrival to last completion */
     double req_per_s, mpix_per_s;  /* over span_s */
+    int64_t split_batches;         /* batches re-rendered in halves after a pair overflow */
+    double est_over_actual;        /* mean over admitted batches of estimated / rendered pairs */
 } gs_serve_stats;
 
 typedef struct gs_server gs_server;
@@ -512,11 +526,16 @@ int gs_serve_create(const gs_gaussians *scene, const gs_lod_table *table, const 
 /* Seconds since the server was created (the clock of arrival times). */
 double gs_serve_now(const gs_server *srv);
 /* Queues one request arriving at t_arrival (server clock; it is not started
- * before).  Selection errors (GS_ERR_BUDGET, GS_ERR_INVALID_ARG) and
- * requests larger than one batch's capacities (GS_ERR_CAPACITY) are returned
- * here; GS_EAGAIN when the queue is full. */
-int gs_serve_submit(gs_server *srv, const gs_camera *cam, int64_t budget, float *out_rgb, double t_arrival,
-                    uint64_t *ticket);
+ * before).  An event is recorded on `stream` (a HIP stream of the server's
+ * device; NULL is the null stream) and the worker writes out_rgb only after
+ * it, so work the caller queued there before submitting (filling or
+ * reusing out_rgb) is ordered before the image.  out_rgb must stay valid
+ * until the request's completion is polled.  Selection errors
+ * (GS_ERR_BUDGET, GS_ERR_INVALID_ARG) and requests larger than one batch's
+ * capacities (GS_ERR_CAPACITY) are returned here; GS_EAGAIN when the queue
+ * is full; GS_ERR_HIP when the event cannot be recorded. */
+int gs_serve_submit(gs_server *srv, const gs_camera *cam, int64_t budget, float *out_rgb, void *stream,
+                    double t_arrival, uint64_t *ticket);
 /* Waits up to timeout_us for completions and returns up to max of them. */
 int gs_serve_poll(gs_server *srv, gs_completion *done, int32_t max, int32_t timeout_us, int32_t *n_done);
 int gs_serve_stats_get(gs_server *srv, gs_serve_stats *out);

@@ -83,7 +83,8 @@ class GsLodTable(C.Structure):
 
 class GsServeConfig(C.Structure):
     _fields_ = [("max_views_per_batch", C.c_int32), ("n_streams", C.c_int32), ("slot_capacity", C.c_int64),
-                ("pair_capacity", C.c_int64), ("pixel_capacity", C.c_int64), ("queue_capacity", C.c_int32)]
+                ("pair_capacity", C.c_int64), ("pixel_capacity", C.c_int64), ("queue_capacity", C.c_int32),
+                ("pipeline_depth", C.c_int32), ("persistent_ctas", C.c_int32), ("pairs_per_gaussian", C.c_double)]
 
 
 class GsCompletion(C.Structure):
@@ -96,7 +97,8 @@ class GsServeStats(C.Structure):
     _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64), ("batches", C.c_int64),
                 ("mean_batch_views", C.c_double), ("p50_ms", C.c_double), ("p99_ms", C.c_double),
                 ("mean_ms", C.c_double), ("max_ms", C.c_double), ("span_s", C.c_double),
-                ("req_per_s", C.c_double), ("mpix_per_s", C.c_double)]
+                ("req_per_s", C.c_double), ("mpix_per_s", C.c_double), ("split_batches", C.c_int64),
+                ("est_over_actual", C.c_double)]
 
 
 # exported symbols and their ctypes signatures
@@ -135,7 +137,7 @@ SIGNATURES = {
     "gs_lod_select": (C.c_int, [_P, _P, _I64, _P, _P]),
     "gs_serve_create": (C.c_int, [_P, _P, _P, _P, _I32, _P]),
     "gs_serve_now": (C.c_double, [_P]),
-    "gs_serve_submit": (C.c_int, [_P, _P, _I64, _P, C.c_double, _P]),
+    "gs_serve_submit": (C.c_int, [_P, _P, _I64, _P, _P, C.c_double, _P]),
     "gs_serve_poll": (C.c_int, [_P, _P, _I32, _I32, _P]),
     "gs_serve_stats_get": (C.c_int, [_P, _P]),
     "gs_serve_destroy": (C.c_int, [_P]),

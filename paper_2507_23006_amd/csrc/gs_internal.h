@@ -219,9 +219,12 @@ hipError_t launch_seg_prepare(const Projected& proj, const uint32_t* pair_vals, 
                               hipStream_t s);
 
 // compositing (render.hip)
+// persistent_ctas > 0: a grid of that many workgroups pulling tiles from
+// `work` (one u32, zeroed here by a fill kernel)
 hipError_t launch_render_fwd(const Projected& proj, const uint32_t* pair_vals, const uint2* ranges,
                              const ViewTable& vt, const OptK& opt, float* rgb, float* depth, float* alpha,
-                             float* T_final, int32_t* last, hipStream_t s);
+                             float* T_final, int32_t* last, hipStream_t s,
+                             int persistent_ctas = 0, uint32_t* work = nullptr);
 hipError_t launch_render_count(const Projected& proj, const uint32_t* pair_vals, const uint2* ranges,
                                const ViewTable& vt, int32_t* n_eval, hipStream_t s);
 hipError_t launch_render_bwd(const Projected& proj, const uint32_t* pair_vals, const uint2* ranges,

@@ -243,18 +243,16 @@ __device__ __forceinline__ int stage_gathered(const Gather& e, int pos, const Pi
     return __popcll(m);
 }
 
-__global__ __launch_bounds__(256) void k_render_fwd(const float4* __restrict__ rec,
+// One wave composites quadrant `quad` of `tile` (staging in its LDS slice
+// `st`) and writes its pixels.
+__device__ __forceinline__ void render_fwd_quadrant(const float4* __restrict__ rec,
                                                     const uint32_t* __restrict__ pair_vals,
-                                                    const uint2* __restrict__ ranges,
-                                                    const uint32_t* __restrict__ tile_order, ViewTable vt, OptK opt,
+                                                    const uint2* __restrict__ ranges, const ViewTable& vt,
+                                                    const OptK& opt, int tile, int quad, int lane, WaveStage& st,
                                                     float* __restrict__ rgb, float* __restrict__ depth,
                                                     float* __restrict__ alpha_out, float* __restrict__ T_out,
                                                     int32_t* __restrict__ last_out) {
-    __shared__ WaveStage stage[kWaves];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int tile = launch_tile(tile_order, vt);
-    const PixelCoords pc = pixel_coords(vt, tile, wave, lane);
-    WaveStage& st = stage[wave];
+    const PixelCoords pc = pixel_coords(vt, tile, quad, lane);
     const uint2 rg = ranges[tile];
 
     float T = 1.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f, D = 0.0f;
@@ -304,6 +302,54 @@ __global__ __launch_bounds__(256) void k_render_fwd(const float4* __restrict__ r
     alpha_out[p] = 1.0f - T;
     T_out[p] = T;
     last_out[p] = last;
+}
+
+__global__ __launch_bounds__(256) void k_render_fwd(const float4* __restrict__ rec,
+                                                    const uint32_t* __restrict__ pair_vals,
+                                                    const uint2* __restrict__ ranges,
+                                                    const uint32_t* __restrict__ tile_order, ViewTable vt, OptK opt,
+                                                    float* __restrict__ rgb, float* __restrict__ depth,
+                                                    float* __restrict__ alpha_out, float* __restrict__ T_out,
+                                                    int32_t* __restrict__ last_out) {
+    __shared__ WaveStage stage[kWaves];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    render_fwd_quadrant(rec, pair_vals, ranges, vt, opt, launch_tile(tile_order, vt), wave, lane, stage[wave], rgb,
+                        depth, alpha_out, T_out, last_out);
+}
+
+// Persistent compositing: a fixed grid whose workgroups take tiles in launch
+// order (longest lists first) from a counter until every tile is taken; the
+// four waves composite the tile's quadrants, as in the one-tile-per-workgroup
+// launch, so a tile's records are fetched into one compute unit's cache.  The
+// next tile is taken while the current one composites.  A grid smaller than
+// the device leaves compute units to work on other streams.
+__global__ __launch_bounds__(256) void k_render_fwd_persistent(const float4* __restrict__ rec,
+                                                               const uint32_t* __restrict__ pair_vals,
+                                                               const uint2* __restrict__ ranges,
+                                                               const uint32_t* __restrict__ tile_order, ViewTable vt,
+                                                               OptK opt, float* __restrict__ rgb,
+                                                               float* __restrict__ depth,
+                                                               float* __restrict__ alpha_out,
+                                                               float* __restrict__ T_out,
+                                                               int32_t* __restrict__ last_out,
+                                                               uint32_t* __restrict__ work) {
+    __shared__ WaveStage stage[kWaves];
+    __shared__ uint32_t s_item[2];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const uint32_t n_items = (uint32_t)vt.total_tiles;
+    if (threadIdx.x == 0) s_item[0] = atomicAdd(work, 1u);
+    __syncthreads();
+    int k = 0;
+    uint32_t item = s_item[0];
+    // every wave of the workgroup reads the same item, so all leave together
+    while (item < n_items) {
+        if (threadIdx.x == 0) s_item[k ^ 1] = atomicAdd(work, 1u);
+        render_fwd_quadrant(rec, pair_vals, ranges, vt, opt, order_tile(tile_order, vt, item), wave, lane,
+                            stage[wave], rgb, depth, alpha_out, T_out, last_out);
+        __syncthreads();     // the next item is in LDS; its slot is rewritten only after the next barrier
+        k ^= 1;
+        item = s_item[k];
+    }
 }
 
 // Per pixel: the number of list entries compositing must evaluate -- those
@@ -702,11 +748,19 @@ __global__ __launch_bounds__(256) void k_zero_seen_rows(const uint32_t* __restri
 
 hipError_t launch_render_fwd(const Projected& proj, const uint32_t* pair_vals, const uint2* ranges,
                              const ViewTable& vt, const OptK& opt, float* rgb, float* depth, float* alpha,
-                             float* T_final, int32_t* last, hipStream_t s) {
+                             float* T_final, int32_t* last, hipStream_t s, int persistent_ctas, uint32_t* work) {
     if (vt.total_tiles <= 0) return hipSuccess;
     const hipEvent_t timed_ = timer_begin(GS_KERNEL_RENDER_FWD, s);
-    hipLaunchKernelGGL(k_render_fwd, dim3(vt.total_tiles), dim3(256), 0, s, proj.rec, pair_vals, ranges,
-                       proj.tile_order, vt, opt, rgb, depth, alpha, T_final, last);
+    if (persistent_ctas > 0 && work) {
+        hipError_t e = fill_u32(work, 0u, 1, s);
+        if (e != hipSuccess) return e;
+        const int grid = persistent_ctas < vt.total_tiles ? persistent_ctas : vt.total_tiles;
+        hipLaunchKernelGGL(k_render_fwd_persistent, dim3(grid), dim3(256), 0, s, proj.rec, pair_vals, ranges,
+                           proj.tile_order, vt, opt, rgb, depth, alpha, T_final, last, work);
+    } else {
+        hipLaunchKernelGGL(k_render_fwd, dim3(vt.total_tiles), dim3(256), 0, s, proj.rec, pair_vals, ranges,
+                           proj.tile_order, vt, opt, rgb, depth, alpha, T_final, last);
+    }
     timer_end(timed_, s);
     return hipGetLastError();
 }

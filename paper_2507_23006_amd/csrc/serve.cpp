@@ -23,6 +23,7 @@
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <map>
 #include <mutex>
 #include <numeric>
 #include <thread>
@@ -187,14 +188,14 @@ struct Request {
     gs_camera cam;
     int64_t budget;
     float* out;
+    hipEvent_t ready = nullptr;   // recorded on the caller's stream at submit
     double t_arrival;
     std::vector<int32_t> level;
     int64_t n_sel, n_pix, n_tiles;
 };
 
-struct Worker {
-    gs_server* srv = nullptr;
-    hipStream_t stream = nullptr;
+// One set of a worker's device buffers and the batch it holds in flight.
+struct BufSet {
     Projected proj{};
     SlotSeg* segs_dev = nullptr;
     SlotSeg* segs_host = nullptr;
@@ -206,6 +207,21 @@ struct Worker {
     int32_t* last = nullptr;
     int64_t* npairs_dev = nullptr;      // the binning's pair count (device)
     int64_t* npairs_host = nullptr;     // its copy after the batch (pinned)
+    uint32_t* work = nullptr;           // work counter of persistent compositing
+    hipEvent_t prepped = nullptr;       // projection and binning done
+    hipEvent_t done = nullptr;          // images and pair count written
+    // the batch in flight
+    std::vector<Request> reqs;
+    int64_t slots = 0;
+    double est_pairs = 0.0, t_start = 0.0;
+    int rc = GS_OK;
+};
+
+struct Worker {
+    gs_server* srv = nullptr;
+    hipStream_t prep = nullptr;         // projection and binning
+    hipStream_t render = nullptr;       // compositing and output copies
+    std::vector<BufSet> sets;
     std::thread th;
 };
 
@@ -225,13 +241,17 @@ struct gs_server {
     bool stop = false;
     uint64_t next_ticket = 1;
     int64_t submitted = 0;
+    // admission model (under mu): pairs per selected Gaussian by resolution
+    std::map<uint64_t, double> ratio;
+    std::vector<hipEvent_t> free_events;
 
     std::mutex done_mu;
     std::condition_variable done_cv;
     std::deque<gs_completion> done;
     std::vector<double> lat_ms;
-    int64_t completed = 0, failed = 0, batches = 0, batch_views = 0, pixels = 0;
-    double first_arrival = INFINITY, last_done = 0.0;
+    int64_t completed = 0, failed = 0, batches = 0, batch_views = 0, pixels = 0, split_batches = 0;
+    double first_arrival = INFINITY, last_done = 0.0, est_over_actual = 0.0;
+    int64_t est_batches = 0;
 
     std::vector<Worker*> workers;
 
@@ -240,16 +260,67 @@ struct gs_server {
 
 namespace {
 
-void free_worker(Worker* w) {
-    if (!w) return;
-    void* dev[] = {w->proj.rec,  w->proj.rect, w->proj.tiles, w->proj.dkey, w->proj.tile_order, w->proj.tile_mask,
-                   w->segs_dev,  w->pairs,     w->ranges,     w->bin_ws,    w->rgb,             w->depth,
-                   w->alpha,     w->T,         w->last,       w->npairs_dev};
+// headroom of the admission estimate over the learned ratio
+constexpr double kAdmitMargin = 1.15;
+constexpr double kDefaultPairsPerGaussian = 8.0;
+
+uint64_t view_class(const gs_camera& c) { return ((uint64_t)(uint32_t)c.width << 32) | (uint32_t)c.height; }
+
+// estimated pairs of one request (caller holds s->mu)
+double estimate_pairs(const gs_server* s, const Request& r) {
+    const auto it = s->ratio.find(view_class(r.cam));
+    double k = s->cfg.pairs_per_gaussian > 0.0 ? s->cfg.pairs_per_gaussian : kDefaultPairsPerGaussian;
+    if (it != s->ratio.end()) k = it->second;
+    return (double)r.n_sel * k;
+}
+
+// after a batch: scale the ratios of its view classes by observed/estimated,
+// at once upward, a quarter of the way downward
+void learn_pairs(gs_server* s, const Request* r, int nb, int64_t observed) {
+    std::lock_guard<std::mutex> lk(s->mu);
+    double est = 0.0;
+    for (int i = 0; i < nb; ++i) est += estimate_pairs(s, r[i]);
+    if (est <= 0.0) return;
+    const double f = (double)observed / est;
+    const double g = f >= 1.0 ? f : 1.0 - 0.25 * (1.0 - f);
+    std::vector<uint64_t> seen;
+    for (int i = 0; i < nb; ++i) {
+        const uint64_t c = view_class(r[i].cam);
+        if (std::find(seen.begin(), seen.end(), c) != seen.end()) continue;
+        seen.push_back(c);
+        const auto it = s->ratio.find(c);
+        const double k = it != s->ratio.end() ? it->second
+                         : (s->cfg.pairs_per_gaussian > 0.0 ? s->cfg.pairs_per_gaussian : kDefaultPairsPerGaussian);
+        s->ratio[c] = std::max(k * g, 1e-3);
+    }
+}
+
+void recycle_events(gs_server* s, Request* r, int nb) {
+    std::lock_guard<std::mutex> lk(s->mu);
+    for (int i = 0; i < nb; ++i)
+        if (r[i].ready) {
+            s->free_events.push_back(r[i].ready);
+            r[i].ready = nullptr;
+        }
+}
+
+void free_set(BufSet& b) {
+    void* dev[] = {b.proj.rec, b.proj.rect, b.proj.tiles, b.proj.dkey, b.proj.tile_order, b.proj.tile_mask,
+                   b.segs_dev, b.pairs,     b.ranges,     b.bin_ws,    b.rgb,              b.depth,
+                   b.alpha,    b.T,         b.last,       b.npairs_dev, b.work};
     for (void* p : dev)
         if (p) (void)hipFree(p);
-    if (w->segs_host) (void)hipHostFree(w->segs_host);
-    if (w->npairs_host) (void)hipHostFree(w->npairs_host);
-    if (w->stream) (void)hipStreamDestroy(w->stream);
+    if (b.segs_host) (void)hipHostFree(b.segs_host);
+    if (b.npairs_host) (void)hipHostFree(b.npairs_host);
+    if (b.prepped) (void)hipEventDestroy(b.prepped);
+    if (b.done) (void)hipEventDestroy(b.done);
+}
+
+void free_worker(Worker* w) {
+    if (!w) return;
+    for (BufSet& b : w->sets) free_set(b);
+    if (w->prep) (void)hipStreamDestroy(w->prep);
+    if (w->render) (void)hipStreamDestroy(w->render);
     delete w;
 }
 
@@ -258,34 +329,50 @@ hipError_t dev_alloc(T** p, size_t count) {
     return hipMalloc(reinterpret_cast<void**>(p), std::max<size_t>(count, 1) * sizeof(T));
 }
 
-int alloc_worker(gs_server* s, Worker* w) {
+int alloc_set(gs_server* s, BufSet& b) {
     const int64_t S = s->cfg.slot_capacity, Pc = s->cfg.pair_capacity, X = s->cfg.pixel_capacity;
-    GS_HIP(hipStreamCreateWithFlags(&w->stream, hipStreamNonBlocking));
-    GS_HIP(dev_alloc(&w->proj.rec, 4 * (size_t)S));
-    GS_HIP(dev_alloc(&w->proj.rect, (size_t)S));
-    GS_HIP(dev_alloc(&w->proj.tiles, (size_t)S));
-    GS_HIP(dev_alloc(&w->proj.dkey, (size_t)S));
-    GS_HIP(dev_alloc(&w->proj.tile_mask, (size_t)S));
-    GS_HIP(dev_alloc(&w->segs_dev, (size_t)s->seg_cap));
-    GS_HIP(hipHostMalloc(reinterpret_cast<void**>(&w->segs_host), (size_t)s->seg_cap * sizeof(SlotSeg),
+    GS_HIP(dev_alloc(&b.proj.rec, 4 * (size_t)S));
+    GS_HIP(dev_alloc(&b.proj.rect, (size_t)S));
+    GS_HIP(dev_alloc(&b.proj.tiles, (size_t)S));
+    GS_HIP(dev_alloc(&b.proj.dkey, (size_t)S));
+    GS_HIP(dev_alloc(&b.proj.tile_mask, (size_t)S));
+    GS_HIP(dev_alloc(&b.segs_dev, (size_t)s->seg_cap));
+    GS_HIP(hipHostMalloc(reinterpret_cast<void**>(&b.segs_host), (size_t)s->seg_cap * sizeof(SlotSeg),
                          hipHostMallocDefault));
-    GS_HIP(dev_alloc(&w->pairs, (size_t)Pc));
-    GS_HIP(dev_alloc(&w->ranges, 2 * (size_t)s->tile_cap));
-    GS_HIP(dev_alloc(&w->proj.tile_order, (size_t)s->tile_cap));
-    w->bin_ws_bytes = bin_workspace_bytes(S, Pc);
-    GS_HIP(hipMalloc(&w->bin_ws, w->bin_ws_bytes));
-    GS_HIP(dev_alloc(&w->rgb, 3 * (size_t)X));
-    GS_HIP(dev_alloc(&w->depth, (size_t)X));
-    GS_HIP(dev_alloc(&w->alpha, (size_t)X));
-    GS_HIP(dev_alloc(&w->T, (size_t)X));
-    GS_HIP(dev_alloc(&w->last, (size_t)X));
-    GS_HIP(dev_alloc(&w->npairs_dev, 1));
-    GS_HIP(hipHostMalloc(reinterpret_cast<void**>(&w->npairs_host), sizeof(int64_t), hipHostMallocDefault));
+    GS_HIP(dev_alloc(&b.pairs, (size_t)Pc));
+    GS_HIP(dev_alloc(&b.ranges, 2 * (size_t)s->tile_cap));
+    GS_HIP(dev_alloc(&b.proj.tile_order, (size_t)s->tile_cap));
+    b.bin_ws_bytes = bin_workspace_bytes(S, Pc);
+    GS_HIP(hipMalloc(&b.bin_ws, b.bin_ws_bytes));
+    GS_HIP(dev_alloc(&b.rgb, 3 * (size_t)X));
+    GS_HIP(dev_alloc(&b.depth, (size_t)X));
+    GS_HIP(dev_alloc(&b.alpha, (size_t)X));
+    GS_HIP(dev_alloc(&b.T, (size_t)X));
+    GS_HIP(dev_alloc(&b.last, (size_t)X));
+    GS_HIP(dev_alloc(&b.npairs_dev, 1));
+    GS_HIP(dev_alloc(&b.work, 1));
+    GS_HIP(hipHostMalloc(reinterpret_cast<void**>(&b.npairs_host), sizeof(int64_t), hipHostMallocDefault));
+    GS_HIP(hipEventCreateWithFlags(&b.prepped, hipEventDisableTiming));
+    GS_HIP(hipEventCreateWithFlags(&b.done, hipEventDisableTiming));
     return GS_OK;
 }
 
-// renders views r[0..nb) in one batch; *n_pairs gets the batch's pair count
-int render_batch(Worker* w, Request* r, int nb, int64_t* n_pairs) {
+int alloc_worker(gs_server* s, Worker* w) {
+    GS_HIP(hipStreamCreateWithFlags(&w->prep, hipStreamNonBlocking));
+    GS_HIP(hipStreamCreateWithFlags(&w->render, hipStreamNonBlocking));
+    w->sets.resize((size_t)s->cfg.pipeline_depth);
+    for (BufSet& b : w->sets) {
+        const int rc = alloc_set(s, b);
+        if (rc) return rc;
+    }
+    return GS_OK;
+}
+
+// Enqueues views r[0..nb) as one batch into buffer set b: projection and
+// binning on the prep stream, compositing and the copies into the callers'
+// images on the render stream (after each request's ready event).  Returns
+// without waiting; b.done marks the end of the batch's work.
+int launch_batch(Worker* w, BufSet& b, Request* r, int nb) {
     gs_server* s = w->srv;
     gs_camera cams[GS_MAX_VIEWS];
     for (int i = 0; i < nb; ++i) cams[i] = r[i].cam;
@@ -302,34 +389,51 @@ int render_batch(Worker* w, Request* r, int nb, int64_t* n_pairs) {
             const size_t k = (size_t)(l - 1) * P + p;
             const int64_t c = s->lod.cnt[k];
             if (c == 0) continue;
-            w->segs_host[ns++] = SlotSeg{s->lod.off[k], (uint32_t)slots, (uint32_t)v};
+            b.segs_host[ns++] = SlotSeg{s->lod.off[k], (uint32_t)slots, (uint32_t)v};
             slots += c;
         }
     if (slots > s->cfg.slot_capacity) return fail(GS_ERR_CAPACITY, "batch selects %lld Gaussians", (long long)slots);
-    *n_pairs = 0;
+    b.slots = slots;
     if (slots > 0) {
-        GS_HIP(hipMemcpyAsync(w->segs_dev, w->segs_host, (size_t)ns * sizeof(SlotSeg), hipMemcpyHostToDevice,
-                              w->stream));
-        GS_HIP(launch_project_slots(s->gp, s->n, vt, s->opt, w->segs_dev, ns, (uint32_t)slots, w->proj, w->stream));
-        rc = bin_sort_slots(w->proj, vt, slots, s->cfg.pair_capacity, w->pairs, w->ranges, w->npairs_dev, w->bin_ws,
-                            w->bin_ws_bytes, w->stream);
+        GS_HIP(hipMemcpyAsync(b.segs_dev, b.segs_host, (size_t)ns * sizeof(SlotSeg), hipMemcpyHostToDevice, w->prep));
+        GS_HIP(launch_project_slots(s->gp, s->n, vt, s->opt, b.segs_dev, ns, (uint32_t)slots, b.proj, w->prep));
+        rc = bin_sort_slots(b.proj, vt, slots, s->cfg.pair_capacity, b.pairs, b.ranges, b.npairs_dev, b.bin_ws,
+                            b.bin_ws_bytes, w->prep);
         if (rc) return rc;
+        GS_HIP(hipEventRecord(b.prepped, w->prep));
+        GS_HIP(hipStreamWaitEvent(w->render, b.prepped, 0));
     } else {
-        GS_HIP(fill_u32(w->ranges, 0u, 2 * (size_t)vt.total_tiles, w->stream));
-        GS_HIP(launch_tile_order(w->ranges, (uint32_t)vt.total_tiles, w->proj.tile_order, w->stream));
+        GS_HIP(fill_u32(b.ranges, 0u, 2 * (size_t)vt.total_tiles, w->render));
+        GS_HIP(launch_tile_order(b.ranges, (uint32_t)vt.total_tiles, b.proj.tile_order, w->render));
     }
-    GS_HIP(launch_render_fwd(w->proj, w->pairs, reinterpret_cast<const uint2*>(w->ranges), vt, s->opt, w->rgb,
-                             w->depth, w->alpha, w->T, w->last, w->stream));
-    for (int v = 0; v < nb; ++v)
-        GS_HIP(hipMemcpyAsync(r[v].out, w->rgb + 3 * vt.v[v].pix_off,
+    GS_HIP(launch_render_fwd(b.proj, b.pairs, reinterpret_cast<const uint2*>(b.ranges), vt, s->opt, b.rgb, b.depth,
+                             b.alpha, b.T, b.last, w->render, s->cfg.persistent_ctas, b.work));
+    for (int v = 0; v < nb; ++v) {
+        if (r[v].ready) GS_HIP(hipStreamWaitEvent(w->render, r[v].ready, 0));
+        GS_HIP(hipMemcpyAsync(r[v].out, b.rgb + 3 * vt.v[v].pix_off,
                               (size_t)r[v].cam.width * r[v].cam.height * 3 * sizeof(float), hipMemcpyDeviceToDevice,
-                              w->stream));
+                              w->render));
+    }
     if (slots > 0)
-        GS_HIP(hipMemcpyAsync(w->npairs_host, w->npairs_dev, sizeof(int64_t), hipMemcpyDeviceToHost, w->stream));
-    GS_HIP(hipStreamSynchronize(w->stream));
-    if (slots > 0) {
-        // a batch over the pair buffer rendered empty lists: the caller splits it
-        *n_pairs = *w->npairs_host;
+        GS_HIP(hipMemcpyAsync(b.npairs_host, b.npairs_dev, sizeof(int64_t), hipMemcpyDeviceToHost, w->render));
+    GS_HIP(hipEventRecord(b.done, w->render));
+    return GS_OK;
+}
+
+// Waits for the batch in b; *n_pairs gets its pair count.  GS_ERR_CAPACITY
+// when the pairs overflowed the buffer (the lists were left empty).
+int wait_batch(Worker* w, BufSet& b, int launch_rc, int64_t* n_pairs) {
+    gs_server* s = w->srv;
+    *n_pairs = 0;
+    if (launch_rc) {
+        // drain whatever part of the batch was enqueued
+        (void)hipStreamSynchronize(w->prep);
+        (void)hipStreamSynchronize(w->render);
+        return launch_rc;
+    }
+    GS_HIP(hipEventSynchronize(b.done));
+    if (b.slots > 0) {
+        *n_pairs = *b.npairs_host;
         if (*n_pairs > s->cfg.pair_capacity)
             return fail(GS_ERR_CAPACITY, "batch needs %lld pairs (capacity %lld)", (long long)*n_pairs,
                         (long long)s->cfg.pair_capacity);
@@ -338,6 +442,7 @@ int render_batch(Worker* w, Request* r, int nb, int64_t* n_pairs) {
 }
 
 void complete(gs_server* s, Request* r, int nb, int status, int64_t n_pairs, double t_start, double t_done) {
+    recycle_events(s, r, nb);
     std::lock_guard<std::mutex> lk(s->done_mu);
     s->batches += 1;
     s->batch_views += nb;
@@ -365,60 +470,130 @@ void complete(gs_server* s, Request* r, int nb, int status, int64_t n_pairs, dou
     s->done_cv.notify_all();
 }
 
-void run_batch(Worker* w, Request* r, int nb) {
+void note_estimate(gs_server* s, double est, int64_t observed) {
+    if (observed <= 0) return;
+    std::lock_guard<std::mutex> lk(s->done_mu);
+    s->est_over_actual += est / (double)observed;
+    s->est_batches += 1;
+}
+
+// Settles a batch whose launch returned launch_rc: waits for it, learns its
+// pair ratio, and completes its requests -- or, when it overflowed a buffer,
+// renders its halves one after the other in the same buffer set.
+void settle(Worker* w, BufSet& b, Request* r, int nb, int launch_rc, double t_start, double est) {
     gs_server* s = w->srv;
-    const double t_start = s->now();
     int64_t n_pairs = 0;
     int rc;
     try {
-        rc = render_batch(w, r, nb, &n_pairs);
+        rc = wait_batch(w, b, launch_rc, &n_pairs);
     } catch (...) {
         rc = GS_ERR_INTERNAL;
     }
+    if (n_pairs > 0) {
+        if (est > 0.0) note_estimate(s, est, n_pairs);
+        learn_pairs(s, r, nb, n_pairs);
+    }
     if (rc == GS_ERR_CAPACITY && nb > 1) {
+        {
+            std::lock_guard<std::mutex> lk(s->done_mu);
+            s->split_batches += 1;
+        }
         const int h = nb / 2;
-        run_batch(w, r, h);
-        run_batch(w, r + h, nb - h);
+        for (int part = 0; part < 2; ++part) {
+            Request* q = part ? r + h : r;
+            const int m = part ? nb - h : h;
+            const double t = s->now();
+            int lrc;
+            try {
+                lrc = launch_batch(w, b, q, m);
+            } catch (...) {
+                lrc = GS_ERR_INTERNAL;
+            }
+            settle(w, b, q, m, lrc, t, -1.0);
+        }
         return;
     }
     complete(s, r, nb, rc, n_pairs, t_start, s->now());
 }
 
+// Takes every arrived request at the head of the queue that fits one batch:
+// views, slots, pixels, tiles, and the estimated pairs against the pair
+// buffer (the first request always).  With `block`, waits for an arrival.
+// Returns false once the server stops.
+bool take_batch(gs_server* s, bool block, std::vector<Request>* batch, double* est_out) {
+    std::unique_lock<std::mutex> lk(s->mu);
+    for (;;) {
+        if (s->stop) return false;
+        if (!s->queue.empty()) {
+            const double wait = s->queue.front().t_arrival - s->now();
+            if (wait <= 0.0) break;
+            if (!block) return true;
+            s->cv.wait_for(lk, std::chrono::duration<double>(wait));
+        } else {
+            if (!block) return true;
+            s->cv.wait(lk);
+        }
+    }
+    int64_t slots = 0, pix = 0, tiles = 0;
+    double est = 0.0;
+    const double now = s->now(), pair_room = (double)s->cfg.pair_capacity;
+    while (!s->queue.empty() && (int)batch->size() < s->cfg.max_views_per_batch) {
+        Request& q = s->queue.front();
+        if (q.t_arrival > now) break;
+        const double e = estimate_pairs(s, q);
+        if (!batch->empty() &&
+            (slots + q.n_sel > s->cfg.slot_capacity || pix + q.n_pix > s->cfg.pixel_capacity ||
+             tiles + q.n_tiles > s->tile_cap || (est + e) * kAdmitMargin > pair_room))
+            break;
+        slots += q.n_sel;
+        pix += q.n_pix;
+        tiles += q.n_tiles;
+        est += e;
+        batch->push_back(std::move(q));
+        s->queue.pop_front();
+    }
+    *est_out = est;
+    lk.unlock();
+    s->cv.notify_all();
+    return true;
+}
+
+// A worker keeps up to pipeline_depth batches in flight, one per buffer
+// set: while batch k composites on the render stream, batch k+1 projects and
+// bins on the prep stream.  Batches are settled in launch order.
 void worker_main(Worker* w) {
     gs_server* s = w->srv;
     (void)hipSetDevice(s->device);
-    std::vector<Request> batch;
+    const int D = (int)w->sets.size();
+    std::deque<int> inflight;
+    int next = 0;
     for (;;) {
-        batch.clear();
-        {
-            std::unique_lock<std::mutex> lk(s->mu);
-            for (;;) {
-                if (s->stop) return;
-                if (!s->queue.empty()) {
-                    const double wait = s->queue.front().t_arrival - s->now();
-                    if (wait <= 0.0) break;
-                    s->cv.wait_for(lk, std::chrono::duration<double>(wait));
-                } else {
-                    s->cv.wait(lk);
-                }
+        std::vector<Request> batch;
+        double est = 0.0;
+        bool running = true;
+        if ((int)inflight.size() < D) running = take_batch(s, inflight.empty(), &batch, &est);
+        if (!batch.empty()) {
+            BufSet& b = w->sets[next];
+            b.reqs = std::move(batch);
+            b.est_pairs = est;
+            b.t_start = s->now();
+            try {
+                b.rc = launch_batch(w, b, b.reqs.data(), (int)b.reqs.size());
+            } catch (...) {
+                b.rc = GS_ERR_INTERNAL;
             }
-            int64_t slots = 0, pix = 0, tiles = 0;
-            const double now = s->now();
-            while (!s->queue.empty() && (int)batch.size() < s->cfg.max_views_per_batch) {
-                Request& q = s->queue.front();
-                if (q.t_arrival > now) break;
-                if (!batch.empty() && (slots + q.n_sel > s->cfg.slot_capacity || pix + q.n_pix > s->cfg.pixel_capacity ||
-                                       tiles + q.n_tiles > s->tile_cap))
-                    break;
-                slots += q.n_sel;
-                pix += q.n_pix;
-                tiles += q.n_tiles;
-                batch.push_back(std::move(q));
-                s->queue.pop_front();
-            }
+            inflight.push_back(next);
+            next = (next + 1) % D;
+            continue;
         }
-        s->cv.notify_all();
-        run_batch(w, batch.data(), (int)batch.size());
+        if (!inflight.empty()) {
+            BufSet& b = w->sets[inflight.front()];
+            inflight.pop_front();
+            settle(w, b, b.reqs.data(), (int)b.reqs.size(), b.rc, b.t_start, b.est_pairs);
+            b.reqs.clear();
+            continue;
+        }
+        if (!running) return;
     }
 }
 
@@ -456,6 +631,10 @@ int gs_serve_create(const gs_gaussians* scene, const gs_lod_table* table, const 
         GS_REQUIRE(cfg->pair_capacity >= 1 && cfg->pair_capacity <= 0xFFFFFF00LL, "pair_capacity out of range");
         GS_REQUIRE(cfg->pixel_capacity >= 256 && cfg->pixel_capacity <= (1LL << 31), "pixel_capacity out of range");
         GS_REQUIRE(cfg->queue_capacity >= 1, "queue_capacity must be >= 1");
+        GS_REQUIRE(cfg->pipeline_depth >= 1 && cfg->pipeline_depth <= 4, "pipeline_depth outside 1..4");
+        GS_REQUIRE(cfg->persistent_ctas >= 0 && cfg->persistent_ctas <= (1 << 20), "persistent_ctas out of range");
+        GS_REQUIRE(std::isfinite(cfg->pairs_per_gaussian) && cfg->pairs_per_gaussian >= 0.0,
+                   "pairs_per_gaussian must be finite and >= 0");
         GS_REQUIRE(((uintptr_t)scene->app & 15) == 0, "appearance offsets must be 16-byte aligned");
         s = new gs_server();
         int rc;
@@ -501,8 +680,8 @@ int gs_serve_create(const gs_gaussians* scene, const gs_lod_table* table, const 
 
 double gs_serve_now(const gs_server* srv) { return srv ? srv->now() : 0.0; }
 
-int gs_serve_submit(gs_server* s, const gs_camera* cam, int64_t budget, float* out_rgb, double t_arrival,
-                    uint64_t* ticket) {
+int gs_serve_submit(gs_server* s, const gs_camera* cam, int64_t budget, float* out_rgb, void* stream,
+                    double t_arrival, uint64_t* ticket) {
     try {
         GS_REQUIRE(s != nullptr && out_rgb != nullptr && ticket != nullptr, "NULL argument");
         int rc = check_camera(cam);
@@ -524,6 +703,29 @@ int gs_serve_submit(gs_server* s, const gs_camera* cam, int64_t budget, float* o
         {
             std::lock_guard<std::mutex> lk(s->mu);
             if ((int64_t)s->queue.size() >= s->cfg.queue_capacity) return fail(GS_EAGAIN, "queue full");
+            if (!s->free_events.empty()) {
+                r.ready = s->free_events.back();
+                s->free_events.pop_back();
+            }
+        }
+        // the ready event: recorded on the caller's stream, on the server's
+        // device, so that the worker writes out_rgb after the caller's work
+        int prev = 0;
+        GS_HIP(hipGetDevice(&prev));
+        hipError_t e = prev == s->device ? hipSuccess : hipSetDevice(s->device);
+        if (e == hipSuccess && !r.ready) e = hipEventCreateWithFlags(&r.ready, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventRecord(r.ready, static_cast<hipStream_t>(stream));
+        if (prev != s->device) (void)hipSetDevice(prev);
+        if (e != hipSuccess) {
+            if (r.ready) recycle_events(s, &r, 1);
+            return fail(GS_ERR_HIP, "recording the ready event failed: %s", hipGetErrorString(e));
+        }
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            if ((int64_t)s->queue.size() >= s->cfg.queue_capacity) {
+                s->free_events.push_back(r.ready);
+                return fail(GS_EAGAIN, "queue full");
+            }
             r.ticket = s->next_ticket++;
             *ticket = r.ticket;
             s->queue.push_back(std::move(r));
@@ -566,6 +768,8 @@ int gs_serve_stats_get(gs_server* s, gs_serve_stats* o) {
         o->failed = s->failed;
         o->batches = s->batches;
         o->mean_batch_views = s->batches ? (double)s->batch_views / s->batches : 0.0;
+        o->split_batches = s->split_batches;
+        o->est_over_actual = s->est_batches ? s->est_over_actual / (double)s->est_batches : 0.0;
         if (!s->lat_ms.empty()) {
             std::vector<double> v = s->lat_ms;
             std::sort(v.begin(), v.end());
@@ -601,6 +805,9 @@ int gs_serve_destroy(gs_server* s) {
         for (Worker* w : s->workers)
             if (w->th.joinable()) w->th.join();
         for (Worker* w : s->workers) free_worker(w);
+        for (Request& r : s->queue)
+            if (r.ready) (void)hipEventDestroy(r.ready);
+        for (hipEvent_t e : s->free_events) (void)hipEventDestroy(e);
         delete s;
         return GS_OK;
     } catch (...) {

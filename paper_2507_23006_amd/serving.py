@@ -74,12 +74,17 @@ class ServeConfig:
     pair_capacity: int = 96_000_000
     pixel_capacity: int = 16_777_216
     queue_capacity: int = 4096
+    pipeline_depth: int = 2
+    persistent_ctas: int = 0
+    pairs_per_gaussian: float = 0.0
 
     def c(self) -> L.GsServeConfig:
         k = L.GsServeConfig()
         k.max_views_per_batch, k.n_streams = int(self.max_views_per_batch), int(self.n_streams)
         k.slot_capacity, k.pair_capacity = int(self.slot_capacity), int(self.pair_capacity)
         k.pixel_capacity, k.queue_capacity = int(self.pixel_capacity), int(self.queue_capacity)
+        k.pipeline_depth, k.persistent_ctas = int(self.pipeline_depth), int(self.persistent_ctas)
+        k.pairs_per_gaussian = float(self.pairs_per_gaussian)
         return k
 
 
@@ -110,15 +115,17 @@ class Server:
 
     def submit(self, cam, budget: int, out: torch.Tensor, t_arrival: float | None = None) -> int:
         """Queues one request; `out` is a contiguous float32 device tensor
-        [H, W, 3] that receives the image."""
+        [H, W, 3] that receives the image, written after the work queued so
+        far on the current stream of its device."""
         if not (out.is_cuda and out.dtype == torch.float32 and out.is_contiguous()
                 and tuple(out.shape) == (int(cam.height), int(cam.width), 3)):
             raise ValueError("out must be a contiguous float32 CUDA tensor [H, W, 3]")
         lib = L.load()
         ticket = C.c_uint64()
         t = self.now() if t_arrival is None else float(t_arrival)
-        L.check(lib.gs_serve_submit(self._srv, L.make_cameras([cam]), int(budget), C.c_void_p(out.data_ptr()), t,
-                                    C.byref(ticket)))
+        stream = torch.cuda.current_stream(out.device).cuda_stream
+        L.check(lib.gs_serve_submit(self._srv, L.make_cameras([cam]), int(budget), C.c_void_p(out.data_ptr()),
+                                    C.c_void_p(stream), t, C.byref(ticket)))
         self._outs[ticket.value] = out
         return int(ticket.value)
 

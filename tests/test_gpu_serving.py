@@ -89,6 +89,12 @@ def test_served_images_match_oracle_and_ignore_batching(lod_setup):
     assert st["completed"] == len(reqs) and st["failed"] == 0
     for a, b in zip(alone, mixed):
         assert torch.equal(a, b)
+    # two batches in flight per worker and persistent compositing: same images
+    cfg = gs.ServeConfig(max_views_per_batch=4, n_streams=1, pipeline_depth=2, persistent_ctas=96, **CAPS)
+    piped, c3, st3 = serve(gs, params, table, opts, reqs, cfg, t_arrival=0.0)
+    assert all(c["status"] == 0 for c in c3) and st3["completed"] == len(reqs)
+    for a, b in zip(alone, piped):
+        assert torch.equal(a, b)
     for i in (0, 4, 8, 10):
         cam, budget = reqs[i]
         idx = selected_subset(table, offsets, cam, budget, gs)
@@ -106,10 +112,33 @@ def test_admission_splits_batches_and_reports_errors(lod_setup):
     # a pair pool of 1.5 requests: batches of 8 must be split to fit
     cfg = gs.ServeConfig(max_views_per_batch=8, n_streams=1, slot_capacity=1_000_000, pair_capacity=int(1.5 * pmax),
                          pixel_capacity=1 << 20)
-    split, c2, _ = serve(gs, params, table, opts, reqs, cfg, t_arrival=0.0)
+    split, c2, st2 = serve(gs, params, table, opts, reqs, cfg, t_arrival=0.0)
     assert all(c["status"] == 0 for c in c2)
     assert all(c["n_pairs"] <= cfg.pair_capacity for c in c2)
     for a, b in zip(alone, split):
+        assert torch.equal(a, b)
+    print(f"pair pool 1.5x: {st2['batches']} batches, {st2['split_batches']} split, "
+          f"estimate/actual {st2['est_over_actual']:.2f}")
+    # admission seeded with the largest ratio seen alone, every request queued
+    # before the first arrival: the first batch is the longest prefix whose
+    # estimate (with its 15 % headroom) fits the pool, and it does not overflow
+    ratio = max(c["n_pairs"] / c["n_gaussians"] for c in c1)
+    cap = int(1.5 * pmax)
+    est, k = 0.0, 0
+    for c in c1:
+        e = c["n_gaussians"] * ratio
+        if k > 0 and (est + e) * 1.15 > cap:
+            break
+        est, k = est + e, k + 1
+    k = min(k, 8)
+    cfg = gs.ServeConfig(max_views_per_batch=8, n_streams=1, pipeline_depth=1, slot_capacity=1_000_000,
+                         pair_capacity=cap, pixel_capacity=1 << 20, pairs_per_gaussian=ratio)
+    seeded, c4, st4 = serve(gs, params, table, opts, reqs, cfg, t_arrival=0.5)
+    assert all(c["status"] == 0 for c in c4)
+    assert all(c["batch_views"] == k for c in c4[:k])
+    assert len({c["t_start"] for c in c4[:k]}) == 1
+    assert c4[0]["n_pairs"] == sum(c["n_pairs"] for c in c1[:k]) <= cap
+    for a, b in zip(alone, seeded):
         assert torch.equal(a, b)
     # a pool smaller than the largest single request: that request fails alone
     big = int(np.argmax([c["n_pairs"] for c in c1]))
@@ -137,5 +166,35 @@ def test_admission_splits_batches_and_reports_errors(lod_setup):
         with pytest.raises(gs.GsError) as e:
             srv.submit(cam, 10 ** 9, torch.empty((cam.height, cam.width, 3), device="cuda"), far)
         assert e.value.code == gs._lib.GS_ERR_CAPACITY
+    finally:
+        srv.close()
+
+
+def test_submit_orders_the_image_after_pending_stream_work(lod_setup):
+    """The worker writes a request's image only after the work queued on the
+    caller's current stream before the submit: here a long kernel followed by
+    a fill of the output, which must not land over the image."""
+    gs, sc, offsets, params, table, reqs = lod_setup
+    opts = gs.RenderOptions(sh_degree=3, aa=True)
+    alone, c1, _ = serve(gs, params, table, opts, reqs[:3], gs.ServeConfig(max_views_per_batch=1, n_streams=1,
+                                                                            **CAPS))
+    srv = gs.Server(params, table, opts, gs.ServeConfig(max_views_per_batch=4, n_streams=2, **CAPS))
+    try:
+        for rep in range(2):
+            outs, tickets = [], []
+            for cam, budget in reqs[:3]:
+                out = torch.zeros((cam.height, cam.width, 3), device="cuda")
+                # about 20 ms of queued work, then the fill the image must follow
+                a = torch.randn(2048, 2048, device="cuda")
+                for _ in range(8):
+                    a = torch.tanh(a @ a * 1e-3)
+                out.fill_(-1.0)
+                out.add_(a[0, 0] * 0.0)
+                tickets.append(srv.submit(cam, budget, out))
+                outs.append(out)
+            done = wait_all(srv, tickets)
+            assert all(done[t]["status"] == 0 for t in tickets)
+            for i, out in enumerate(outs):
+                assert torch.equal(out, alone[i]), f"repeat {rep}, request {i}"
     finally:
         srv.close()
