@@ -230,13 +230,16 @@ int gs_render_bwd(const gs_gaussians *g, const gs_camera *cams, int32_t n_views,
 /* The two halves of gs_render_bwd, for callers that schedule or time them
  * separately.  gs_composite_bwd overwrites the rows of grad2d [slots][12]
  * (fields as in gs_render_bwd_grad2d) whose slot has tiles > 0 with the
- * compositing backward and leaves the other rows unwritten; gs_project_bwd
- * chains grad2d to the parameters (outputs as in gs_render_bwd), reading
- * only those rows. */
+ * compositing backward and leaves the other rows unwritten; the AbsGS sums
+ * (fields 10, 11) are accumulated only when abs_sums is nonzero, else they
+ * are 0 (gs_render_bwd accumulates them when its absgrad output is given).
+ * gs_project_bwd chains grad2d to the parameters (outputs as in
+ * gs_render_bwd), reading only those rows. */
 int gs_composite_bwd(const gs_projected *proj, const uint32_t *pair_vals, const uint32_t *tile_ranges,
                      const gs_camera *cams, int32_t n_views, const gs_options *opt, const float *T_final,
                      const int32_t *last, const float *d_rgb, const float *d_depth, const float *d_alpha,
-                     int64_t n_slots, float *grad2d, void *seg_ws, size_t seg_ws_bytes, void *stream);
+                     int32_t abs_sums, int64_t n_slots, float *grad2d, void *seg_ws, size_t seg_ws_bytes,
+                     void *stream);
 int gs_project_bwd(const gs_gaussians *g, const gs_camera *cams, int32_t n_views, const gs_options *opt,
                    const gs_projected *proj, const float *grad2d, const gs_gaussians_grad *out,
                    float *mean2d_grad_norm, float *absgrad, void *stream);

@@ -520,7 +520,7 @@ int gs_render_bwd(const gs_gaussians* g, const gs_camera* cams, int32_t n_views,
         const uint2* rg = reinterpret_cast<const uint2*>(tile_ranges);
         if (plan.work_off) GS_HIP(launch_seg_prepare(pr, pair_vals, rg, vt, last, cap, plan, s));
         GS_HIP(launch_render_bwd(pr, pair_vals, rg, vt, ok, T_final, last, d_rgb, d_depth, d_alpha, grad2d, plan, cap,
-                                 s));
+                                 absgrad != nullptr, s));
         GaussPtrs gp = gauss_ptrs(g);
         GradPtrs go = grad_ptrs(g, out);
         GS_REQUIRE(((uintptr_t)go.app & 15) == 0, "d_app must be 16-byte aligned");
@@ -534,7 +534,8 @@ int gs_render_bwd(const gs_gaussians* g, const gs_camera* cams, int32_t n_views,
 int gs_composite_bwd(const gs_projected* proj, const uint32_t* pair_vals, const uint32_t* tile_ranges,
                      const gs_camera* cams, int32_t n_views, const gs_options* opt, const float* T_final,
                      const int32_t* last, const float* d_rgb, const float* d_depth, const float* d_alpha,
-                     int64_t n_slots, float* grad2d, void* seg_ws, size_t seg_ws_bytes, void* stream) {
+                     int32_t abs_sums, int64_t n_slots, float* grad2d, void* seg_ws, size_t seg_ws_bytes,
+                     void* stream) {
     try {
         ViewTable vt;
         OptK ok;
@@ -553,7 +554,7 @@ int gs_composite_bwd(const gs_projected* proj, const uint32_t* pair_vals, const 
         const uint2* rg = reinterpret_cast<const uint2*>(tile_ranges);
         if (plan.work_off) GS_HIP(launch_seg_prepare(pr, pair_vals, rg, vt, last, cap, plan, s));
         GS_HIP(launch_render_bwd(pr, pair_vals, rg, vt, ok, T_final, last, d_rgb, d_depth, d_alpha, grad2d, plan, cap,
-                                 s));
+                                 abs_sums != 0, s));
         return GS_OK;
     } catch (...) {
         return fail(GS_ERR_INTERNAL, "unexpected exception in gs_composite_bwd");

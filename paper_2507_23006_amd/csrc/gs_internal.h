@@ -230,7 +230,7 @@ hipError_t launch_render_count(const Projected& proj, const uint32_t* pair_vals,
 hipError_t launch_render_bwd(const Projected& proj, const uint32_t* pair_vals, const uint2* ranges,
                              const ViewTable& vt, const OptK& opt, const float* T_final, const int32_t* last,
                              const float* d_rgb, const float* d_depth, const float* d_alpha, float* grad2d,
-                             const SegPlan& plan, uint32_t capacity, hipStream_t s);
+                             const SegPlan& plan, uint32_t capacity, bool abs_sums, hipStream_t s);
 
 // training loss (loss.hip): per-workgroup partial sums, then a fixed-order total
 size_t loss_partials(int64_t n_pix);

@@ -2,11 +2,16 @@
 //
 // A workgroup owns a span of 1024 consecutive Gaussians.  It first finds
 // which of them some view sees (tiles > 0), writes the per-view statistics
-// and the zero gradients of the others with coalesced stores, and packs the
-// seen ones into an LDS list; then one thread per listed Gaussian reads its
-// parameters once, recomputes the projection in FP64 for each view that
-// sees it, chains that view's 2D gradients (mean2d, conic, opacity', colour,
-// depth) back to the parameters, and writes the sums once.  Only a small
+// and the zero colour-coefficient rows of the others with coalesced stores,
+// and packs the seen ones into an LDS list; then one thread per listed
+// Gaussian reads its parameters once, recomputes the projection in FP64 for
+// each view that sees it, chains that view's 2D gradients (mean2d, conic,
+// opacity', colour, depth) back to the parameters, and writes the sums once:
+// the coefficient rows directly, the one-float-per-Gaussian rows (means,
+// scales, quats, opacity, appearance) into LDS rows of the span that start
+// at zero and are streamed out whole at the end, so every cache line of
+// those arrays is written once and completely instead of in two partial
+// halves (zeros, then the seen Gaussians' values).  Only a small
 // fraction of a large scene is in view, so the compaction keeps the FP64
 // chain on full waves and the parameter reads on the Gaussians that need
 // them; 2D gradients of unseen slots are never read.  With
@@ -60,10 +65,18 @@ constexpr int kPB = 256;                  // threads per workgroup
 constexpr int kSpanPer = 4;               // Gaussians per thread in the scan
 constexpr int kSpan = kPB * kSpanPer;     // Gaussians per workgroup
 
-// full chain for one seen Gaussian g; vis = mask of the views that see it
+// gradient rows staged in LDS per workgroup span: means (3), scales (3),
+// quats (4), opacity (1), appearance offsets (4)
+constexpr int kStageRows = 15;
+constexpr int kStageApp = 11;
+
+// full chain for one seen Gaussian g (local index loc of the span); vis =
+// mask of the views that see it.  Writes its SH coefficient gradients to
+// out.sh and the other gradients to the span's LDS rows `stage`.
 __device__ __forceinline__ void project_bwd_one(const GaussPtrs& gp, int64_t n, const ViewTable& vt,
                                                 const OptK& opt, const float* __restrict__ grad2d,
-                                                const GradPtrs& out, int64_t g, uint32_t vis) {
+                                                const GradPtrs& out, int64_t g, uint32_t vis, float* stage,
+                                                int loc) {
     const int nb = (opt.sh_degree + 1) * (opt.sh_degree + 1);
     const int nq = (3 * nb + 3) >> 2;    // float4s of a coefficient row in use
     const float4* shq = reinterpret_cast<const float4*>(gp.sh) + 12 * g;
@@ -261,12 +274,17 @@ __device__ __forceinline__ void project_bwd_one(const GaussPtrs& gp, int64_t n, 
     // normalisation q / |q|
     const double dot = dq[0] * w + dq[1] * x + dq[2] * y + dq[3] * z;
     const double qh[4] = {w, x, y, z};
-    for (int c = 0; c < 3; ++c) __builtin_nontemporal_store((float)dmu[c], out.means + c * n + g);
-    for (int c = 0; c < 3; ++c) __builtin_nontemporal_store((float)ds[c], out.scales + c * n + g);
-    for (int c = 0; c < 4; ++c) __builtin_nontemporal_store((float)((dq[c] - qh[c] * dot) / qn), out.quats + c * n + g);
+    for (int c = 0; c < 3; ++c) stage[c * kSpan + loc] = (float)dmu[c];
+    for (int c = 0; c < 3; ++c) stage[(3 + c) * kSpan + loc] = (float)ds[c];
+    for (int c = 0; c < 4; ++c) stage[(6 + c) * kSpan + loc] = (float)((dq[c] - qh[c] * dot) / qn);
     // dop is the gradient with respect to o (1 - do)
-    __builtin_nontemporal_store((float)(gp.app ? dop * (1.0 - (double)app.w) : dop), out.opac + g);
-    if (out.app) reinterpret_cast<float4*>(out.app)[g] = make_float4(dcb0, dcb1, dcb2, (float)(-dop * o_raw));
+    stage[10 * kSpan + loc] = (float)(gp.app ? dop * (1.0 - (double)app.w) : dop);
+    if (out.app) {
+        stage[(kStageApp + 0) * kSpan + loc] = dcb0;
+        stage[(kStageApp + 1) * kSpan + loc] = dcb1;
+        stage[(kStageApp + 2) * kSpan + loc] = dcb2;
+        stage[(kStageApp + 3) * kSpan + loc] = (float)(-dop * o_raw);
+    }
 }
 
 
@@ -276,12 +294,15 @@ __global__ __launch_bounds__(kPB) void k_project_bwd(GaussPtrs gp, int64_t n, Vi
     __shared__ uint32_t s_list[kSpan];     // local index | view mask << 16
     __shared__ uint8_t s_seen[kSpan];
     __shared__ uint32_t s_count;
+    // the span's gradient rows: zeros, then the chain's values, then one
+    // coalesced write of every row (each cache line written once, whole)
+    __shared__ float s_grad[kStageRows * kSpan];
     const int tid = threadIdx.x, lane = tid & 63;
     const int64_t g0 = (int64_t)blockIdx.x * kSpan;
     if (tid == 0) s_count = 0;
     __syncthreads();
 
-    // pass 1: statistics, visibility, zeros of unseen Gaussians, compaction
+    // pass 1: statistics, visibility, zeroed LDS rows, compaction
     for (int i = 0; i < kSpanPer; ++i) {
         const int loc = i * kPB + tid;
         const int64_t g = g0 + loc;
@@ -305,15 +326,9 @@ __global__ __launch_bounds__(kPB) void k_project_bwd(GaussPtrs gp, int64_t n, Vi
                     __builtin_nontemporal_store(ay, absgrad + 2 * slot + 1);
                 }
             }
-            if (!vis) {
-                // streaming stores: the zero rows are not read again here
-                for (int c = 0; c < 3; ++c) __builtin_nontemporal_store(0.0f, out.means + c * n + g);
-                for (int c = 0; c < 3; ++c) __builtin_nontemporal_store(0.0f, out.scales + c * n + g);
-                for (int c = 0; c < 4; ++c) __builtin_nontemporal_store(0.0f, out.quats + c * n + g);
-                __builtin_nontemporal_store(0.0f, out.opac + g);
-                if (out.app) __builtin_nontemporal_store(F4{0.0f, 0.0f, 0.0f, 0.0f}, reinterpret_cast<F4*>(out.app) + g);
-            }
         }
+#pragma unroll
+        for (int c = 0; c < kStageRows; ++c) s_grad[c * kSpan + loc] = 0.0f;
         s_seen[loc] = vis ? 1 : 0;
         const uint64_t m = __ballot(vis != 0);
         if (m) {
@@ -336,8 +351,21 @@ __global__ __launch_bounds__(kPB) void k_project_bwd(GaussPtrs gp, int64_t n, Vi
     const uint32_t cnt = s_count;
     for (uint32_t j = tid; j < cnt; j += kPB) {
         const uint32_t e = s_list[j];
-        project_bwd_one(gp, n, vt, opt, grad2d, out, g0 + (e & 0xFFFFu), e >> 16);
+        project_bwd_one(gp, n, vt, opt, grad2d, out, g0 + (e & 0xFFFFu), e >> 16, s_grad, (int)(e & 0xFFFFu));
     }
+    __syncthreads();
+
+    // pass 3: the span's rows, streamed out (not read again here)
+    for (int c = 0; c < 11; ++c) {
+        float* row = c < 3 ? out.means + c * n : c < 6 ? out.scales + (c - 3) * n
+                   : c < 10 ? out.quats + (c - 6) * n : out.opac;
+        for (int loc = tid; loc < rows; loc += kPB) __builtin_nontemporal_store(s_grad[c * kSpan + loc], row + g0 + loc);
+    }
+    if (out.app)
+        for (int loc = tid; loc < rows; loc += kPB)
+            __builtin_nontemporal_store(F4{s_grad[(kStageApp + 0) * kSpan + loc], s_grad[(kStageApp + 1) * kSpan + loc],
+                                           s_grad[(kStageApp + 2) * kSpan + loc], s_grad[(kStageApp + 3) * kSpan + loc]},
+                                        reinterpret_cast<F4*>(out.app) + g0 + loc);
 }
 
 }  // namespace

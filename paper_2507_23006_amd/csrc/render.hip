@@ -432,6 +432,26 @@ __device__ __forceinline__ void wave_sum12(const float v[12], float out[3]) {
     }
 }
 
+// The same for fields 0 .. 9 (no AbsGS sums): five half swaps, three row
+// swaps (the last with zeros).  Lane 16 r + 15 ends with fields b, b + 2
+// and, for even r, b + 4 in out[0..2], where b = (r & 1) + 5 (r >> 1).
+__device__ __forceinline__ void wave_sum10(const float v[10], float out[3]) {
+    float a[5];
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+        const auto p = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[j]), __float_as_uint(v[j + 5]), false,
+                                                        false);
+        // lanes 0-31: field j over (l, l + 32); lanes 32-63: field j + 5
+        a[j] = __uint_as_float(p[0]) + __uint_as_float(p[1]);
+    }
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const uint32_t x = __float_as_uint(a[2 * j]), y = j < 2 ? __float_as_uint(a[2 * j + 1]) : 0u;
+        const auto p = __builtin_amdgcn_permlane16_swap(x, y, false, false);
+        out[j] = row_total_lane15(__uint_as_float(p[0]) + __uint_as_float(p[1]));
+    }
+}
+
 constexpr int kG2 = GS_GRAD2D_FLOATS;   // per-slot 2D gradient fields
 
 // Per-field factors applied once per entry, after the wave sum: the lanes
@@ -452,6 +472,7 @@ __device__ __forceinline__ float grad2d_field_scale(int f) {
 // The colour and depth behind an entry enter the gradient only through
 // their dot product with the pixel's upstream gradient, so the walk carries
 // that one scalar, S = g_rgb . R_rgb + g_depth R_depth, instead of R itself.
+template <bool kAbs>
 __global__ __launch_bounds__(256) void k_render_bwd(const float4* __restrict__ rec,
                                                     const uint32_t* __restrict__ pair_vals,
                                                     const uint2* __restrict__ ranges,
@@ -534,9 +555,10 @@ __global__ __launch_bounds__(256) void k_render_bwd(const float4* __restrict__ r
         return b_end_ > lo ? load_slot(pair_vals, rg.x + (uint32_t)(b_start_ + lane), rg.x + (uint32_t)b_end_) : kNoSlot;
     };
     // adds chunk sums of the last staged chunk (n entries) to grad2d
+    constexpr int kFields = kAbs ? kG2 : 10;
     auto flush = [&](int n_) {
-        for (int i = lane; i < n_ * kG2; i += 64) {
-            const int k = i / kG2, f = i - k * kG2;
+        for (int i = lane; i < n_ * kFields; i += 64) {
+            const int k = i / kFields, f = i - k * kFields;
             const float sum = s_red[wave][k][f];
             if (sum != 0.0f)
                 atomicAdd(&grad2d[(size_t)(uint32_t)st.ps[k].y * kG2 + f], sum * grad2d_field_scale(f));
@@ -587,23 +609,38 @@ __global__ __launch_bounds__(256) void k_render_bwd(const float4* __restrict__ r
             g[2] = dpx * e.dx;
             g[3] = dpx * e.dy;
             g[4] = dpy * e.dy;
-            g[10] = fabsf(g[0]);
-            g[11] = fabsf(g[1]);
+            if (kAbs) {
+                g[10] = fabsf(g[0]);
+                g[11] = fabsf(g[1]);
+            }
             S = fmaf(S, one_m, gc * al);
             Q *= one_m;
             T = con ? Ti : T;
-            // lane 16 r + 15 writes fields 3 r .. 3 r + 2 of the entry's row
-            float* row = &s_red[wave][k][3 * (lane >> 4)];
-            if (__ballot(con)) {
-                float tot[3];
-                wave_sum12(g, tot);
+            if (kAbs) {
+                // lane 16 r + 15 writes fields 3 r .. 3 r + 2 of the entry's row
+                float* row = &s_red[wave][k][3 * (lane >> 4)];
+                if (__ballot(con)) {
+                    float tot[3];
+                    wave_sum12(g, tot);
+                    if ((lane & 15) == 15) {
+                        row[0] = tot[0];
+                        row[1] = tot[1];
+                        row[2] = tot[2];
+                    }
+                } else if ((lane & 15) == 15) {
+                    row[0] = row[1] = row[2] = 0.0f;
+                }
+            } else {
+                // lane 16 r + 15 writes its fields of the entry's row
+                const int r = lane >> 4;
+                float* row = &s_red[wave][k][(r & 1) + 5 * (r >> 1)];
+                float tot[3] = {0.0f, 0.0f, 0.0f};
+                if (__ballot(con)) wave_sum10(g, tot);
                 if ((lane & 15) == 15) {
                     row[0] = tot[0];
-                    row[1] = tot[1];
-                    row[2] = tot[2];
+                    row[2] = tot[1];
+                    if (!(r & 1)) row[4] = tot[2];
                 }
-            } else if ((lane & 15) == 15) {
-                row[0] = row[1] = row[2] = 0.0f;
             }
         }
         __builtin_amdgcn_wave_barrier();
@@ -787,12 +824,16 @@ hipError_t launch_seg_prepare(const Projected& proj, const uint32_t* pair_vals, 
 hipError_t launch_render_bwd(const Projected& proj, const uint32_t* pair_vals, const uint2* ranges,
                              const ViewTable& vt, const OptK& opt, const float* T_final, const int32_t* last,
                              const float* d_rgb, const float* d_depth, const float* d_alpha, float* grad2d,
-                             const SegPlan& plan, uint32_t capacity, hipStream_t s) {
+                             const SegPlan& plan, uint32_t capacity, bool abs_sums, hipStream_t s) {
     // with a plan, blocks beyond the planned work items exit at once
     const unsigned blocks = (unsigned)vt.total_tiles + (plan.work_off ? capacity : 0u);
     const hipEvent_t timed_ = timer_begin(GS_KERNEL_RENDER_BWD, s);
-    hipLaunchKernelGGL(k_render_bwd, dim3(blocks), dim3(256), 0, s, proj.rec, pair_vals, ranges,
-                       proj.tile_order, vt, opt, T_final, last, d_rgb, d_depth, d_alpha, grad2d, plan);
+    if (abs_sums)
+        hipLaunchKernelGGL(k_render_bwd<true>, dim3(blocks), dim3(256), 0, s, proj.rec, pair_vals, ranges,
+                           proj.tile_order, vt, opt, T_final, last, d_rgb, d_depth, d_alpha, grad2d, plan);
+    else
+        hipLaunchKernelGGL(k_render_bwd<false>, dim3(blocks), dim3(256), 0, s, proj.rec, pair_vals, ranges,
+                           proj.tile_order, vt, opt, T_final, last, d_rgb, d_depth, d_alpha, grad2d, plan);
     timer_end(timed_, s);
     return hipGetLastError();
 }

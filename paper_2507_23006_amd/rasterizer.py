@@ -297,7 +297,8 @@ def render_bwd(params, cams, opts: RenderOptions, proj: Projected, pair_vals, ra
     cams_c, opt_c, proj_c = L.make_cameras(cams), opts.c(), proj.c()
     _mark("bwd_begin")
     L.check(lib.gs_composite_bwd(C.byref(proj_c), _ptr(pair_vals), _ptr(ranges), cams_c, V, C.byref(opt_c), _ptr(T),
-                                 _ptr(last), _ptr(d_rgb), _ptr(d_depth), _ptr(d_alpha), n * V, g2,
+                                 _ptr(last), _ptr(d_rgb), _ptr(d_depth), _ptr(d_alpha), int(bool(opts.absgrad)), n * V,
+                                 g2,
                                  C.c_void_p(Workspace.aligned(sbuf)), ssz, _stream()))
     _mark("composite_bwd")
     L.check(lib.gs_project_bwd(C.byref(g), cams_c, V, C.byref(opt_c), C.byref(proj_c), g2, C.byref(go), _ptr(norm),

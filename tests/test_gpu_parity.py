@@ -405,7 +405,9 @@ def test_loss_kernel_matches_oracle(gpu_lib, n_pix, with_depth):
 def test_segmented_backward_matches_whole_lists(gpu_lib):
     """Lists longer than 512 positions are walked in segments by separate
     workgroups (state behind each segment folded from a pre-pass); the 2D
-    gradients must equal those of whole-list walks to float rounding."""
+    gradients must equal those of whole-list walks to float rounding.  The
+    walk without the AbsGS sums (a 10-field reduction) gives the same
+    fields 0-9 and leaves fields 10 and 11 zero."""
     import ctypes as C
     from paper_2507_23006_amd import _lib as L
     cam = S.Camera(60.0, 60.0, 24.0, 20.0, S.look_at((0.3, -0.2, -3.0), (0.0, 0.0, 0.0)), 48, 40)
@@ -419,7 +421,7 @@ def test_segmented_backward_matches_whole_lists(gpu_lib):
     gen = torch.Generator(device="cuda").manual_seed(1)
     d = [torch.randn(s, device="cuda", generator=gen) for s in ((npx, 3), (npx,), (npx,))]
     res = []
-    for seg in (False, True):
+    for seg, absum in ((False, 1), (True, 1), (True, 0)):
         g2 = torch.zeros((n_slots, 12), device="cuda")
         ssz = lib.gs_seg_workspace_size(cam.n_tiles, P) if seg else 0
         sbuf = torch.empty(ssz + 512, dtype=torch.uint8, device="cuda")
@@ -427,12 +429,16 @@ def test_segmented_backward_matches_whole_lists(gpu_lib):
         L.check(lib.gs_composite_bwd(C.byref(proj.c()), C.c_void_p(pairs.data_ptr()), C.c_void_p(ranges.data_ptr()),
                                      L.make_cameras([cam]), 1, C.byref(opts.c()), C.c_void_p(out["T"].data_ptr()),
                                      C.c_void_p(out["last"].data_ptr()), *[C.c_void_p(t.data_ptr()) for t in d],
-                                     n_slots, C.c_void_p(g2.data_ptr()), sp, ssz,
+                                     absum, n_slots, C.c_void_p(g2.data_ptr()), sp, ssz,
                                      C.c_void_p(torch.cuda.current_stream().cuda_stream)))
         torch.cuda.synchronize()
         res.append(g2.cpu().numpy().astype(np.float64) * (proj.tiles.cpu().numpy()[:, None] > 0))
-    a, b = res
+    a, b, c = res
     rel = np.linalg.norm(a - b, axis=0) / np.maximum(np.linalg.norm(a, axis=0), 1e-30)
+    assert rel.max() < 1e-5, rel
+    assert np.linalg.norm(a[:, 10:], axis=0).min() > 0
+    assert not c[:, 10:].any()
+    rel = np.linalg.norm(c[:, :10] - b[:, :10], axis=0) / np.maximum(np.linalg.norm(b[:, :10], axis=0), 1e-30)
     assert rel.max() < 1e-5, rel
 
 
