@@ -234,7 +234,8 @@ int bin_sort_slots(const Projected& pr, const ViewTable& vt, int64_t n_slots, in
     //    which is compaction order); per depth rank its tile count, rectangle,
     //    mask and slot; exclusive scan -> pair offsets
     bool alt = false;
-    GS_HIP(radix_sort_pairs(w.dkeys, w.dvals, w.dkeys_alt, w.dvals_alt, N, 0, 32, w.hist, s, &alt, w.cnt));
+    GS_HIP(radix_sort_pairs(w.dkeys, w.dvals, w.dkeys_alt, w.dvals_alt, N, 0, 32, w.hist, s, &alt, w.cnt,
+                            /*small_tiles=*/true));
     const uint32_t* sorted_pos = alt ? w.dvals_alt : w.dvals;
     GS_HIP(launch_gather_sorted(sorted_pos, w.desc, N, w.cnt, w.tiles_s, w.rect_s, w.mask_s, w.slot_s, s));
     GS_HIP(exclusive_scan_u32(w.tiles_s, w.offsets, N, w.scan_tmp, w.total + 8, s, w.cnt));

@@ -160,10 +160,12 @@ size_t radix_hist_elems(uint32_t n);        // counters needed per pass
 int radix_passes(uint32_t n, int begin_bit, int end_bit);
 hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt,
                             uint32_t n, int begin_bit, int end_bit, uint32_t* hist, hipStream_t s,
-                            bool* result_in_alt, const uint32_t* n_dev = nullptr);
+                            bool* result_in_alt, const uint32_t* n_dev = nullptr, bool small_tiles = false);
 size_t scan_tmp_elems(uint32_t n);
+// with n_dev, the scanned count is ceil(*n_dev / div) * mul, at most n
 hipError_t exclusive_scan_u32(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* tmp,
-                              unsigned long long* total, hipStream_t s, const uint32_t* n_dev = nullptr);
+                              unsigned long long* total, hipStream_t s, const uint32_t* n_dev = nullptr,
+                              uint32_t div = 1, uint32_t mul = 1);
 // exclusive scan of (in[i] != 0); the sum of in[] itself is added to
 // sum_parts (kBinPairParts partial sums, 16 u64 apart, zeroed by the caller)
 hipError_t exclusive_scan_nonzero_u32(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* tmp,

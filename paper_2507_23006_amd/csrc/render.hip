@@ -483,7 +483,10 @@ __global__ __launch_bounds__(256) void k_render_bwd(const float4* __restrict__ r
                                                     const float* __restrict__ d_alpha, float* __restrict__ grad2d,
                                                     SegPlan plan) {
     __shared__ WaveStage stage[kWaves];
-    __shared__ float s_red[kWaves][kChunk][kG2];
+    // one row of reduced fields per staged entry (10 without the AbsGS sums:
+    // the smaller area lets six workgroups share a compute unit's LDS)
+    constexpr int kRow = kAbs ? kG2 : 10;
+    __shared__ float s_red[kWaves][kChunk][kRow];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     int tile, seg = 0, nseg = 1;
     uint32_t st0 = 0;

@@ -51,6 +51,16 @@ __device__ __forceinline__ uint32_t count_of(uint32_t n, const uint32_t* __restr
     return n_dev ? min(*n_dev, n) : n;
 }
 
+// The element count of a scan over a table derived from a device count:
+// ceil(*n_dev / div) * mul (the digit table of a sort: tiles x radix), at
+// most n; n itself without n_dev.
+__device__ __forceinline__ uint32_t scaled_count_of(uint32_t n, const uint32_t* __restrict__ n_dev, uint32_t div,
+                                                    uint32_t mul) {
+    if (!n_dev) return n;
+    const uint64_t c = ((uint64_t)*n_dev + div - 1) / div * mul;
+    return c < n ? (uint32_t)c : n;
+}
+
 template <int kSortIpt>
 __global__ __launch_bounds__(kSortThreads) void k_radix_upsweep(const uint32_t* __restrict__ keys, uint32_t n_max,
                                                                 const uint32_t* __restrict__ n_dev, int shift,
@@ -58,8 +68,13 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_upsweep(const uint32_t* 
                                                                 uint32_t n_tiles) {
     constexpr int kSortTile = kSortThreads * kSortIpt, kWaveItems = 64 * kSortIpt;
     __shared__ uint32_t cnt[4][1 << kMaxRadixBits];
-    // every workgroup writes its column of the digit table (zeros past n)
+    // the digit table has one column per tile that holds keys: its row
+    // stride is the tile count of the device count, and workgroups past it
+    // write nothing
     const uint32_t n = count_of(n_max, n_dev);
+    const uint32_t n_tab = (uint32_t)(((uint64_t)n + kSortTile - 1) / kSortTile);
+    if (blockIdx.x >= n_tab) return;
+    (void)n_tiles;
     const int radix = 1 << bits;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     // rows are (1 << kMaxRadixBits) apart: clear the whole table, not 4 * radix entries
@@ -76,7 +91,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_upsweep(const uint32_t* 
     }
     __syncthreads();
     for (int d = threadIdx.x; d < radix; d += kSortThreads)
-        hist[(size_t)d * n_tiles + blockIdx.x] = cnt[0][d] + cnt[1][d] + cnt[2][d] + cnt[3][d];
+        hist[(size_t)d * n_tab + blockIdx.x] = cnt[0][d] + cnt[1][d] + cnt[2][d] + cnt[3][d];
 }
 
 template <int kSortIpt>
@@ -87,6 +102,8 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_downsweep(
     constexpr int kSortTile = kSortThreads * kSortIpt, kWaveItems = 64 * kSortIpt;
     const uint32_t n = count_of(n_max, n_dev);
     if (blockIdx.x * (uint32_t)kSortTile >= n) return;     // no keys in this tile
+    const uint32_t n_tab = (uint32_t)(((uint64_t)n + kSortTile - 1) / kSortTile);   // digit-table stride
+    (void)n_tiles;
     __shared__ uint32_t s_keys[kSortTile];
     __shared__ uint32_t s_vals[kSortTile];
     __shared__ uint32_t s_wcnt[4][1 << kMaxRadixBits];
@@ -140,7 +157,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_downsweep(
         s_wcnt[2][d] = c0 + c1;
         s_wcnt[3][d] = c0 + c1 + c2;
         total = c0 + c1 + c2 + c3;
-        s_goff[d] = hist_scan[(size_t)d * n_tiles + blockIdx.x];
+        s_goff[d] = hist_scan[(size_t)d * n_tab + blockIdx.x];
     }
     // block-wide exclusive scan of `total` (thread d holds digit d)
     uint32_t incl = total;
@@ -208,12 +225,14 @@ __device__ __forceinline__ uint32_t scan_value(uint32_t x) {
 // thousands of workgroups from all XCDs); the counters must start at 0.
 template <bool kFlags>
 __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint32_t* __restrict__ in, uint32_t n_max,
-                                                              const uint32_t* __restrict__ n_dev,
-                                                              uint32_t* __restrict__ tsum,
+                                                              const uint32_t* __restrict__ n_dev, uint32_t div,
+                                                              uint32_t mul, uint32_t* __restrict__ tsum,
                                                               unsigned long long* __restrict__ raw_parts) {
     __shared__ uint32_t s_w[4];
     __shared__ unsigned long long s_raw[4];
-    const uint32_t n = count_of(n_max, n_dev);
+    const uint32_t n = scaled_count_of(n_max, n_dev, div, mul);
+    // workgroups past the count exit (the first always runs)
+    if (blockIdx.x > 0 && blockIdx.x * (uint32_t)kScanTile >= n) return;
     const uint32_t base = blockIdx.x * kScanTile;
     uint32_t acc = 0;
     unsigned long long raw = 0;
@@ -246,15 +265,18 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint32_t* __
 // tile's offset is the sum of the earlier tiles' sums, which every
 // workgroup adds up itself (64-bit, at most a few thousand values) rather
 // than waiting for a separate one-workgroup launch; the last workgroup
-// writes the 64-bit total.
+// that holds elements (the first, for none) writes the 64-bit total.
 template <bool kFlags>
 __global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t* __restrict__ in,
                                                             uint32_t* __restrict__ out, uint32_t n_max,
-                                                            const uint32_t* __restrict__ n_dev,
-                                                            const uint32_t* __restrict__ tsum,
+                                                            const uint32_t* __restrict__ n_dev, uint32_t div,
+                                                            uint32_t mul, const uint32_t* __restrict__ tsum,
                                                             unsigned long long* __restrict__ total) {
     __shared__ uint32_t s_buf[kScanTile];
-    const uint32_t n = count_of(n_max, n_dev);
+    const uint32_t n = scaled_count_of(n_max, n_dev, div, mul);
+    const uint32_t n_act = (uint32_t)(((uint64_t)n + kScanTile - 1) / kScanTile);
+    const uint32_t last_wg = n_act > 0 ? n_act - 1 : 0;
+    if (blockIdx.x > last_wg) return;
     __shared__ uint32_t s_w[4];
     __shared__ unsigned long long s_off[4];
     const uint32_t base = blockIdx.x * kScanTile;
@@ -282,7 +304,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t* __re
     if ((threadIdx.x & 63) == 63) s_w[threadIdx.x >> 6] = incl;
     __syncthreads();
     const unsigned long long tile_off = s_off[0] + s_off[1] + s_off[2] + s_off[3];
-    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *total = tile_off + tsum[blockIdx.x];
+    if (blockIdx.x == last_wg && threadIdx.x == 0) *total = tile_off + tsum[blockIdx.x];
     uint32_t pre = (uint32_t)tile_off + incl - acc;
     for (int w = 0; w < (int)(threadIdx.x >> 6); ++w) pre += s_w[w];
 #pragma unroll
@@ -328,15 +350,17 @@ hipError_t fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s) {
 }
 
 hipError_t exclusive_scan_u32(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* tmp,
-                              unsigned long long* total, hipStream_t s, const uint32_t* n_dev) {
+                              unsigned long long* total, hipStream_t s, const uint32_t* n_dev, uint32_t div,
+                              uint32_t mul) {
     const uint32_t nt = (n + kScanTile - 1) / kScanTile;
     if (n == 0) {
         hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, (uint32_t*)total, 0u, (size_t)2);
         return hipGetLastError();
     }
-    hipLaunchKernelGGL(k_scan_reduce<false>, dim3(nt), dim3(kScanThreads), 0, s, in, n, n_dev, tmp,
+    hipLaunchKernelGGL(k_scan_reduce<false>, dim3(nt), dim3(kScanThreads), 0, s, in, n, n_dev, div, mul, tmp,
                        (unsigned long long*)nullptr);
-    hipLaunchKernelGGL(k_scan_down<false>, dim3(nt), dim3(kScanThreads), 0, s, in, out, n, n_dev, tmp, total);
+    hipLaunchKernelGGL(k_scan_down<false>, dim3(nt), dim3(kScanThreads), 0, s, in, out, n, n_dev, div, mul, tmp,
+                       total);
     return hipGetLastError();
 }
 
@@ -347,10 +371,10 @@ hipError_t exclusive_scan_nonzero_u32(const uint32_t* in, uint32_t* out, uint32_
         hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, (uint32_t*)total, 0u, (size_t)2);
         return hipGetLastError();
     }
-    hipLaunchKernelGGL(k_scan_reduce<true>, dim3(nt), dim3(kScanThreads), 0, s, in, n, (const uint32_t*)nullptr,
-                       tmp, sum_parts);
+    hipLaunchKernelGGL(k_scan_reduce<true>, dim3(nt), dim3(kScanThreads), 0, s, in, n, (const uint32_t*)nullptr, 1u,
+                       1u, tmp, sum_parts);
     hipLaunchKernelGGL(k_scan_down<true>, dim3(nt), dim3(kScanThreads), 0, s, in, out, n, (const uint32_t*)nullptr,
-                       tmp, total);
+                       1u, 1u, tmp, total);
     return hipGetLastError();
 }
 
@@ -362,15 +386,17 @@ int radix_passes(uint32_t n, int begin_bit, int end_bit) {
 // near-equal width.  The result lands in (keys, vals) or in the alternate
 // buffers; *result_in_alt says which.  `hist` needs radix_hist_elems(n).
 // With n_dev the key count is read on the device (at most n, which sizes
-// the launches), so the sort needs no host knowledge of it.
+// the launches), so the sort needs no host knowledge of it: the digit
+// table and its scan cover only the tiles that hold keys.  small_tiles
+// forces 1024-key tiles (for a device count expected well below n).
 hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt, uint32_t n,
                             int begin_bit, int end_bit, uint32_t* hist, hipStream_t s, bool* result_in_alt,
-                            const uint32_t* n_dev) {
+                            const uint32_t* n_dev, bool small_tiles) {
     *result_in_alt = false;
     if (radix_passes(n, begin_bit, end_bit) == 0) return hipSuccess;
     const int total_bits = end_bit - begin_bit;
     const int passes = (total_bits + kMaxRadixBits - 1) / kMaxRadixBits;
-    const bool small = n <= kSmallSortMax;
+    const bool small = small_tiles || n <= kSmallSortMax;
     const uint32_t sort_tile = (uint32_t)kSortThreads * (small ? 4u : 8u);
     const uint32_t tiles = (n + sort_tile - 1) / sort_tile;
     const size_t hist_elems = (size_t)tiles * (1 << kMaxRadixBits);
@@ -388,7 +414,7 @@ hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, 
         else
             hipLaunchKernelGGL(k_radix_upsweep<8>, dim3(tiles), dim3(kSortThreads), 0, s, ki, n, n_dev, shift, bits,
                                hist, tiles);
-        hipError_t e = exclusive_scan_u32(hist, hist, radix_elems, scan_tmp, total, s);
+        hipError_t e = exclusive_scan_u32(hist, hist, radix_elems, scan_tmp, total, s, n_dev, sort_tile, 1u << bits);
         if (e != hipSuccess) return e;
         if (small)
             hipLaunchKernelGGL(k_radix_downsweep<4>, dim3(tiles), dim3(kSortThreads), 0, s, ki, vi, ko, vo, n, n_dev,
