@@ -214,6 +214,21 @@ int gs_render_count(const gs_projected *proj, const uint32_t *pair_vals, const u
 size_t gs_render_bwd_workspace_size(int64_t n_slots);
 size_t gs_seg_workspace_size(int64_t n_tiles, int64_t n_pairs);
 
+/* gs_render_fwd that also prepares the segmented backward in seg_ws
+ * (gs_seg_workspace_size(n_tiles, n_pairs) bytes, 256-byte aligned; a
+ * smaller area plans no segments): it plans the segments of the lists
+ * longer than 512 positions and, while compositing them, writes each
+ * segment's state (transmittance and colour and depth with T restarted at
+ * the segment's start, over the pixel's composited entries) -- the states
+ * the backward otherwise computes in a second walk of those lists.  Pass
+ * the same seg_ws, unchanged, to gs_composite_bwd with seg_ready = 1,
+ * together with these lists, T_final and last.  Outputs as gs_render_fwd,
+ * bit for bit. */
+int gs_render_fwd_seg(const gs_projected *proj, const uint32_t *pair_vals, const uint32_t *tile_ranges,
+                      const gs_camera *cams, int32_t n_views, const gs_options *opt, float *rgb, float *depth,
+                      float *alpha, float *T_final, int32_t *last, void *seg_ws, size_t seg_ws_bytes,
+                      void *stream);
+
 /* Backward of compositing and projection.  Transmittance is recovered back
  * to front from T_final and last instead of stored per-pixel lists.  Inputs
  * d_rgb [pix][3], d_depth [pix], d_alpha [pix] (any may be NULL = zero).
@@ -233,13 +248,15 @@ int gs_render_bwd(const gs_gaussians *g, const gs_camera *cams, int32_t n_views,
  * compositing backward and leaves the other rows unwritten; the AbsGS sums
  * (fields 10, 11) are accumulated only when abs_sums is nonzero, else they
  * are 0 (gs_render_bwd accumulates them when its absgrad output is given).
- * gs_project_bwd chains grad2d to the parameters (outputs as in
- * gs_render_bwd), reading only those rows. */
+ * seg_ready = 1: seg_ws holds the plan and segment states that
+ * gs_render_fwd_seg wrote for these lists (no second walk here); 0: they
+ * are computed here.  gs_project_bwd chains grad2d to the parameters
+ * (outputs as in gs_render_bwd), reading only those rows. */
 int gs_composite_bwd(const gs_projected *proj, const uint32_t *pair_vals, const uint32_t *tile_ranges,
                      const gs_camera *cams, int32_t n_views, const gs_options *opt, const float *T_final,
                      const int32_t *last, const float *d_rgb, const float *d_depth, const float *d_alpha,
                      int32_t abs_sums, int64_t n_slots, float *grad2d, void *seg_ws, size_t seg_ws_bytes,
-                     void *stream);
+                     int32_t seg_ready, void *stream);
 int gs_project_bwd(const gs_gaussians *g, const gs_camera *cams, int32_t n_views, const gs_options *opt,
                    const gs_projected *proj, const float *grad2d, const gs_gaussians_grad *out,
                    float *mean2d_grad_norm, float *absgrad, void *stream);

@@ -10,7 +10,7 @@ whose offsets the rasterizer applies, and the densification bookkeeping and
 """
 from ._lib import GsError, load, LIB_PATH
 from .rasterizer import (RenderOptions, RenderStats, Projected, Workspace, GsRasterize, rasterize, project,
-                         bin_sort, render_fwd, render_bwd, split_views, views_extent, grad2d_view, check_params, set_stage_hook, render_count,
+                         bin_sort, render_fwd, render_bwd, seg_workspace, split_views, views_extent, grad2d_view, check_params, set_stage_hook, render_count,
                          kernel_timing, kernel_timing_read, L1DepthLoss, l1_depth_loss, DSSIMLoss, dssim_loss)
 from .serving import LodTable, lod_select, ServeConfig, Server
 from . import densify
@@ -23,7 +23,7 @@ def build(verbose: bool = False) -> str:
 
 
 __all__ = ["GsError", "load", "LIB_PATH", "RenderOptions", "RenderStats", "Projected", "Workspace", "GsRasterize",
-           "rasterize", "project", "bin_sort", "render_fwd", "render_bwd", "split_views", "views_extent",
+           "rasterize", "project", "bin_sort", "render_fwd", "render_bwd", "seg_workspace", "split_views", "views_extent",
            "grad2d_view", "check_params", "set_stage_hook", "render_count", "kernel_timing", "kernel_timing_read", "build", "L1DepthLoss", "l1_depth_loss", "DSSIMLoss", "dssim_loss", "LodTable", "lod_select",
            "ServeConfig", "Server", "AppearanceParams", "AppearanceOffsets", "appearance_offsets",
            "appearance_mlp_fwd", "appearance_mlp_bwd", "densify"]

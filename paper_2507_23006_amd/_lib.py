@@ -111,10 +111,12 @@ SIGNATURES = {
     "gs_bin_workspace_size": (_SZ, [_I64, _I64]),
     "gs_bin_sort": (C.c_int, [_P, _P, _I32, _I64, _I64, _P, _P, _P, _P, _SZ, _P]),
     "gs_render_fwd": (C.c_int, [_P, _P, _P, _P, _I32, _P, _P, _P, _P, _P, _P, _P]),
+    "gs_render_fwd_seg": (C.c_int, [_P, _P, _P, _P, _I32, _P, _P, _P, _P, _P, _P, _P, _SZ, _P]),
     "gs_render_bwd_workspace_size": (_SZ, [_I64]),
     "gs_render_bwd": (C.c_int, [_P, _P, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _SZ, _P]),
     "gs_render_bwd_grad2d": (_P, [_P]),
-    "gs_composite_bwd": (C.c_int, [_P, _P, _P, _P, _I32, _P, _P, _P, _P, _P, _P, _I32, _I64, _P, _P, _SZ, _P]),
+    "gs_composite_bwd": (C.c_int, [_P, _P, _P, _P, _I32, _P, _P, _P, _P, _P, _P, _I32, _I64, _P, _P, _SZ, _I32,
+                                   _P]),
     "gs_seg_workspace_size": (_SZ, [_I64, _I64]),
     "gs_project_bwd": (C.c_int, [_P, _P, _I32, _P, _P, _P, _P, _P, _P, _P]),
     "gs_render_count": (C.c_int, [_P, _P, _P, _P, _I32, _P, _P]),

@@ -461,11 +461,13 @@ const float* gs_render_bwd_grad2d(void* ws) { return static_cast<const float*>(w
 
 namespace {
 
-// segment area: work_off [T + 1] | state_off [T + 1] | states [capacity][kSegFields][256]
+// segment area: work_off [T + 1] | state_off [T + 1] | stop_seg [T][256] |
+// states [capacity][kSegFields][256]
 size_t seg_fixed_bytes(int64_t n_tiles) {
     Carver c(nullptr);
     c.take<uint32_t>((size_t)n_tiles + 1);
     c.take<uint32_t>((size_t)n_tiles + 1);
+    c.take<int32_t>((size_t)n_tiles * 256);
     return c.off;
 }
 
@@ -473,15 +475,17 @@ constexpr size_t kSegStateBytes = (size_t)kSegFields * 256 * sizeof(float);
 
 // a plan over `base` (NULL or too small: no segments)
 void seg_layout(void* base, size_t bytes, int64_t n_tiles, SegPlan* plan, uint32_t* capacity) {
-    *plan = SegPlan{nullptr, nullptr, nullptr, (uint32_t)n_tiles};
+    *plan = SegPlan{nullptr, nullptr, nullptr, (uint32_t)n_tiles, nullptr, 0u};
     *capacity = 0;
     const size_t fixed = seg_fixed_bytes(n_tiles);
     if (!base || bytes < fixed) return;
     Carver c(base);
     plan->work_off = c.take<uint32_t>((size_t)n_tiles + 1);
     plan->state_off = c.take<uint32_t>((size_t)n_tiles + 1);
+    plan->stop_seg = c.take<int32_t>((size_t)n_tiles * 256);
     plan->state = reinterpret_cast<float*>(static_cast<char*>(base) + fixed);
     *capacity = (uint32_t)std::min<size_t>((bytes - fixed) / kSegStateBytes, 1u << 24);
+    plan->capacity = *capacity;
 }
 
 }  // namespace
@@ -490,6 +494,33 @@ size_t gs_seg_workspace_size(int64_t n_tiles, int64_t n_pairs) {
     if (n_tiles < 1) n_tiles = 1;
     if (n_pairs < 0) n_pairs = 0;
     return seg_fixed_bytes(n_tiles) + ((size_t)n_pairs / kSegLen + 1) * kSegStateBytes;
+}
+
+int gs_render_fwd_seg(const gs_projected* proj, const uint32_t* pair_vals, const uint32_t* tile_ranges,
+                      const gs_camera* cams, int32_t n_views, const gs_options* opt, float* rgb, float* depth,
+                      float* alpha, float* T_final, int32_t* last, void* seg_ws, size_t seg_ws_bytes,
+                      void* stream) {
+    try {
+        ViewTable vt;
+        OptK ok;
+        int rc;
+        if ((rc = build_views(cams, n_views, &vt)) || (rc = build_opt(opt, &ok)) || (rc = check_proj(proj)))
+            return rc;
+        GS_REQUIRE(pair_vals && tile_ranges && rgb && depth && alpha && T_final && last, "NULL buffer");
+        GS_REQUIRE(((uintptr_t)seg_ws & (kAlign - 1)) == 0, "segment workspace must be 256-byte aligned");
+        hipStream_t s = (hipStream_t)stream;
+        SegPlan plan;
+        uint32_t cap;
+        seg_layout(seg_ws, seg_ws_bytes, vt.total_tiles, &plan, &cap);
+        const Projected pr = to_proj(proj);
+        const uint2* rg = reinterpret_cast<const uint2*>(tile_ranges);
+        if (plan.work_off) GS_HIP(launch_seg_plan(pr, rg, vt, cap, plan, s));
+        GS_HIP(launch_render_fwd(pr, pair_vals, rg, vt, ok, rgb, depth, alpha, T_final, last, s, 0, nullptr,
+                                 plan.work_off ? &plan : nullptr));
+        return GS_OK;
+    } catch (...) {
+        return fail(GS_ERR_INTERNAL, "unexpected exception in gs_render_fwd_seg");
+    }
 }
 
 int gs_render_bwd(const gs_gaussians* g, const gs_camera* cams, int32_t n_views, const gs_options* opt,
@@ -536,7 +567,7 @@ int gs_composite_bwd(const gs_projected* proj, const uint32_t* pair_vals, const 
                      const gs_camera* cams, int32_t n_views, const gs_options* opt, const float* T_final,
                      const int32_t* last, const float* d_rgb, const float* d_depth, const float* d_alpha,
                      int32_t abs_sums, int64_t n_slots, float* grad2d, void* seg_ws, size_t seg_ws_bytes,
-                     void* stream) {
+                     int32_t seg_ready, void* stream) {
     try {
         ViewTable vt;
         OptK ok;
@@ -553,7 +584,8 @@ int gs_composite_bwd(const gs_projected* proj, const uint32_t* pair_vals, const 
         GS_HIP(zero_seen_grad2d(proj->tiles, grad2d, n_slots, s));
         const Projected pr = to_proj(proj);
         const uint2* rg = reinterpret_cast<const uint2*>(tile_ranges);
-        if (plan.work_off) GS_HIP(launch_seg_prepare(pr, pair_vals, rg, vt, last, cap, plan, s));
+        // seg_ready: the plan and the states are those gs_render_fwd_seg wrote
+        if (plan.work_off && !seg_ready) GS_HIP(launch_seg_prepare(pr, pair_vals, rg, vt, last, cap, plan, s));
         GS_HIP(launch_render_bwd(pr, pair_vals, rg, vt, ok, T_final, last, d_rgb, d_depth, d_alpha, grad2d, plan, cap,
                                  abs_sums != 0, s));
         return GS_OK;

@@ -200,33 +200,42 @@ hipError_t launch_bin_counts(const unsigned long long* total, const unsigned lon
 // tile launch order for compositing, longest lists first
 hipError_t launch_tile_order(const uint32_t* ranges, uint32_t n_tiles, uint32_t* order, hipStream_t s);
 
-// Segmented backward: lists longer than kSegLen positions are walked in
-// segments of kSegLen by separate workgroups.  work_off [T + 1] and
-// state_off [T + 1] are exclusive prefix sums, over the tiles in launch
-// order, of the work items (segments) and of the stored segment states
-// (segments 1 .. n - 1 of a segmented tile); state holds kSegFields planes
-// of 256 pixels per stored segment: T_seg, C_seg (r, g, b), D_seg.
+// Segmented compositing: lists longer than kSegLen positions are walked in
+// segments of kSegLen by separate workgroups, forward and backward.
+// work_off [T + 1] and state_off [T + 1] are exclusive prefix sums, over the
+// tiles in launch order, of the work items (segments) and of the stored
+// segment states (segments 1 .. n - 1 of a segmented tile); state holds
+// kSegFields planes of 256 pixels per stored segment: T_seg, C_seg (r, g,
+// b), D_seg and (int) the position of the segment's last entry; stop_seg
+// [T][256] (by tile) is the segment a pixel stops in, -1 for none, for the
+// segmented forward.
 constexpr int kSegLen = 512;
-constexpr int kSegFields = 5;
+constexpr int kSegFields = 6;
 struct SegPlan {
     uint32_t* work_off;    // null: one work item per tile, no segments
     uint32_t* state_off;
     float* state;
     uint32_t n_tiles;
+    int32_t* stop_seg;
+    uint32_t capacity;     // stored states the area holds
 };
 // plans the segments of every tile (segments disabled when they need more
-// than `capacity` stored states) and writes their states
+// than `capacity` stored states)
+hipError_t launch_seg_plan(const Projected& proj, const uint2* ranges, const ViewTable& vt, uint32_t capacity,
+                           const SegPlan& plan, hipStream_t s);
+// the plan, then the states by a walk of the stored segments
 hipError_t launch_seg_prepare(const Projected& proj, const uint32_t* pair_vals, const uint2* ranges,
                               const ViewTable& vt, const int32_t* last, uint32_t capacity, const SegPlan& plan,
                               hipStream_t s);
 
 // compositing (render.hip)
 // persistent_ctas > 0: a grid of that many workgroups pulling tiles from
-// `work` (one u32, zeroed here by a fill kernel)
+// `work` (one u32, zeroed here by a fill kernel); plan (one workgroup per
+// tile only): also write the segment states of the planned tiles
 hipError_t launch_render_fwd(const Projected& proj, const uint32_t* pair_vals, const uint2* ranges,
                              const ViewTable& vt, const OptK& opt, float* rgb, float* depth, float* alpha,
                              float* T_final, int32_t* last, hipStream_t s,
-                             int persistent_ctas = 0, uint32_t* work = nullptr);
+                             int persistent_ctas = 0, uint32_t* work = nullptr, const SegPlan* plan = nullptr);
 hipError_t launch_render_count(const Projected& proj, const uint32_t* pair_vals, const uint2* ranges,
                                const ViewTable& vt, int32_t* n_eval, hipStream_t s);
 hipError_t launch_render_bwd(const Projected& proj, const uint32_t* pair_vals, const uint2* ranges,

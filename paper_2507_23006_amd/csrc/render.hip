@@ -243,28 +243,38 @@ __device__ __forceinline__ int stage_gathered(const Gather& e, int pos, const Pi
     return __popcll(m);
 }
 
+// segmented forward: stop_seg value of a pixel still compositing after
+// the first segment
+constexpr int32_t kSegAlive = 0x7fffffff;
+
 // One wave composites quadrant `quad` of `tile` (staging in its LDS slice
-// `st`) and writes its pixels.
+// `st`) and writes its pixels: the whole list, front to back.  With
+// head_stop (the tile's stop_seg row; a list the plan segments) only the
+// first kSegLen positions: pixels that stop there get their outputs and
+// stop_seg = -1, the others their state after it (rgb without background,
+// depth, T, last) and stop_seg = kSegAlive.
 __device__ __forceinline__ void render_fwd_quadrant(const float4* __restrict__ rec,
                                                     const uint32_t* __restrict__ pair_vals,
                                                     const uint2* __restrict__ ranges, const ViewTable& vt,
                                                     const OptK& opt, int tile, int quad, int lane, WaveStage& st,
                                                     float* __restrict__ rgb, float* __restrict__ depth,
                                                     float* __restrict__ alpha_out, float* __restrict__ T_out,
-                                                    int32_t* __restrict__ last_out) {
+                                                    int32_t* __restrict__ last_out,
+                                                    int32_t* __restrict__ head_stop = nullptr) {
     const PixelCoords pc = pixel_coords(vt, tile, quad, lane);
     const uint2 rg = ranges[tile];
+    const uint32_t end = head_stop ? min(rg.x + (uint32_t)kSegLen, rg.y) : rg.y;
 
     float T = 1.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f, D = 0.0f;
     int last = 0;
     bool alive = pc.inside;
-    Gather cur = load_entry(rec, load_slot(pair_vals, rg.x + lane, rg.y));
-    uint32_t s_next = load_slot(pair_vals, rg.x + kChunk + lane, rg.y);
-    for (uint32_t j0 = rg.x; j0 < rg.y; j0 += kChunk) {
+    Gather cur = load_entry(rec, load_slot(pair_vals, rg.x + lane, end));
+    uint32_t s_next = load_slot(pair_vals, rg.x + kChunk + lane, end);
+    for (uint32_t j0 = rg.x; j0 < end; j0 += kChunk) {
         if (__ballot(alive) == 0) break;     // every pixel of the quadrant has stopped
         const int n = stage_gathered(cur, (int)(j0 - rg.x) + lane + 1, pc, lane, st);
         cur = load_entry(rec, s_next);                                   // next chunk's records
-        s_next = load_slot(pair_vals, j0 + 2 * kChunk + lane, rg.y);     // and the one after's slots
+        s_next = load_slot(pair_vals, j0 + 2 * kChunk + lane, end);      // and the one after's slots
         // entry k + 1 is read from LDS while entry k is evaluated; the
         // position of the pixel's last composited entry is read once per chunk
         int last_k = -1;
@@ -295,26 +305,262 @@ __device__ __forceinline__ void render_fwd_quadrant(const float4* __restrict__ r
     }
     if (!pc.inside) return;
     const int64_t p = pc.pix;
-    rgb[3 * p + 0] = fmaf(T, opt.bg[0], c0);
-    rgb[3 * p + 1] = fmaf(T, opt.bg[1], c1);
-    rgb[3 * p + 2] = fmaf(T, opt.bg[2], c2);
+    const bool more = head_stop && alive;    // compositing continues after the head
+    if (head_stop) head_stop[pc.ly * kTile + pc.lx] = more ? kSegAlive : -1;
+    rgb[3 * p + 0] = more ? c0 : fmaf(T, opt.bg[0], c0);
+    rgb[3 * p + 1] = more ? c1 : fmaf(T, opt.bg[1], c1);
+    rgb[3 * p + 2] = more ? c2 : fmaf(T, opt.bg[2], c2);
     depth[p] = D;
-    alpha_out[p] = 1.0f - T;
+    if (!more) alpha_out[p] = 1.0f - T;
     T_out[p] = T;
     last_out[p] = last;
 }
 
+// Segmented forward, pass 2: one wave walks segment `seg` >= 1 (list
+// positions [seg S, (seg + 1) S), S = kSegLen) of a long list for the
+// pixels of its quadrant still compositing after the first segment (`on`),
+// and keeps, over the entries that pass the alpha test, the segment's
+// state with T restarted at 1: T_seg = prod (1 - alpha), C_seg = sum c
+// alpha T_local (colour and depth) and the position of its last such entry
+// -- as if no pixel stopped in the segment -- in its stored-state row
+// (planes T, r, g, b, depth, last; the other pixels get the empty state).
+// A pixel whose T_local falls below T_min is certain to stop in this
+// segment or an earlier one (T before it is at most 1); it is left there
+// (the fold then stops in or before this segment, whose exact walk pass 4
+// redoes), and the wave stops when all its pixels are.
+__device__ __forceinline__ void render_fwd_segment(const float4* __restrict__ rec,
+                                                   const uint32_t* __restrict__ pair_vals, const uint2 rg,
+                                                   const PixelCoords& pc, bool on, int seg, int lane, WaveStage& st,
+                                                   float* __restrict__ state_row) {
+    const uint32_t lo = rg.x + (uint32_t)seg * kSegLen, hi = min(lo + (uint32_t)kSegLen, rg.y);
+    float Tl = 1.0f, l0 = 0.0f, l1 = 0.0f, l2 = 0.0f, Dl = 0.0f;
+    int last = 0;
+    Gather cur = load_entry(rec, load_slot(pair_vals, lo + lane, hi));
+    uint32_t s_next = load_slot(pair_vals, lo + kChunk + lane, hi);
+    for (uint32_t j0 = lo; j0 < hi; j0 += kChunk) {
+        if (__ballot(on) == 0) break;
+        const int n = stage_gathered(cur, (int)(j0 - rg.x) + lane + 1, pc, lane, st);
+        cur = load_entry(rec, s_next);
+        s_next = load_slot(pair_vals, j0 + 2 * kChunk + lane, hi);
+        int last_k = -1;
+#pragma unroll 4
+        for (int k = 0; k < n; ++k) {
+            const float4 a = st.g[k], b = st.b[k], c = st.c[k];
+            const Eval e = eval_entry(a, b, pc.fpx, pc.fpy);
+            const bool use = on && e.keep;
+            const float w = use ? e.alpha * Tl : 0.0f;
+            l0 = fmaf(c.x, w, l0);
+            l1 = fmaf(c.y, w, l1);
+            l2 = fmaf(c.z, w, l2);
+            Dl = fmaf(b.z, w, Dl);
+            Tl = use ? Tl * (1.0f - e.alpha) : Tl;
+            last_k = use ? k : last_k;
+        }
+        if (last_k >= 0) last = st.ps[last_k].x;
+        on = on && Tl >= kTMin;
+        __builtin_amdgcn_wave_barrier();
+    }
+    const int px = pc.ly * kTile + pc.lx;
+    state_row[0 * 256 + px] = Tl;
+    state_row[1 * 256 + px] = l0;
+    state_row[2 * 256 + px] = l1;
+    state_row[3 * 256 + px] = l2;
+    state_row[4 * 256 + px] = Dl;
+    reinterpret_cast<int32_t*>(state_row)[5 * 256 + px] = last;
+}
+
+// stored segment b of a plan -> launch position, segment (>= 1), count
+struct SegItem {
+    uint32_t i;
+    int seg, nseg;
+};
+__device__ __forceinline__ SegItem stored_seg(const SegPlan& plan, uint32_t b) {
+    SegItem it;
+    it.i = last_le(plan.state_off, plan.n_tiles, b);
+    it.seg = (int)(b - plan.state_off[it.i]) + 1;
+    it.nseg = (int)(plan.work_off[it.i + 1] - plan.work_off[it.i]);
+    return it;
+}
+
+// One workgroup per tile, in launch order.  With a segment plan, the lists
+// it segments composite their first segment only (the head: pass 1 of the
+// segmented forward).
 __global__ __launch_bounds__(256) void k_render_fwd(const float4* __restrict__ rec,
                                                     const uint32_t* __restrict__ pair_vals,
                                                     const uint2* __restrict__ ranges,
                                                     const uint32_t* __restrict__ tile_order, ViewTable vt, OptK opt,
                                                     float* __restrict__ rgb, float* __restrict__ depth,
                                                     float* __restrict__ alpha_out, float* __restrict__ T_out,
-                                                    int32_t* __restrict__ last_out) {
+                                                    int32_t* __restrict__ last_out, SegPlan plan) {
     __shared__ WaveStage stage[kWaves];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    render_fwd_quadrant(rec, pair_vals, ranges, vt, opt, launch_tile(tile_order, vt), wave, lane, stage[wave], rgb,
-                        depth, alpha_out, T_out, last_out);
+    const int tile = launch_tile(tile_order, vt);
+    int32_t* head_stop = nullptr;
+    if (plan.work_off) {
+        const uint32_t i = blockIdx.x;
+        if (plan.work_off[i + 1] - plan.work_off[i] > 1u) head_stop = plan.stop_seg + (size_t)tile * 256;
+    }
+    render_fwd_quadrant(rec, pair_vals, ranges, vt, opt, tile, wave, lane, stage[wave], rgb, depth, alpha_out, T_out,
+                        last_out, head_stop);
+}
+
+// Pass 2, one workgroup per stored segment: the segment's state for the
+// pixels still compositing after the head (a quadrant with none exits).
+// (256, 7): at most 72 VGPRs, 7 waves per SIMD, no spills.
+__global__ __launch_bounds__(256, 7) void k_fwd_segments(const float4* __restrict__ rec,
+                                                      const uint32_t* __restrict__ pair_vals,
+                                                      const uint2* __restrict__ ranges,
+                                                      const uint32_t* __restrict__ tile_order, ViewTable vt,
+                                                      SegPlan plan) {
+    __shared__ WaveStage stage[kWaves];
+    const uint32_t b = blockIdx.x;
+    if (b >= plan.state_off[plan.n_tiles]) return;
+    const SegItem it = stored_seg(plan, b);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int tile = order_tile(tile_order, vt, it.i);
+    const PixelCoords pc = pixel_coords(vt, tile, wave, lane);
+    const bool on = pc.inside && plan.stop_seg[(size_t)tile * 256 + pc.ly * kTile + pc.lx] == kSegAlive;
+    if (__ballot(on) == 0) return;
+    render_fwd_segment(rec, pair_vals, ranges[tile], pc, on, it.seg, lane, stage[wave],
+                       plan.state + (size_t)b * kSegFields * 256);
+}
+
+// Pass 3, one thread per pixel still compositing after the head of a
+// segmented list: fold the later segments front to back (C += T C_seg,
+// T *= T_seg).  T only decreases along the list, so the pixel stops inside
+// segment j exactly when T T_seg_j < T_min; then its state before segment j
+// is left in the outputs and stop_seg = j for pass 4.  Otherwise the
+// outputs are final and stop_seg = -1.
+__global__ __launch_bounds__(256) void k_fwd_combine(const uint32_t* __restrict__ tile_order, ViewTable vt,
+                                                     OptK opt, SegPlan plan, float* __restrict__ rgb,
+                                                     float* __restrict__ depth, float* __restrict__ alpha_out,
+                                                     float* __restrict__ T_out, int32_t* __restrict__ last_out) {
+    const uint32_t i = blockIdx.x;
+    const int nseg = (int)(plan.work_off[i + 1] - plan.work_off[i]);
+    if (nseg <= 1) return;
+    const int tile = order_tile(tile_order, vt, i);
+    const PixelCoords pc = pixel_coords(vt, tile, threadIdx.x >> 6, threadIdx.x & 63);
+    const int px = pc.ly * kTile + pc.lx;
+    int32_t* stop_row = plan.stop_seg + (size_t)tile * 256;
+    if (!pc.inside || stop_row[px] != kSegAlive) return;
+    const int64_t p = pc.pix;
+    float T = T_out[p], c0 = rgb[3 * p + 0], c1 = rgb[3 * p + 1], c2 = rgb[3 * p + 2], D = depth[p];
+    int last = last_out[p];
+    int stop = -1;
+    const uint32_t st0 = plan.state_off[i];
+    for (int j = 1; j < nseg; ++j) {
+        const float* r = plan.state + (size_t)(st0 + (uint32_t)(j - 1)) * kSegFields * 256;
+        const float Ts = r[px];
+        if (T * Ts < kTMin) {
+            stop = j;
+            break;
+        }
+        c0 = fmaf(T, r[1 * 256 + px], c0);
+        c1 = fmaf(T, r[2 * 256 + px], c1);
+        c2 = fmaf(T, r[3 * 256 + px], c2);
+        D = fmaf(T, r[4 * 256 + px], D);
+        T *= Ts;
+        const int lj = reinterpret_cast<const int32_t*>(r)[5 * 256 + px];
+        last = lj > 0 ? lj : last;
+    }
+    stop_row[px] = stop;
+    if (stop < 0) {
+        rgb[3 * p + 0] = fmaf(T, opt.bg[0], c0);
+        rgb[3 * p + 1] = fmaf(T, opt.bg[1], c1);
+        rgb[3 * p + 2] = fmaf(T, opt.bg[2], c2);
+        alpha_out[p] = 1.0f - T;
+    } else {
+        rgb[3 * p + 0] = c0;
+        rgb[3 * p + 1] = c1;
+        rgb[3 * p + 2] = c2;
+    }
+    depth[p] = D;
+    T_out[p] = T;
+    last_out[p] = last;
+}
+
+// Pass 4, one workgroup per stored segment: the pixels that stop in this
+// segment walk it again from their state before it, with the stop rule,
+// T = T_start T_local and T_local recomputed as in pass 2 (so the pixel
+// stops here, at the latest at the segment's last entry); they write their
+// final outputs and the segment's state over the entries they composited
+// (the state the backward folds).  (256, 7): 7 waves per SIMD, no spills.
+__global__ __launch_bounds__(256, 7) void k_fwd_fix(const float4* __restrict__ rec,
+                                                 const uint32_t* __restrict__ pair_vals,
+                                                 const uint2* __restrict__ ranges,
+                                                 const uint32_t* __restrict__ tile_order, ViewTable vt, OptK opt,
+                                                 SegPlan plan, float* __restrict__ rgb, float* __restrict__ depth,
+                                                 float* __restrict__ alpha_out, float* __restrict__ T_out,
+                                                 int32_t* __restrict__ last_out) {
+    __shared__ WaveStage stage[kWaves];
+    const uint32_t b = blockIdx.x;
+    if (b >= plan.state_off[plan.n_tiles]) return;
+    const SegItem it = stored_seg(plan, b);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int tile = order_tile(tile_order, vt, it.i);
+    const PixelCoords pc = pixel_coords(vt, tile, wave, lane);
+    const int px = pc.ly * kTile + pc.lx;
+    bool alive = pc.inside && plan.stop_seg[(size_t)tile * 256 + px] == it.seg;
+    const bool mine = alive;
+    if (__ballot(alive) == 0) return;      // no pixel of the quadrant stops here
+    WaveStage& st = stage[wave];
+    const uint2 rg = ranges[tile];
+    float Ts = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f, D0 = 0.0f;
+    int last = 0;
+    if (mine) {
+        const int64_t p = pc.pix;
+        Ts = T_out[p];
+        C0 = rgb[3 * p + 0];
+        C1 = rgb[3 * p + 1];
+        C2 = rgb[3 * p + 2];
+        D0 = depth[p];
+        last = last_out[p];
+    }
+    const uint32_t lo = rg.x + (uint32_t)it.seg * kSegLen, hi = min(lo + (uint32_t)kSegLen, rg.y);
+    float Tl = 1.0f, l0 = 0.0f, l1 = 0.0f, l2 = 0.0f, Dl = 0.0f;
+    Gather cur = load_entry(rec, load_slot(pair_vals, lo + lane, hi));
+    uint32_t s_next = load_slot(pair_vals, lo + kChunk + lane, hi);
+    for (uint32_t j0 = lo; j0 < hi; j0 += kChunk) {
+        if (__ballot(alive) == 0) break;
+        const int n = stage_gathered(cur, (int)(j0 - rg.x) + lane + 1, pc, lane, st);
+        cur = load_entry(rec, s_next);
+        s_next = load_slot(pair_vals, j0 + 2 * kChunk + lane, hi);
+        int last_k = -1;
+        for (int k = 0; k < n; ++k) {
+            const float4 a = st.g[k], bb = st.b[k], c = st.c[k];
+            const Eval e = eval_entry(a, bb, pc.fpx, pc.fpy);
+            const bool keep = alive && e.keep;
+            const float Tln = Tl * (1.0f - e.alpha);
+            const bool stop = keep && Ts * Tln < kTMin;
+            const bool use = keep && !stop;
+            const float w = use ? e.alpha * Tl : 0.0f;
+            l0 = fmaf(c.x, w, l0);
+            l1 = fmaf(c.y, w, l1);
+            l2 = fmaf(c.z, w, l2);
+            Dl = fmaf(bb.z, w, Dl);
+            Tl = use ? Tln : Tl;
+            last_k = use ? k : last_k;
+            alive = alive && !stop;
+        }
+        if (last_k >= 0) last = st.ps[last_k].x;
+        __builtin_amdgcn_wave_barrier();
+    }
+    if (!mine) return;
+    const int64_t p = pc.pix;
+    const float T = Ts * Tl;
+    rgb[3 * p + 0] = fmaf(T, opt.bg[0], fmaf(Ts, l0, C0));
+    rgb[3 * p + 1] = fmaf(T, opt.bg[1], fmaf(Ts, l1, C1));
+    rgb[3 * p + 2] = fmaf(T, opt.bg[2], fmaf(Ts, l2, C2));
+    depth[p] = fmaf(Ts, Dl, D0);
+    alpha_out[p] = 1.0f - T;
+    T_out[p] = T;
+    last_out[p] = last;
+    float* r = plan.state + (size_t)b * kSegFields * 256;
+    r[0 * 256 + px] = Tl;
+    r[1 * 256 + px] = l0;
+    r[2 * 256 + px] = l1;
+    r[3 * 256 + px] = l2;
+    r[4 * 256 + px] = Dl;
 }
 
 // Persistent compositing: a fixed grid whose workgroups take tiles in launch
@@ -788,7 +1034,8 @@ __global__ __launch_bounds__(256) void k_zero_seen_rows(const uint32_t* __restri
 
 hipError_t launch_render_fwd(const Projected& proj, const uint32_t* pair_vals, const uint2* ranges,
                              const ViewTable& vt, const OptK& opt, float* rgb, float* depth, float* alpha,
-                             float* T_final, int32_t* last, hipStream_t s, int persistent_ctas, uint32_t* work) {
+                             float* T_final, int32_t* last, hipStream_t s, int persistent_ctas, uint32_t* work,
+                             const SegPlan* plan) {
     if (vt.total_tiles <= 0) return hipSuccess;
     const hipEvent_t timed_ = timer_begin(GS_KERNEL_RENDER_FWD, s);
     if (persistent_ctas > 0 && work) {
@@ -798,8 +1045,19 @@ hipError_t launch_render_fwd(const Projected& proj, const uint32_t* pair_vals, c
         hipLaunchKernelGGL(k_render_fwd_persistent, dim3(grid), dim3(256), 0, s, proj.rec, pair_vals, ranges,
                            proj.tile_order, vt, opt, rgb, depth, alpha, T_final, last, work);
     } else {
+        const SegPlan none{nullptr, nullptr, nullptr, (uint32_t)vt.total_tiles, nullptr, 0u};
         hipLaunchKernelGGL(k_render_fwd, dim3(vt.total_tiles), dim3(256), 0, s, proj.rec, pair_vals, ranges,
-                           proj.tile_order, vt, opt, rgb, depth, alpha, T_final, last);
+                           proj.tile_order, vt, opt, rgb, depth, alpha, T_final, last, plan ? *plan : none);
+        if (plan && plan->capacity) {
+            // the later segments of the planned lists, the fold, and the
+            // re-walk of the segments pixels stop in
+            hipLaunchKernelGGL(k_fwd_segments, dim3(plan->capacity), dim3(256), 0, s, proj.rec, pair_vals, ranges,
+                               proj.tile_order, vt, *plan);
+            hipLaunchKernelGGL(k_fwd_combine, dim3(vt.total_tiles), dim3(256), 0, s, proj.tile_order, vt, opt, *plan,
+                               rgb, depth, alpha, T_final, last);
+            hipLaunchKernelGGL(k_fwd_fix, dim3(plan->capacity), dim3(256), 0, s, proj.rec, pair_vals, ranges,
+                               proj.tile_order, vt, opt, *plan, rgb, depth, alpha, T_final, last);
+        }
     }
     timer_end(timed_, s);
     return hipGetLastError();
@@ -813,11 +1071,18 @@ hipError_t launch_render_count(const Projected& proj, const uint32_t* pair_vals,
     return hipGetLastError();
 }
 
+hipError_t launch_seg_plan(const Projected& proj, const uint2* ranges, const ViewTable& vt, uint32_t capacity,
+                           const SegPlan& plan, hipStream_t s) {
+    hipLaunchKernelGGL(k_seg_plan, dim3(1), dim3(1024), 0, s, ranges, proj.tile_order, vt, capacity, plan.work_off,
+                       plan.state_off);
+    return hipGetLastError();
+}
+
 hipError_t launch_seg_prepare(const Projected& proj, const uint32_t* pair_vals, const uint2* ranges,
                               const ViewTable& vt, const int32_t* last, uint32_t capacity, const SegPlan& plan,
                               hipStream_t s) {
-    hipLaunchKernelGGL(k_seg_plan, dim3(1), dim3(1024), 0, s, ranges, proj.tile_order, vt, capacity, plan.work_off,
-                       plan.state_off);
+    hipError_t e = launch_seg_plan(proj, ranges, vt, capacity, plan, s);
+    if (e != hipSuccess) return e;
     if (capacity)
         hipLaunchKernelGGL(k_seg_prepass, dim3(capacity), dim3(256), 0, s, proj.rec, pair_vals, ranges, proj.tile_order,
                            vt, last, plan);

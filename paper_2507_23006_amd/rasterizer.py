@@ -208,7 +208,30 @@ def bin_sort(proj: Projected, cams, n: int, ws: Workspace | None = None, capacit
     raise L.GsError(L.GS_ERR_CAPACITY, "pair buffer could not be grown")
 
 
-def render_fwd(proj: Projected, pair_vals, ranges, cams, opts: RenderOptions) -> dict:
+def seg_workspace(cams, pair_vals) -> torch.Tensor:
+    """A device area for the segmented backward of these lists
+    (gs_seg_workspace_size bytes, plus alignment slack)."""
+    n_tiles, _ = views_extent(cams)
+    ssz = L.load().gs_seg_workspace_size(n_tiles, int(pair_vals.numel()))
+    return torch.empty(ssz + 256, dtype=torch.uint8, device=pair_vals.device)
+
+
+def _seg_args(seg: torch.Tensor):
+    base = Workspace.aligned(seg)
+    return C.c_void_p(base), seg.numel() - (base - seg.data_ptr())
+
+
+def render_fwd(proj: Projected, pair_vals, ranges, cams, opts: RenderOptions, seg=None, ws: Workspace | None = None) -> dict:
+    """Compositing.  Lists longer than 512 positions are walked in segments
+    by separate workgroups (gs_render_fwd_seg) in a workspace area; with
+    `seg` (from seg_workspace) in that area, whose segment states the
+    backward can then read (pass it to render_bwd).  seg=False: every list
+    walked whole by one workgroup (gs_render_fwd)."""
+    if seg is None:
+        ws = ws or _default_ws
+        n_tiles, _ = views_extent(cams)
+        seg = ws.get("seg_fwd", L.load().gs_seg_workspace_size(n_tiles, int(pair_vals.numel())) + 256,
+                     proj.rec.device)
     lib = L.load()
     dev = proj.rec.device
     _, npx = views_extent(cams)
@@ -217,9 +240,12 @@ def render_fwd(proj: Projected, pair_vals, ranges, cams, opts: RenderOptions) ->
            "alpha": torch.empty((npx,), dtype=torch.float32, device=dev),
            "T": torch.empty((npx,), dtype=torch.float32, device=dev),
            "last": torch.empty((npx,), dtype=torch.int32, device=dev)}
-    L.check(lib.gs_render_fwd(C.byref(proj.c()), _ptr(pair_vals), _ptr(ranges), L.make_cameras(cams), len(cams),
-                              C.byref(opts.c()), _ptr(out["rgb"]), _ptr(out["depth"]), _ptr(out["alpha"]),
-                              _ptr(out["T"]), _ptr(out["last"]), _stream()))
+    args = (C.byref(proj.c()), _ptr(pair_vals), _ptr(ranges), L.make_cameras(cams), len(cams), C.byref(opts.c()),
+            _ptr(out["rgb"]), _ptr(out["depth"]), _ptr(out["alpha"]), _ptr(out["T"]), _ptr(out["last"]))
+    if seg is False:
+        L.check(lib.gs_render_fwd(*args, _stream()))
+    else:
+        L.check(lib.gs_render_fwd_seg(*args, *_seg_args(seg), _stream()))
     return out
 
 
@@ -268,7 +294,10 @@ def _mark(name: str) -> None:
 
 
 def render_bwd(params, cams, opts: RenderOptions, proj: Projected, pair_vals, ranges, T, last, d_rgb, d_depth,
-               d_alpha, ws: Workspace | None = None, app=None) -> dict:
+               d_alpha, ws: Workspace | None = None, app=None, seg: torch.Tensor | None = None) -> dict:
+    """Backward of compositing and projection; `seg`: the area the forward
+    filled (render_fwd(..., seg=...)) for these lists, else the segment
+    states are computed here."""
     lib = L.load()
     ws = ws or _default_ws
     means, scales, quats, opacities, sh = params
@@ -289,17 +318,19 @@ def render_bwd(params, cams, opts: RenderOptions, proj: Projected, pair_vals, ra
     wsz = lib.gs_render_bwd_workspace_size(n * V)
     wbuf = ws.get("bwd", wsz + 256, dev)
     g2 = C.c_void_p(Workspace.aligned(wbuf))
-    n_tiles, _ = views_extent(cams)
-    ssz = lib.gs_seg_workspace_size(n_tiles, int(pair_vals.numel()))
-    sbuf = ws.get("seg", ssz + 256, dev)
+    if seg is None:
+        n_tiles, _ = views_extent(cams)
+        ssz = lib.gs_seg_workspace_size(n_tiles, int(pair_vals.numel()))
+        seg_ptr, seg_bytes, seg_ready = *_seg_args(ws.get("seg", ssz + 256, dev)), 0
+    else:
+        seg_ptr, seg_bytes, seg_ready = *_seg_args(seg), 1
     cont = lambda t: t.contiguous() if t is not None else None
     d_rgb, d_depth, d_alpha = cont(d_rgb), cont(d_depth), cont(d_alpha)
     cams_c, opt_c, proj_c = L.make_cameras(cams), opts.c(), proj.c()
     _mark("bwd_begin")
     L.check(lib.gs_composite_bwd(C.byref(proj_c), _ptr(pair_vals), _ptr(ranges), cams_c, V, C.byref(opt_c), _ptr(T),
                                  _ptr(last), _ptr(d_rgb), _ptr(d_depth), _ptr(d_alpha), int(bool(opts.absgrad)), n * V,
-                                 g2,
-                                 C.c_void_p(Workspace.aligned(sbuf)), ssz, _stream()))
+                                 g2, seg_ptr, seg_bytes, seg_ready, _stream()))
     _mark("composite_bwd")
     L.check(lib.gs_project_bwd(C.byref(g), cams_c, V, C.byref(opt_c), C.byref(proj_c), g2, C.byref(go), _ptr(norm),
                                _ptr(absg), _stream()))
@@ -344,11 +375,15 @@ class GsRasterize(torch.autograd.Function):
         known = (n * len(cams), views_extent(cams)[0]) in _default_ws.pair_caps
         pair_vals, ranges, P = bin_sort(proj, cams, n, sync=not known)
         _mark("bin_sort")
-        out = render_fwd(proj, pair_vals, ranges, cams, opts)
+        # the forward writes the segment states of the long lists into an
+        # area of this call's own, which the backward reads
+        seg = seg_workspace(cams, pair_vals)
+        out = render_fwd(proj, pair_vals, ranges, cams, opts, seg=seg)
         _mark("render_fwd")
         ctx.save_for_backward(*params, proj.rec, proj.rect, proj.tiles, proj.depth_key, proj.tile_order, pair_vals,
                               ranges, out["T"], out["last"], app)
         ctx.cams, ctx.opts, ctx.stats, ctx.n_pairs, ctx.n_slots = list(cams), opts, stats, P, n * len(cams)
+        ctx.seg = seg
         if stats is not None:
             stats.n_pairs = P
         return out["rgb"], out["depth"], out["alpha"]
@@ -359,7 +394,8 @@ class GsRasterize(torch.autograd.Function):
          last, app) = ctx.saved_tensors
         proj = Projected(rec, rect, tiles, dkey, order)
         g = render_bwd((means, scales, quats, opacities, sh), ctx.cams, ctx.opts, proj, pair_vals, ranges, T, last,
-                       d_rgb, d_depth, d_alpha, app=app)
+                       d_rgb, d_depth, d_alpha, app=app, seg=ctx.seg)
+        ctx.seg = None
         if ctx.stats is not None:
             ctx.stats.mean2d_grad_norm = g["mean2d_grad_norm"]
             ctx.stats.absgrad = g["absgrad"]
