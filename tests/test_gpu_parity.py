@@ -320,6 +320,39 @@ def test_forward_is_deterministic(gpu_lib):
         assert torch.equal(a[k], b[k]), k
 
 
+def test_backward_run_to_run_spread(gpu_lib):
+    """The forward is atomic-free and bitwise repeatable; the backward sums
+    per-pixel contributions with float atomics, whose order varies from run
+    to run.  Over repeated runs on the same inputs each gradient group must
+    stay within 1e-6 of its norm (relative spread, measured and printed)."""
+    scene = S.random_scene(20000, seed=12, log_scale_mu=-3.0)
+    cams = [oblique_cam(320, 240, 240.0), oblique_cam(160, 120, 120.0)]
+    opts = gpu_lib.RenderOptions(aa=True, absgrad=True)
+    params = to_dev(scene, requires_grad=True)
+    gen = torch.Generator(device="cuda").manual_seed(4)
+    npx = sum(c.width * c.height for c in cams)
+    w = [torch.randn(sh, device="cuda", generator=gen) for sh in ((npx, 3), (npx,), (npx,))]
+    runs, outs = [], []
+    for _ in range(6):
+        for p in params:
+            p.grad = None
+        stats = gpu_lib.RenderStats()
+        rgb, depth, alpha = gpu_lib.rasterize(*params, cams, opts, stats)
+        ((rgb * w[0]).sum() + (depth * w[1]).sum() + (alpha * w[2]).sum()).backward()
+        runs.append([p.grad.detach().clone() for p in params] + [stats.mean2d_grad_norm.clone(),
+                                                                   stats.absgrad.clone()])
+        outs.append((rgb.detach().clone(), depth.detach().clone(), alpha.detach().clone()))
+    for o in outs[1:]:
+        assert all(torch.equal(a, b) for a, b in zip(outs[0], o))
+    names = ("means", "scales", "quats", "opacities", "sh", "mean2d_grad_norm", "absgrad")
+    spread = {}
+    for k, name in enumerate(names):
+        ref = runs[0][k].double()
+        spread[name] = max(float((r[k].double() - ref).norm() / ref.norm()) for r in runs[1:])
+    print("backward run-to-run relative spread:", {k: f"{v:.1e}" for k, v in spread.items()})
+    assert max(spread.values()) < 1e-6, spread
+
+
 def test_permutation_invariance_bitwise(gpu_lib):
     scene = S.random_scene(3000, seed=10, log_scale_mu=-2.7)
     cams = [oblique_cam(128, 96, 100.0)]
