@@ -518,13 +518,13 @@ def counted_traffic(kernel):
 def serve_modes(gs, n_requests):
     """Server configurations of the serving trace: "plain" (one request per
     launch, one worker, one batch in flight: FIFO) and "served" (continuous
-    batching of up to 8 views admitted by estimated pairs, two workers, two
-    batches in flight per worker so the next batch's projection and binning
-    overlap the current compositing)."""
+    batching of up to 8 views admitted by estimated pairs, one worker with two
+    batches in flight, so the next batch's projection and binning overlap the
+    current compositing; a second worker measured no faster)."""
     return {
         "plain": gs.ServeConfig(max_views_per_batch=1, n_streams=1, pipeline_depth=1, slot_capacity=6_000_000,
                                 pair_capacity=48_000_000, pixel_capacity=1 << 21, queue_capacity=n_requests),
-        "served": gs.ServeConfig(max_views_per_batch=8, n_streams=2, pipeline_depth=2, slot_capacity=24_000_000,
+        "served": gs.ServeConfig(max_views_per_batch=8, n_streams=1, pipeline_depth=2, slot_capacity=24_000_000,
                                  pair_capacity=96_000_000, pixel_capacity=1 << 24, queue_capacity=n_requests),
     }
 

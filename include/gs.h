@@ -502,8 +502,9 @@ int gs_lod_select(const gs_lod_table *table, const gs_camera *cam, int64_t budge
  * A batch whose pairs still overflow pair_capacity is split in halves and
  * re-rendered (counted in split_batches); a single request that overflows
  * completes with GS_ERR_CAPACITY.  The rendered image is the image
- * gs_render_fwd gives for the selected Gaussians alone, whatever the batch,
- * the pipeline depth or the compositing mode. */
+ * gs_render_fwd_seg gives for the selected Gaussians alone (with
+ * persistent compositing, gs_render_fwd's), whatever the batch or the
+ * pipeline depth. */
 typedef struct gs_serve_config {
     int32_t max_views_per_batch;   /* 1..GS_MAX_VIEWS; 1 = one request per launch */
     int32_t n_streams;             /* worker threads, 1..8 */
@@ -512,8 +513,9 @@ typedef struct gs_serve_config {
     int64_t pixel_capacity;        /* pixels per batch */
     int32_t queue_capacity;        /* pending requests; gs_serve_submit returns GS_EAGAIN beyond */
     int32_t pipeline_depth;        /* batches in flight per worker (buffer sets), 1..4 */
-    int32_t persistent_ctas;       /* 0: one workgroup per tile; > 0: persistent compositing with at most
-                                      this many workgroups taking tiles from a counter */
+    int32_t persistent_ctas;       /* 0: lists longer than 512 positions composited in segments
+                                      (gs_render_fwd_seg); > 0: persistent compositing, every list walked
+                                      whole, by at most this many workgroups taking tiles from a counter */
     double pairs_per_gaussian;     /* admission ratio for image sizes not yet rendered; 0 = 8 */
 } gs_serve_config;
 

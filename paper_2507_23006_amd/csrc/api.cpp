@@ -202,6 +202,33 @@ size_t bin_layout(int64_t n_slots, int64_t cap, void* base, BinWs* w) {
 
 }  // namespace
 
+// segment area: work_off [T + 1] | state_off [T + 1] | stop_seg [T][256] |
+// states [capacity][kSegFields][256]
+size_t seg_fixed_bytes(int64_t n_tiles) {
+    Carver c(nullptr);
+    c.take<uint32_t>((size_t)n_tiles + 1);
+    c.take<uint32_t>((size_t)n_tiles + 1);
+    c.take<int32_t>((size_t)n_tiles * 256);
+    return c.off;
+}
+
+constexpr size_t kSegStateBytes = (size_t)kSegFields * 256 * sizeof(float);
+
+// a plan over `base` (NULL or too small: no segments)
+void seg_layout(void* base, size_t bytes, int64_t n_tiles, SegPlan* plan, uint32_t* capacity) {
+    *plan = SegPlan{nullptr, nullptr, nullptr, (uint32_t)n_tiles, nullptr, 0u};
+    *capacity = 0;
+    const size_t fixed = seg_fixed_bytes(n_tiles);
+    if (!base || bytes < fixed) return;
+    Carver c(base);
+    plan->work_off = c.take<uint32_t>((size_t)n_tiles + 1);
+    plan->state_off = c.take<uint32_t>((size_t)n_tiles + 1);
+    plan->stop_seg = c.take<int32_t>((size_t)n_tiles * 256);
+    plan->state = reinterpret_cast<float*>(static_cast<char*>(base) + fixed);
+    *capacity = (uint32_t)std::min<size_t>((bytes - fixed) / kSegStateBytes, 1u << 24);
+    plan->capacity = *capacity;
+}
+
 size_t bin_workspace_bytes(int64_t n_slots, int64_t pair_capacity) {
     if (n_slots < 1) n_slots = 1;
     BinWs w;
@@ -459,36 +486,6 @@ size_t gs_render_bwd_workspace_size(int64_t n_slots) {
 
 const float* gs_render_bwd_grad2d(void* ws) { return static_cast<const float*>(ws); }
 
-namespace {
-
-// segment area: work_off [T + 1] | state_off [T + 1] | stop_seg [T][256] |
-// states [capacity][kSegFields][256]
-size_t seg_fixed_bytes(int64_t n_tiles) {
-    Carver c(nullptr);
-    c.take<uint32_t>((size_t)n_tiles + 1);
-    c.take<uint32_t>((size_t)n_tiles + 1);
-    c.take<int32_t>((size_t)n_tiles * 256);
-    return c.off;
-}
-
-constexpr size_t kSegStateBytes = (size_t)kSegFields * 256 * sizeof(float);
-
-// a plan over `base` (NULL or too small: no segments)
-void seg_layout(void* base, size_t bytes, int64_t n_tiles, SegPlan* plan, uint32_t* capacity) {
-    *plan = SegPlan{nullptr, nullptr, nullptr, (uint32_t)n_tiles, nullptr, 0u};
-    *capacity = 0;
-    const size_t fixed = seg_fixed_bytes(n_tiles);
-    if (!base || bytes < fixed) return;
-    Carver c(base);
-    plan->work_off = c.take<uint32_t>((size_t)n_tiles + 1);
-    plan->state_off = c.take<uint32_t>((size_t)n_tiles + 1);
-    plan->stop_seg = c.take<int32_t>((size_t)n_tiles * 256);
-    plan->state = reinterpret_cast<float*>(static_cast<char*>(base) + fixed);
-    *capacity = (uint32_t)std::min<size_t>((bytes - fixed) / kSegStateBytes, 1u << 24);
-    plan->capacity = *capacity;
-}
-
-}  // namespace
 
 size_t gs_seg_workspace_size(int64_t n_tiles, int64_t n_pairs) {
     if (n_tiles < 1) n_tiles = 1;

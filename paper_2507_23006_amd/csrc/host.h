@@ -50,6 +50,13 @@ struct Carver {
 int build_views(const gs_camera* cams, int32_t n_views, ViewTable* vt);
 int build_opt(const gs_options* o, OptK* k);
 
+// segment area of the segmented compositing: work_off [T + 1] | state_off
+// [T + 1] | stop_seg [T][256] | states [capacity][kSegFields][256]; the
+// fixed part's bytes, and the plan over an area (NULL or smaller than the
+// fixed part: no segments)
+size_t seg_fixed_bytes(int64_t n_tiles);
+void seg_layout(void* base, size_t bytes, int64_t n_tiles, SegPlan* plan, uint32_t* capacity);
+
 // workspace bytes of bin_sort_slots
 size_t bin_workspace_bytes(int64_t n_slots, int64_t pair_capacity);
 

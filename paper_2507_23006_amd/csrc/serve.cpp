@@ -208,6 +208,8 @@ struct BufSet {
     int64_t* npairs_dev = nullptr;      // the binning's pair count (device)
     int64_t* npairs_host = nullptr;     // its copy after the batch (pinned)
     uint32_t* work = nullptr;           // work counter of persistent compositing
+    void* seg = nullptr;                // segment area of the segmented forward
+    size_t seg_bytes = 0;
     hipEvent_t prepped = nullptr;       // projection and binning done
     hipEvent_t done = nullptr;          // images and pair count written
     // the batch in flight
@@ -307,7 +309,7 @@ void recycle_events(gs_server* s, Request* r, int nb) {
 void free_set(BufSet& b) {
     void* dev[] = {b.proj.rec, b.proj.rect, b.proj.tiles, b.proj.dkey, b.proj.tile_order, b.proj.tile_mask,
                    b.segs_dev, b.pairs,     b.ranges,     b.bin_ws,    b.rgb,              b.depth,
-                   b.alpha,    b.T,         b.last,       b.npairs_dev, b.work};
+                   b.alpha,    b.T,         b.last,       b.npairs_dev, b.work,           b.seg};
     for (void* p : dev)
         if (p) (void)hipFree(p);
     if (b.segs_host) (void)hipHostFree(b.segs_host);
@@ -351,6 +353,8 @@ int alloc_set(gs_server* s, BufSet& b) {
     GS_HIP(dev_alloc(&b.last, (size_t)X));
     GS_HIP(dev_alloc(&b.npairs_dev, 1));
     GS_HIP(dev_alloc(&b.work, 1));
+    b.seg_bytes = gs_seg_workspace_size(s->tile_cap, Pc);
+    GS_HIP(hipMalloc(&b.seg, b.seg_bytes));
     GS_HIP(hipHostMalloc(reinterpret_cast<void**>(&b.npairs_host), sizeof(int64_t), hipHostMallocDefault));
     GS_HIP(hipEventCreateWithFlags(&b.prepped, hipEventDisableTiming));
     GS_HIP(hipEventCreateWithFlags(&b.done, hipEventDisableTiming));
@@ -406,8 +410,17 @@ int launch_batch(Worker* w, BufSet& b, Request* r, int nb) {
         GS_HIP(fill_u32(b.ranges, 0u, 2 * (size_t)vt.total_tiles, w->render));
         GS_HIP(launch_tile_order(b.ranges, (uint32_t)vt.total_tiles, b.proj.tile_order, w->render));
     }
+    // long lists composited in segments (one workgroup per tile when the
+    // compositing is persistent)
+    SegPlan plan;
+    uint32_t cap = 0;
+    seg_layout(b.seg, b.seg_bytes, vt.total_tiles, &plan, &cap);
+    const bool segmented = plan.work_off && slots > 0 && s->cfg.persistent_ctas == 0;
+    if (segmented)
+        GS_HIP(launch_seg_plan(b.proj, reinterpret_cast<const uint2*>(b.ranges), vt, cap, plan, w->render));
     GS_HIP(launch_render_fwd(b.proj, b.pairs, reinterpret_cast<const uint2*>(b.ranges), vt, s->opt, b.rgb, b.depth,
-                             b.alpha, b.T, b.last, w->render, s->cfg.persistent_ctas, b.work));
+                             b.alpha, b.T, b.last, w->render, s->cfg.persistent_ctas, b.work,
+                             segmented ? &plan : nullptr));
     for (int v = 0; v < nb; ++v) {
         if (r[v].ready) GS_HIP(hipStreamWaitEvent(w->render, r[v].ready, 0));
         GS_HIP(hipMemcpyAsync(r[v].out, b.rgb + 3 * vt.v[v].pix_off,

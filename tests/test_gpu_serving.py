@@ -89,12 +89,23 @@ def test_served_images_match_oracle_and_ignore_batching(lod_setup):
     assert st["completed"] == len(reqs) and st["failed"] == 0
     for a, b in zip(alone, mixed):
         assert torch.equal(a, b)
-    # two batches in flight per worker and persistent compositing: same images
-    cfg = gs.ServeConfig(max_views_per_batch=4, n_streams=1, pipeline_depth=2, persistent_ctas=96, **CAPS)
+    # two batches in flight per worker: same images
+    cfg = gs.ServeConfig(max_views_per_batch=4, n_streams=1, pipeline_depth=2, **CAPS)
     piped, c3, st3 = serve(gs, params, table, opts, reqs, cfg, t_arrival=0.0)
     assert all(c["status"] == 0 for c in c3) and st3["completed"] == len(reqs)
     for a, b in zip(alone, piped):
         assert torch.equal(a, b)
+    # persistent compositing walks every list whole (no segments): the
+    # images match the oracle as well
+    cfg = gs.ServeConfig(max_views_per_batch=4, n_streams=1, pipeline_depth=2, persistent_ctas=96, **CAPS)
+    pers, c5, st5 = serve(gs, params, table, opts, reqs, cfg, t_arrival=0.0)
+    assert all(c["status"] == 0 for c in c5) and st5["completed"] == len(reqs)
+    for i in (1, 5):
+        cam, budget = reqs[i]
+        idx = selected_subset(table, offsets, cam, budget, gs)
+        f = oracle.forward(sc.subset(idx), cam, oracle_opt(opts), guard_eps=oracle.DEFAULT_GUARD)
+        check_image(cam, oracle_opt(opts), 0, f["twod"], f["bins"]["pair_slot"], f["bins"]["ranges"], f["images"][0],
+                    {"rgb": pers[i].cpu().numpy().reshape(cam.height, cam.width, 3)}, f"persistent request {i}")
     for i in (0, 4, 8, 10):
         cam, budget = reqs[i]
         idx = selected_subset(table, offsets, cam, budget, gs)
