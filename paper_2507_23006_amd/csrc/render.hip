@@ -244,15 +244,22 @@ __device__ __forceinline__ int stage_gathered(const Gather& e, int pos, const Pi
 }
 
 // segmented forward: stop_seg value of a pixel still compositing after
-// the first segment
+// the head; segments in the head (walked by the tile's workgroup)
 constexpr int32_t kSegAlive = 0x7fffffff;
+constexpr int kHeadSegs = 2;
 
 // One wave composites quadrant `quad` of `tile` (staging in its LDS slice
 // `st`) and writes its pixels: the whole list, front to back.  With
 // head_stop (the tile's stop_seg row; a list the plan segments) only the
-// first kSegLen positions: pixels that stop there get their outputs and
-// stop_seg = -1, the others their state after it (rgb without background,
-// depth, T, last) and stop_seg = kSegAlive.
+// head, the first kHeadSegs segments: pixels that stop there (or whose list
+// ends there) get their outputs and stop_seg = -1, the others their state
+// after it (rgb without background, depth, T, last) and stop_seg =
+// kSegAlive.  The head also writes the backward's states of its segments
+// 1 .. kHeadSegs - 1 (head_states: the tile's first stored state) from the
+// pixel's (T, C, D) at the segment's ends: T_seg = T_end / T_start and
+// C_seg = (C_end - C_start) / T_start -- the segment's composite with T
+// restarted at 1; the backward uses C_seg scaled back by T_start, so the
+// subtraction's rounding stays at the size of C's.
 __device__ __forceinline__ void render_fwd_quadrant(const float4* __restrict__ rec,
                                                     const uint32_t* __restrict__ pair_vals,
                                                     const uint2* __restrict__ ranges, const ViewTable& vt,
@@ -260,17 +267,40 @@ __device__ __forceinline__ void render_fwd_quadrant(const float4* __restrict__ r
                                                     float* __restrict__ rgb, float* __restrict__ depth,
                                                     float* __restrict__ alpha_out, float* __restrict__ T_out,
                                                     int32_t* __restrict__ last_out,
-                                                    int32_t* __restrict__ head_stop = nullptr) {
+                                                    int32_t* __restrict__ head_stop = nullptr,
+                                                    float* __restrict__ head_states = nullptr) {
     const PixelCoords pc = pixel_coords(vt, tile, quad, lane);
     const uint2 rg = ranges[tile];
-    const uint32_t end = head_stop ? min(rg.x + (uint32_t)kSegLen, rg.y) : rg.y;
+    const uint32_t end = head_stop ? min(rg.x + (uint32_t)(kHeadSegs * kSegLen), rg.y) : rg.y;
 
     float T = 1.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f, D = 0.0f;
     int last = 0;
     bool alive = pc.inside;
+    // (T, C, D) at the start of the current segment (head walks only)
+    float sT = 1.0f, s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, sD = 0.0f;
+    int seg = 0;
+    const int px = pc.ly * kTile + pc.lx;
+    auto seg_state = [&]() {      // state of segment `seg` >= 1 from its start to now
+        float* o = head_states + (size_t)(seg - 1) * kSegFields * 256;
+        const float inv = 1.0f / sT;
+        o[0 * 256 + px] = T * inv;
+        o[1 * 256 + px] = (c0 - s0) * inv;
+        o[2 * 256 + px] = (c1 - s1) * inv;
+        o[3 * 256 + px] = (c2 - s2) * inv;
+        o[4 * 256 + px] = (D - sD) * inv;
+    };
     Gather cur = load_entry(rec, load_slot(pair_vals, rg.x + lane, end));
     uint32_t s_next = load_slot(pair_vals, rg.x + kChunk + lane, end);
     for (uint32_t j0 = rg.x; j0 < end; j0 += kChunk) {
+        if (head_states && j0 != rg.x && (j0 - rg.x) % (uint32_t)kSegLen == 0) {
+            if (seg >= 1) seg_state();
+            ++seg;
+            sT = T;
+            s0 = c0;
+            s1 = c1;
+            s2 = c2;
+            sD = D;
+        }
         if (__ballot(alive) == 0) break;     // every pixel of the quadrant has stopped
         const int n = stage_gathered(cur, (int)(j0 - rg.x) + lane + 1, pc, lane, st);
         cur = load_entry(rec, s_next);                                   // next chunk's records
@@ -303,10 +333,11 @@ __device__ __forceinline__ void render_fwd_quadrant(const float4* __restrict__ r
         if (last_k >= 0) last = st.ps[last_k].x;
         __builtin_amdgcn_wave_barrier();     // the chunk is consumed before the next one is staged
     }
+    if (head_states && seg >= 1) seg_state();
     if (!pc.inside) return;
     const int64_t p = pc.pix;
-    const bool more = head_stop && alive;    // compositing continues after the head
-    if (head_stop) head_stop[pc.ly * kTile + pc.lx] = more ? kSegAlive : -1;
+    const bool more = head_stop && alive && end < rg.y;    // compositing continues after the head
+    if (head_stop) head_stop[px] = more ? kSegAlive : -1;
     rgb[3 * p + 0] = more ? c0 : fmaf(T, opt.bg[0], c0);
     rgb[3 * p + 1] = more ? c1 : fmaf(T, opt.bg[1], c1);
     rgb[3 * p + 2] = more ? c2 : fmaf(T, opt.bg[2], c2);
@@ -316,9 +347,9 @@ __device__ __forceinline__ void render_fwd_quadrant(const float4* __restrict__ r
     last_out[p] = last;
 }
 
-// Segmented forward, pass 2: one wave walks segment `seg` >= 1 (list
-// positions [seg S, (seg + 1) S), S = kSegLen) of a long list for the
-// pixels of its quadrant still compositing after the first segment (`on`),
+// Segmented forward, pass 2: one wave walks segment `seg` >= kHeadSegs
+// (list positions [seg S, (seg + 1) S), S = kSegLen) of a long list for the
+// pixels of its quadrant still compositing after the head (`on`),
 // and keeps, over the entries that pass the alpha test, the segment's
 // state with T restarted at 1: T_seg = prod (1 - alpha), C_seg = sum c
 // alpha T_local (colour and depth) and the position of its last such entry
@@ -383,9 +414,9 @@ __device__ __forceinline__ SegItem stored_seg(const SegPlan& plan, uint32_t b) {
 }
 
 // One workgroup per tile, in launch order.  With a segment plan, the lists
-// it segments composite their first segment only (the head: pass 1 of the
-// segmented forward).
-__global__ __launch_bounds__(256) void k_render_fwd(const float4* __restrict__ rec,
+// it segments composite their head only (pass 1 of the segmented forward).
+// (256, 7): at most 72 VGPRs, 7 waves per SIMD, no spills.
+__global__ __launch_bounds__(256, 7) void k_render_fwd(const float4* __restrict__ rec,
                                                     const uint32_t* __restrict__ pair_vals,
                                                     const uint2* __restrict__ ranges,
                                                     const uint32_t* __restrict__ tile_order, ViewTable vt, OptK opt,
@@ -396,12 +427,16 @@ __global__ __launch_bounds__(256) void k_render_fwd(const float4* __restrict__ r
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int tile = launch_tile(tile_order, vt);
     int32_t* head_stop = nullptr;
+    float* head_states = nullptr;
     if (plan.work_off) {
         const uint32_t i = blockIdx.x;
-        if (plan.work_off[i + 1] - plan.work_off[i] > 1u) head_stop = plan.stop_seg + (size_t)tile * 256;
+        if (plan.work_off[i + 1] - plan.work_off[i] > 1u) {
+            head_stop = plan.stop_seg + (size_t)tile * 256;
+            head_states = plan.state + (size_t)plan.state_off[i] * kSegFields * 256;
+        }
     }
     render_fwd_quadrant(rec, pair_vals, ranges, vt, opt, tile, wave, lane, stage[wave], rgb, depth, alpha_out, T_out,
-                        last_out, head_stop);
+                        last_out, head_stop, head_states);
 }
 
 // Pass 2, one workgroup per stored segment: the segment's state for the
@@ -416,6 +451,7 @@ __global__ __launch_bounds__(256, 7) void k_fwd_segments(const float4* __restric
     const uint32_t b = blockIdx.x;
     if (b >= plan.state_off[plan.n_tiles]) return;
     const SegItem it = stored_seg(plan, b);
+    if (it.seg < kHeadSegs) return;        // the head's segments
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int tile = order_tile(tile_order, vt, it.i);
     const PixelCoords pc = pixel_coords(vt, tile, wave, lane);
@@ -426,7 +462,7 @@ __global__ __launch_bounds__(256, 7) void k_fwd_segments(const float4* __restric
 }
 
 // Pass 3, one thread per pixel still compositing after the head of a
-// segmented list: fold the later segments front to back (C += T C_seg,
+// segmented list: fold the segments after it front to back (C += T C_seg,
 // T *= T_seg).  T only decreases along the list, so the pixel stops inside
 // segment j exactly when T T_seg_j < T_min; then its state before segment j
 // is left in the outputs and stop_seg = j for pass 4.  Otherwise the
@@ -448,7 +484,7 @@ __global__ __launch_bounds__(256) void k_fwd_combine(const uint32_t* __restrict_
     int last = last_out[p];
     int stop = -1;
     const uint32_t st0 = plan.state_off[i];
-    for (int j = 1; j < nseg; ++j) {
+    for (int j = kHeadSegs; j < nseg; ++j) {
         const float* r = plan.state + (size_t)(st0 + (uint32_t)(j - 1)) * kSegFields * 256;
         const float Ts = r[px];
         if (T * Ts < kTMin) {
