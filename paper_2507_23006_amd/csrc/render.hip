@@ -765,10 +765,13 @@ __global__ __launch_bounds__(256) void k_render_bwd(const float4* __restrict__ r
                                                     const float* __restrict__ d_alpha, float* __restrict__ grad2d,
                                                     SegPlan plan) {
     __shared__ WaveStage stage[kWaves];
-    // one row of reduced fields per staged entry (10 without the AbsGS sums:
-    // the smaller area lets six workgroups share a compute unit's LDS)
+    // one row of reduced fields per staged entry of half a chunk (10 without
+    // the AbsGS sums); the rows of a chunk's later half are flushed before
+    // its earlier half reuses them, so seven workgroups share a compute
+    // unit's LDS
     constexpr int kRow = kAbs ? kG2 : 10;
-    __shared__ float s_red[kWaves][kChunk][kRow];
+    constexpr int kRedRows = kChunk / 2;
+    __shared__ float s_red[kWaves][kRedRows][kRow];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     int tile, seg = 0, nseg = 1;
     uint32_t st0 = 0;
@@ -839,12 +842,13 @@ __global__ __launch_bounds__(256) void k_render_bwd(const float4* __restrict__ r
         const int b_start_ = max(lo, b_end_ - kChunk);
         return b_end_ > lo ? load_slot(pair_vals, rg.x + (uint32_t)(b_start_ + lane), rg.x + (uint32_t)b_end_) : kNoSlot;
     };
-    // adds chunk sums of the last staged chunk (n entries) to grad2d
+    // adds the sums of staged entries [k0, k1) (one half of the staged
+    // chunk, rows k mod kRedRows) to grad2d
     constexpr int kFields = kAbs ? kG2 : 10;
-    auto flush = [&](int n_) {
-        for (int i = lane; i < n_ * kFields; i += 64) {
-            const int k = i / kFields, f = i - k * kFields;
-            const float sum = s_red[wave][k][f];
+    auto flush = [&](int k0, int k1) {
+        for (int i = lane; i < (k1 - k0) * kFields; i += 64) {
+            const int j = i / kFields, f = i - j * kFields, k = k0 + j;
+            const float sum = s_red[wave][k & (kRedRows - 1)][f];
             if (sum != 0.0f)
                 atomicAdd(&grad2d[(size_t)(uint32_t)st.ps[k].y * kG2 + f], sum * grad2d_field_scale(f));
         }
@@ -859,7 +863,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(const float4* __restrict__ r
         // chunk's atomics: loads and atomics share one in-order counter, so
         // atomics issued before the wait would be waited for as well.
         __asm__ volatile("" ::"v"(cur.r0.x), "v"(cur.r1.x), "v"(cur.r2.x), "v"(cur.r3.x), "v"(s_next));
-        flush(n_prev);
+        flush(0, min(n_prev, kRedRows));
         const int n = stage_gathered(cur, b_start + lane + 1, pc, lane, st);
         n_prev = n;
         cur = load_entry(rec, s_next);
@@ -903,7 +907,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(const float4* __restrict__ r
             T = con ? Ti : T;
             if (kAbs) {
                 // lane 16 r + 15 writes fields 3 r .. 3 r + 2 of the entry's row
-                float* row = &s_red[wave][k][3 * (lane >> 4)];
+                float* row = &s_red[wave][k & (kRedRows - 1)][3 * (lane >> 4)];
                 if (__ballot(con)) {
                     float tot[3];
                     wave_sum12(g, tot);
@@ -918,7 +922,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(const float4* __restrict__ r
             } else {
                 // lane 16 r + 15 writes its fields of the entry's row
                 const int r = lane >> 4;
-                float* row = &s_red[wave][k][(r & 1) + 5 * (r >> 1)];
+                float* row = &s_red[wave][k & (kRedRows - 1)][(r & 1) + 5 * (r >> 1)];
                 float tot[3] = {0.0f, 0.0f, 0.0f};
                 if (__ballot(con)) wave_sum10(g, tot);
                 if ((lane & 15) == 15) {
@@ -927,10 +931,12 @@ __global__ __launch_bounds__(256) void k_render_bwd(const float4* __restrict__ r
                     if (!(r & 1)) row[4] = tot[2];
                 }
             }
+            // the later half's rows go out before the earlier half reuses them
+            if (k == kRedRows) flush(kRedRows, n);
         }
         __builtin_amdgcn_wave_barrier();
     }
-    flush(n_prev);
+    flush(0, min(n_prev, kRedRows));
 }
 
 // exclusive scan of v over the 1024 threads of the workgroup; *total gets the sum
