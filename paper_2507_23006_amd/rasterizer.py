@@ -449,8 +449,9 @@ class L1DepthLoss(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, g):
-        d_rgb, d_depth, d_alpha = ctx.saved_tensors
-        return d_rgb * g, d_depth * g, d_alpha * g, None, None, None
+        # one multi-tensor launch scales the three gradients
+        d_rgb, d_depth, d_alpha = torch._foreach_mul(list(ctx.saved_tensors), g)
+        return d_rgb, d_depth, d_alpha, None, None, None
 
 
 def l1_depth_loss(rgb, depth, alpha, target_rgb, target_depth=None, lambda_depth: float = 0.5):
