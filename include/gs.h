@@ -214,16 +214,23 @@ int gs_render_count(const gs_projected *proj, const uint32_t *pair_vals, const u
 size_t gs_render_bwd_workspace_size(int64_t n_slots);
 size_t gs_seg_workspace_size(int64_t n_tiles, int64_t n_pairs);
 
-/* gs_render_fwd that also prepares the segmented backward in seg_ws
- * (gs_seg_workspace_size(n_tiles, n_pairs) bytes, 256-byte aligned; a
- * smaller area plans no segments): it plans the segments of the lists
- * longer than 512 positions and, while compositing them, writes each
- * segment's state (transmittance and colour and depth with T restarted at
- * the segment's start, over the pixel's composited entries) -- the states
- * the backward otherwise computes in a second walk of those lists.  Pass
- * the same seg_ws, unchanged, to gs_composite_bwd with seg_ready = 1,
- * together with these lists, T_final and last.  Outputs as gs_render_fwd,
- * bit for bit. */
+/* Compositing (Eq. 2) with the lists longer than 512 positions split into
+ * 512-position segments walked by several workgroups, in the segment area
+ * seg_ws (gs_seg_workspace_size(n_tiles, n_pairs) bytes, 256-byte aligned;
+ * a smaller area, or one too small for the states, walks every list whole
+ * as gs_render_fwd does).  A long list's workgroup walks its first two
+ * segments with the stop rule; for the pixels still compositing, one
+ * workgroup per later segment keeps the segment's state with T restarted
+ * at 1; one thread per such pixel folds the segments (T only decreases, so
+ * the pixel stops in segment j exactly when T T_seg_j < 1e-4) and the stop
+ * segment is walked again from the pixel's state before it.  Outputs as
+ * gs_render_fwd up to the grouping of the products: equal to float
+ * rounding, a stop decision moving only where T is within rounding of the
+ * threshold.  seg_ws then holds each segment's state (transmittance and
+ * colour and depth with T restarted at the segment's start, over the
+ * pixel's composited entries) -- the states the segmented backward folds:
+ * pass the same seg_ws, unchanged, to gs_composite_bwd with seg_ready = 1,
+ * together with these lists, T_final and last. */
 int gs_render_fwd_seg(const gs_projected *proj, const uint32_t *pair_vals, const uint32_t *tile_ranges,
                       const gs_camera *cams, int32_t n_views, const gs_options *opt, float *rgb, float *depth,
                       float *alpha, float *T_final, int32_t *last, void *seg_ws, size_t seg_ws_bytes,
