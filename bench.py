@@ -60,8 +60,8 @@ PROJ_BWD_BYTES_VIS = 536.0
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-crop", type=int, default=16, help="oracle baseline renders 1/crop of the pixels")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving trace")
@@ -84,6 +84,25 @@ def copy_probe(mib):
         dst.copy_(src)
     torch.cuda.synchronize()
     print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4, "copies": 3}))
+
+
+def copy_rate(torch, mib=1024, reps=5):
+    """Achievable HBM rate: a plain 1 GiB device-to-device copy timed with
+    events, (bytes read + bytes written) / median time, GB/s."""
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    times = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        b.record()
+        b.synchronize()
+        times.append(a.elapsed_time(b))
+    del src, dst
+    return 2.0 * n * 4 / (pct(times, 50) * 1e-3) / 1e9
 
 
 def pct(xs, q):
@@ -304,6 +323,11 @@ def main():
     # every timed kernel against its model; the roofline object is the
     # longest-running one
     kroof = {k: kernel_roofline(k, ms, scene.n, n_vis, P, e_fwd, e_bwd) for k, ms in kernel_ms.items()}
+    # the HBM-bound ones also against what a plain device copy achieves
+    hbm_copy = copy_rate(torch)
+    for r in kroof.values():
+        if r["bound"] == "hbm":
+            r["frac_of_copy"] = round(r["achieved"] / hbm_copy, 4)
     dom = max(kernel_ms, key=kernel_ms.get) if kernel_ms else None
     roof = dict(kroof[dom]) if dom else None
 
@@ -312,7 +336,7 @@ def main():
     serve = None
     if not args.no_serve:
         del params, stats, proj, pv, rg, out
-        serve = serve_bench(gs, S, torch, scene, opts, args.serve_requests)
+        serve = serve_bench(gs, S, torch, scene, opts, args.serve_requests, with_cpu=not args.no_cpu)
 
     if roof is not None:
         roof["traffic"] = counted_traffic(roof["kernel"])
@@ -354,6 +378,7 @@ def main():
         "workload_stats": {"visible": n_vis, "in_front": n_front, "pairs": P, "evals_fwd": e_fwd, "evals_bwd": e_bwd},
         "roofline": roof,
         "kernel_roofline": kroof,
+        "hbm_copy_GB_s": round(hbm_copy, 1),
         "cpu_baseline": cpu,
         "configs": configs,
         "next_rows": nxt,
@@ -529,7 +554,33 @@ def serve_modes(gs, n_requests):
     }
 
 
-def serve_bench(gs, S, torch, fine, opts, n_requests, modes=None, loads=("", "_800", "_burst")):
+def serve_oracle(gs, sc, offsets, table, trace, opts):
+    """The FP64 oracle on sampled requests of the trace (the first of each
+    resolution): the level-of-detail selection the server makes, then the
+    oracle's projection, binning and compositing of exactly the selected
+    Gaussians, on the host's threads; oracle req/s = requests / seconds."""
+    import oracle
+    picked, seen = [], set()
+    for r in trace:
+        key = (r["camera"].width, r["camera"].height)
+        if key not in seen:
+            seen.add(key)
+            picked.append(r)
+    opt = dict(sh_degree=opts.sh_degree, dilation=opts.dilation, aa=opts.aa, bg=opts.bg)
+    secs, n_sel = 0.0, 0
+    for r in picked:
+        lv, tot = gs.lod_select(table, r["camera"], r["budget"])
+        idx = [np.arange(offsets[l - 1, p], offsets[l - 1, p] + table.counts[l - 1, p]) for p, l in enumerate(lv) if l > 0]
+        sub = sc.subset(np.concatenate(idx) if idx else np.zeros(0, np.int64))
+        n_sel += sub.n
+        a = time.perf_counter()
+        oracle.forward(sub, r["camera"], opt)
+        secs += time.perf_counter() - a
+    return {"value": round(len(picked) / secs, 4), "unit": "req/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{len(picked)} requests (one per resolution, {n_sel} Gaussians selected in all)"}
+
+
+def serve_bench(gs, S, torch, fine, opts, n_requests, modes=None, loads=("", "_800", "_burst"), with_cpu=False):
     """Open-loop serving trace on the level-of-detail stand-in of the urban
     block: levels of 1M, 3M and 6M Gaussians resident in HBM, 30 m render-time
     partitions, thresholds (30, 60, inf) m; Poisson arrivals at 150 req/s,
@@ -583,6 +634,10 @@ def serve_bench(gs, S, torch, fine, opts, n_requests, modes=None, loads=("", "_8
         print(f"# {name}: {res[name]}", file=sys.stderr, flush=True)
     res["trace"] = (f"{len(trace)} requests, Poisson {len(trace) / trace[-1]['t']:.0f} req/s over "
                     f"{trace[-1]['t']:.1f} s, offered {sum(npx) / trace[-1]['t'] / 1e6:.0f} Mpix/s")
+    if with_cpu:
+        del params, flat, outs
+        res["oracle"] = serve_oracle(gs, sc, offsets, table, trace, opts)
+        print(f"# serving oracle: {res['oracle']}", file=sys.stderr, flush=True)
     return res
 
 
