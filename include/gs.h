@@ -258,7 +258,9 @@ int gs_render_bwd(const gs_gaussians *g, const gs_camera *cams, int32_t n_views,
  * seg_ready = 1: seg_ws holds the plan and segment states that
  * gs_render_fwd_seg wrote for these lists (no second walk here); 0: they
  * are computed here.  gs_project_bwd chains grad2d to the parameters
- * (outputs as in gs_render_bwd), reading only those rows. */
+ * (outputs as in gs_render_bwd; grads_zeroed = 1: the outputs already hold
+ * zeros and only the rows of Gaussians some view sees are written), reading
+ * only those rows of grad2d. */
 int gs_composite_bwd(const gs_projected *proj, const uint32_t *pair_vals, const uint32_t *tile_ranges,
                      const gs_camera *cams, int32_t n_views, const gs_options *opt, const float *T_final,
                      const int32_t *last, const float *d_rgb, const float *d_depth, const float *d_alpha,
@@ -266,7 +268,18 @@ int gs_composite_bwd(const gs_projected *proj, const uint32_t *pair_vals, const 
                      int32_t seg_ready, void *stream);
 int gs_project_bwd(const gs_gaussians *g, const gs_camera *cams, int32_t n_views, const gs_options *opt,
                    const gs_projected *proj, const float *grad2d, const gs_gaussians_grad *out,
-                   float *mean2d_grad_norm, float *absgrad, void *stream);
+                   float *mean2d_grad_norm, float *absgrad, int32_t grads_zeroed, void *stream);
+/* Zeroes the parameter-gradient arrays of n Gaussians (d_app too when not
+ * NULL), device pointers as in gs_gaussians_grad, with launches of at most
+ * 64 workgroups each.  With it, gs_project_bwd's grads_zeroed = 1 writes
+ * only the rows of Gaussians some view sees (the others are 84 % of the
+ * rows of a large street-level scene): enqueued on a second stream after
+ * gs_composite_bwd, which is bound by instruction issue and leaves most of
+ * the memory bandwidth free, the fill runs beside it and takes few of its
+ * wave slots; the caller orders gs_project_bwd after both (an event).
+ * Returns GS_ERR_INVALID_ARG for a NULL array (other than d_app) or n < 0,
+ * else the launch status. */
+int gs_grads_zero(const gs_gaussians_grad *out, int64_t n, void *stream);
 
 /* Per-slot 2D gradients of the last gs_render_bwd call that used `ws`
  * ([slots][12]: d mean2d x, y; d conic A, B, C; d opacity'; d rgb; d depth;

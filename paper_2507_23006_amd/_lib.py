@@ -118,7 +118,8 @@ SIGNATURES = {
     "gs_composite_bwd": (C.c_int, [_P, _P, _P, _P, _I32, _P, _P, _P, _P, _P, _P, _I32, _I64, _P, _P, _SZ, _I32,
                                    _P]),
     "gs_seg_workspace_size": (_SZ, [_I64, _I64]),
-    "gs_project_bwd": (C.c_int, [_P, _P, _I32, _P, _P, _P, _P, _P, _P, _P]),
+    "gs_project_bwd": (C.c_int, [_P, _P, _I32, _P, _P, _P, _P, _P, _P, _I32, _P]),
+    "gs_grads_zero": (C.c_int, [_P, _I64, _P]),
     "gs_render_count": (C.c_int, [_P, _P, _P, _P, _I32, _P, _P]),
     "gs_loss_workspace_size": (_SZ, [_I64]),
     "gs_loss_l1_depth": (C.c_int, [_P, _P, _P, _P, _P, _I64, C.c_float, _P, _P, _P, _P, _P, _SZ, _P]),

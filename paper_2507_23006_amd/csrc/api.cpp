@@ -591,9 +591,22 @@ int gs_composite_bwd(const gs_projected* proj, const uint32_t* pair_vals, const 
     }
 }
 
+int gs_grads_zero(const gs_gaussians_grad* out, int64_t n, void* stream) {
+    try {
+        GS_REQUIRE(out && out->d_means && out->d_scales && out->d_quats && out->d_opacities && out->d_sh,
+                   "NULL gradient output");
+        GS_REQUIRE(n >= 0, "n=%lld must be >= 0", (long long)n);
+        const GradPtrs go{out->d_means, out->d_scales, out->d_quats, out->d_opacities, out->d_sh, out->d_app};
+        GS_HIP(launch_zero_grads(go, n, (hipStream_t)stream));
+        return GS_OK;
+    } catch (...) {
+        return fail(GS_ERR_INTERNAL, "unexpected exception in gs_grads_zero");
+    }
+}
+
 int gs_project_bwd(const gs_gaussians* g, const gs_camera* cams, int32_t n_views, const gs_options* opt,
                    const gs_projected* proj, const float* grad2d, const gs_gaussians_grad* out,
-                   float* mean2d_grad_norm, float* absgrad, void* stream) {
+                   float* mean2d_grad_norm, float* absgrad, int32_t grads_zeroed, void* stream) {
     try {
         ViewTable vt;
         OptK ok;
@@ -608,7 +621,7 @@ int gs_project_bwd(const gs_gaussians* g, const gs_camera* cams, int32_t n_views
         GradPtrs go = grad_ptrs(g, out);
         GS_REQUIRE(((uintptr_t)go.app & 15) == 0, "d_app must be 16-byte aligned");
         GS_HIP(launch_project_bwd(gp, g->n, vt, ok, to_proj(proj), grad2d, go, mean2d_grad_norm, absgrad,
-                                  (hipStream_t)stream));
+                                  (hipStream_t)stream, grads_zeroed != 0));
         return GS_OK;
     } catch (...) {
         return fail(GS_ERR_INTERNAL, "unexpected exception in gs_project_bwd");

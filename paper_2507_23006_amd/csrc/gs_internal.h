@@ -259,9 +259,13 @@ hipError_t launch_dssim(const float* x, const float* y, int W, int H, float weig
                         float* Pb, float* Pc, double* partial, hipStream_t s);
 
 // projection backward (project_bwd.hip)
+// grads_zeroed: the outputs hold zeros already (launch_zero_grads); only the
+// rows of Gaussians some view sees are written
 hipError_t launch_project_bwd(const GaussPtrs& g, int64_t n, const ViewTable& vt, const OptK& opt,
                               const Projected& proj, const float* grad2d, const GradPtrs& out,
-                              float* mean2d_norm, float* absgrad, hipStream_t s);
+                              float* mean2d_norm, float* absgrad, hipStream_t s, bool grads_zeroed = false);
+// zeroes every parameter-gradient array of n Gaussians (narrow grid)
+hipError_t launch_zero_grads(const GradPtrs& out, int64_t n, hipStream_t s);
 
 // appearance transform MLP (appearance.hip)
 struct AppMlp {

@@ -288,6 +288,10 @@ __device__ __forceinline__ void project_bwd_one(const GaussPtrs& gp, int64_t n, 
 }
 
 
+// kZeroed: the gradient outputs already hold zeros (k_zero_grads, run
+// beside the compositing backward), so only the rows of Gaussians some view
+// sees are written
+template <bool kZeroed>
 __global__ __launch_bounds__(kPB) void k_project_bwd(GaussPtrs gp, int64_t n, ViewTable vt, OptK opt,
                                                      Projected proj, const float* __restrict__ grad2d, GradPtrs out,
                                                      float* __restrict__ mean2d_norm, float* __restrict__ absgrad) {
@@ -327,8 +331,10 @@ __global__ __launch_bounds__(kPB) void k_project_bwd(GaussPtrs gp, int64_t n, Vi
                 }
             }
         }
+        if (!kZeroed) {
 #pragma unroll
-        for (int c = 0; c < kStageRows; ++c) s_grad[c * kSpan + loc] = 0.0f;
+            for (int c = 0; c < kStageRows; ++c) s_grad[c * kSpan + loc] = 0.0f;
+        }
         s_seen[loc] = vis ? 1 : 0;
         const uint64_t m = __ballot(vis != 0);
         if (m) {
@@ -344,8 +350,9 @@ __global__ __launch_bounds__(kPB) void k_project_bwd(GaussPtrs gp, int64_t n, Vi
     // zero coefficient rows of unseen Gaussians: coalesced 16-byte stores
     const int64_t rows = n - g0 < kSpan ? n - g0 : kSpan;
     F4* dsh = reinterpret_cast<F4*>(out.sh) + 12 * g0;
-    for (int q = tid; q < 12 * rows; q += kPB)
-        if (!s_seen[q / 12]) __builtin_nontemporal_store(F4{0.0f, 0.0f, 0.0f, 0.0f}, dsh + q);
+    if (!kZeroed)
+        for (int q = tid; q < 12 * rows; q += kPB)
+            if (!s_seen[q / 12]) __builtin_nontemporal_store(F4{0.0f, 0.0f, 0.0f, 0.0f}, dsh + q);
 
     // pass 2: the chain, one thread per seen Gaussian
     const uint32_t cnt = s_count;
@@ -355,7 +362,24 @@ __global__ __launch_bounds__(kPB) void k_project_bwd(GaussPtrs gp, int64_t n, Vi
     }
     __syncthreads();
 
-    // pass 3: the span's rows, streamed out (not read again here)
+    // pass 3: the span's rows, streamed out (not read again here); with
+    // zeroed outputs the seen Gaussians' entries only
+    if (kZeroed) {
+        for (uint32_t j = tid; j < cnt; j += kPB) {
+            const int loc = (int)(s_list[j] & 0xFFFFu);
+            const int64_t g = g0 + loc;
+            for (int c = 0; c < 11; ++c) {
+                float* row = c < 3 ? out.means + c * n : c < 6 ? out.scales + (c - 3) * n
+                           : c < 10 ? out.quats + (c - 6) * n : out.opac;
+                __builtin_nontemporal_store(s_grad[c * kSpan + loc], row + g);
+            }
+            if (out.app)
+                __builtin_nontemporal_store(F4{s_grad[(kStageApp + 0) * kSpan + loc], s_grad[(kStageApp + 1) * kSpan + loc],
+                                               s_grad[(kStageApp + 2) * kSpan + loc], s_grad[(kStageApp + 3) * kSpan + loc]},
+                                            reinterpret_cast<F4*>(out.app) + g);
+        }
+        return;
+    }
     for (int c = 0; c < 11; ++c) {
         float* row = c < 3 ? out.means + c * n : c < 6 ? out.scales + (c - 3) * n
                    : c < 10 ? out.quats + (c - 6) * n : out.opac;
@@ -372,12 +396,54 @@ __global__ __launch_bounds__(kPB) void k_project_bwd(GaussPtrs gp, int64_t n, Vi
 
 hipError_t launch_project_bwd(const GaussPtrs& g, int64_t n, const ViewTable& vt, const OptK& opt,
                               const Projected& proj, const float* grad2d, const GradPtrs& out, float* mean2d_norm,
-                              float* absgrad, hipStream_t s) {
+                              float* absgrad, hipStream_t s, bool grads_zeroed) {
     const unsigned blocks = (unsigned)((n + kSpan - 1) / kSpan);
     const hipEvent_t timed_ = timer_begin(GS_KERNEL_PROJECT_BWD, s);
-    hipLaunchKernelGGL(k_project_bwd, dim3(blocks), dim3(kPB), 0, s, g, n, vt, opt, proj, grad2d, out, mean2d_norm,
-                       absgrad);
+    if (grads_zeroed)
+        hipLaunchKernelGGL(k_project_bwd<true>, dim3(blocks), dim3(kPB), 0, s, g, n, vt, opt, proj, grad2d, out,
+                           mean2d_norm, absgrad);
+    else
+        hipLaunchKernelGGL(k_project_bwd<false>, dim3(blocks), dim3(kPB), 0, s, g, n, vt, opt, proj, grad2d, out,
+                           mean2d_norm, absgrad);
     timer_end(timed_, s);
+    return hipGetLastError();
+}
+
+namespace {
+
+// Zeroes n floats with 16-byte streaming stores from a grid of at most
+// kZeroGrid workgroups (grid-stride).  Beside the issue-bound compositing
+// backward, one workgroup on a quarter of the compute units writes over
+// 2 TB/s and takes a seventh of those units' wave slots; a grid over every
+// unit slows the backward by more than the fill saves.
+constexpr unsigned kZeroGrid = 64;
+__global__ __launch_bounds__(256) void k_zero_floats(float* __restrict__ p, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    const int64_t head = (int64_t)(((16 - ((uintptr_t)p & 15)) & 15) / 4);     // floats before the first 16-byte boundary
+    const int64_t h = head < n ? head : n;
+    const int64_t i0 = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i0 < h) p[i0] = 0.0f;
+    F4* q = reinterpret_cast<F4*>(p + h);
+    const int64_t n4 = (n - h) / 4;
+    for (int64_t i = i0; i < n4; i += stride) __builtin_nontemporal_store(F4{0.0f, 0.0f, 0.0f, 0.0f}, q + i);
+    const int64_t t = h + 4 * n4 + i0;
+    if (t < n) p[t] = 0.0f;
+}
+
+}  // namespace
+
+hipError_t launch_zero_grads(const GradPtrs& out, int64_t n, hipStream_t s) {
+    const struct {
+        float* p;
+        int64_t count;
+    } parts[] = {{out.means, 3 * n}, {out.scales, 3 * n}, {out.quats, 4 * n}, {out.opac, n}, {out.sh, 48 * n},
+                 {out.app, out.app ? 4 * n : 0}};
+    for (const auto& a : parts) {
+        if (!a.p || a.count <= 0) continue;
+        const int64_t need = (a.count / 4 + 255) / 256 + 1;
+        const unsigned grid = (unsigned)(need < (int64_t)kZeroGrid ? need : (int64_t)kZeroGrid);
+        hipLaunchKernelGGL(k_zero_floats, dim3(grid), dim3(256), 0, s, a.p, a.count);
+    }
     return hipGetLastError();
 }
 

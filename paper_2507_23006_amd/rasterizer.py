@@ -293,6 +293,47 @@ def _mark(name: str) -> None:
         _stage_hook(name)
 
 
+_side_streams = {}
+
+
+def _side_stream(dev) -> torch.cuda.Stream:
+    """A second stream per device (default priority) for work that runs beside
+    the main stream's."""
+    key = torch.device(dev).index or 0
+    if key not in _side_streams:
+        _side_streams[key] = torch.cuda.Stream(device=dev)
+    return _side_streams[key]
+
+
+def _grad_struct(grads: dict) -> L.GsGaussiansGrad:
+    go = L.GsGaussiansGrad()
+    go.d_means, go.d_scales, go.d_quats = grads["means"].data_ptr(), grads["scales"].data_ptr(), grads["quats"].data_ptr()
+    go.d_opacities, go.d_sh = grads["opacities"].data_ptr(), grads["sh"].data_ptr()
+    if "app" in grads:
+        go.d_app = grads["app"].data_ptr()
+    return go
+
+
+def _zeroed_grads(params, app, after: torch.cuda.Event, n: int):
+    """Gradient arrays shaped like the parameters (and `app`), zeroed by
+    gs_grads_zero on a second stream once the main stream has reached
+    `after`, beside the main stream's next launches.  Returns (grads, event),
+    the event recorded when they hold zeros."""
+    lib = L.load()
+    dev = params[0].device
+    grads = {k: torch.empty_like(t) for k, t in zip(("means", "scales", "quats", "opacities", "sh"), params)}
+    if app is not None:
+        grads["app"] = torch.empty_like(app)
+    side = _side_stream(dev)
+    side.wait_event(after)
+    for t in grads.values():
+        t.record_stream(side)
+    L.check(lib.gs_grads_zero(C.byref(_grad_struct(grads)), n, C.c_void_p(side.cuda_stream)))
+    zeroed = torch.cuda.Event()
+    zeroed.record(side)
+    return grads, zeroed
+
+
 def render_bwd(params, cams, opts: RenderOptions, proj: Projected, pair_vals, ranges, T, last, d_rgb, d_depth,
                d_alpha, ws: Workspace | None = None, app=None, seg: torch.Tensor | None = None) -> dict:
     """Backward of compositing and projection; `seg`: the area the forward
@@ -305,16 +346,9 @@ def render_bwd(params, cams, opts: RenderOptions, proj: Projected, pair_vals, ra
     check_app(app, n)
     V = len(cams)
     dev = means.device
-    grads = {k: torch.empty_like(t) for k, t in zip(("means", "scales", "quats", "opacities", "sh"), params)}
     norm = torch.empty((V, n), dtype=torch.float32, device=dev)
     absg = torch.empty((V, n, 2), dtype=torch.float32, device=dev) if opts.absgrad else None
     g = gaussians_struct(*params, app)
-    go = L.GsGaussiansGrad()
-    go.d_means, go.d_scales, go.d_quats = grads["means"].data_ptr(), grads["scales"].data_ptr(), grads["quats"].data_ptr()
-    go.d_opacities, go.d_sh = grads["opacities"].data_ptr(), grads["sh"].data_ptr()
-    if app is not None:
-        grads["app"] = torch.empty_like(app)
-        go.d_app = grads["app"].data_ptr()
     wsz = lib.gs_render_bwd_workspace_size(n * V)
     wbuf = ws.get("bwd", wsz + 256, dev)
     g2 = C.c_void_p(Workspace.aligned(wbuf))
@@ -328,12 +362,22 @@ def render_bwd(params, cams, opts: RenderOptions, proj: Projected, pair_vals, ra
     d_rgb, d_depth, d_alpha = cont(d_rgb), cont(d_depth), cont(d_alpha)
     cams_c, opt_c, proj_c = L.make_cameras(cams), opts.c(), proj.c()
     _mark("bwd_begin")
+    main = torch.cuda.current_stream(dev)
+    before = torch.cuda.Event()
+    before.record(main)
     L.check(lib.gs_composite_bwd(C.byref(proj_c), _ptr(pair_vals), _ptr(ranges), cams_c, V, C.byref(opt_c), _ptr(T),
                                  _ptr(last), _ptr(d_rgb), _ptr(d_depth), _ptr(d_alpha), int(bool(opts.absgrad)), n * V,
                                  g2, seg_ptr, seg_bytes, seg_ready, _stream()))
+    # the gradient arrays are zeroed on a second stream beside the
+    # compositing backward (issue-bound, it leaves most of the memory
+    # bandwidth free; beside binning or the compositing forward the fill
+    # slows them by more than it saves); the projection backward then
+    # writes the seen Gaussians' rows only
+    grads, zeroed = _zeroed_grads(params, app, before, n)
     _mark("composite_bwd")
-    L.check(lib.gs_project_bwd(C.byref(g), cams_c, V, C.byref(opt_c), C.byref(proj_c), g2, C.byref(go), _ptr(norm),
-                               _ptr(absg), _stream()))
+    main.wait_event(zeroed)
+    L.check(lib.gs_project_bwd(C.byref(g), cams_c, V, C.byref(opt_c), C.byref(proj_c), g2, C.byref(_grad_struct(grads)),
+                               _ptr(norm), _ptr(absg), 1, _stream()))
     _mark("project_bwd")
     grads["mean2d_grad_norm"] = norm
     grads["absgrad"] = absg

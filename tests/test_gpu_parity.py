@@ -353,6 +353,44 @@ def test_backward_run_to_run_spread(gpu_lib):
     assert max(spread.values()) < 1e-6, spread
 
 
+def test_projection_backward_with_and_without_zeroed_outputs(gpu_lib):
+    """gs_project_bwd writing every row (zeros for Gaussians no view sees)
+    and, after gs_grads_zero, only the seen rows give the same gradients bit
+    for bit; the first overwrites outputs that held NaN."""
+    import ctypes as C
+    from paper_2507_23006_amd import _lib as L
+    from paper_2507_23006_amd.rasterizer import gaussians_struct
+    scene = S.random_scene(30000, seed=14, log_scale_mu=-3.0)
+    cams = [oblique_cam(160, 120, 400.0), oblique_cam(96, 80, 300.0)]     # narrow: about a quarter unseen
+    opts = gpu_lib.RenderOptions(aa=True)
+    params = to_dev(scene)
+    proj = gpu_lib.project(*params, cams, opts)
+    pairs, ranges, P = gpu_lib.bin_sort(proj, cams, scene.n)
+    out = gpu_lib.render_fwd(proj, pairs, ranges, cams, opts)
+    npx = sum(c.width * c.height for c in cams)
+    gen = torch.Generator(device="cuda").manual_seed(8)
+    d = [torch.randn(sh, device="cuda", generator=gen) for sh in ((npx, 3), (npx,), (npx,))]
+    ref = gpu_lib.render_bwd(params, cams, opts, proj, pairs, ranges, out["T"], out["last"], *d)
+    torch.cuda.synchronize()
+    seen = (proj.tiles.view(len(cams), -1) > 0).any(0)
+    assert 0 < int(seen.sum()) < scene.n
+    lib = L.load()
+    grads = {k: torch.full_like(ref[k], float("nan")) for k in ("means", "scales", "quats", "opacities", "sh")}
+    go = L.GsGaussiansGrad()
+    go.d_means, go.d_scales, go.d_quats = grads["means"].data_ptr(), grads["scales"].data_ptr(), grads["quats"].data_ptr()
+    go.d_opacities, go.d_sh = grads["opacities"].data_ptr(), grads["sh"].data_ptr()
+    norm = torch.empty((len(cams), scene.n), device="cuda")
+    g2 = gpu_lib.grad2d_view(ref)
+    L.check(lib.gs_project_bwd(C.byref(gaussians_struct(*params)), L.make_cameras(cams), len(cams),
+                               C.byref(opts.c()), C.byref(proj.c()), C.c_void_p(g2.data_ptr()), C.byref(go),
+                               C.c_void_p(norm.data_ptr()), None, 0,
+                               C.c_void_p(torch.cuda.current_stream().cuda_stream)))
+    torch.cuda.synchronize()
+    for k, t in grads.items():
+        assert torch.equal(t, ref[k]), k
+    assert torch.equal(norm, ref["mean2d_grad_norm"])
+
+
 def test_permutation_invariance_bitwise(gpu_lib):
     scene = S.random_scene(3000, seed=10, log_scale_mu=-2.7)
     cams = [oblique_cam(128, 96, 100.0)]

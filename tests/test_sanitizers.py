@@ -131,6 +131,9 @@ def test_library_host_code_under_asan_ubsan(tmp_path):
         # argument validation: malformed calls return errors without touching a device
         assert lib.gs_project(None, None, 0, None, None, None) == L.GS_ERR_INVALID_ARG
         assert lib.gs_lod_select(None, None, 0, None, None) == L.GS_ERR_INVALID_ARG
+        assert lib.gs_grads_zero(None, 0, None) == L.GS_ERR_INVALID_ARG
+        go = L.GsGaussiansGrad()
+        assert lib.gs_grads_zero(C.byref(go), 10, None) == L.GS_ERR_INVALID_ARG
         assert lib.gs_last_error()
         assert lib.gs_render_bwd_workspace_size(1000) > 0 and lib.gs_seg_workspace_size(100, 10000) > 0
         # server creation fails cleanly (no GPU here, or a bad configuration)
