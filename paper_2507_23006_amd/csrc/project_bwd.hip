@@ -70,13 +70,31 @@ constexpr int kSpan = kPB * kSpanPer;     // Gaussians per workgroup
 constexpr int kStageRows = 15;
 constexpr int kStageApp = 11;
 
-// full chain for one seen Gaussian g (local index loc of the span); vis =
-// mask of the views that see it.  Writes its SH coefficient gradients to
-// out.sh and the other gradients to the span's LDS rows `stage`.
+// Destinations of a seen Gaussian's one-float gradients, by row c (means
+// 0-2, scales 3-5, quats 6-9, opacity 10, appearance offsets 11-14): the
+// span's LDS rows, or the output arrays themselves
+struct StageRows {
+    float* s;
+    int loc;
+    __device__ void put(int c, float v) const { s[c * kSpan + loc] = v; }
+};
+struct OutRows {
+    const GradPtrs& out;
+    int64_t n, g;
+    __device__ void put(int c, float v) const {
+        float* p = c < 3 ? out.means + c * n + g : c < 6 ? out.scales + (c - 3) * n + g
+                 : c < 10 ? out.quats + (c - 6) * n + g : c == 10 ? out.opac + g : out.app + 4 * g + (c - kStageApp);
+        __builtin_nontemporal_store(v, p);
+    }
+};
+
+// full chain for one seen Gaussian g; vis = mask of the views that see it.
+// Writes its SH coefficient gradients to out.sh and the other gradients to
+// `rows`.
+template <class Rows>
 __device__ __forceinline__ void project_bwd_one(const GaussPtrs& gp, int64_t n, const ViewTable& vt,
                                                 const OptK& opt, const float* __restrict__ grad2d,
-                                                const GradPtrs& out, int64_t g, uint32_t vis, float* stage,
-                                                int loc) {
+                                                const GradPtrs& out, int64_t g, uint32_t vis, const Rows& rows) {
     const int nb = (opt.sh_degree + 1) * (opt.sh_degree + 1);
     const int nq = (3 * nb + 3) >> 2;    // float4s of a coefficient row in use
     const float4* shq = reinterpret_cast<const float4*>(gp.sh) + 12 * g;
@@ -124,43 +142,49 @@ __device__ __forceinline__ void project_bwd_one(const GaussPtrs& gp, int64_t n, 
             const float d0 = (float)(e0d * inv), d1 = (float)(e1d * inv), d2 = (float)(e2d * inv);
             float Y[16];
             sh_eval_basis<float>(d0, d1, d2, opt.sh_degree, Y);
-            float shv[48];
+            // one pass over the coefficient row gives the colour and, per
+            // channel c, S_c = sum_k sh_kc grad Y_k, so that the direction
+            // gradient is sum_c gr_c S_c and the row is not held in registers
+            // (coefficient e of the row is channel e % 3 of basis e / 3)
+            float raw[3] = {app.x, app.y, app.z};
+            float S[3][3] = {{0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f}};
 #pragma unroll
             for (int q = 0; q < 12; ++q) {
-                const float4 t = q < nq ? shq[q] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-                shv[4 * q + 0] = t.x; shv[4 * q + 1] = t.y; shv[4 * q + 2] = t.z; shv[4 * q + 3] = t.w;
-            }
-            float raw0 = app.x, raw1 = app.y, raw2 = app.z;
+                if (q < nq) {
+                    const float4 t = shq[q];
+                    const float tv[4] = {t.x, t.y, t.z, t.w};
 #pragma unroll
-            for (int k = 0; k < 16; ++k) {
-                if (k < nb) {
-                    raw0 = fmaf(shv[3 * k + 0], Y[k], raw0);
-                    raw1 = fmaf(shv[3 * k + 1], Y[k], raw1);
-                    raw2 = fmaf(shv[3 * k + 2], Y[k], raw2);
+                    for (int j = 0; j < 4; ++j) {
+                        const int k = (4 * q + j) / 3, c = (4 * q + j) % 3;
+                        if (k < nb) {
+                            raw[c] = fmaf(tv[j], Y[k], raw[c]);
+                            if (k > 0) {
+                                float bx, by, bz;
+                                sh_basis_grad(d0, d1, d2, k, bx, by, bz);
+                                S[c][0] = fmaf(tv[j], bx, S[c][0]);
+                                S[c][1] = fmaf(tv[j], by, S[c][1]);
+                                S[c][2] = fmaf(tv[j], bz, S[c][2]);
+                            }
+                        }
+                    }
                 }
             }
-            const float gr0 = raw0 < 0.0f ? 0.0f : g2[6];
-            const float gr1 = raw1 < 0.0f ? 0.0f : g2[7];
-            const float gr2 = raw2 < 0.0f ? 0.0f : g2[8];
-            dcb0 += gr0; dcb1 += gr1; dcb2 += gr2;
-            float e0 = 0.0f, e1 = 0.0f, e2 = 0.0f;
-            float dsh[48];
-#pragma unroll
-            for (int k = 0; k < 16; ++k) {
-                const float yk = k < nb ? Y[k] : 0.0f;
-                dsh[3 * k + 0] = gr0 * yk;
-                dsh[3 * k + 1] = gr1 * yk;
-                dsh[3 * k + 2] = gr2 * yk;
-                if (k > 0 && k < nb) {
-                    const float gk = gr0 * shv[3 * k + 0] + gr1 * shv[3 * k + 1] + gr2 * shv[3 * k + 2];
-                    float bx, by, bz;
-                    sh_basis_grad(d0, d1, d2, k, bx, by, bz);
-                    e0 = fmaf(gk, bx, e0); e1 = fmaf(gk, by, e1); e2 = fmaf(gk, bz, e2);
-                }
-            }
+            const float gr[3] = {raw[0] < 0.0f ? 0.0f : g2[6], raw[1] < 0.0f ? 0.0f : g2[7],
+                                 raw[2] < 0.0f ? 0.0f : g2[8]};
+            dcb0 += gr[0]; dcb1 += gr[1]; dcb2 += gr[2];
+            const float e0 = gr[0] * S[0][0] + gr[1] * S[1][0] + gr[2] * S[2][0];
+            const float e1 = gr[0] * S[0][1] + gr[1] * S[1][1] + gr[2] * S[2][1];
+            const float e2 = gr[0] * S[0][2] + gr[1] * S[1][2] + gr[2] * S[2][2];
+            // d sh_kc = gr_c Y_k, added to the earlier views' sums
 #pragma unroll
             for (int q = 0; q < 12; ++q) {
-                float4 t = make_float4(dsh[4 * q + 0], dsh[4 * q + 1], dsh[4 * q + 2], dsh[4 * q + 3]);
+                float d[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int k = (4 * q + j) / 3, c = (4 * q + j) % 3;
+                    d[j] = k < nb ? gr[c] * Y[k] : 0.0f;
+                }
+                float4 t = make_float4(d[0], d[1], d[2], d[3]);
                 if (!first && q < nq) {
                     const float4 p = dshq[q];
                     t.x += p.x; t.y += p.y; t.z += p.z; t.w += p.w;
@@ -274,23 +298,24 @@ __device__ __forceinline__ void project_bwd_one(const GaussPtrs& gp, int64_t n, 
     // normalisation q / |q|
     const double dot = dq[0] * w + dq[1] * x + dq[2] * y + dq[3] * z;
     const double qh[4] = {w, x, y, z};
-    for (int c = 0; c < 3; ++c) stage[c * kSpan + loc] = (float)dmu[c];
-    for (int c = 0; c < 3; ++c) stage[(3 + c) * kSpan + loc] = (float)ds[c];
-    for (int c = 0; c < 4; ++c) stage[(6 + c) * kSpan + loc] = (float)((dq[c] - qh[c] * dot) / qn);
+    for (int c = 0; c < 3; ++c) rows.put(c, (float)dmu[c]);
+    for (int c = 0; c < 3; ++c) rows.put(3 + c, (float)ds[c]);
+    for (int c = 0; c < 4; ++c) rows.put(6 + c, (float)((dq[c] - qh[c] * dot) / qn));
     // dop is the gradient with respect to o (1 - do)
-    stage[10 * kSpan + loc] = (float)(gp.app ? dop * (1.0 - (double)app.w) : dop);
+    rows.put(10, (float)(gp.app ? dop * (1.0 - (double)app.w) : dop));
     if (out.app) {
-        stage[(kStageApp + 0) * kSpan + loc] = dcb0;
-        stage[(kStageApp + 1) * kSpan + loc] = dcb1;
-        stage[(kStageApp + 2) * kSpan + loc] = dcb2;
-        stage[(kStageApp + 3) * kSpan + loc] = (float)(-dop * o_raw);
+        rows.put(kStageApp + 0, dcb0);
+        rows.put(kStageApp + 1, dcb1);
+        rows.put(kStageApp + 2, dcb2);
+        rows.put(kStageApp + 3, (float)(-dop * o_raw));
     }
 }
 
 
-// kZeroed: the gradient outputs already hold zeros (k_zero_grads, run
-// beside the compositing backward), so only the rows of Gaussians some view
-// sees are written
+// kZeroed: the gradient outputs already hold zeros (gs_grads_zero, run
+// beside the compositing backward), so only the entries of Gaussians some
+// view sees are written, straight from the chain (scattered either way):
+// no LDS rows, so more workgroups fit on a compute unit
 template <bool kZeroed>
 __global__ __launch_bounds__(kPB) void k_project_bwd(GaussPtrs gp, int64_t n, ViewTable vt, OptK opt,
                                                      Projected proj, const float* __restrict__ grad2d, GradPtrs out,
@@ -300,7 +325,7 @@ __global__ __launch_bounds__(kPB) void k_project_bwd(GaussPtrs gp, int64_t n, Vi
     __shared__ uint32_t s_count;
     // the span's gradient rows: zeros, then the chain's values, then one
     // coalesced write of every row (each cache line written once, whole)
-    __shared__ float s_grad[kStageRows * kSpan];
+    __shared__ float s_grad[kZeroed ? 1 : kStageRows * kSpan];
     const int tid = threadIdx.x, lane = tid & 63;
     const int64_t g0 = (int64_t)blockIdx.x * kSpan;
     if (tid == 0) s_count = 0;
@@ -358,28 +383,16 @@ __global__ __launch_bounds__(kPB) void k_project_bwd(GaussPtrs gp, int64_t n, Vi
     const uint32_t cnt = s_count;
     for (uint32_t j = tid; j < cnt; j += kPB) {
         const uint32_t e = s_list[j];
-        project_bwd_one(gp, n, vt, opt, grad2d, out, g0 + (e & 0xFFFFu), e >> 16, s_grad, (int)(e & 0xFFFFu));
+        const int64_t g = g0 + (e & 0xFFFFu);
+        if (kZeroed)
+            project_bwd_one(gp, n, vt, opt, grad2d, out, g, e >> 16, OutRows{out, n, g});
+        else
+            project_bwd_one(gp, n, vt, opt, grad2d, out, g, e >> 16, StageRows{s_grad, (int)(e & 0xFFFFu)});
     }
+    if (kZeroed) return;
     __syncthreads();
 
-    // pass 3: the span's rows, streamed out (not read again here); with
-    // zeroed outputs the seen Gaussians' entries only
-    if (kZeroed) {
-        for (uint32_t j = tid; j < cnt; j += kPB) {
-            const int loc = (int)(s_list[j] & 0xFFFFu);
-            const int64_t g = g0 + loc;
-            for (int c = 0; c < 11; ++c) {
-                float* row = c < 3 ? out.means + c * n : c < 6 ? out.scales + (c - 3) * n
-                           : c < 10 ? out.quats + (c - 6) * n : out.opac;
-                __builtin_nontemporal_store(s_grad[c * kSpan + loc], row + g);
-            }
-            if (out.app)
-                __builtin_nontemporal_store(F4{s_grad[(kStageApp + 0) * kSpan + loc], s_grad[(kStageApp + 1) * kSpan + loc],
-                                               s_grad[(kStageApp + 2) * kSpan + loc], s_grad[(kStageApp + 3) * kSpan + loc]},
-                                            reinterpret_cast<F4*>(out.app) + g);
-        }
-        return;
-    }
+    // pass 3: the span's rows, streamed out (not read again here)
     for (int c = 0; c < 11; ++c) {
         float* row = c < 3 ? out.means + c * n : c < 6 ? out.scales + (c - 3) * n
                    : c < 10 ? out.quats + (c - 6) * n : out.opac;
