@@ -39,10 +39,10 @@ __device__ __forceinline__ void view_point(const ViewK& V, double mu0, double mu
     tz = (double)V.R[6] * mu0 + (double)V.R[7] * mu1 + (double)V.R[8] * mu2 + (double)V.t[2];
 }
 
-// M = R(q) diag(s) and the opacity of Gaussian g (times 1 - do under
-// appearance offsets); false for a zero quaternion
-__device__ __forceinline__ bool load_shape(const GaussPtrs& gp, int64_t n, int64_t g, double M[9], double& opac) {
-    const double s0 = gp.scales[g], s1 = gp.scales[n + g], s2 = gp.scales[2 * n + g];
+// M = R(q) diag(s) of Gaussian g with scales s0..s2, and its opacity op
+// (times 1 - do under appearance offsets); false for a zero quaternion
+__device__ __forceinline__ bool load_shape(const GaussPtrs& gp, int64_t n, int64_t g, double s0, double s1, double s2,
+                                           double op, double M[9], double& opac) {
     double qw = gp.quats[g], qx = gp.quats[n + g], qy = gp.quats[2 * n + g], qz = gp.quats[3 * n + g];
     const double qn = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
     if (!(qn > 0.0)) return false;
@@ -52,7 +52,7 @@ __device__ __forceinline__ bool load_shape(const GaussPtrs& gp, int64_t n, int64
     M[0] = Rq[0] * s0; M[1] = Rq[1] * s1; M[2] = Rq[2] * s2;
     M[3] = Rq[3] * s0; M[4] = Rq[4] * s1; M[5] = Rq[5] * s2;
     M[6] = Rq[6] * s0; M[7] = Rq[7] * s1; M[8] = Rq[8] * s2;
-    opac = gp.opac[g];
+    opac = op;
     if (gp.app) opac *= 1.0 - (double)gp.app[4 * g + 3];
     return true;
 }
@@ -101,11 +101,12 @@ __device__ uint64_t covered_tiles(const ViewK& V, double mx, double my, double A
 }
 
 // 2D Gaussian of (t, M, opac) in view V: writes the record's geometry words
-// (float4s 0, 1, 3 and the .w of 2) and the rectangle of `slot`; returns the
-// number of tiles covered, 0 when culled
+// (float4s 0, 1 and 3; the .w of float4 2 is returned in yfrac for the
+// colour's write) and the rectangle of `slot`; returns the number of tiles
+// covered, 0 when culled
 __device__ __forceinline__ uint32_t project_view(const ViewK& V, const OptK& opt, double tx, double ty, double tz,
                                                  const double M[9], double opac, const Projected& out,
-                                                 int64_t slot) {
+                                                 int64_t slot, float& yfrac) {
     const double W0 = V.R[0], W1 = V.R[1], W2 = V.R[2], W3 = V.R[3], W4 = V.R[4], W5 = V.R[5], W6 = V.R[6],
                  W7 = V.R[7], W8 = V.R[8];
     const double fx = V.fx, fy = V.fy;
@@ -181,18 +182,19 @@ __device__ __forceinline__ uint32_t project_view(const ViewK& V, const OptK& opt
     const double fmx = floor(mx), fmy = floor(my);
     out.rec[4 * slot + 0] = make_float4((float)fmx, (float)fmy, (float)(-0.5 * kLog2e * A), (float)(-kLog2e * B));
     out.rec[4 * slot + 1] = make_float4((float)(-0.5 * kLog2e * C), (float)(opac * rho), (float)tz, (float)(mx - fmx));
-    out.rec[4 * slot + 2].w = (float)(my - fmy);
+    yfrac = (float)(my - fmy);
     out.rec[4 * slot + 3] = make_float4((float)hxd, (float)hyd, 0.0f, 0.0f);
     out.rect[slot] = make_uint2((uint32_t)(V.tile_off + iy0 * TW + ix0), (uint32_t)w | ((uint32_t)TW << 16));
     return covered;
 }
 
 // view-dependent colour of a mean seen by V into the record's .xyz of
-// float4 2; the coefficient row is read as 16-byte vectors; cb is the
-// constant of the polynomial (1/2, or the appearance colour offset)
+// float4 2 (written whole, with yfrac as its .w); the coefficient row is
+// read as 16-byte vectors; cb is the constant of the polynomial (1/2, or
+// the appearance colour offset)
 __device__ __forceinline__ void colour_view(const ViewK& V, const OptK& opt, double mu0, double mu1, double mu2,
                                             const float4* __restrict__ shq, float4 cb, const Projected& out,
-                                            int64_t slot) {
+                                            int64_t slot, float yfrac) {
     const int nb = (opt.sh_degree + 1) * (opt.sh_degree + 1);
     const int nq = (3 * nb + 3) >> 2;    // float4s that hold the used coefficients
     // direction in FP64 (mu and the camera centre are large numbers), the
@@ -216,11 +218,7 @@ __device__ __forceinline__ void colour_view(const ViewK& V, const OptK& opt, dou
             c[2] = fmaf(shv[3 * k + 2], Y[k], c[2]);
         }
     }
-    float4 r2 = out.rec[4 * slot + 2];
-    r2.x = fmaxf(c[0], 0.0f);
-    r2.y = fmaxf(c[1], 0.0f);
-    r2.z = fmaxf(c[2], 0.0f);
-    out.rec[4 * slot + 2] = r2;
+    out.rec[4 * slot + 2] = make_float4(fmaxf(c[0], 0.0f), fmaxf(c[1], 0.0f), fmaxf(c[2], 0.0f), yfrac);
 }
 
 // Conservative pre-test of project_view: false only when the Gaussian
@@ -244,30 +242,30 @@ __device__ __forceinline__ bool may_cover(const ViewK& V, const OptK& opt, doubl
            fmy - rb <= (double)(V.tiles_y * kTile - 1);
 }
 
-// exact projection and colour of Gaussian g into the views of `cand`; slot
-// of view v = slot_base + v * slot_stride
+// exact projection and colour of Gaussian g (mean mu, scales s, opacity
+// op, as stored) into the views of `cand`; slot of view v = slot_base +
+// v * slot_stride
 __device__ __forceinline__ void project_candidate(const GaussPtrs& gp, int64_t n, const ViewTable& vt,
                                                   const OptK& opt, const Projected& out, int64_t g, uint32_t cand,
-                                                  int64_t slot_base, int64_t slot_stride) {
-    const double mu0 = gp.means[g], mu1 = gp.means[n + g], mu2 = gp.means[2 * n + g];
+                                                  int64_t slot_base, int64_t slot_stride, const float mu[3],
+                                                  const float sc[3], float op) {
+    const double mu0 = mu[0], mu1 = mu[1], mu2 = mu[2];
     double M[9], opac = 0.0;
-    const bool shape_ok = load_shape(gp, n, g, M, opac);
-    uint32_t vis = 0;
+    const bool shape_ok = load_shape(gp, n, g, sc[0], sc[1], sc[2], op, M, opac);
+    const float4* shq = reinterpret_cast<const float4*>(gp.sh) + 12 * g;
+    const float4 cb = gp.app ? reinterpret_cast<const float4*>(gp.app)[g] : make_float4(0.5f, 0.5f, 0.5f, 0.0f);
     for (int v = 0; v < vt.n_views; ++v) {
         if (!(cand & (1u << v))) continue;
         const ViewK& V = vt.v[v];
         const int64_t slot = slot_base + v * slot_stride;
         double tx, ty, tz;
         view_point(V, mu0, mu1, mu2, tx, ty, tz);
-        const uint32_t ntiles = shape_ok ? project_view(V, opt, tx, ty, tz, M, opac, out, slot) : 0u;
-        if (ntiles) vis |= 1u << v;
+        float yfrac = 0.0f;
+        const uint32_t ntiles = shape_ok ? project_view(V, opt, tx, ty, tz, M, opac, out, slot, yfrac) : 0u;
+        if (ntiles) colour_view(V, opt, mu0, mu1, mu2, shq, cb, out, slot, yfrac);
         out.tiles[slot] = ntiles;
         out.dkey[slot] = ntiles ? __float_as_uint((float)tz) : 0xFFFFFFFFu;
     }
-    const float4* shq = reinterpret_cast<const float4*>(gp.sh) + 12 * g;
-    const float4 cb = gp.app ? reinterpret_cast<const float4*>(gp.app)[g] : make_float4(0.5f, 0.5f, 0.5f, 0.0f);
-    for (int v = 0; v < vt.n_views; ++v)
-        if (vis & (1u << v)) colour_view(vt.v[v], opt, mu0, mu1, mu2, shq, cb, out, slot_base + v * slot_stride);
 }
 
 constexpr int kPF = 256;                 // threads per workgroup
@@ -290,13 +288,15 @@ __device__ __forceinline__ void list_append(uint32_t cand, int loc, int lane, ui
 // A workgroup owns 1024 Gaussians.  Pass 1 reads each mean (and, for
 // Gaussians in front of some camera, its scales and opacity), runs the
 // conservative pre-test per view, writes the culled slots' count and key
-// with coalesced stores and lists the rest in LDS; pass 2 runs the FP64 EWA
-// and the colour on full waves of listed Gaussians only (a large scene
-// leaves most lanes culled, which would otherwise idle through the FP64
-// chain of their wave's few visible neighbours).
-__global__ __launch_bounds__(kPF) void k_project_fwd(GaussPtrs gp, int64_t n, ViewTable vt, OptK opt,
+// with coalesced stores and lists the rest in LDS with the values it read;
+// pass 2 runs the FP64 EWA and the colour on full waves of listed Gaussians
+// only (a large scene leaves most lanes culled, which would otherwise idle
+// through the FP64 chain of their wave's few visible neighbours), reading
+// from HBM only their quaternions and coefficient rows.
+__global__ __launch_bounds__(kPF, 4) void k_project_fwd(GaussPtrs gp, int64_t n, ViewTable vt, OptK opt,
                                                      Projected out) {
     __shared__ uint32_t s_list[kPFSpan];
+    __shared__ float s_par[7][kPFSpan];     // listed Gaussians' mean, scales, opacity
     __shared__ uint32_t s_count;
     const int tid = threadIdx.x, lane = tid & 63;
     const int64_t g0 = (int64_t)blockIdx.x * kPFSpan;
@@ -327,14 +327,15 @@ __global__ __launch_bounds__(kPF) void k_project_fwd(GaussPtrs gp, int64_t n, Vi
             if (tz >= (double)V.znear && tz <= (double)V.zfar) front[i] |= 1u << v;
         }
     }
-    float sm[kPFPer], op[kPFPer];
+    float sc[kPFPer][3], op[kPFPer];
 #pragma unroll
     for (int i = 0; i < kPFPer; ++i) {
         const int64_t g = g0 + i * kPF + tid;
-        sm[i] = 0.0f;
-        op[i] = 0.0f;
+        sc[i][0] = sc[i][1] = sc[i][2] = op[i] = 0.0f;
         if (front[i]) {
-            sm[i] = fmaxf(fabsf(gp.scales[g]), fmaxf(fabsf(gp.scales[n + g]), fabsf(gp.scales[2 * n + g])));
+            sc[i][0] = gp.scales[g];
+            sc[i][1] = gp.scales[n + g];
+            sc[i][2] = gp.scales[2 * n + g];
             op[i] = gp.opac[g];
         }
     }
@@ -348,13 +349,19 @@ __global__ __launch_bounds__(kPF) void k_project_fwd(GaussPtrs gp, int64_t n, Vi
                 if (front[i] & (1u << v)) {
                     double tx, ty, tz;
                     view_point(V, mu[i][0], mu[i][1], mu[i][2], tx, ty, tz);
-                    if (may_cover(V, opt, tx, ty, tz, (double)sm[i], op[i])) cand |= 1u << v;
+                    const float sm = fmaxf(fabsf(sc[i][0]), fmaxf(fabsf(sc[i][1]), fabsf(sc[i][2])));
+                    if (may_cover(V, opt, tx, ty, tz, (double)sm, op[i])) cand |= 1u << v;
                 }
                 if (!(cand & (1u << v))) {
                     const int64_t slot = (int64_t)v * n + g;
                     __builtin_nontemporal_store(0u, out.tiles + slot);
                     __builtin_nontemporal_store(0xFFFFFFFFu, out.dkey + slot);
                 }
+            }
+            if (cand) {
+                s_par[0][loc] = mu[i][0]; s_par[1][loc] = mu[i][1]; s_par[2][loc] = mu[i][2];
+                s_par[3][loc] = sc[i][0]; s_par[4][loc] = sc[i][1]; s_par[5][loc] = sc[i][2];
+                s_par[6][loc] = op[i];
             }
         }
         list_append(cand, loc, lane, s_list, &s_count);
@@ -363,8 +370,10 @@ __global__ __launch_bounds__(kPF) void k_project_fwd(GaussPtrs gp, int64_t n, Vi
     const uint32_t cnt = s_count;
     for (uint32_t j = tid; j < cnt; j += kPF) {
         const uint32_t e = s_list[j];
-        const int64_t g = g0 + (e & 0xFFFFu);
-        project_candidate(gp, n, vt, opt, out, g, e >> 16, g, n);
+        const int loc = (int)(e & 0xFFFFu);
+        const float mu[3] = {s_par[0][loc], s_par[1][loc], s_par[2][loc]};
+        const float sc[3] = {s_par[3][loc], s_par[4][loc], s_par[5][loc]};
+        project_candidate(gp, n, vt, opt, out, g0 + loc, e >> 16, g0 + loc, n, mu, sc, s_par[6][loc]);
     }
 }
 
@@ -420,7 +429,9 @@ __global__ __launch_bounds__(kPF) void k_project_slots(GaussPtrs gp, int64_t n, 
         const SlotSeg sg = segs[segment_of(segs, n_seg, s)];
         const int64_t g = sg.gstart + (int64_t)(s - sg.slot_start);
         // one view bit: the slot is s itself (stride 0)
-        project_candidate(gp, n, vt, opt, out, g, e >> 16, (int64_t)s, 0);
+        const float mu[3] = {gp.means[g], gp.means[n + g], gp.means[2 * n + g]};
+        const float sc[3] = {gp.scales[g], gp.scales[n + g], gp.scales[2 * n + g]};
+        project_candidate(gp, n, vt, opt, out, g, e >> 16, (int64_t)s, 0, mu, sc, gp.opac[g]);
     }
 }
 
