@@ -964,48 +964,53 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* s_wave
 // One workgroup: segments per tile in launch order (ceil(L / kSegLen) for a
 // list of L > kSegLen positions, else 1) and the stored states (segments
 // 1 .. n - 1); exclusive prefix sums into work_off / state_off.  When the
-// states would exceed `capacity`, every tile keeps a single segment.
+// states would exceed `capacity`, every tile keeps a single segment.  Thread
+// t takes the consecutive positions [t k, t k + k), so the prefix sums need
+// one workgroup scan of the threads' totals, not one per 1024 tiles; the
+// counts of up to kPlanCache tiles stay in LDS between the two passes.
+constexpr uint32_t kPlanCache = 32640;
 __global__ __launch_bounds__(1024) void k_seg_plan(const uint2* __restrict__ ranges,
                                                    const uint32_t* __restrict__ tile_order, ViewTable vt,
                                                    uint32_t capacity, uint32_t* __restrict__ work_off,
                                                    uint32_t* __restrict__ state_off) {
     __shared__ uint32_t s_wave[16];
-    __shared__ uint32_t s_flag;
+    __shared__ uint16_t s_nseg[kPlanCache];
     const uint32_t n_tiles = (uint32_t)vt.total_tiles;
     auto nseg_of = [&](uint32_t i) -> uint32_t {
         const uint2 r = ranges[order_tile(tile_order, vt, i)];
         const uint32_t L = r.y - r.x;
         return L > (uint32_t)kSegLen ? (L + kSegLen - 1) / kSegLen : 1u;
     };
-    // pass 1: do the states fit?
-    uint32_t need = 0;
-    for (uint32_t i = threadIdx.x; i < n_tiles; i += 1024) need += nseg_of(i) - 1u;
-    uint32_t total_need = 0;
-    (void)block_excl_scan(need, s_wave, &total_need);
-    const bool on = total_need <= capacity;
-    // pass 2: prefix sums
-    if (threadIdx.x == 0) s_flag = 0;
-    uint32_t base_w = 0, base_s = 0;
-    for (uint32_t c0 = 0; c0 < n_tiles; c0 += 1024) {
-        const uint32_t i = c0 + threadIdx.x;
-        uint32_t nw = 0, ns = 0;
-        if (i < n_tiles) {
-            nw = on ? nseg_of(i) : 1u;
-            ns = nw - 1u;
-        }
-        uint32_t tw = 0, ts = 0;
-        const uint32_t ew = block_excl_scan(nw, s_wave, &tw);
-        const uint32_t es = block_excl_scan(ns, s_wave, &ts);
-        if (i < n_tiles) {
-            work_off[i] = base_w + ew;
-            state_off[i] = base_s + es;
-        }
-        base_w += tw;
-        base_s += ts;
+    const uint32_t k = (n_tiles + 1023) / 1024;
+    const uint32_t i0 = threadIdx.x * k, i1 = min(i0 + k, n_tiles);
+    // pass 1: the thread's segment total (cached counts below 2^16)
+    uint32_t mine = 0, big = 0;
+    for (uint32_t i = i0; i < i1; ++i) {
+        const uint32_t c = nseg_of(i);
+        mine += c;
+        if (i < kPlanCache) s_nseg[i] = (uint16_t)c;
+        big |= c > 0xFFFFu ? 1u : 0u;
     }
-    if (threadIdx.x == 0) {
-        work_off[n_tiles] = base_w;
-        state_off[n_tiles] = base_s;
+    // the threads' prefix and the total (do the states fit?), and whether
+    // any count was too large for the cache
+    uint32_t total_seg = 0, total_big = 0;
+    const uint32_t before_seg = block_excl_scan(mine, s_wave, &total_seg);
+    (void)block_excl_scan(big, s_wave, &total_big);      // its barriers also publish s_nseg
+    const uint32_t total_need = total_seg - n_tiles;
+    const bool on = total_need <= capacity;
+    const bool cached = total_big == 0;
+    // pass 2: each position's offsets from the thread's exclusive prefix
+    uint32_t w = on ? before_seg : i0, st = on ? before_seg - i0 : 0u;
+    for (uint32_t i = i0; i < i1; ++i) {
+        const uint32_t c = on ? (cached && i < kPlanCache ? (uint32_t)s_nseg[i] : nseg_of(i)) : 1u;
+        work_off[i] = w;
+        state_off[i] = st;
+        w += c;
+        st += c - 1u;
+    }
+    if (threadIdx.x == 1023) {
+        work_off[n_tiles] = on ? total_seg : n_tiles;
+        state_off[n_tiles] = on ? total_need : 0u;
     }
 }
 

@@ -515,6 +515,13 @@ def test_segmented_backward_matches_whole_lists(gpu_lib):
         assert np.abs(a1 - a2)[~moved].max() <= tol * scale, k
         if moved.any():
             assert np.abs(a1 - a2)[moved].max() <= 1e-3 * scale, k
+    # an area with room for one segment state: the plan keeps every list
+    # whole, and the images are those of the plain forward bit for bit
+    small = torch.empty(lib.gs_seg_workspace_size(cam.n_tiles, 0) + 256, dtype=torch.uint8, device="cuda")
+    out3 = gpu_lib.render_fwd(proj, pairs, ranges, [cam], opts, seg=small)
+    torch.cuda.synchronize()
+    for k in ("rgb", "depth", "alpha", "T", "last"):
+        assert torch.equal(out[k], out3[k]), k
     res = []
     # (segmented, AbsGS sums, states from the segmented forward, forward used)
     runs = ((False, 1, 0, out), (True, 1, 0, out), (True, 0, 0, out), (True, 1, 1, out2), (True, 1, 0, out2))
