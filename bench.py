@@ -253,27 +253,29 @@ def main():
         loss.backward()
         return loss
 
-    # stage timing with stream events between the library calls, and the
-    # library's own events around each main kernel
+    # the timed steps alone: W untimed steps, then K steps between two
+    # synchronisations (one event per step boundary for the percentiles)
+    ms_step, per_step = step_times(torch, step, args.steps, args.warmup)
+
+    # then, outside the timed region, stage times from stream events between
+    # the library calls and the library's own events around each main
+    # kernel, over a separate run of at most 20 steps (an event per stage
+    # and step held until the end of a long run makes the runtime stall
+    # now and then, which the timed run must not see)
+    n_inst = min(args.steps, 20)
     marks = []
 
     def hook(name):
         marks.append((name, _ev(torch)))
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-
     gs.set_stage_hook(hook)
     gs.kernel_timing(True)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(n_inst):
         marks.append(("start", _ev(torch)))
         step()
     marks.append(("start", _ev(torch)))
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
     gs.set_stage_hook(None)
     kernel_ms = {}
     for k in gs.rasterizer.KERNELS_TIMED:
@@ -281,21 +283,16 @@ def main():
         if cnt:
             kernel_ms[k] = tot / cnt
     gs.kernel_timing(False)
-    stage_ms, per_step, prev, start = {}, [], None, None
+    stage_ms, prev = {}, None
     for name, ev in marks:
-        if name == "start":
-            if start is not None:
-                per_step.append(start.elapsed_time(ev))
-            start = ev
         if prev is not None and name != "start":
             stage_ms[name] = stage_ms.get(name, 0.0) + prev.elapsed_time(ev)
         prev = ev
     for k in stage_ms:
-        stage_ms[k] /= args.steps
+        stage_ms[k] /= n_inst
     # the interval ending at bwd_begin is the loss (torch ops between the two passes)
     if "bwd_begin" in stage_ms:
         stage_ms["loss"] = stage_ms.pop("bwd_begin")
-    ms_step = (t1 - t0) * 1000.0 / args.steps
 
     # forward-only render rate
     with torch.no_grad():

@@ -334,8 +334,12 @@ def _zeroed_grads(params, app, after: torch.cuda.Event, n: int):
         grads["app"] = torch.empty_like(app)
     side = _side_stream(dev)
     side.wait_event(after)
-    for t in grads.values():
-        t.record_stream(side)
+    # no record_stream: the caller's stream waits for `zeroed` before its
+    # next launch, so the arrays (allocated on that stream, whose later
+    # allocations alone can reuse their memory) are never reused under the
+    # fill; recorded, their blocks would be held back from the allocator
+    # until it saw the fill done, and a step allocating before that would
+    # take fresh device memory
     L.check(lib.gs_grads_zero(C.byref(_grad_struct(grads)), n, C.c_void_p(side.cuda_stream)))
     zeroed = torch.cuda.Event()
     zeroed.record(side)
