@@ -626,7 +626,8 @@ def serve_bench(gs, S, torch, fine, opts, n_requests, modes=None, loads=("", "_8
                      "mean_ms": round(st["mean_ms"], 3), "max_ms": round(st["max_ms"], 3),
                      "req_per_s": round(st["req_per_s"], 2), "mpix_per_s": round(st["mpix_per_s"], 1),
                      "mean_batch_views": round(st["mean_batch_views"], 3), "batches": st["batches"],
-                     "split_batches": st["split_batches"], "est_over_actual": round(st["est_over_actual"], 3),
+                     "split_batches": st["split_batches"], "rebinned_batches": st["rebinned_batches"],
+                     "est_over_actual": round(st["est_over_actual"], 3),
                      "completed": st["completed"], "failed": st["failed"]}
         print(f"# {name}: {res[name]}", file=sys.stderr, flush=True)
     res["trace"] = (f"{len(trace)} requests, Poisson {len(trace) / trace[-1]['t']:.0f} req/s over "

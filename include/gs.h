@@ -556,6 +556,8 @@ typedef struct gs_serve_stats {
     double req_per_s, mpix_per_s;  /* over span_s */
     int64_t split_batches;         /* batches re-rendered in halves after a pair overflow */
     double est_over_actual;        /* mean over admitted batches of estimated / rendered pairs */
+    int64_t rebinned_batches;      /* batches binned again with the whole pair buffer after their
+                                      estimate-sized bound (1.5 x estimate + 4096) fell short */
 } gs_serve_stats;
 
 typedef struct gs_server gs_server;

@@ -98,7 +98,7 @@ class GsServeStats(C.Structure):
                 ("mean_batch_views", C.c_double), ("p50_ms", C.c_double), ("p99_ms", C.c_double),
                 ("mean_ms", C.c_double), ("max_ms", C.c_double), ("span_s", C.c_double),
                 ("req_per_s", C.c_double), ("mpix_per_s", C.c_double), ("split_batches", C.c_int64),
-                ("est_over_actual", C.c_double)]
+                ("est_over_actual", C.c_double), ("rebinned_batches", C.c_int64)]
 
 
 # exported symbols and their ctypes signatures

@@ -215,6 +215,7 @@ struct BufSet {
     // the batch in flight
     std::vector<Request> reqs;
     int64_t slots = 0;
+    int64_t pair_bound = 0;             // the binning's pair bound for this batch
     double est_pairs = 0.0, t_start = 0.0;
     int rc = GS_OK;
 };
@@ -251,7 +252,8 @@ struct gs_server {
     std::condition_variable done_cv;
     std::deque<gs_completion> done;
     std::vector<double> lat_ms;
-    int64_t completed = 0, failed = 0, batches = 0, batch_views = 0, pixels = 0, split_batches = 0;
+    int64_t completed = 0, failed = 0, batches = 0, batch_views = 0, pixels = 0, split_batches = 0,
+            rebinned_batches = 0;
     double first_arrival = INFINITY, last_done = 0.0, est_over_actual = 0.0;
     int64_t est_batches = 0;
 
@@ -264,6 +266,12 @@ namespace {
 
 // headroom of the admission estimate over the learned ratio
 constexpr double kAdmitMargin = 1.15;
+// a batch bins with a pair bound of its estimate times kBoundMargin plus
+// kBoundFloor (at most the pair capacity): the binning launches are sized
+// by that bound, so a lone small request does not pay for grids sized for
+// the whole pair buffer; a count above it re-bins at the full capacity
+constexpr double kBoundMargin = 1.5;
+constexpr int64_t kBoundFloor = 4096;
 constexpr double kDefaultPairsPerGaussian = 8.0;
 
 uint64_t view_class(const gs_camera& c) { return ((uint64_t)(uint32_t)c.width << 32) | (uint32_t)c.height; }
@@ -376,7 +384,7 @@ int alloc_worker(gs_server* s, Worker* w) {
 // binning on the prep stream, compositing and the copies into the callers'
 // images on the render stream (after each request's ready event).  Returns
 // without waiting; b.done marks the end of the batch's work.
-int launch_batch(Worker* w, BufSet& b, Request* r, int nb) {
+int launch_batch(Worker* w, BufSet& b, Request* r, int nb, bool full_bound = false) {
     gs_server* s = w->srv;
     gs_camera cams[GS_MAX_VIEWS];
     for (int i = 0; i < nb; ++i) cams[i] = r[i].cam;
@@ -398,10 +406,20 @@ int launch_batch(Worker* w, BufSet& b, Request* r, int nb) {
         }
     if (slots > s->cfg.slot_capacity) return fail(GS_ERR_CAPACITY, "batch selects %lld Gaussians", (long long)slots);
     b.slots = slots;
+    b.pair_bound = s->cfg.pair_capacity;
+    if (!full_bound) {
+        double est = 0.0;
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            for (int i = 0; i < nb; ++i) est += estimate_pairs(s, r[i]);
+        }
+        const double bound = est * kBoundMargin + (double)kBoundFloor;
+        if (bound < (double)b.pair_bound) b.pair_bound = (int64_t)bound;
+    }
     if (slots > 0) {
         GS_HIP(hipMemcpyAsync(b.segs_dev, b.segs_host, (size_t)ns * sizeof(SlotSeg), hipMemcpyHostToDevice, w->prep));
         GS_HIP(launch_project_slots(s->gp, s->n, vt, s->opt, b.segs_dev, ns, (uint32_t)slots, b.proj, w->prep));
-        rc = bin_sort_slots(b.proj, vt, slots, s->cfg.pair_capacity, b.pairs, b.ranges, b.npairs_dev, b.bin_ws,
+        rc = bin_sort_slots(b.proj, vt, slots, b.pair_bound, b.pairs, b.ranges, b.npairs_dev, b.bin_ws,
                             b.bin_ws_bytes, w->prep);
         if (rc) return rc;
         GS_HIP(hipEventRecord(b.prepped, w->prep));
@@ -434,7 +452,7 @@ int launch_batch(Worker* w, BufSet& b, Request* r, int nb) {
 }
 
 // Waits for the batch in b; *n_pairs gets its pair count.  GS_ERR_CAPACITY
-// when the pairs overflowed the buffer (the lists were left empty).
+// when the pairs overflowed the batch's bound (the lists were left empty).
 int wait_batch(Worker* w, BufSet& b, int launch_rc, int64_t* n_pairs) {
     gs_server* s = w->srv;
     *n_pairs = 0;
@@ -447,9 +465,9 @@ int wait_batch(Worker* w, BufSet& b, int launch_rc, int64_t* n_pairs) {
     GS_HIP(hipEventSynchronize(b.done));
     if (b.slots > 0) {
         *n_pairs = *b.npairs_host;
-        if (*n_pairs > s->cfg.pair_capacity)
-            return fail(GS_ERR_CAPACITY, "batch needs %lld pairs (capacity %lld)", (long long)*n_pairs,
-                        (long long)s->cfg.pair_capacity);
+        if (*n_pairs > b.pair_bound)
+            return fail(GS_ERR_CAPACITY, "batch needs %lld pairs (bound %lld, capacity %lld)", (long long)*n_pairs,
+                        (long long)b.pair_bound, (long long)s->cfg.pair_capacity);
     }
     return GS_OK;
 }
@@ -505,6 +523,21 @@ void settle(Worker* w, BufSet& b, Request* r, int nb, int launch_rc, double t_st
     if (n_pairs > 0) {
         if (est > 0.0) note_estimate(s, est, n_pairs);
         learn_pairs(s, r, nb, n_pairs);
+    }
+    if (rc == GS_ERR_CAPACITY && n_pairs > 0 && n_pairs <= s->cfg.pair_capacity && b.pair_bound < s->cfg.pair_capacity) {
+        // the estimate fell short of the count: bin again with the whole buffer
+        {
+            std::lock_guard<std::mutex> lk(s->done_mu);
+            s->rebinned_batches += 1;
+        }
+        int lrc;
+        try {
+            lrc = launch_batch(w, b, r, nb, /*full_bound=*/true);
+        } catch (...) {
+            lrc = GS_ERR_INTERNAL;
+        }
+        settle(w, b, r, nb, lrc, t_start, -1.0);
+        return;
     }
     if (rc == GS_ERR_CAPACITY && nb > 1) {
         {
@@ -782,6 +815,7 @@ int gs_serve_stats_get(gs_server* s, gs_serve_stats* o) {
         o->batches = s->batches;
         o->mean_batch_views = s->batches ? (double)s->batch_views / s->batches : 0.0;
         o->split_batches = s->split_batches;
+        o->rebinned_batches = s->rebinned_batches;
         o->est_over_actual = s->est_batches ? s->est_over_actual / (double)s->est_batches : 0.0;
         if (!s->lat_ms.empty()) {
             std::vector<double> v = s->lat_ms;

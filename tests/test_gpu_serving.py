@@ -151,6 +151,16 @@ def test_admission_splits_batches_and_reports_errors(lod_setup):
     assert c4[0]["n_pairs"] == sum(c["n_pairs"] for c in c1[:k]) <= cap
     for a, b in zip(alone, seeded):
         assert torch.equal(a, b)
+    # an estimate far below the counts: each request's estimate-sized pair
+    # bound overflows and the batch is binned again with the whole buffer
+    # (until the learned ratio catches up); the images are unchanged
+    cfg = gs.ServeConfig(max_views_per_batch=1, n_streams=1, pipeline_depth=1, pairs_per_gaussian=1e-3, **CAPS)
+    low, c6, st6 = serve(gs, params, table, opts, reqs, cfg)
+    assert all(c["status"] == 0 for c in c6) and st6["split_batches"] == 0
+    assert max(c["n_pairs"] for c in c1) > 1.5 * 1e-3 * max(c["n_gaussians"] for c in c1) + 4096
+    assert st6["rebinned_batches"] >= 1
+    for a, b in zip(alone, low):
+        assert torch.equal(a, b)
     # a pool smaller than the largest single request: that request fails alone
     big = int(np.argmax([c["n_pairs"] for c in c1]))
     cfg = gs.ServeConfig(max_views_per_batch=4, n_streams=1, slot_capacity=1_000_000, pair_capacity=max(1, pmax - 1),
