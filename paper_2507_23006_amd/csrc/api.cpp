@@ -259,19 +259,23 @@ int bin_sort_slots(const Projected& pr, const ViewTable& vt, int64_t n_slots, in
     GS_HIP(launch_compact_visible(pr, w.offsets, N, w.dkeys, w.dvals, w.desc, s));
     // 2. depth order of the visible slots (stable: ties stay in slot order,
     //    which is compaction order); per depth rank its tile count, rectangle,
-    //    mask and slot; exclusive scan -> pair offsets
+    //    mask and slot; exclusive scan -> pair offsets.  A visible slot emits
+    //    at least one pair, so within the pair capacity there are at most
+    //    min(N, capacity) of them (beyond it the counts read 0): the launches
+    //    over visible slots are sized by that bound
+    const uint32_t Nv = (uint32_t)std::min<int64_t>(n_slots, std::max<int64_t>(pair_capacity, 1));
     bool alt = false;
-    GS_HIP(radix_sort_pairs(w.dkeys, w.dvals, w.dkeys_alt, w.dvals_alt, N, 0, 32, w.hist, s, &alt, w.cnt,
+    GS_HIP(radix_sort_pairs(w.dkeys, w.dvals, w.dkeys_alt, w.dvals_alt, Nv, 0, 32, w.hist, s, &alt, w.cnt,
                             /*small_tiles=*/true));
     const uint32_t* sorted_pos = alt ? w.dvals_alt : w.dvals;
-    GS_HIP(launch_gather_sorted(sorted_pos, w.desc, N, w.cnt, w.tiles_s, w.rect_s, w.mask_s, w.slot_s, s));
-    GS_HIP(exclusive_scan_u32(w.tiles_s, w.offsets, N, w.scan_tmp, w.total + 8, s, w.cnt));
+    GS_HIP(launch_gather_sorted(sorted_pos, w.desc, Nv, w.cnt, w.tiles_s, w.rect_s, w.mask_s, w.slot_s, s));
+    GS_HIP(exclusive_scan_u32(w.tiles_s, w.offsets, Nv, w.scan_tmp, w.total + 8, s, w.cnt));
     // 3. expand into (tile, slot) pairs in depth order, then stable sort by tile id
     const int bits = tile_bits(vt.total_tiles);
     const int passes = radix_passes(Pc, 0, bits);
     uint32_t* vals_primary = (passes % 2 == 0) ? pair_vals : w.pvals_alt;
     uint32_t* vals_alt = (passes % 2 == 0) ? w.pvals_alt : pair_vals;
-    GS_HIP(launch_emit_pairs(w.offsets, w.rect_s, pr.tile_mask ? w.mask_s : nullptr, w.slot_s, N, Pc, w.cnt, w.pkeys,
+    GS_HIP(launch_emit_pairs(w.offsets, w.rect_s, pr.tile_mask ? w.mask_s : nullptr, w.slot_s, Nv, Pc, w.cnt, w.pkeys,
                              vals_primary, s));
     bool palt = false;
     GS_HIP(radix_sort_pairs(w.pkeys, vals_primary, w.pkeys_alt, vals_alt, Pc, 0, bits, w.hist, s, &palt, w.cnt + 1));
