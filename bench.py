@@ -198,7 +198,7 @@ def train_config(gs, torch, S, scene, cams, opts, tgt, steps, warmup, depth_term
         return P
 
     with torch.no_grad():
-        _, per_f = step_times(torch, fwd, steps, 3)
+        _, per_f = step_times(torch, fwd, steps, warmup)
         assert not fwd().overflowed()
         proj = gs.project(*pd, cams, opts)
         pv, rg, P = gs.bin_sort(proj, cams, scene.n)
@@ -304,7 +304,7 @@ def main():
             gs.render_fwd(proj, pv, rg, cams, opts)
             return P
 
-        _, per_fwd = step_times(torch, fwd, args.steps, 3)
+        _, per_fwd = step_times(torch, fwd, args.steps, args.warmup)
         assert not fwd().overflowed()
         ms_fwd = pct(per_fwd, 50)
         # workload statistics for the cost models (outside the timed regions)

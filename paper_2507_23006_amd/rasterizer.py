@@ -150,17 +150,9 @@ class PairCount:
     def __init__(self, dev_count: torch.Tensor, capacity: int):
         self.capacity = int(capacity)
         self._host = torch.empty((1,), dtype=torch.int64, pin_memory=True)
-        # the copy runs on the second stream, so that the main stream's next
-        # launches do not queue behind it
-        written = torch.cuda.Event()
-        written.record(torch.cuda.current_stream(dev_count.device))
-        side = _side_stream(dev_count.device)
-        side.wait_event(written)
-        dev_count.record_stream(side)
-        with torch.cuda.stream(side):
-            self._host.copy_(dev_count, non_blocking=True)
+        self._host.copy_(dev_count, non_blocking=True)
         self._event = torch.cuda.Event()
-        self._event.record(side)
+        self._event.record()
 
     def __int__(self) -> int:
         self._event.synchronize()
