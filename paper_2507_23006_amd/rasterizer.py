@@ -314,6 +314,12 @@ def _grad_struct(grads: dict) -> L.GsGaussiansGrad:
     return go
 
 
+# Gaussian count from which the backward zeroes the gradient arrays on a
+# second stream (below it the two cross-stream waits cost more than the
+# fill saves)
+FILL_BESIDE_MIN = 1 << 21
+
+
 def _zeroed_grads(params, app, after: torch.cuda.Event, n: int):
     """Gradient arrays shaped like the parameters (and `app`), zeroed by
     gs_grads_zero on a second stream once the main stream has reached
@@ -367,21 +373,31 @@ def render_bwd(params, cams, opts: RenderOptions, proj: Projected, pair_vals, ra
     cams_c, opt_c, proj_c = L.make_cameras(cams), opts.c(), proj.c()
     _mark("bwd_begin")
     main = torch.cuda.current_stream(dev)
-    before = torch.cuda.Event()
-    before.record(main)
+    beside = n >= FILL_BESIDE_MIN
+    if beside:
+        before = torch.cuda.Event()
+        before.record(main)
     L.check(lib.gs_composite_bwd(C.byref(proj_c), _ptr(pair_vals), _ptr(ranges), cams_c, V, C.byref(opt_c), _ptr(T),
                                  _ptr(last), _ptr(d_rgb), _ptr(d_depth), _ptr(d_alpha), int(bool(opts.absgrad)), n * V,
                                  g2, seg_ptr, seg_bytes, seg_ready, _stream()))
-    # the gradient arrays are zeroed on a second stream beside the
-    # compositing backward (issue-bound, it leaves most of the memory
-    # bandwidth free; beside binning or the compositing forward the fill
-    # slows them by more than it saves); the projection backward then
-    # writes the seen Gaussians' rows only
-    grads, zeroed = _zeroed_grads(params, app, before, n)
-    _mark("composite_bwd")
-    main.wait_event(zeroed)
+    if beside:
+        # the gradient arrays are zeroed on a second stream beside the
+        # compositing backward (issue-bound, it leaves most of the memory
+        # bandwidth free; beside binning or the compositing forward the
+        # fill slows them by more than it saves); the projection backward
+        # then writes the seen Gaussians' rows only
+        grads, zeroed = _zeroed_grads(params, app, before, n)
+        _mark("composite_bwd")
+        main.wait_event(zeroed)
+    else:
+        # few Gaussians: the projection backward writes every row itself
+        # (the two cross-stream waits would cost more than the fill saves)
+        grads = {k: torch.empty_like(t) for k, t in zip(("means", "scales", "quats", "opacities", "sh"), params)}
+        if app is not None:
+            grads["app"] = torch.empty_like(app)
+        _mark("composite_bwd")
     L.check(lib.gs_project_bwd(C.byref(g), cams_c, V, C.byref(opt_c), C.byref(proj_c), g2, C.byref(_grad_struct(grads)),
-                               _ptr(norm), _ptr(absg), 1, _stream()))
+                               _ptr(norm), _ptr(absg), int(beside), _stream()))
     _mark("project_bwd")
     grads["mean2d_grad_norm"] = norm
     grads["absgrad"] = absg

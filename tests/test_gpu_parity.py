@@ -370,7 +370,13 @@ def test_projection_backward_with_and_without_zeroed_outputs(gpu_lib):
     npx = sum(c.width * c.height for c in cams)
     gen = torch.Generator(device="cuda").manual_seed(8)
     d = [torch.randn(sh, device="cuda", generator=gen) for sh in ((npx, 3), (npx,), (npx,))]
-    ref = gpu_lib.render_bwd(params, cams, opts, proj, pairs, ranges, out["T"], out["last"], *d)
+    R = gpu_lib.rasterizer
+    keep = R.FILL_BESIDE_MIN
+    R.FILL_BESIDE_MIN = 0       # the second-stream fill at any size
+    try:
+        ref = gpu_lib.render_bwd(params, cams, opts, proj, pairs, ranges, out["T"], out["last"], *d)
+    finally:
+        R.FILL_BESIDE_MIN = keep
     torch.cuda.synchronize()
     seen = (proj.tiles.view(len(cams), -1) > 0).any(0)
     assert 0 < int(seen.sum()) < scene.n
