@@ -290,6 +290,7 @@ def main():
         prev = ev
     for k in stage_ms:
         stage_ms[k] /= n_inst
+    del marks     # recorded events kept alive make later runs stall now and then
     # the interval ending at bwd_begin is the loss (torch ops between the two passes)
     if "bwd_begin" in stage_ms:
         stage_ms["loss"] = stage_ms.pop("bwd_begin")

@@ -292,7 +292,8 @@ const float *gs_render_bwd_grad2d(void *ws);
  * is launched on (binning: around the whole gs_bin_sort sequence);
  * gs_kernel_timing_read waits for the recorded pairs of one kernel, returns
  * their summed elapsed time and count, and forgets them.  Enabling or
- * disabling forgets every pending pair.  For benchmarks: the event records
+ * disabling forgets every pending pair; disabling also waits for and
+ * releases the library's timing events.  For benchmarks: the event records
  * cost about a microsecond per launch. */
 #define GS_KERNEL_PROJECT_FWD 0   /* k_project_fwd */
 #define GS_KERNEL_BIN_SORT 1      /* the binning launches of one gs_bin_sort */

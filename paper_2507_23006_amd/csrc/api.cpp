@@ -303,7 +303,19 @@ const char* gs_version(void) { return "gsmi-rasterizer 0.1 (gfx950)"; }
 
 int gs_kernel_timing(int32_t enable) {
     std::lock_guard<std::mutex> lk(g_timer_mu);
-    for (auto& p : g_timers) p.used = 0;
+    for (auto& p : g_timers) {
+        p.used = 0;
+        if (!enable) {
+            // disabling releases the pool: the runtime stalls now and then
+            // when many recorded events stay alive
+            for (auto& pr : p.ev) {
+                (void)hipEventSynchronize(pr.second);
+                (void)hipEventDestroy(pr.first);
+                (void)hipEventDestroy(pr.second);
+            }
+            p.ev.clear();
+        }
+    }
     g_timing.store(enable != 0);
     return GS_OK;
 }

@@ -11,6 +11,7 @@ row-major); ``split_views`` reshapes them into per-view images.
 from __future__ import annotations
 
 import ctypes as C
+import weakref
 from dataclasses import dataclass
 
 import torch
@@ -140,6 +141,35 @@ def project(means, scales, quats, opacities, sh, cams, opts: RenderOptions, app=
     return out
 
 
+class _PinnedRing:
+    """Pinned host slots for pair counts, taken round-robin, so that a loop
+    that runs ahead of the device does not allocate pinned memory on every
+    call.  A slot is reused only once the copy into it has completed; its
+    previous count is then kept in its PairCount before the slot is
+    overwritten (else a fresh pinned tensor is taken)."""
+
+    SLOTS = 256
+
+    def __init__(self):
+        self.buf = torch.empty((self.SLOTS,), dtype=torch.int64, pin_memory=True)
+        self.owners = [None] * self.SLOTS
+        self.next = 0
+
+    def take(self, pc: "PairCount"):
+        i = self.next
+        self.next = (i + 1) % self.SLOTS
+        prev = self.owners[i]() if self.owners[i] is not None else None
+        if prev is not None and prev._value is None:
+            if not prev._event.query():
+                return torch.empty((1,), dtype=torch.int64, pin_memory=True)
+            prev._value = int(prev._host[0])
+        self.owners[i] = weakref.ref(pc)
+        return self.buf[i:i + 1]
+
+
+_pinned_rings = {}
+
+
 class PairCount:
     """The pair count of an asynchronous binning: the library writes it to
     device memory; int() waits for that write (a copy to pinned host memory
@@ -149,14 +179,21 @@ class PairCount:
 
     def __init__(self, dev_count: torch.Tensor, capacity: int):
         self.capacity = int(capacity)
-        self._host = torch.empty((1,), dtype=torch.int64, pin_memory=True)
-        self._host.copy_(dev_count, non_blocking=True)
+        self._value = None
+        key = dev_count.device.index or 0
+        ring = _pinned_rings.get(key)
+        if ring is None:
+            ring = _pinned_rings[key] = _PinnedRing()
         self._event = torch.cuda.Event()
+        self._host = ring.take(self)
+        self._host.copy_(dev_count, non_blocking=True)
         self._event.record()
 
     def __int__(self) -> int:
-        self._event.synchronize()
-        return int(self._host[0])
+        if self._value is None:
+            self._event.synchronize()
+            self._value = int(self._host[0])
+        return self._value
 
     def overflowed(self) -> bool:
         return int(self) > self.capacity

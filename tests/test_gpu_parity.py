@@ -585,7 +585,8 @@ def test_async_binning_matches_and_reports_overflow(gpu_lib):
     make, cams, od = CASES["multiview"]
     scene = make()
     opts = _opts(gpu_lib, od)
-    proj = gpu_lib.project(*to_dev(scene), cams, opts)
+    params = to_dev(scene)
+    proj = gpu_lib.project(*params, cams, opts)
     pv, rg, P = gpu_lib.bin_sort(proj, cams, scene.n)
     pv2, rg2, P2 = gpu_lib.bin_sort(proj, cams, scene.n, sync=False, capacity_hint=P + 10)
     assert int(P2) == P and not P2.overflowed()
@@ -593,6 +594,15 @@ def test_async_binning_matches_and_reports_overflow(gpu_lib):
     pv3, rg3, P3 = gpu_lib.bin_sort(proj, cams, scene.n, sync=False, capacity_hint=P // 2)
     assert int(P3) == P and P3.overflowed()
     assert int(rg3.to(torch.int64).abs().sum()) == 0
+    # more asynchronous counts in flight than the pinned slots they are read
+    # through, two different counts alternating, read only at the end
+    half = gpu_lib.project(*params, cams[:1], opts)
+    P_half = int(gpu_lib.bin_sort(half, cams[:1], scene.n)[2])
+    assert P_half != P
+    n_ring = gpu_lib.rasterizer._PinnedRing.SLOTS
+    counts = [gpu_lib.bin_sort(*((proj, cams) if i % 2 == 0 else (half, cams[:1])), scene.n, sync=False,
+                               capacity_hint=P + 10)[2] for i in range(n_ring + 40)]
+    assert [int(c) for c in counts] == [P if i % 2 == 0 else P_half for i in range(len(counts))]
     ws = gpu_lib.rasterizer._default_ws
     key = (scene.n * len(cams), sum(c.n_tiles for c in cams))
     saved = ws.pair_caps.get(key)
