@@ -259,9 +259,9 @@ def main():
 
     # then, outside the timed region, stage times from stream events between
     # the library calls and the library's own events around each main
-    # kernel, over a separate run of at most 20 steps (an event per stage
-    # and step held until the end of a long run makes the runtime stall
-    # now and then, which the timed run must not see)
+    # kernel, over a separate run of at most 20 steps, each read out (and
+    # its events freed) before the next: many recorded events kept alive
+    # make the runtime stall now and then
     n_inst = min(args.steps, 20)
     marks = []
 
@@ -271,26 +271,27 @@ def main():
     gs.set_stage_hook(hook)
     gs.kernel_timing(True)
     torch.cuda.synchronize()
+    stage_ms, k_tot, k_cnt = {}, {}, {}
     for _ in range(n_inst):
+        marks.clear()
         marks.append(("start", _ev(torch)))
         step()
-    marks.append(("start", _ev(torch)))
-    torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        prev = None
+        for name, ev in marks:
+            if prev is not None and name != "start":
+                stage_ms[name] = stage_ms.get(name, 0.0) + prev.elapsed_time(ev)
+            prev = ev
+        for k in gs.rasterizer.KERNELS_TIMED:
+            tot, cnt = gs.kernel_timing_read(k)
+            k_tot[k] = k_tot.get(k, 0.0) + tot
+            k_cnt[k] = k_cnt.get(k, 0) + cnt
     gs.set_stage_hook(None)
-    kernel_ms = {}
-    for k in gs.rasterizer.KERNELS_TIMED:
-        tot, cnt = gs.kernel_timing_read(k)
-        if cnt:
-            kernel_ms[k] = tot / cnt
     gs.kernel_timing(False)
-    stage_ms, prev = {}, None
-    for name, ev in marks:
-        if prev is not None and name != "start":
-            stage_ms[name] = stage_ms.get(name, 0.0) + prev.elapsed_time(ev)
-        prev = ev
+    marks.clear()
+    kernel_ms = {k: k_tot[k] / k_cnt[k] for k in k_tot if k_cnt[k]}
     for k in stage_ms:
         stage_ms[k] /= n_inst
-    del marks     # recorded events kept alive make later runs stall now and then
     # the interval ending at bwd_begin is the loss (torch ops between the two passes)
     if "bwd_begin" in stage_ms:
         stage_ms["loss"] = stage_ms.pop("bwd_begin")
