@@ -50,7 +50,16 @@ hipEvent_t timer_begin(int kernel, hipStream_t s) {
 }
 
 void timer_end(hipEvent_t closing, hipStream_t s) {
-    if (closing) (void)hipEventRecord(closing, s);
+    if (!closing) return;
+    // the pool may have been released (timing disabled from another thread)
+    // since timer_begin handed the event out
+    std::lock_guard<std::mutex> lk(g_timer_mu);
+    for (const auto& p : g_timers)
+        for (size_t i = 0; i < p.used && i < p.ev.size(); ++i)
+            if (p.ev[i].second == closing) {
+                (void)hipEventRecord(closing, s);
+                return;
+            }
 }
 
 namespace host {
