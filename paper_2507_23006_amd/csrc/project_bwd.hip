@@ -11,10 +11,13 @@
 // scales, quats, opacity, appearance) into LDS rows of the span that start
 // at zero and are streamed out whole at the end, so every cache line of
 // those arrays is written once and completely instead of in two partial
-// halves (zeros, then the seen Gaussians' values).  Only a small
-// fraction of a large scene is in view, so the compaction keeps the FP64
-// chain on full waves and the parameter reads on the Gaussians that need
-// them; 2D gradients of unseen slots are never read.  With
+// halves (zeros, then the seen Gaussians' values).  When the outputs were
+// zeroed beforehand (k_zero_floats on a second stream beside the
+// compositing backward), the chain writes the seen Gaussians' entries
+// directly and the unseen ones are left alone.  Only a small fraction of a
+// large scene is in view, so the compaction keeps the FP64 chain on full
+// waves and the parameter reads on the Gaussians that need them; 2D
+// gradients of unseen slots are never read.  With
 // Sigma_2D = V V^T and V = (J W) M, M = R(q) diag(s), the covariance
 // gradient flows as dV = 2 G V, d(JW) = dV M^T, dM += (JW)^T dV; dM is
 // accumulated over views and pushed through R(q) and s once at the end.
