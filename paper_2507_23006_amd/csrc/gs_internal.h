@@ -101,6 +101,41 @@ __device__ __forceinline__ void sh_eval_basis(Real x, Real y, Real z, int degree
     Y[15] = -(Real)ShK::k9 * x * (xx - (Real)3 * yy);
 }
 
+// Copies the first cnt entries of a workgroup's list (local index | view
+// mask << 16) to out, grouped by the mask's low 8 bits, so that the lanes
+// of a wave share few views and a loop over the views of a launch runs
+// fewer passes per wave.  The order inside a group is arbitrary (each entry
+// is handled alone, so results do not depend on it).  Every thread of the
+// workgroup (at least 64) calls it; hist holds 256 counters.
+__device__ __forceinline__ void group_by_views(const uint32_t* list, uint32_t cnt, uint32_t* out, uint32_t* hist) {
+    for (uint32_t b = threadIdx.x; b < 256u; b += blockDim.x) hist[b] = 0u;
+    __syncthreads();
+    for (uint32_t j = threadIdx.x; j < cnt; j += blockDim.x) atomicAdd(&hist[(list[j] >> 16) & 255u], 1u);
+    __syncthreads();
+    if (threadIdx.x < 64) {      // exclusive scan of the 256 counters, four per lane
+        const uint32_t l = threadIdx.x;
+        const uint32_t a0 = hist[4 * l], a1 = hist[4 * l + 1], a2 = hist[4 * l + 2], a3 = hist[4 * l + 3];
+        const uint32_t sum = a0 + a1 + a2 + a3;
+        uint32_t incl = sum;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(incl, off, 64);
+            if ((int)l >= off) incl += y;
+        }
+        const uint32_t base = incl - sum;
+        hist[4 * l] = base;
+        hist[4 * l + 1] = base + a0;
+        hist[4 * l + 2] = base + a0 + a1;
+        hist[4 * l + 3] = base + a0 + a1 + a2;
+    }
+    __syncthreads();
+    for (uint32_t j = threadIdx.x; j < cnt; j += blockDim.x) {
+        const uint32_t e = list[j];
+        out[atomicAdd(&hist[(e >> 16) & 255u], 1u)] = e;
+    }
+    __syncthreads();
+}
+
 }  // namespace gs
 
 // ---------------------------------------------------------------------------

@@ -296,6 +296,8 @@ __device__ __forceinline__ void list_append(uint32_t cand, int loc, int lane, ui
 __global__ __launch_bounds__(kPF, 4) void k_project_fwd(GaussPtrs gp, int64_t n, ViewTable vt, OptK opt,
                                                      Projected out) {
     __shared__ uint32_t s_list[kPFSpan];
+    __shared__ uint32_t s_group[kPFSpan];   // the list grouped by view mask (several views)
+    __shared__ uint32_t s_hist[256];
     __shared__ float s_par[7][kPFSpan];     // listed Gaussians' mean, scales, opacity
     __shared__ uint32_t s_count;
     const int tid = threadIdx.x, lane = tid & 63;
@@ -368,8 +370,13 @@ __global__ __launch_bounds__(kPF, 4) void k_project_fwd(GaussPtrs gp, int64_t n,
     }
     __syncthreads();
     const uint32_t cnt = s_count;
+    const uint32_t* lst = s_list;
+    if (vt.n_views > 1) {      // Gaussians that are candidates in the same views side by side
+        group_by_views(s_list, cnt, s_group, s_hist);
+        lst = s_group;
+    }
     for (uint32_t j = tid; j < cnt; j += kPF) {
-        const uint32_t e = s_list[j];
+        const uint32_t e = lst[j];
         const int loc = (int)(e & 0xFFFFu);
         const float mu[3] = {s_par[0][loc], s_par[1][loc], s_par[2][loc]};
         const float sc[3] = {s_par[3][loc], s_par[4][loc], s_par[5][loc]};

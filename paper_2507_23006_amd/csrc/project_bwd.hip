@@ -324,6 +324,8 @@ __global__ __launch_bounds__(kPB) void k_project_bwd(GaussPtrs gp, int64_t n, Vi
                                                      Projected proj, const float* __restrict__ grad2d, GradPtrs out,
                                                      float* __restrict__ mean2d_norm, float* __restrict__ absgrad) {
     __shared__ uint32_t s_list[kSpan];     // local index | view mask << 16
+    __shared__ uint32_t s_group[kSpan];    // the list grouped by view mask (several views)
+    __shared__ uint32_t s_hist[256];
     __shared__ uint8_t s_seen[kSpan];
     __shared__ uint32_t s_count;
     // the span's gradient rows: zeros, then the chain's values, then one
@@ -382,10 +384,16 @@ __global__ __launch_bounds__(kPB) void k_project_bwd(GaussPtrs gp, int64_t n, Vi
         for (int q = tid; q < 12 * rows; q += kPB)
             if (!s_seen[q / 12]) __builtin_nontemporal_store(F4{0.0f, 0.0f, 0.0f, 0.0f}, dsh + q);
 
-    // pass 2: the chain, one thread per seen Gaussian
+    // pass 2: the chain, one thread per seen Gaussian (with several views,
+    // Gaussians seen by the same views side by side)
     const uint32_t cnt = s_count;
+    const uint32_t* lst = s_list;
+    if (vt.n_views > 1) {
+        group_by_views(s_list, cnt, s_group, s_hist);
+        lst = s_group;
+    }
     for (uint32_t j = tid; j < cnt; j += kPB) {
-        const uint32_t e = s_list[j];
+        const uint32_t e = lst[j];
         const int64_t g = g0 + (e & 0xFFFFu);
         if (kZeroed)
             project_bwd_one(gp, n, vt, opt, grad2d, out, g, e >> 16, OutRows{out, n, g});
