@@ -66,6 +66,8 @@ def parse():
     ap.add_argument("--cpu-crop", type=int, default=16, help="oracle baseline renders 1/crop of the pixels")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving trace")
     ap.add_argument("--no-configs", action="store_true", help="skip the C1, C2 and C5 lines")
+    ap.add_argument("--config", choices=("C1", "C2", "C5"), default=None,
+                    help="time only this configuration's step (for profiling) and print its record")
     ap.add_argument("--serve-requests", type=int, default=2000, help="requests of the serving trace")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-MiB device buffer 3 times (reference kernel for HBM byte counters)")
@@ -231,6 +233,10 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     gs.load()
+    if args.config:
+        rec = other_configs(gs, torch, S, args, not args.no_cpu, only=args.config)[args.config]
+        print(json.dumps({"config": args.config, **rec}), flush=True)
+        return
     dev = torch.device("cuda:0")
     t_gen = time.time()
     scene = S.scene_c3(seed=0)
@@ -385,7 +391,7 @@ def main():
     print(json.dumps(rec), flush=True)
 
 
-def other_configs(gs, torch, S, args, with_cpu):
+def other_configs(gs, torch, S, args, with_cpu, only=None):
     """C1 (4096 Gaussians, 160x120), C2 (1M, 1600x1066) and C5 (12M, eight
     views, 25.57 Mpix per launch): step times on the GPU beside the oracle
     on the host (C1 whole, C2 and C5 on a cropped sample)."""
@@ -397,6 +403,8 @@ def other_configs(gs, torch, S, args, with_cpu):
         ("C5", lambda: (S.scene_urban(12_000_000, 400, seed=0), S.cameras_c5()), True, True, 64),
     ]
     for name, make, aa, depth_term, crop in specs:
+        if only and name != only:
+            continue
         t = time.time()
         scene, cams = make()
         tgt_rgb = torch.cat([torch.from_numpy(S.target_rgb(c.height, c.width, seed=1)).view(-1, 3) for c in cams]).to(dev)

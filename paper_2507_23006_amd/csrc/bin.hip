@@ -96,14 +96,23 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit_pairs(const uint32_t* __r
     const uint32_t n_pairs = counts ? min(counts[1], n_pairs_max) : n_pairs_max;
     const uint32_t p0 = blockIdx.x * kEmitChunk;
     if (p0 >= n_pairs) return;
-    if (threadIdx.x == 0) {
-        // last d with offsets[d] <= p0 (offsets[0] == 0 <= p0)
+    if (threadIdx.x < 64) {
+        // last d with offsets[d] <= p0 (offsets[0] == 0 <= p0; offsets never
+        // decrease): a 64-way search by the first wave, one probe per lane,
+        // so the chain of dependent loads is log64(n) long, not log2(n)
+        const int lane = threadIdx.x;
         uint32_t lo = 0, hi = n;      // invariant: offsets[lo] <= p0, answer in [lo, hi)
         while (hi - lo > 1) {
-            const uint32_t mid = lo + (hi - lo) / 2;
-            if (offsets[mid] <= p0) lo = mid; else hi = mid;
+            const uint32_t step = (hi - lo + 63) / 64;
+            const uint32_t q = lo + (uint32_t)lane * step;
+            const bool le = lane == 0 || (q < hi && offsets[q] <= p0);
+            const unsigned long long m = __ballot(le);      // lanes 0 .. L hold: offsets are sorted
+            const uint32_t L = 63u - (uint32_t)__clzll(m);
+            const uint32_t nlo = lo + L * step;
+            hi = min(hi, nlo + step);
+            lo = nlo;
         }
-        s_d0 = lo;
+        if (lane == 0) s_d0 = lo;
     }
     __syncthreads();
     const uint32_t d0 = s_d0;
@@ -135,15 +144,24 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit_pairs(const uint32_t* __r
     }
 }
 
-__global__ void k_tile_ranges(const uint32_t* __restrict__ keys, uint32_t n_max, const uint32_t* __restrict__ counts,
-                              uint2* __restrict__ ranges, uint32_t n_tiles) {
+// kRangePer pairs per thread, kRangeThreads apart (coalesced), so that each
+// wave keeps several loads in flight instead of one round trip per wave
+constexpr int kRangeThreads = 256, kRangePer = 4;
+
+__global__ __launch_bounds__(kRangeThreads) void k_tile_ranges(const uint32_t* __restrict__ keys, uint32_t n_max,
+                                                               const uint32_t* __restrict__ counts,
+                                                               uint2* __restrict__ ranges, uint32_t n_tiles) {
     const uint32_t n = counts ? min(counts[1], n_max) : n_max;
-    const uint32_t p = blockIdx.x * 256 + threadIdx.x;
-    if (p >= n) return;
-    const uint32_t k = keys[p];
-    if (k >= n_tiles) return;     // keys are tile ids by construction; guards the write
-    if (p == 0 || keys[p - 1] != k) ranges[k].x = p;
-    if (p == n - 1 || keys[p + 1] != k) ranges[k].y = p + 1;
+    const uint32_t base = blockIdx.x * (kRangeThreads * kRangePer) + threadIdx.x;
+#pragma unroll
+    for (int j = 0; j < kRangePer; ++j) {
+        const uint32_t p = base + j * kRangeThreads;
+        if (p >= n) break;
+        const uint32_t k = keys[p];
+        if (k >= n_tiles) continue;     // keys are tile ids by construction; guards the write
+        if (p == 0 || keys[p - 1] != k) ranges[k].x = p;
+        if (p == n - 1 || keys[p + 1] != k) ranges[k].y = p + 1;
+    }
 }
 
 // The binning's sizes from the visibility scan: visible slots (total[0]) and
@@ -189,14 +207,8 @@ __global__ __launch_bounds__(kOrderThreads) void k_tile_order(const uint2* __res
     __syncthreads();
     for (uint32_t t = tid; t < n_tiles; t += kOrderThreads) atomicAdd(&s_cnt[order_bucket(ranges[t])], 1u);
     __syncthreads();
-    if (tid == 0) {
-        uint32_t run = 0;
-        for (int b = 0; b < kOrderBuckets; ++b) {
-            const uint32_t c = s_cnt[b];
-            s_cnt[b] = run;
-            run += c;
-        }
-    }
+    static_assert(kOrderBuckets == 256, "one wave scans the buckets, four per lane");
+    if (tid < 64) wave_excl_scan256(s_cnt);
     __syncthreads();
     for (uint32_t t = tid; t < n_tiles; t += kOrderThreads) {
         const uint32_t at = atomicAdd(&s_cnt[order_bucket(ranges[t])], 1u);
@@ -241,8 +253,9 @@ hipError_t launch_tile_ranges(const uint32_t* sorted_keys, uint32_t n_pairs, con
                               uint32_t n_tiles, hipStream_t s) {
     hipError_t e = fill_u32(ranges, 0u, (size_t)n_tiles * 2, s);
     if (e != hipSuccess || !n_pairs) return e;
-    hipLaunchKernelGGL(k_tile_ranges, dim3((n_pairs + 255) / 256), dim3(256), 0, s, sorted_keys, n_pairs, counts,
-                       reinterpret_cast<uint2*>(ranges), n_tiles);
+    constexpr uint32_t per_block = kRangeThreads * kRangePer;
+    hipLaunchKernelGGL(k_tile_ranges, dim3((n_pairs + per_block - 1) / per_block), dim3(kRangeThreads), 0, s,
+                       sorted_keys, n_pairs, counts, reinterpret_cast<uint2*>(ranges), n_tiles);
     return hipGetLastError();
 }
 

@@ -101,6 +101,25 @@ __device__ __forceinline__ void sh_eval_basis(Real x, Real y, Real z, int degree
     Y[15] = -(Real)ShK::k9 * x * (xx - (Real)3 * yy);
 }
 
+// In-place exclusive scan of 256 counters in LDS by one whole wave (the
+// calling threads are exactly the 64 lanes of one wave), four per lane.
+__device__ __forceinline__ void wave_excl_scan256(uint32_t* c) {
+    const uint32_t l = threadIdx.x & 63u;
+    const uint32_t a0 = c[4 * l], a1 = c[4 * l + 1], a2 = c[4 * l + 2], a3 = c[4 * l + 3];
+    const uint32_t sum = a0 + a1 + a2 + a3;
+    uint32_t incl = sum;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(incl, off, 64);
+        if ((int)l >= off) incl += y;
+    }
+    const uint32_t base = incl - sum;
+    c[4 * l] = base;
+    c[4 * l + 1] = base + a0;
+    c[4 * l + 2] = base + a0 + a1;
+    c[4 * l + 3] = base + a0 + a1 + a2;
+}
+
 // Copies the first cnt entries of a workgroup's list (local index | view
 // mask << 16) to out, grouped by the mask's low 8 bits, so that the lanes
 // of a wave share few views and a loop over the views of a launch runs
@@ -112,22 +131,7 @@ __device__ __forceinline__ void group_by_views(const uint32_t* list, uint32_t cn
     __syncthreads();
     for (uint32_t j = threadIdx.x; j < cnt; j += blockDim.x) atomicAdd(&hist[(list[j] >> 16) & 255u], 1u);
     __syncthreads();
-    if (threadIdx.x < 64) {      // exclusive scan of the 256 counters, four per lane
-        const uint32_t l = threadIdx.x;
-        const uint32_t a0 = hist[4 * l], a1 = hist[4 * l + 1], a2 = hist[4 * l + 2], a3 = hist[4 * l + 3];
-        const uint32_t sum = a0 + a1 + a2 + a3;
-        uint32_t incl = sum;
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const uint32_t y = __shfl_up(incl, off, 64);
-            if ((int)l >= off) incl += y;
-        }
-        const uint32_t base = incl - sum;
-        hist[4 * l] = base;
-        hist[4 * l + 1] = base + a0;
-        hist[4 * l + 2] = base + a0 + a1;
-        hist[4 * l + 3] = base + a0 + a1 + a2;
-    }
+    if (threadIdx.x < 64) wave_excl_scan256(hist);
     __syncthreads();
     for (uint32_t j = threadIdx.x; j < cnt; j += blockDim.x) {
         const uint32_t e = list[j];

@@ -969,6 +969,7 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* s_wave
 // one workgroup scan of the threads' totals, not one per 1024 tiles; the
 // counts of up to kPlanCache tiles stay in LDS between the two passes.
 constexpr uint32_t kPlanCache = 32640;
+constexpr int kPlanBatch = 8;
 __global__ __launch_bounds__(1024) void k_seg_plan(const uint2* __restrict__ ranges,
                                                    const uint32_t* __restrict__ tile_order, ViewTable vt,
                                                    uint32_t capacity, uint32_t* __restrict__ work_off,
@@ -976,20 +977,37 @@ __global__ __launch_bounds__(1024) void k_seg_plan(const uint2* __restrict__ ran
     __shared__ uint32_t s_wave[16];
     __shared__ uint16_t s_nseg[kPlanCache];
     const uint32_t n_tiles = (uint32_t)vt.total_tiles;
-    auto nseg_of = [&](uint32_t i) -> uint32_t {
-        const uint2 r = ranges[order_tile(tile_order, vt, i)];
-        const uint32_t L = r.y - r.x;
-        return L > (uint32_t)kSegLen ? (L + kSegLen - 1) / kSegLen : 1u;
+    // segment counts of the launch positions [ib, min(ib + kPlanBatch, end))
+    auto nseg_batch = [&](uint32_t ib, uint32_t end, uint32_t* c) {
+        int t[kPlanBatch];
+#pragma unroll
+        for (int u = 0; u < kPlanBatch; ++u) t[u] = ib + u < end ? order_tile(tile_order, vt, ib + u) : -1;
+        uint2 r[kPlanBatch];
+#pragma unroll
+        for (int u = 0; u < kPlanBatch; ++u) r[u] = t[u] >= 0 ? ranges[t[u]] : make_uint2(0u, 0u);
+#pragma unroll
+        for (int u = 0; u < kPlanBatch; ++u) {
+            const uint32_t L = r[u].y - r[u].x;
+            c[u] = L > (uint32_t)kSegLen ? (L + kSegLen - 1) / kSegLen : 1u;
+        }
     };
     const uint32_t k = (n_tiles + 1023) / 1024;
     const uint32_t i0 = threadIdx.x * k, i1 = min(i0 + k, n_tiles);
-    // pass 1: the thread's segment total (cached counts below 2^16)
+    // pass 1: the thread's segment total (cached counts below 2^16).  The
+    // positions are read kPlanBatch at a time, all loads first, so a thread
+    // waits for one round of gathers per batch instead of one per position
     uint32_t mine = 0, big = 0;
-    for (uint32_t i = i0; i < i1; ++i) {
-        const uint32_t c = nseg_of(i);
-        mine += c;
-        if (i < kPlanCache) s_nseg[i] = (uint16_t)c;
-        big |= c > 0xFFFFu ? 1u : 0u;
+    for (uint32_t ib = i0; ib < i1; ib += kPlanBatch) {
+        uint32_t c[kPlanBatch];
+        nseg_batch(ib, i1, c);
+#pragma unroll
+        for (int u = 0; u < kPlanBatch; ++u) {
+            const uint32_t i = ib + u;
+            if (i >= i1) break;
+            mine += c[u];
+            if (i < kPlanCache) s_nseg[i] = (uint16_t)c[u];
+            big |= c[u] > 0xFFFFu ? 1u : 0u;
+        }
     }
     // the threads' prefix and the total (do the states fit?), and whether
     // any count was too large for the cache
@@ -1001,12 +1019,19 @@ __global__ __launch_bounds__(1024) void k_seg_plan(const uint2* __restrict__ ran
     const bool cached = total_big == 0;
     // pass 2: each position's offsets from the thread's exclusive prefix
     uint32_t w = on ? before_seg : i0, st = on ? before_seg - i0 : 0u;
-    for (uint32_t i = i0; i < i1; ++i) {
-        const uint32_t c = on ? (cached && i < kPlanCache ? (uint32_t)s_nseg[i] : nseg_of(i)) : 1u;
-        work_off[i] = w;
-        state_off[i] = st;
-        w += c;
-        st += c - 1u;
+    for (uint32_t ib = i0; ib < i1; ib += kPlanBatch) {
+        uint32_t c[kPlanBatch];
+        if (on && !(cached && ib + kPlanBatch <= kPlanCache)) nseg_batch(ib, i1, c);
+#pragma unroll
+        for (int u = 0; u < kPlanBatch; ++u) {
+            const uint32_t i = ib + u;
+            if (i >= i1) break;
+            const uint32_t ci = on ? (cached && i < kPlanCache ? (uint32_t)s_nseg[i] : c[u]) : 1u;
+            work_off[i] = w;
+            state_off[i] = st;
+            w += ci;
+            st += ci - 1u;
+        }
     }
     if (threadIdx.x == 1023) {
         work_off[n_tiles] = on ? total_seg : n_tiles;
