@@ -235,7 +235,7 @@ def main():
     gs.load()
     if args.config:
         rec = other_configs(gs, torch, S, args, not args.no_cpu, only=args.config)[args.config]
-        print(json.dumps({"config": args.config, **rec}), flush=True)
+        print(json.dumps({"configuration": args.config, **rec}), flush=True)
         return
     dev = torch.device("cuda:0")
     t_gen = time.time()
