@@ -42,6 +42,17 @@ def oblique_cam(W, H, f):
     return S.Camera(f, f, W / 2.0, H / 2.0, S.look_at((1.6, -1.1, -3.3), (0.05, 0.1, 0.0), up=(0.3, -1, 0.2)), W, H)
 
 
+def ring_cam(k, n=12):
+    """One of n narrow views around the unit box from different directions,
+    so that Gaussians are seen by many different subsets of the views."""
+    a = 0.9 * np.pi * k / n
+    sizes = ((48, 40), (64, 48), (37, 29), (80, 60))
+    W, H = sizes[k % len(sizes)]
+    eye = (3.5 * np.sin(a), 0.6 * np.sin(3 * a), -3.5 * np.cos(a))
+    target = (0.4 * np.sin(2 * a), 0.3 * np.cos(3 * a), 0.0)
+    return S.Camera(4.0 * W, 4.0 * W, W / 2.0, H / 2.0, S.look_at(eye, target, up=(0.0, -1.0, 0.0)), W, H)
+
+
 CASES = {
     # name: (scene factory, cams, options)
     "c1": (lambda: S.scene_c1(), [S.camera_c1()], dict(aa=False)),
@@ -49,6 +60,9 @@ CASES = {
                   dict(aa=True, bg=(0.1, 0.2, 0.3))),
     "multiview": (lambda: S.random_scene(2500, seed=6, log_scale_mu=-2.5),
                   [S.camera_c1(), oblique_cam(100, 70, 80.0), small_cam(37, 53, 40.0)], dict(aa=True, sh_degree=2)),
+    # twelve views: view masks beyond the low 8 bits, many distinct view sets per workgroup
+    "manyview": (lambda: S.random_scene(1800, seed=8, log_scale_mu=-2.6), [ring_cam(k) for k in range(12)],
+                 dict(aa=True)),
 }
 
 
