@@ -66,6 +66,8 @@ def parse():
     ap.add_argument("--cpu-crop", type=int, default=16, help="oracle baseline renders 1/crop of the pixels")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving trace")
     ap.add_argument("--no-configs", action="store_true", help="skip the C1, C2 and C5 lines")
+    ap.add_argument("--serve-only", action="store_true",
+                    help="run only the serving trace (for profiling) and print its record")
     ap.add_argument("--config", choices=("C1", "C2", "C5"), default=None,
                     help="time only this configuration's step (for profiling) and print its record")
     ap.add_argument("--serve-requests", type=int, default=2000, help="requests of the serving trace")
@@ -240,6 +242,11 @@ def main():
     dev = torch.device("cuda:0")
     t_gen = time.time()
     scene = S.scene_c3(seed=0)
+    if args.serve_only:
+        opts = gs.RenderOptions(sh_degree=3, dilation=0.3, aa=True, absgrad=False)
+        serve = serve_bench(gs, S, torch, scene, opts, args.serve_requests, with_cpu=False)
+        print(json.dumps({"serving": serve}), flush=True)
+        return
     cam = S.camera_c3(seed=2)
     cams = [cam]
     H, W = cam.height, cam.width
