@@ -396,34 +396,110 @@ __device__ __forceinline__ int segment_of(const SlotSeg* __restrict__ segs, int3
 
 // Views with their own selections of Gaussians (served requests): slot s
 // maps to Gaussian gstart + (s - slot_start) of its segment, seen by the
-// segment's view.  Same two passes as k_project_fwd, over 1024 slots.
-__global__ __launch_bounds__(kPF) void k_project_slots(GaussPtrs gp, int64_t n, ViewTable vt, OptK opt,
-                                                       const SlotSeg* __restrict__ segs, int32_t n_seg,
-                                                       uint32_t n_slots, Projected out) {
+// segment's view.  Same two passes as k_project_fwd, over 1024 slots, with
+// the values pass 1 read kept in LDS for pass 2; the segments that the
+// workgroup's slots fall in are staged in LDS when there are at most
+// kSlotSegCache of them (else each slot searches them in global memory).
+constexpr int kSlotSegCache = 128;
+__global__ __launch_bounds__(kPF, 4) void k_project_slots(GaussPtrs gp, int64_t n, ViewTable vt, OptK opt,
+                                                          const SlotSeg* __restrict__ segs, int32_t n_seg,
+                                                          uint32_t n_slots, Projected out) {
     __shared__ uint32_t s_list[kPFSpan];
+    __shared__ float s_par[7][kPFSpan];     // listed slots' mean, scales, opacity
+    __shared__ uint32_t s_gid[kPFSpan];     // listed slots' Gaussian (n < 2^32, checked at launch)
+    __shared__ SlotSeg s_seg[kSlotSegCache];
+    __shared__ int32_t s_seg_lo, s_seg_n;
     __shared__ uint32_t s_count;
     const int tid = threadIdx.x, lane = tid & 63;
     const uint32_t s0 = blockIdx.x * kPFSpan;
-    if (tid == 0) s_count = 0;
+    // the segments of this workgroup's slots, staged in LDS when few
+    if (tid == 0) {
+        s_count = 0;
+        const int32_t lo = segment_of(segs, n_seg, s0);
+        const int32_t hi = segment_of(segs, n_seg, min(s0 + (uint32_t)kPFSpan, n_slots) - 1u);
+        s_seg_lo = lo;
+        s_seg_n = hi - lo + 1;
+    }
     __syncthreads();
+    const int32_t seg_lo = s_seg_lo, seg_n = s_seg_n;
+    const bool staged = seg_n <= kSlotSegCache;
+    if (staged)
+        for (int k = tid; k < seg_n; k += kPF) s_seg[k] = segs[seg_lo + k];
+    __syncthreads();
+    // the thread's kPFSpan / kPF slots move through each phase together, so
+    // that their independent loads are in flight at once
+    constexpr uint32_t kNone = 0xFFFFFFFFu;      // no slot (n < 2^32, so no Gaussian has this index)
+    uint32_t g[kPFPer], view[kPFPer];
+#pragma unroll
+    for (int i = 0; i < kPFPer; ++i) {
+        const uint32_t s = s0 + i * kPF + tid;
+        g[i] = kNone;
+        view[i] = 0;
+        if (s < n_slots) {
+            SlotSeg sg;
+            if (staged) {
+                int lo = 0, hi = seg_n;      // invariant: s_seg[lo].slot_start <= s, answer in [lo, hi)
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (s_seg[mid].slot_start <= s) lo = mid; else hi = mid;
+                }
+                sg = s_seg[lo];
+            } else {
+                sg = segs[seg_lo + segment_of(segs + seg_lo, seg_n, s)];
+            }
+            g[i] = (uint32_t)(sg.gstart + (int64_t)(s - sg.slot_start));
+            view[i] = sg.view;
+        }
+    }
+    float mu[kPFPer][3];
+#pragma unroll
+    for (int i = 0; i < kPFPer; ++i) {
+        const bool ok = g[i] != kNone;
+        mu[i][0] = ok ? gp.means[g[i]] : 0.0f;
+        mu[i][1] = ok ? gp.means[n + g[i]] : 0.0f;
+        mu[i][2] = ok ? gp.means[2 * n + g[i]] : 0.0f;
+    }
+    bool front[kPFPer];
+#pragma unroll
+    for (int i = 0; i < kPFPer; ++i) {
+        front[i] = false;
+        if (g[i] == kNone) continue;
+        const ViewK& V = vt.v[view[i]];
+        double tx, ty, tz;
+        view_point(V, mu[i][0], mu[i][1], mu[i][2], tx, ty, tz);
+        front[i] = tz >= (double)V.znear && tz <= (double)V.zfar;
+    }
+    float sc[kPFPer][3], op[kPFPer];
+#pragma unroll
+    for (int i = 0; i < kPFPer; ++i) {
+        sc[i][0] = sc[i][1] = sc[i][2] = op[i] = 0.0f;
+        if (front[i]) {
+            sc[i][0] = gp.scales[g[i]];
+            sc[i][1] = gp.scales[n + g[i]];
+            sc[i][2] = gp.scales[2 * n + g[i]];
+            op[i] = gp.opac[g[i]];
+        }
+    }
     for (int i = 0; i < kPFPer; ++i) {
         const int loc = i * kPF + tid;
-        const uint32_t s = s0 + loc;
+        const uint32_t s = s0 + (uint32_t)loc;
         uint32_t cand = 0;
-        if (s < n_slots) {
-            const SlotSeg sg = segs[segment_of(segs, n_seg, s)];
-            const int64_t g = sg.gstart + (int64_t)(s - sg.slot_start);
-            const ViewK& V = vt.v[sg.view];
-            double tx, ty, tz;
-            view_point(V, gp.means[g], gp.means[n + g], gp.means[2 * n + g], tx, ty, tz);
-            if (tz >= (double)V.znear && tz <= (double)V.zfar) {
-                const double smax = fmax(fabs((double)gp.scales[g]),
-                                         fmax(fabs((double)gp.scales[n + g]), fabs((double)gp.scales[2 * n + g])));
-                if (may_cover(V, opt, tx, ty, tz, smax, gp.opac[g])) cand = 1u << sg.view;
+        if (g[i] != kNone) {
+            if (front[i]) {
+                const ViewK& V = vt.v[view[i]];
+                double tx, ty, tz;
+                view_point(V, mu[i][0], mu[i][1], mu[i][2], tx, ty, tz);
+                const double smax = fmax(fabs((double)sc[i][0]), fmax(fabs((double)sc[i][1]), fabs((double)sc[i][2])));
+                if (may_cover(V, opt, tx, ty, tz, smax, op[i])) cand = 1u << view[i];
             }
             if (!cand) {
                 out.tiles[s] = 0u;
                 out.dkey[s] = 0xFFFFFFFFu;
+            } else {
+                s_par[0][loc] = mu[i][0]; s_par[1][loc] = mu[i][1]; s_par[2][loc] = mu[i][2];
+                s_par[3][loc] = sc[i][0]; s_par[4][loc] = sc[i][1]; s_par[5][loc] = sc[i][2];
+                s_par[6][loc] = op[i];
+                s_gid[loc] = g[i];
             }
         }
         list_append(cand, loc, lane, s_list, &s_count);
@@ -432,13 +508,12 @@ __global__ __launch_bounds__(kPF) void k_project_slots(GaussPtrs gp, int64_t n, 
     const uint32_t cnt = s_count;
     for (uint32_t j = tid; j < cnt; j += kPF) {
         const uint32_t e = s_list[j];
-        const uint32_t s = s0 + (e & 0xFFFFu);
-        const SlotSeg sg = segs[segment_of(segs, n_seg, s)];
-        const int64_t g = sg.gstart + (int64_t)(s - sg.slot_start);
+        const int loc = (int)(e & 0xFFFFu);
+        const uint32_t s = s0 + (uint32_t)loc;
         // one view bit: the slot is s itself (stride 0)
-        const float mu[3] = {gp.means[g], gp.means[n + g], gp.means[2 * n + g]};
-        const float sc[3] = {gp.scales[g], gp.scales[n + g], gp.scales[2 * n + g]};
-        project_candidate(gp, n, vt, opt, out, g, e >> 16, (int64_t)s, 0, mu, sc, gp.opac[g]);
+        const float mu1[3] = {s_par[0][loc], s_par[1][loc], s_par[2][loc]};
+        const float sc1[3] = {s_par[3][loc], s_par[4][loc], s_par[5][loc]};
+        project_candidate(gp, n, vt, opt, out, (int64_t)s_gid[loc], e >> 16, (int64_t)s, 0, mu1, sc1, s_par[6][loc]);
     }
 }
 
@@ -457,6 +532,7 @@ hipError_t launch_project_slots(const GaussPtrs& g, int64_t n, const ViewTable& 
                                 const SlotSeg* segs, int32_t n_seg, uint32_t n_slots, const Projected& out,
                                 hipStream_t s) {
     if (!n_slots) return hipSuccess;
+    if (n > 0xFFFFFFFFLL) return hipErrorInvalidValue;     // listed Gaussians are kept as 32-bit indices
     hipLaunchKernelGGL(k_project_slots, dim3((n_slots + kPFSpan - 1) / kPFSpan), dim3(kPF), 0, s, g, n, vt, opt, segs,
                        n_seg, n_slots, out);
     return hipGetLastError();
